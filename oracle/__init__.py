@@ -1,0 +1,42 @@
+"""CPU oracle for frequency-response evaluation -- TEST INFRASTRUCTURE ONLY.
+
+Nothing in the product path may import, call or execute this package: only
+the test-suite, the smoke check and the CPU-baseline leg of the benchmark use
+it.  It shares no code with the GPU library (no kernels, headers, helpers or
+constants); the only thing both sides see is the seeded input generator,
+which holds none of the method's arithmetic.
+
+What it computes (all plain, slow and in float64 unless stated):
+
+* ``freqresp``           the definition G(jw) = C (jw I - A)^{-1} B + D, one
+                         dense LU with partial pivoting per frequency
+                         (LAPACK zgesv through numpy.linalg.solve);
+* ``freqresp_extended``  the same solve followed by iterative refinement whose
+                         residual and iterate are held in extended precision
+                         (x87 80-bit ``clongdouble``); the oracle of record for
+                         ill-conditioned points;
+* ``cond2``              2-norm condition number of jw I - A per frequency;
+* ``rel_err``            the per-frequency relative Frobenius error metric;
+* ``exact.freqresp_exact``  exact rational evaluation for tiny systems;
+* ``hessenberg.hessenberg`` unblocked Householder reduction to upper
+                         Hessenberg form with Q^T B and C Q.
+
+The mathematical problem: for a continuous-time LTI system
+x' = A x + B u, y = C x + D u, the transfer matrix evaluated on the imaginary
+axis s = jw is G(jw) = C (jw I - A)^{-1} B + D (any linear-systems text, e.g.
+Kailath, *Linear Systems*, 1980, ch. 2).  The paper this project follows is
+silent on this problem; every function here cites the textbook or published
+method it restates instead.
+"""
+from .freqresp import freqresp, freqresp_extended, cond2, rel_err, rel_err_max
+from . import exact, hessenberg
+
+__all__ = [
+    "freqresp",
+    "freqresp_extended",
+    "cond2",
+    "rel_err",
+    "rel_err_max",
+    "exact",
+    "hessenberg",
+]

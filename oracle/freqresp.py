@@ -1,0 +1,119 @@
+"""Frequency response by the definition -- oracle (test infrastructure only).
+
+G(jw_k) = C (jw_k I - A)^{-1} B + D  for every w_k.
+
+Each frequency is one dense complex solve with partial pivoting (LAPACK
+zgesv through ``numpy.linalg.solve``), exactly the textbook definition: form
+M = jw I - A, solve M X = B, return C X + D.  No Hessenberg form, no shared
+factorisation between frequencies, no reordering.
+
+``freqresp_extended`` adds classical iterative refinement (Wilkinson 1963;
+Higham, *Accuracy and Stability of Numerical Algorithms*, 2nd ed., ch. 12):
+the correction equation is solved with the float64 LU, while the residual
+r = B - M X and the iterate X are held in extended precision
+(``np.clongdouble``, 64-bit significand, unit roundoff 2^-64).  The limiting
+forward error is then about kappa(M) * 2^-64 instead of kappa(M) * 2^-53.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["freqresp", "freqresp_extended", "cond2", "rel_err", "rel_err_max"]
+
+
+def _check(A, B, C, D, omega):
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    n = A.shape[0]
+    if A.shape != (n, n):
+        raise ValueError("A must be square")
+    m = B.shape[1]
+    p = C.shape[0]
+    if B.shape != (n, m) or C.shape != (p, n):
+        raise ValueError("B must be n x m and C p x n")
+    D = np.zeros((p, m)) if D is None else np.asarray(D, dtype=np.float64)
+    if D.shape != (p, m):
+        raise ValueError("D must be p x m")
+    omega = np.atleast_1d(np.asarray(omega, dtype=np.float64))
+    return A, B, C, D, omega
+
+
+def freqresp(A, B, C, D, omega, chunk: int = 256) -> np.ndarray:
+    """G[k] = C (j omega[k] I - A)^{-1} B + D, shape (K, p, m), complex128.
+
+    Frequencies are stacked ``chunk`` at a time into one batched
+    ``numpy.linalg.solve`` call; each matrix in the stack is still factored on
+    its own with partial pivoting.
+    """
+    A, B, C, D, omega = _check(A, B, C, D, omega)
+    n = A.shape[0]
+    K = omega.shape[0]
+    G = np.empty((K, C.shape[0], B.shape[1]), dtype=np.complex128)
+    eye = np.eye(n)
+    Bc = B.astype(np.complex128)
+    for k0 in range(0, K, chunk):
+        w = omega[k0:k0 + chunk]
+        M = 1j * w[:, None, None] * eye[None, :, :] - A[None, :, :]
+        X = np.linalg.solve(M, np.broadcast_to(Bc, (len(w),) + Bc.shape))
+        G[k0:k0 + chunk] = C[None, :, :] @ X + D[None, :, :]
+    return G
+
+
+def freqresp_extended(A, B, C, D, omega, iters: int = 3, return_longdouble: bool = False):
+    """Oracle of record: float64 LU plus ``iters`` refinement steps with the
+    residual and the iterate in extended precision.
+
+    M = jw I - A is exact in clongdouble (its entries are float64 values).
+    Each step: r = B - M X (extended), d = LU \\ r (float64 solve of the
+    rounded residual), X = X + d (extended).  G = C X + D is formed in
+    extended precision and rounded once at the end.
+    """
+    A, B, C, D, omega = _check(A, B, C, D, omega)
+    n = A.shape[0]
+    K = omega.shape[0]
+    ld = np.clongdouble
+    A_ld = A.astype(ld)
+    B_ld = B.astype(ld)
+    C_ld = C.astype(ld)
+    D_ld = D.astype(ld)
+    eye = np.eye(n)
+    out = np.empty((K, C.shape[0], B.shape[1]), dtype=ld if return_longdouble else np.complex128)
+    for k, w in enumerate(omega):
+        M64 = 1j * w * eye - A
+        M_ld = (1j * np.longdouble(w)) * np.eye(n, dtype=ld) - A_ld
+        X = np.linalg.solve(M64, B.astype(np.complex128)).astype(ld)
+        for _ in range(iters):
+            r = B_ld - M_ld @ X
+            d = np.linalg.solve(M64, r.astype(np.complex128))
+            X = X + d.astype(ld)
+        G = C_ld @ X + D_ld
+        out[k] = G if return_longdouble else G.astype(np.complex128)
+    return out
+
+
+def cond2(A, omega) -> np.ndarray:
+    """kappa_2(jw I - A) = sigma_max / sigma_min per frequency (SVD)."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    omega = np.atleast_1d(np.asarray(omega, dtype=np.float64))
+    out = np.empty(len(omega))
+    for k, w in enumerate(omega):
+        s = np.linalg.svd(1j * w * np.eye(n) - A, compute_uv=False)
+        out[k] = np.inf if s[-1] == 0 else s[0] / s[-1]
+    return out
+
+
+def rel_err(G, G_ref, floor: float = 1e-300) -> np.ndarray:
+    """err_k = ||G_k - G_ref,k||_F / max(||G_ref,k||_F, floor), shape (K,)."""
+    G = np.asarray(G)
+    G_ref = np.asarray(G_ref)
+    K = G_ref.shape[0]
+    num = np.linalg.norm((G - G_ref).reshape(K, -1).astype(np.complex128), axis=1)
+    den = np.linalg.norm(G_ref.reshape(K, -1).astype(np.complex128), axis=1)
+    return num / np.maximum(den, floor)
+
+
+def rel_err_max(G, G_ref) -> float:
+    e = rel_err(G, G_ref)
+    return float(e.max()) if e.size else 0.0

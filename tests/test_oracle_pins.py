@@ -1,0 +1,293 @@
+"""Pins for the CPU oracle: each checks it against something other than itself.
+
+Every pin is chosen so that a plausible slip in the oracle fails at least one:
+a wrong sign of jw (first-order imaginary part), a dropped D (first order with
+d != 0, brute force), A used transposed (companion form, brute force with a
+non-symmetric A), a wrong index or operand order (MIMO brute force,
+superposition), a broken refinement (ill-conditioned exact cases).
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact, hessenberg
+from paper_2401_04068_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.txt")
+
+
+def _first_order(a, b, c, d):
+    return (np.array([[-a]]), np.array([[b]]), np.array([[c]]), np.array([[d]]))
+
+
+def _second_order(wn, zeta):
+    A = np.array([[0.0, 1.0], [-wn * wn, -2.0 * zeta * wn]])
+    B = np.array([[0.0], [1.0]])
+    C = np.array([[wn * wn, 0.0]])
+    D = np.zeros((1, 1))
+    return A, B, C, D
+
+
+def _golden_rows():
+    rows = []
+    with open(GOLDEN) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            kind, *vals = line.split()
+            rows.append((kind, [float(v) for v in vals]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_rows(), ids=lambda r: f"{r[0]}-{r[1]}")
+def test_golden_closed_forms(row):
+    kind, (x1, x2, c, d, w, re, im) = row
+    sys_ = _first_order(x1, x2, c, d) if kind == "first" else _second_order(x1, x2)
+    G = oracle.freqresp(*sys_, [w])[0, 0, 0]
+    ref = complex(re, im)
+    assert abs(G - ref) <= 1e-14 * max(abs(ref), 1e-300) + 1e-300, (G, ref)
+
+
+def test_first_order_closed_form_grid():
+    a, b, c, d = 0.7, -1.3, 2.1, 0.4
+    w = np.concatenate([-np.logspace(-3, 3, 50), [0.0], np.logspace(-3, 3, 50)])
+    G = oracle.freqresp(*_first_order(a, b, c, d), w)[:, 0, 0]
+    ref = c * b * (a - 1j * w) / (a * a + w * w) + d
+    assert np.max(np.abs(G - ref) / np.abs(ref)) < 1e-14
+
+
+def test_second_order_textbook():
+    for wn, zeta in [(1.0, 0.1), (7.0, 1e-3), (50.0, 0.7)]:
+        w = np.logspace(-2, 3, 80) * wn / 10
+        G = oracle.freqresp(*_second_order(wn, zeta), w)[:, 0, 0]
+        ref = wn * wn / (wn * wn - w * w + 2j * zeta * wn * w)
+        assert np.max(np.abs(G - ref) / np.abs(ref)) < 1e-12
+        g = oracle.freqresp(*_second_order(wn, zeta), [wn])[0, 0, 0]
+        assert abs(abs(g) - 1.0 / (2.0 * zeta)) <= 1e-12 / zeta
+        assert abs(np.angle(g, deg=True) + 90.0) < 1e-9
+
+
+def _rand_small_int_system(rng, n, m, p):
+    A = rng.integers(-4, 5, (n, n)).astype(float)
+    B = rng.integers(-3, 4, (n, m)).astype(float)
+    C = rng.integers(-3, 4, (p, n)).astype(float)
+    D = rng.integers(-2, 3, (p, m)).astype(float)
+    return A, B, C, D
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_exact_rational(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 1 + seed % 4
+    m = 1 + (seed % 3)
+    p = 1 + ((seed + 1) % 3)
+    A, B, C, D = _rand_small_int_system(rng, n, m, p)
+    for w in [Fraction(0), Fraction(3, 8), Fraction(-5, 4), Fraction(7, 2), Fraction(33, 16)]:
+        try:
+            Gx = exact.freqresp_exact(A.tolist(), B.tolist(), C.tolist(), D.tolist(), w)
+        except ZeroDivisionError:
+            continue
+        Gref = np.array([[exact.to_complex(z) for z in row] for row in Gx])
+        G = oracle.freqresp(A, B, C, D, [float(w)])[0]
+        kappa = oracle.cond2(A, [float(w)])[0]
+        err = np.linalg.norm(G - Gref) / max(np.linalg.norm(Gref), 1e-300)
+        assert err <= 1e-15 * max(kappa, 1.0) * 10, (seed, w, err, kappa)
+
+
+def test_brute_force_catches_transpose():
+    """Sanity of the pin itself: A^T in place of A gives a different answer."""
+    rng = np.random.default_rng(7)
+    A, B, C, D = _rand_small_int_system(rng, 3, 2, 2)
+    w = Fraction(1, 2)
+    Gx = exact.freqresp_exact(A.T.tolist(), B.tolist(), C.tolist(), D.tolist(), w)
+    Gwrong = np.array([[exact.to_complex(z) for z in row] for row in Gx])
+    G = oracle.freqresp(A, B, C, D, [0.5])[0]
+    assert np.linalg.norm(G - Gwrong) > 1e-3 * np.linalg.norm(G)
+
+
+def test_conjugate_symmetry():
+    mdl = wl.mimo64(K=64)
+    G = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    Gm = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, -mdl.omega)
+    assert np.max(oracle.rel_err(Gm, np.conj(G))) < 1e-13
+
+
+def test_dc_gain():
+    mdl = wl.mimo64(K=4)
+    G0 = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, [0.0])[0]
+    dc = mdl.D - mdl.C @ np.linalg.solve(mdl.A, mdl.B)
+    assert np.max(np.abs(G0.imag)) == 0.0 or np.max(np.abs(G0.imag)) < 1e-14 * np.abs(dc).max()
+    assert np.linalg.norm(G0.real - dc) / np.linalg.norm(dc) < 1e-13
+
+
+def test_similarity_invariance():
+    mdl = wl.siso8()
+    rng = np.random.default_rng(11)
+    n = mdl.n
+    # T with kappa(T) about 10: orthogonal times a graded diagonal
+    U = wl.haar_orthogonal(rng, n)
+    T = U @ np.diag(np.logspace(0, 1, n))
+    Ti = np.linalg.inv(T)
+    G1 = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    G2 = oracle.freqresp(T @ mdl.A @ Ti, T @ mdl.B, mdl.C @ Ti, mdl.D, mdl.omega)
+    kappa = oracle.cond2(mdl.A, mdl.omega).max()
+    assert np.max(oracle.rel_err(G2, G1)) < 10 * kappa * 1e-15 * 10
+
+
+def _modal_freqresp(mdl, omega):
+    """D + (C Q)(jw I - Lambda)^{-1}(Q^T B) with closed-form block inverses:
+    scalar blocks 1/(jw - lam); 2x2 blocks [[x, y], [-y, x]] with
+    x = jw - sigma, y = -omega_d have inverse [[x, -y], [y, x]] / (x^2 + y^2)."""
+    Lam = mdl.Lam
+    n = mdl.n
+    CQ = mdl.C @ mdl.Q
+    QB = mdl.Q.T @ mdl.B
+    out = np.empty((len(omega), mdl.p, mdl.m), dtype=complex)
+    for k, w in enumerate(omega):
+        Y = np.zeros((n, mdl.m), dtype=complex)
+        i = 0
+        while i < n:
+            if i + 1 < n and Lam[i, i + 1] != 0.0:
+                x = 1j * w - Lam[i, i]
+                y = -Lam[i, i + 1]
+                det = x * x + y * y
+                Y[i] = (x * QB[i] - y * QB[i + 1]) / det
+                Y[i + 1] = (y * QB[i] + x * QB[i + 1]) / det
+                i += 2
+            else:
+                Y[i] = QB[i] / (1j * w - Lam[i, i])
+                i += 1
+        out[k] = CQ @ Y + mdl.D
+    return out
+
+
+@pytest.mark.parametrize("which", ["siso8", "mimo64"])
+def test_modal_form(which):
+    mdl = wl.siso8() if which == "siso8" else wl.mimo64(K=200)
+    G = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    Gm = _modal_freqresp(mdl, mdl.omega)
+    assert np.max(oracle.rel_err(G, Gm)) < 1e-12
+
+
+def test_high_frequency_asymptote():
+    mdl = wl.mimo64(K=4)
+    normA = np.linalg.norm(mdl.A, 2)
+    for w in [1e6, 1e8]:
+        G = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, [w])[0]
+        approx = mdl.C @ mdl.B / (1j * w)
+        rel = np.linalg.norm((G - mdl.D) - approx) / np.linalg.norm(approx)
+        assert rel < 3 * normA / w
+
+
+def test_mimo_superposition():
+    mdl = wl.mimo64(K=50)
+    G = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    for j in range(mdl.m):
+        Gj = oracle.freqresp(mdl.A, mdl.B[:, j:j + 1], mdl.C, mdl.D[:, j:j + 1], mdl.omega)
+        assert np.max(np.abs(Gj[:, :, 0] - G[:, :, j])) < 1e-13 * np.abs(G).max()
+
+
+def test_cond2_normal_closed_form():
+    mdl = wl.mimo64(K=100)
+    kap = oracle.cond2(mdl.A, mdl.omega)
+    d = np.abs(1j * mdl.omega[:, None] - mdl.poles[None, :])
+    ref = d.max(axis=1) / d.min(axis=1)
+    assert np.max(np.abs(kap - ref) / ref) < 1e-10
+
+
+def _exact_matrix(A, B, C, D, w):
+    Gx = exact.freqresp_exact(A.tolist(), B.tolist(), C.tolist(), D.tolist(), Fraction(w))
+    return np.array([[exact.to_complex(z) for z in row] for row in Gx])
+
+
+@pytest.mark.parametrize("case", ["rotation", "marginal"])
+def test_extended_oracle_ill_conditioned(case):
+    """Refinement with an extended-precision residual recovers the exact answer
+    where kappa * u64 is large."""
+    if case == "rotation":
+        eps = 2.0 ** -24
+        w0 = 1.5
+        A = np.array([[-eps, w0, 0.0], [-w0, -eps, 1.0], [0.0, 0.0, -2.0]])
+        w = w0
+    else:
+        A = np.array([[0.0, 3.0, 1.0], [-3.0, 0.0, 0.0], [0.0, 0.0, -1.0]])
+        w = 3.0 + 2.0 ** -22
+    B = np.array([[1.0, 0.0], [0.5, -1.0], [2.0, 1.0]])
+    C = np.array([[1.0, -2.0, 0.25], [0.0, 1.0, 3.0]])
+    D = np.array([[0.5, 0.0], [-1.0, 2.0]])
+    kappa = oracle.cond2(A, [w])[0]
+    assert kappa > 1e6
+    Gx = _exact_matrix(A, B, C, D, w)
+    Ge = oracle.freqresp_extended(A, B, C, D, [w])[0]
+    G64 = oracle.freqresp(A, B, C, D, [w])[0]
+    e_ext = np.linalg.norm(Ge - Gx) / np.linalg.norm(Gx)
+    e_64 = np.linalg.norm(G64 - Gx) / np.linalg.norm(Gx)
+    # limiting accuracy of refinement with an extended residual: about
+    # kappa * u_ext (Higham, ch. 12); the plain float64 solve sits near kappa * u64
+    u_ext = float(np.finfo(np.longdouble).eps)
+    assert u_ext < 2e-19
+    assert e_ext < kappa * u_ext + 4e-16, (e_ext, e_64, kappa)
+    assert e_ext < e_64 / 100, (e_ext, e_64)
+    assert e_64 < 1e-15 * kappa * 10
+
+
+def test_extended_matches_plain_when_well_conditioned():
+    mdl = wl.siso8()
+    Ge = oracle.freqresp_extended(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[::10])
+    G = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[::10])
+    assert np.max(oracle.rel_err(G, Ge)) < 1e-14
+
+
+def test_rel_err_metric():
+    G = np.ones((3, 2, 2), dtype=complex)
+    H = G.copy()
+    H[1, 0, 0] += 1e-3j
+    e = oracle.rel_err(H, G)
+    assert e[0] == 0 and e[2] == 0
+    assert abs(e[1] - 1e-3 / 2.0) < 1e-15
+
+
+# ------------------------------------------------------------ Hessenberg oracle
+
+@pytest.mark.parametrize("n", [3, 8, 33, 64])
+def test_hessenberg_invariants(n):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n))
+    B = rng.standard_normal((n, 3))
+    C = rng.standard_normal((2, n))
+    H, Bt, Ct, Q = hessenberg.hessenberg(A, B, C, want_q=True)
+    u = np.finfo(float).eps
+    assert np.all(H[np.tril_indices(n, -2)] == 0.0)
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) < 10 * n * u
+    assert np.linalg.norm(A @ Q - Q @ H) / np.linalg.norm(A) < 10 * n * u
+    assert np.allclose(Q[:, 0], np.eye(n)[:, 0])
+    assert np.linalg.norm(Bt - Q.T @ B) < 10 * n * u * np.linalg.norm(B)
+    assert np.linalg.norm(Ct - C @ Q) < 10 * n * u * np.linalg.norm(C)
+
+
+@pytest.mark.parametrize("n", [5, 16, 64])
+def test_hessenberg_matches_lapack(n):
+    """Implicit-Q theorem: same H up to a diagonal +-1 similarity."""
+    import scipy.linalg
+
+    rng = np.random.default_rng(1000 + n)
+    A = rng.standard_normal((n, n))
+    H, _, _ = hessenberg.hessenberg(A)
+    Hl = scipy.linalg.hessenberg(A)
+    Hn, _, _ = hessenberg.normalize_signs(H)
+    Hln, _, _ = hessenberg.normalize_signs(Hl)
+    assert np.max(np.abs(Hn - Hln)) < 1e-12 * np.abs(A).max() * n
+
+
+def test_hessenberg_preserves_transfer_function():
+    mdl = wl.mimo64(K=100)
+    H, Bt, Ct = hessenberg.hessenberg(mdl.A, mdl.B, mdl.C)
+    G1 = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    G2 = oracle.freqresp(H, Bt, Ct, mdl.D, mdl.omega)
+    assert np.max(oracle.rel_err(G2, G1)) < 1e-12
+    ev = np.sort_complex(np.linalg.eigvals(H))
+    assert np.max(np.abs(ev - np.sort_complex(mdl.poles))) < 1e-11
