@@ -1,0 +1,215 @@
+/*
+ * lti_freqresp.h -- C ABI of the MI355X frequency-response engine.
+ *
+ * Problem (the definition every entry point follows): for a continuous-time
+ * LTI state-space model  x' = A x + B u,  y = C x + D u  with nx states,
+ * nu inputs and ny outputs, evaluate the transfer matrix on the imaginary
+ * axis
+ *
+ *        G(j w_k) = C (j w_k I - A)^{-1} B + D ,   k = 0 .. n_omega-1 ,
+ *
+ * (Kailath, *Linear Systems*, 1980, ch. 2).  The method: one Householder
+ * reduction H = Q^T A Q to upper Hessenberg form per model (Golub & Van
+ * Loan, *Matrix Computations*, 4th ed., sec. 7.4.3), after which every
+ * frequency costs one shifted Hessenberg solve (Laub, "Efficient
+ * multivariable frequency response computations", IEEE TAC 26(2), 1981):
+ *
+ *        G(j w) = (C Q) (j w I - H)^{-1} (Q^T B) + D .
+ *
+ * The shifted solve is done with Givens rotations (one unitary column
+ * rotation per subdiagonal entry) fused with column back-substitution.
+ * Two precisions exist: plain float64, and complex-float32 solves with
+ * float64 residual-based iterative refinement (Higham, *Accuracy and
+ * Stability of Numerical Algorithms*, 2nd ed., ch. 12) whose stalled points
+ * fall back to float64.
+ *
+ * Serving model: a context owns a scheduler thread.  submit() copies a
+ * request's host inputs and returns at once; the scheduler admits requests
+ * as arena memory allows, reduces each model once (reduced models with a
+ * nonzero model_key stay resident for repeat queries), and batches the
+ * per-frequency solves of all live requests into shared kernel launches.
+ * poll() collects a finished request.
+ *
+ * Conventions for every entry point:
+ *   - All matrices are float64, row-major, densely packed.
+ *   - Complex outputs are interleaved (re, im) float64 pairs.
+ *   - Functions return 0 (LTI_OK) on success, LTI_PENDING (> 0) where
+ *     documented, and a negative LTI_E* code on error.  Nothing throws or
+ *     aborts across this boundary.
+ *   - One internal mutex per context; every call may come from any thread.
+ */
+#ifndef LTI_FREQRESP_H
+#define LTI_FREQRESP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LTI_ABI_VERSION 1u
+
+/* ---------------------------------------------------------------- codes */
+#define LTI_OK            0
+#define LTI_PENDING       1   /* poll(): request not finished yet          */
+#define LTI_EINVAL      (-1)  /* bad argument: NULL, dims <= 0, non-finite  */
+#define LTI_ENOSPC      (-2)  /* request can never fit in the arena budget  */
+#define LTI_EAGAIN      (-3)  /* pending queue full; retry after a poll()   */
+#define LTI_ENOENT      (-4)  /* unknown or already collected id / key      */
+#define LTI_EDEVICE     (-5)  /* HIP error; the context is unusable         */
+#define LTI_ENOMEM      (-6)  /* host allocation failed                     */
+#define LTI_EUNSUPPORTED (-7) /* dimensions outside what the kernels cover  */
+
+/* request.precision */
+#define LTI_PREC_FP64     0   /* float64 Givens solve per frequency          */
+#define LTI_PREC_REFINED  1   /* complex-float32 solves + float64 refinement */
+
+/* request.mem */
+#define LTI_MEM_HOST      0   /* A,B,C,D,omega,G_out,info_out are host memory   */
+#define LTI_MEM_DEVICE    1   /* ... are device memory on the context's device */
+
+/* lti_point_info.path */
+#define LTI_PATH_FP64      0  /* plain float64 solve                          */
+#define LTI_PATH_REFINED   1  /* float32 solves, float64 refinement converged  */
+#define LTI_PATH_FALLBACK  2  /* refinement stalled; float64 solve used        */
+#define LTI_PATH_SINGULAR  3  /* j w I - A singular to working precision       */
+
+/* config.flags */
+#define LTI_CFG_KERNEL_TIMING 1u  /* bracket every kernel launch with HIP events */
+
+/* Per-frequency result information, 8 bytes. */
+typedef struct lti_point_info {
+  float   est_rel_err;  /* estimated relative error of G(j w_k) (see below) */
+  uint8_t iters;        /* float32 solves used (refined path); 1 for fp64   */
+  uint8_t path;         /* LTI_PATH_*                                        */
+  uint16_t reserved;
+} lti_point_info;
+/* est_rel_err: for LTI_PATH_REFINED the last correction norm
+ * ||dX||_F / ||X||_F; for LTI_PATH_FP64 / _FALLBACK the product of the
+ * float64 unit roundoff and the ratio of the largest to the smallest
+ * diagonal entry of the triangular factor (a lower bound on kappa). */
+
+/* Create-time configuration. */
+typedef struct lti_config {
+  uint32_t abi_version;   /* must equal LTI_ABI_VERSION                          */
+  int32_t  device;        /* HIP device ordinal                                  */
+  void*    arena;         /* caller-owned device memory, 256-byte aligned; the
+                             library sub-allocates inside it and never frees it */
+  size_t   arena_bytes;   /* size of the arena = the HBM budget                  */
+  void*    stream;        /* hipStream_t to launch on (must stay valid until
+                             destroy); NULL: the library creates its own        */
+  int32_t  max_pending;   /* bound on submitted, not yet collected requests;
+                             <= 0 selects 8192                                   */
+  uint32_t flags;         /* LTI_CFG_*                                            */
+  int32_t  tile_points;   /* frequencies per wave tile; 0 = automatic            */
+  int32_t  max_batch_tiles; /* tiles per kernel launch; 0 = automatic            */
+  size_t   host_staging_bytes; /* pinned host staging for host-memory requests;
+                                  0 selects 256 MiB.  Requests that do not fit
+                                  fall back to (slower) pageable copies         */
+} lti_config;
+
+/* One request: one model evaluated on one frequency grid. */
+typedef struct lti_request {
+  int32_t nx, nu, ny;     /* n >= 1, m >= 1, p >= 1                              */
+  int32_t mem;            /* LTI_MEM_HOST or LTI_MEM_DEVICE                      */
+  const double* A;        /* nx*nx                                               */
+  const double* B;        /* nx*nu                                               */
+  const double* C;        /* ny*nx                                               */
+  const double* D;        /* ny*nu; NULL means D = 0                             */
+  const double* omega;    /* n_omega frequencies in rad/s, any finite value      */
+  int64_t  n_omega;       /* >= 1                                                */
+  int32_t  precision;     /* LTI_PREC_*                                          */
+  int32_t  reserved0;     /* must be 0                                           */
+  double   rtol;          /* refined path: stop when ||dX||/||X|| <= rtol / 10;
+                             <= 0 selects 1e-10                                   */
+  uint64_t model_key;     /* 0: no reuse.  Otherwise the reduced model stays
+                             resident and later requests with the same key,
+                             dimensions and (host memory) content reuse it     */
+  double*  G_out;         /* n_omega*ny*nu complex = 2*n_omega*ny*nu doubles,
+                             layout [k][i][j] (re, im)                           */
+  lti_point_info* info_out; /* optional, n_omega entries                          */
+} lti_request;
+/* Ownership: with LTI_MEM_HOST, submit() copies A, B, C, D and omega before
+ * it returns; G_out and info_out must stay valid until poll() reports the
+ * request done (or until destroy()).  With LTI_MEM_DEVICE nothing is copied:
+ * every pointer must stay valid and unmodified until the request is done,
+ * and inputs are not checked for finiteness. */
+
+/* Result of a finished request (filled by poll()). */
+typedef struct lti_result {
+  int32_t status;           /* LTI_OK, or the error that ended the request   */
+  int32_t reduction_reused; /* 1 when a resident reduced model was reused    */
+  int64_t n_points;
+  int64_t n_refined, n_fallback, n_singular;
+  double  max_est_rel_err;
+  double  t_submit_us;      /* microseconds since the context was created    */
+  double  t_admit_us;
+  double  t_first_launch_us;
+  double  t_done_us;        /* results visible to poll()                     */
+} lti_result;
+
+/* Counters of one context. */
+typedef struct lti_stats {
+  uint64_t requests_submitted, requests_done, requests_failed;
+  uint64_t reductions, reduction_cache_hits;
+  uint64_t sweep_launches, tiles_launched, points_done;
+  uint64_t arena_bytes_in_use, arena_peak_bytes;
+  /* with LTI_CFG_KERNEL_TIMING: summed HIP-event durations */
+  double   sweep_kernel_ms;
+  double   reduce_kernel_ms;
+  uint64_t timed_sweep_launches, timed_reduce_launches;
+} lti_stats;
+
+typedef struct lti_ctx lti_ctx;
+
+/* Create a context on config->device.  Validates the config (abi_version,
+ * non-NULL arena of at least 1 MiB, 256-byte alignment), creates the stream
+ * if none is given, and starts the scheduler thread.
+ * Returns LTI_OK and *out, or LTI_EINVAL / LTI_EDEVICE / LTI_ENOMEM. */
+int lti_freqresp_create(const lti_config* config, lti_ctx** out);
+
+/* Queue one request and return without waiting for the GPU.
+ * LTI_EINVAL: NULL pointers, dims <= 0, n_omega <= 0, unknown precision or
+ *             mem, non-finite host input.
+ * LTI_EUNSUPPORTED: nx > 256, or nu or ny > 16.
+ * LTI_ENOSPC: the request alone needs more than the whole arena.
+ * LTI_EAGAIN: max_pending requests are outstanding.
+ * LTI_EDEVICE: the context saw a HIP error.
+ * On LTI_OK, *out_id identifies the request for poll(). */
+int lti_freqresp_submit(lti_ctx* ctx, const lti_request* req, uint64_t* out_id);
+
+/* Wait up to timeout_us microseconds (< 0: forever, 0: do not wait) for
+ * request id.  Returns LTI_OK with *out filled once the request is done (the
+ * id is then collected: a second poll gives LTI_ENOENT), LTI_PENDING if it is
+ * still running, LTI_ENOENT for an unknown id, or the request's own error
+ * (also reported in out->status) if it failed. */
+int lti_freqresp_poll(lti_ctx* ctx, uint64_t id, int32_t timeout_us, lti_result* out);
+
+/* Stop the scheduler, wait for the device work already launched, release
+ * every sub-allocation and the context.  Requests not yet collected are
+ * dropped; their output buffers may be partly written.  The arena itself is
+ * not freed (it belongs to the caller). */
+int lti_freqresp_destroy(lti_ctx* ctx);
+
+/* Copy the resident reduced model of (model_key, nx, nu, ny) to host memory:
+ * H (nx*nx, upper Hessenberg, zeros below the subdiagonal), Bt = Q^T B
+ * (nx*nu) and Ct = C Q (ny*nx), all row-major float64.  Any of the three
+ * pointers may be NULL.  Waits for the reduction to finish.
+ * Returns LTI_ENOENT if no such model is resident. */
+int lti_freqresp_get_reduced(lti_ctx* ctx, uint64_t model_key, int32_t nx, int32_t nu,
+                             int32_t ny, double* H, double* Bt, double* Ct);
+
+/* Snapshot of the context's counters. */
+int lti_freqresp_stats(lti_ctx* ctx, lti_stats* out);
+
+/* Static description of a return code; never NULL. */
+const char* lti_freqresp_strerror(int code);
+
+/* LTI_ABI_VERSION of the loaded library. */
+uint32_t lti_freqresp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTI_FREQRESP_H */

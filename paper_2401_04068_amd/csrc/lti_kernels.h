@@ -1,0 +1,96 @@
+// Internal interface between the runtime (runtime.cpp) and the HIP kernels
+// (reduce.hip, sweep.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lti_freqresp.h"
+
+namespace lti {
+
+// Packed column-major upper Hessenberg storage: column j holds rows
+// 0 .. min(j+1, n-1), so column j starts at j(j+3)/2 and the whole matrix
+// takes (n-1)(n+2)/2 + n entries.
+__host__ __device__ inline int64_t hoff(int j) { return (int64_t)j * (j + 3) / 2; }
+__host__ __device__ inline int64_t hlen(int n) { return (int64_t)(n - 1) * (n + 2) / 2 + n; }
+
+// The resident reduced model of one state-space system, all in one arena
+// block.  H = Q^T A Q (packed), Bt = Q^T B (n x m row-major), Ct = (C Q)^T
+// (n x p row-major, so row i holds column i of C Q), D (p x m row-major),
+// plus float32 copies of H, Bt and Ct for the refined path.
+struct ReducedModel {
+  double* H;
+  double* Bt;
+  double* Ct;
+  double* D;
+  float* H32;
+  float* Bt32;
+  float* Ct32;
+  int n, m, p, pad;
+};
+
+size_t reduced_bytes(int n, int m, int p);
+void reduced_layout(void* base, int n, int m, int p, ReducedModel* out);
+
+// One reduction job: read A, B, C, D (device pointers, row-major; D may be
+// null), write the reduced model.  `work` is a scratch area of
+// reduce_work_bytes(n, m, p) bytes (unused when the model fits in LDS).
+struct ReduceJob {
+  const double* A;
+  const double* B;
+  const double* C;
+  const double* D;
+  ReducedModel out;
+  double* work;
+};
+
+constexpr int kMaxReduceN = 1024;
+// Whether the working matrix of an (n, m, p) model fits in LDS, the LDS bytes
+// that kernel needs, and the global scratch bytes the other kernel needs.
+bool reduce_fits_lds(int n, int m, int p);
+size_t reduce_lds_bytes(int n, int m, int p);
+size_t reduce_work_bytes(int n, int m, int p);
+// Launch jobs[0..njobs) (device array) of one kind (lds or global);
+// lds_bytes is the largest reduce_lds_bytes() among LDS jobs.
+hipError_t launch_reduce(const ReduceJob* jobs, int njobs, bool lds, size_t lds_bytes,
+                         hipStream_t s);
+
+// Per-request descriptor, resident in device memory while the request lives.
+struct ReqDesc {
+  const double* H;
+  const double* Bt;
+  const double* Ct;
+  const double* D;
+  const float* H32;
+  const float* Bt32;
+  const float* Ct32;
+  const double* omega;
+  double* G;
+  lti_point_info* info;
+  int n, m, p, precision;
+  double rtol;
+};
+
+// A tile: `count` consecutive frequencies of one request, solved by one
+// wavefront.
+struct TileDesc {
+  const ReqDesc* rd;
+  uint32_t start;
+  uint32_t count;
+};
+static_assert(sizeof(TileDesc) == 16, "TileDesc must stay 16 bytes");
+
+// Sweep kernel classes: precision x rows-per-lane (1, 2, 4 -> n <= 64, 128,
+// 256) x right-hand-side capacity (1, 2, 4, 8, 16).
+constexpr int kNumRowClasses = 3;
+constexpr int kNumRhsClasses = 5;
+constexpr int kNumSweepClasses = 2 * kNumRowClasses * kNumRhsClasses;
+constexpr int kMaxN = 256;
+constexpr int kMaxRhs = 16;
+int sweep_class(int precision, int n, int m);
+hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, hipStream_t s);
+
+}  // namespace lti

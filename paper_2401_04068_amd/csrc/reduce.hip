@@ -1,0 +1,234 @@
+// Householder reduction to upper Hessenberg form, one workgroup per model.
+//
+// For k = 0 .. n-3 a reflector P_k = I - tau v v^T (v[k+1] = 1, LAPACK
+// dlarfg sign convention: P_k x = beta e_1, beta = -sign(x_1) ||x||)
+// annihilates column k below the subdiagonal, and is applied from the left
+// to rows k+1..n-1 of [A | B] and from the right to columns k+1..n-1 of
+// [A ; C] (Golub & Van Loan, Matrix Computations, 4th ed., Algorithm 7.4.2).
+// At the end the working matrix holds H = Q^T A Q, Q^T B and C Q.
+//
+// The augmented (n+p) x (n+m) working matrix W = [[A, B], [C, *]] lives in
+// LDS when it fits (n <= 128 with m, p <= 8 does: at most 149 KB of the
+// 160 KB per CU), otherwise in a global scratch area that stays hot in L2.
+// W is column-major with an odd leading dimension so that the row-strided
+// accesses of the right update spread over the LDS banks.
+//
+// Every reflector costs three workgroup barriers: build v (wave 0), left
+// update (groups of 16 lanes per column: dot product, then rank-1 update of
+// the same column), right update (groups of 16 lanes per row).
+#include "lti_kernels.h"
+
+namespace lti {
+
+namespace {
+
+constexpr int kGroup = 16;
+
+__device__ __forceinline__ double group_sum16(double x) {
+  x += __shfl_xor(x, 8, 64);
+  x += __shfl_xor(x, 4, 64);
+  x += __shfl_xor(x, 2, 64);
+  x += __shfl_xor(x, 1, 64);
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+  x += __shfl_xor(x, 32, 64);
+  x += __shfl_xor(x, 16, 64);
+  return group_sum16(x);
+}
+
+__host__ __device__ inline int ld_of(int n, int p) { return (n + p) | 1; }
+
+template <int NT, bool kLds>
+__global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ jobs) {
+  extern __shared__ double smem[];
+  const ReduceJob job = jobs[blockIdx.x];
+  const int n = job.out.n, m = job.out.m, p = job.out.p;
+  const int ldw = ld_of(n, p);
+  const int ncol = n + m;
+  const int nrow = n + p;
+  const int tid = threadIdx.x;
+  double* W;
+  double* v;
+  double* sc;
+  if (kLds) {
+    W = smem;
+    v = smem + (size_t)ldw * ncol;
+  } else {
+    W = job.work;
+    v = smem;
+  }
+  sc = v + n;
+
+  // load [[A, B], [C, *]] column-major
+  for (int idx = tid; idx < nrow * ncol; idx += NT) {
+    const int i = idx % nrow;
+    const int c = idx / nrow;
+    double x = 0.0;
+    if (i < n) {
+      x = (c < n) ? job.A[(size_t)i * n + c] : job.B[(size_t)i * m + (c - n)];
+    } else if (c < n) {
+      x = job.C[(size_t)(i - n) * n + c];
+    }
+    W[(size_t)i + (size_t)ldw * c] = x;
+  }
+  __syncthreads();
+
+  const int lane16 = tid & (kGroup - 1);
+  const int group = tid / kGroup;
+  constexpr int kGroups = NT / kGroup;
+
+  for (int k = 0; k + 2 < n; ++k) {
+    double* colk = W + (size_t)ldw * k;
+    if (tid < 64) {
+      const double alpha = colk[k + 1];
+      double ss = 0.0;
+      for (int i = k + 2 + tid; i < n; i += 64) {
+        const double x = colk[i];
+        ss = fma(x, x, ss);
+      }
+      ss = wave_sum(ss);
+      double tau = 0.0, beta = alpha, scale = 0.0;
+      if (ss != 0.0) {
+        const double nrm = sqrt(fma(alpha, alpha, ss));
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int i = k + 2 + tid; i < n; i += 64) {
+        v[i] = colk[i] * scale;
+        colk[i] = 0.0;
+      }
+      if (tid == 0) {
+        v[k + 1] = 1.0;
+        colk[k + 1] = beta;
+        sc[0] = tau;
+      }
+    }
+    __syncthreads();
+    // tau == 0 (column already reduced) makes both updates exact no-ops; they
+    // still run so that every wave passes the same barriers.
+    const double tau = sc[0];
+
+    // left: rows k+1..n-1, columns k+1..n+m-1 (A and B)
+    for (int c = k + 1 + group; c < ncol; c += kGroups) {
+      double* col = W + (size_t)ldw * c;
+      double s = 0.0;
+      for (int i = k + 1 + lane16; i < n; i += kGroup) s = fma(v[i], col[i], s);
+      s = group_sum16(s) * tau;
+      for (int i = k + 1 + lane16; i < n; i += kGroup) col[i] = fma(-v[i], s, col[i]);
+    }
+    __syncthreads();
+
+    // right: rows 0..n+p-1 (A and C), columns k+1..n-1
+    for (int r = group; r < nrow; r += kGroups) {
+      double s = 0.0;
+      for (int c = k + 1 + lane16; c < n; c += kGroup) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
+      s = group_sum16(s) * tau;
+      for (int c = k + 1 + lane16; c < n; c += kGroup) {
+        double* x = W + (size_t)r + (size_t)ldw * c;
+        *x = fma(-s, v[c], *x);
+      }
+    }
+    __syncthreads();
+  }
+
+  // write the reduced model
+  const ReducedModel& o = job.out;
+  for (int j = 0; j < n; ++j) {
+    const int len = (j + 2 < n) ? j + 2 : n;
+    const int64_t off = hoff(j);
+    for (int i = tid; i < len; i += NT) {
+      const double x = W[(size_t)i + (size_t)ldw * j];
+      o.H[off + i] = x;
+      o.H32[off + i] = (float)x;
+    }
+  }
+  for (int idx = tid; idx < n * m; idx += NT) {
+    const int i = idx / m, j = idx % m;
+    const double x = W[(size_t)i + (size_t)ldw * (n + j)];
+    o.Bt[idx] = x;
+    o.Bt32[idx] = (float)x;
+  }
+  for (int idx = tid; idx < n * p; idx += NT) {
+    const int i = idx / p, a = idx % p;
+    const double x = W[(size_t)(n + a) + (size_t)ldw * i];
+    o.Ct[idx] = x;
+    o.Ct32[idx] = (float)x;
+  }
+  for (int idx = tid; idx < p * m; idx += NT) o.D[idx] = job.D ? job.D[idx] : 0.0;
+}
+
+constexpr int kLdsThreads = 512;
+constexpr int kGlobalThreads = 1024;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+size_t lds_bytes(int n, int m, int p) {
+  return ((size_t)ld_of(n, p) * (size_t)(n + m) + (size_t)n + 8) * sizeof(double);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+bool reduce_fits_lds(int n, int m, int p) { return lds_bytes(n, m, p) <= kLdsLimit; }
+
+size_t reduce_lds_bytes(int n, int m, int p) { return lds_bytes(n, m, p); }
+
+size_t reduce_work_bytes(int n, int m, int p) {
+  if (reduce_fits_lds(n, m, p)) return 0;
+  return align256((size_t)ld_of(n, p) * (size_t)(n + m) * sizeof(double));
+}
+
+size_t reduced_bytes(int n, int m, int p) {
+  const size_t hl = (size_t)hlen(n);
+  return align256(hl * 8) + align256((size_t)n * m * 8) + align256((size_t)n * p * 8) +
+         align256((size_t)p * m * 8) + align256(hl * 4) + align256((size_t)n * m * 4) +
+         align256((size_t)n * p * 4);
+}
+
+void reduced_layout(void* base, int n, int m, int p, ReducedModel* o) {
+  char* b = static_cast<char*>(base);
+  const size_t hl = (size_t)hlen(n);
+  o->H = reinterpret_cast<double*>(b);
+  b += align256(hl * 8);
+  o->Bt = reinterpret_cast<double*>(b);
+  b += align256((size_t)n * m * 8);
+  o->Ct = reinterpret_cast<double*>(b);
+  b += align256((size_t)n * p * 8);
+  o->D = reinterpret_cast<double*>(b);
+  b += align256((size_t)p * m * 8);
+  o->H32 = reinterpret_cast<float*>(b);
+  b += align256(hl * 4);
+  o->Bt32 = reinterpret_cast<float*>(b);
+  b += align256((size_t)n * m * 4);
+  o->Ct32 = reinterpret_cast<float*>(b);
+  o->n = n;
+  o->m = m;
+  o->p = p;
+  o->pad = 0;
+}
+
+hipError_t launch_reduce(const ReduceJob* jobs, int njobs, bool lds, size_t lds_need,
+                         hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  if (lds && lds_need > kLdsLimit) return hipErrorInvalidValue;
+  if (lds) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hess_kernel<kLdsThreads, true>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    hess_kernel<kLdsThreads, true><<<njobs, kLdsThreads, lds_need, s>>>(jobs);
+  } else {
+    // v (n <= 1024 doubles) plus scalars
+    const size_t sh = (kMaxReduceN + 8) * sizeof(double);
+    hess_kernel<kGlobalThreads, false><<<njobs, kGlobalThreads, sh, s>>>(jobs);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lti

@@ -1,0 +1,1022 @@
+// Serving runtime behind the C ABI: arena sub-allocation, resident reduced
+// models, admission by memory budget, and continuous batching of the
+// per-frequency solves of every live request into shared kernel launches.
+//
+// One scheduler thread per context owns all device work, issued in order on
+// one stream:
+//
+//   admit    pending requests in arrival order while their memory fits:
+//            upload inputs, reuse a resident reduced model or queue a
+//            reduction job (all reduction jobs of one pass share one launch);
+//   launch   gather up to max_batch_tiles tiles from the live requests
+//            (oldest first), group them by kernel class and launch; at most
+//            kInflight batches are outstanding, so requests that arrive
+//            meanwhile join the next batch;
+//   retire   when a batch's event has fired, credit its tiles; a request
+//            whose tiles are all done gets its D2H copy and then becomes
+//            visible to poll().
+//
+// Host inputs are copied at submit() into pinned staging owned by the
+// library, so every H2D and D2H copy is a true asynchronous DMA that never
+// stalls the scheduler behind queued kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lti_freqresp.h"
+#include "lti_kernels.h"
+
+namespace lti {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kInflight = 3;
+constexpr int kJobSlots = 4;
+constexpr int kMaxJobs = 1024;
+constexpr int kDefaultMaxPending = 8192;
+constexpr int kDefaultBatchTiles = 16384;
+constexpr size_t kDefaultStaging = size_t(256) << 20;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over a fixed range with coalescing frees.
+class Arena {
+ public:
+  void init(char* base, size_t size) {
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    if (size) free_[0] = size;
+    used_ = peak_ = 0;
+  }
+  void* alloc(size_t bytes) {
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const size_t off = it->first;
+        const size_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  void release(void* p, size_t bytes) {
+    if (!p) return;
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    const size_t off = static_cast<char*>(p) - base_;
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  bool can_ever_fit(size_t bytes) const { return align_up(bytes) <= size_; }
+  size_t size() const { return size_; }
+  size_t used() const { return used_; }
+  size_t peak() const { return peak_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0, peak_ = 0;
+};
+
+struct Resident {
+  uint64_t key = 0;
+  uint64_t hash = 0;
+  int n = 0, m = 0, p = 0;
+  void* block = nullptr;
+  size_t bytes = 0;
+  ReducedModel rm{};
+  int refs = 0;
+  uint64_t last_use = 0;
+};
+
+enum class RState { kPending, kLive, kFinishing, kDone, kFailed };
+
+// Host-side staging of one request: A, B, C, D, omega, the ReqDesc and (at
+// completion) G and info, in one pinned block when the pool has room.
+struct HostStage {
+  char* base = nullptr;  // pinned block, or fallback.data()
+  size_t bytes = 0;
+  bool pinned = false;
+  std::vector<char> fallback;
+  size_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0, offDesc = 0, offG = 0, offInfo = 0;
+};
+
+struct Request {
+  uint64_t id = 0;
+  lti_request req{};
+  RState state = RState::kPending;
+  int status = LTI_OK;
+  uint64_t hash = 0;
+  HostStage hs;
+  Resident* model = nullptr;
+  bool reused = false;
+  void* block = nullptr;  // device: omega, G, info, ReqDesc, A..D, reduction scratch
+  size_t block_bytes = 0;
+  size_t dOffG = 0, dOffInfo = 0;
+  ReqDesc* d_desc = nullptr;
+  int kclass = -1;
+  int64_t K = 0;
+  int F = 1;
+  int64_t ntiles = 0, next_tile = 0, tiles_done = 0;
+  hipEvent_t d2h_ev = nullptr;
+  lti_result res{};
+};
+
+struct Batch {
+  hipEvent_t done = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  bool timed = false;
+  int slot = 0;
+  std::vector<std::pair<Request*, int>> credit;
+};
+
+struct TimedPair {
+  hipEvent_t a, b;
+};
+
+uint64_t fnv1a(const void* data, size_t bytes, uint64_t h) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < bytes; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+bool all_finite(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace lti
+
+using namespace lti;
+
+struct lti_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint32_t flags = 0;
+  int max_pending = kDefaultMaxPending;
+  int tile_points = 0;
+  int batch_tiles = kDefaultBatchTiles;
+  Arena arena;
+  Arena staging;  // pinned host pool
+  char* staging_base = nullptr;
+  Clock::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv_work;
+  std::condition_variable cv_done;
+  std::thread thread;
+  bool stop = false;
+  bool device_error = false;
+
+  uint64_t next_id = 1;
+  uint64_t use_clock = 0;
+  std::deque<Request*> pending;
+  std::vector<Request*> live;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
+  std::vector<std::unique_ptr<Resident>> residents;
+  std::deque<Batch> inflight;
+  std::deque<TimedPair> reduce_timing;
+
+  TileDesc* h_tiles = nullptr;  // pinned, kInflight slots
+  TileDesc* d_tiles = nullptr;  // arena
+  std::vector<int> free_slots;
+  ReduceJob* h_jobs = nullptr;  // pinned, kJobSlots slots of kMaxJobs
+  ReduceJob* d_jobs = nullptr;
+  hipEvent_t job_ev[kJobSlots] = {};
+  int job_next = 0;
+  size_t fixed_bytes = 0;
+  std::vector<hipEvent_t> event_pool, timing_pool;
+
+  lti_stats stats{};
+
+  double now_us() const {
+    return std::chrono::duration<double, std::micro>(Clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+hipEvent_t get_event(lti_ctx* c, bool timing) {
+  auto& pool = timing ? c->timing_pool : c->event_pool;
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, timing ? hipEventDefault : hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+void put_event(lti_ctx* c, hipEvent_t e, bool timing) {
+  if (e) (timing ? c->timing_pool : c->event_pool).push_back(e);
+}
+
+void fail_all(lti_ctx* c, int code) {
+  c->device_error = true;
+  for (auto& kv : c->all) {
+    Request* r = kv.second.get();
+    if (r->state != RState::kDone && r->state != RState::kFailed) {
+      r->state = RState::kFailed;
+      r->status = code;
+      r->res.status = code;
+      c->stats.requests_failed++;
+    }
+  }
+  c->pending.clear();
+  c->live.clear();
+  c->cv_done.notify_all();
+}
+
+void release_stage(lti_ctx* c, HostStage& hs) {
+  if (hs.pinned && hs.base) c->staging.release(hs.base, hs.bytes);
+  hs.base = nullptr;
+  hs.pinned = false;
+  hs.fallback.clear();
+  hs.fallback.shrink_to_fit();
+}
+
+// Device bytes of a request (besides a shared resident model).
+struct Need {
+  size_t omega = 0, G = 0, info = 0, desc = 0, inputs = 0, work = 0, model = 0;
+  size_t block() const { return omega + G + info + desc + inputs + work; }
+};
+
+Need request_need(const lti_request& q, bool needs_model) {
+  const int n = q.nx, m = q.nu, p = q.ny;
+  Need nd;
+  if (q.mem == LTI_MEM_HOST) {
+    nd.omega = align_up(sizeof(double) * q.n_omega);
+    nd.G = align_up(sizeof(double) * 2 * (size_t)q.n_omega * p * m);
+    nd.info = q.info_out ? align_up(sizeof(lti_point_info) * q.n_omega) : 0;
+  }
+  nd.desc = align_up(sizeof(ReqDesc));
+  if (needs_model) {
+    if (q.mem == LTI_MEM_HOST)  // same per-matrix alignment as the host staging
+      nd.inputs = align_up(sizeof(double) * n * n) + align_up(sizeof(double) * n * m) +
+                  align_up(sizeof(double) * p * n) + align_up(sizeof(double) * p * m);
+    nd.work = reduce_work_bytes(n, m, p);
+    nd.model = align_up(reduced_bytes(n, m, p));
+  }
+  return nd;
+}
+
+Resident* find_resident(lti_ctx* c, const Request& r) {
+  if (r.req.model_key == 0) return nullptr;
+  for (auto& up : c->residents) {
+    Resident* res = up.get();
+    if (res->key == r.req.model_key && res->n == r.req.nx && res->m == r.req.nu && res->p == r.req.ny &&
+        res->hash == r.hash)
+      return res;
+  }
+  return nullptr;
+}
+
+void drop_resident(lti_ctx* c, Resident* res) {
+  c->arena.release(res->block, res->bytes);
+  for (auto it = c->residents.begin(); it != c->residents.end(); ++it) {
+    if (it->get() == res) {
+      c->residents.erase(it);
+      return;
+    }
+  }
+}
+
+// Allocate, evicting unreferenced resident models (least recently used
+// first) while that helps.
+void* alloc_evicting(lti_ctx* c, size_t bytes) {
+  void* p = c->arena.alloc(bytes);
+  while (!p) {
+    Resident* victim = nullptr;
+    for (auto& up : c->residents)
+      if (up->refs == 0 && (!victim || up->last_use < victim->last_use)) victim = up.get();
+    if (!victim) return nullptr;
+    drop_resident(c, victim);
+    p = c->arena.alloc(bytes);
+  }
+  return p;
+}
+
+void release_request_memory(lti_ctx* c, Request* r) {
+  if (r->block) c->arena.release(r->block, r->block_bytes);
+  r->block = nullptr;
+  if (r->model) {
+    Resident* res = r->model;
+    res->refs--;
+    r->model = nullptr;
+    if (res->key == 0 && res->refs == 0) drop_resident(c, res);
+  }
+}
+
+bool job_slot_free(lti_ctx* c) {
+  hipEvent_t e = c->job_ev[c->job_next];
+  return !e || hipEventQuery(e) != hipErrorNotReady;
+}
+
+// Try to admit one request.  Returns false when it has to wait for memory.
+bool admit_one(lti_ctx* c, Request* r, std::vector<ReduceJob>& jobs_lds, std::vector<ReduceJob>& jobs_glb,
+               size_t& lds_need, bool jobs_allowed) {
+  const lti_request& q = r->req;
+  const int n = q.nx, m = q.nu, p = q.ny;
+  Resident* res = find_resident(c, *r);
+  const bool needs_model = (res == nullptr);
+  if (needs_model && (!jobs_allowed || (int)(jobs_lds.size() + jobs_glb.size()) >= kMaxJobs)) return false;
+  const Need nd = request_need(q, needs_model);
+  void* mblock = nullptr;
+  if (needs_model) {
+    mblock = alloc_evicting(c, nd.model);
+    if (!mblock) return false;
+  }
+  void* block = alloc_evicting(c, nd.block());
+  if (!block) {
+    if (mblock) c->arena.release(mblock, nd.model);
+    return false;
+  }
+  if (needs_model) {
+    auto up = std::make_unique<Resident>();
+    res = up.get();
+    res->key = q.model_key;
+    res->hash = r->hash;
+    res->n = n;
+    res->m = m;
+    res->p = p;
+    res->block = mblock;
+    res->bytes = nd.model;
+    reduced_layout(mblock, n, m, p, &res->rm);
+    c->residents.push_back(std::move(up));
+    c->stats.reductions++;
+  } else {
+    c->stats.reduction_cache_hits++;
+  }
+  res->refs++;
+  res->last_use = ++c->use_clock;
+  r->model = res;
+  r->reused = !needs_model;
+  r->block = block;
+  r->block_bytes = nd.block();
+
+  char* b = static_cast<char*>(block);
+  HostStage& hs = r->hs;
+  const bool host = q.mem == LTI_MEM_HOST;
+  const double* d_omega = q.omega;
+  double* d_G = q.G_out;
+  lti_point_info* d_info = q.info_out;
+  hipError_t e = hipSuccess;
+  if (host) {
+    d_omega = reinterpret_cast<const double*>(b);
+    e = hipMemcpyAsync(b, hs.base + hs.offW, sizeof(double) * q.n_omega, hipMemcpyHostToDevice, c->stream);
+    b += nd.omega;
+    r->dOffG = nd.omega;
+    d_G = reinterpret_cast<double*>(b);
+    b += nd.G;
+    r->dOffInfo = nd.omega + nd.G;
+    d_info = nd.info ? reinterpret_cast<lti_point_info*>(b) : nullptr;
+    b += nd.info;
+  }
+  ReqDesc* d_desc = reinterpret_cast<ReqDesc*>(b);
+  b += nd.desc;
+  if (needs_model) {
+    ReduceJob job{};
+    if (host) {
+      char* dIn = b;
+      const size_t bytes = (size_t)(hs.offW - hs.offA);  // A, B, C, D are contiguous in staging
+      if (e == hipSuccess) e = hipMemcpyAsync(dIn, hs.base + hs.offA, bytes, hipMemcpyHostToDevice, c->stream);
+      job.A = reinterpret_cast<const double*>(dIn);
+      job.B = reinterpret_cast<const double*>(dIn + (hs.offB - hs.offA));
+      job.C = reinterpret_cast<const double*>(dIn + (hs.offC - hs.offA));
+      job.D = reinterpret_cast<const double*>(dIn + (hs.offD - hs.offA));
+      b += nd.inputs;
+    } else {
+      job.A = q.A;
+      job.B = q.B;
+      job.C = q.C;
+      job.D = q.D;
+    }
+    job.out = res->rm;
+    job.work = nd.work ? reinterpret_cast<double*>(b) : nullptr;
+    b += nd.work;
+    if (reduce_fits_lds(n, m, p)) {
+      jobs_lds.push_back(job);
+      lds_need = std::max(lds_need, reduce_lds_bytes(n, m, p));
+    } else {
+      jobs_glb.push_back(job);
+    }
+  }
+  ReqDesc* desc = reinterpret_cast<ReqDesc*>(hs.base + hs.offDesc);
+  *desc = ReqDesc{};
+  desc->H = res->rm.H;
+  desc->Bt = res->rm.Bt;
+  desc->Ct = res->rm.Ct;
+  desc->D = res->rm.D;
+  desc->H32 = res->rm.H32;
+  desc->Bt32 = res->rm.Bt32;
+  desc->Ct32 = res->rm.Ct32;
+  desc->omega = d_omega;
+  desc->G = d_G;
+  desc->info = d_info;
+  desc->n = n;
+  desc->m = m;
+  desc->p = p;
+  desc->precision = q.precision;
+  desc->rtol = q.rtol;
+  r->d_desc = d_desc;
+  if (e == hipSuccess) e = hipMemcpyAsync(d_desc, desc, sizeof(ReqDesc), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) {
+    fail_all(c, LTI_EDEVICE);
+    return true;
+  }
+  r->kclass = sweep_class(q.precision, n, m);
+  r->K = q.n_omega;
+  int F = c->tile_points;
+  if (F <= 0) F = (int)std::min<int64_t>(8, std::max<int64_t>(1, r->K / 2048));
+  r->F = F;
+  r->ntiles = (r->K + F - 1) / F;
+  r->next_tile = 0;
+  r->tiles_done = 0;
+  r->state = RState::kLive;
+  r->res.t_admit_us = c->now_us();
+  r->res.reduction_reused = r->reused ? 1 : 0;
+  return true;
+}
+
+void admit(lti_ctx* c) {
+  std::vector<ReduceJob> jobs_lds, jobs_glb;
+  size_t lds_need = 0;
+  const bool jobs_allowed = job_slot_free(c);
+  while (!c->pending.empty() && !c->device_error) {
+    Request* r = c->pending.front();
+    if (!admit_one(c, r, jobs_lds, jobs_glb, lds_need, jobs_allowed)) break;
+    c->pending.pop_front();
+    if (r->state == RState::kLive) c->live.push_back(r);
+  }
+  if (c->device_error || (jobs_lds.empty() && jobs_glb.empty())) return;
+  const size_t nl = jobs_lds.size(), ng = jobs_glb.size();
+  const int slot = c->job_next;
+  c->job_next = (c->job_next + 1) % kJobSlots;
+  ReduceJob* hj = c->h_jobs + (size_t)slot * kMaxJobs;
+  ReduceJob* dj = c->d_jobs + (size_t)slot * kMaxJobs;
+  std::copy(jobs_lds.begin(), jobs_lds.end(), hj);
+  std::copy(jobs_glb.begin(), jobs_glb.end(), hj + nl);
+  hipError_t e = hipMemcpyAsync(dj, hj, sizeof(ReduceJob) * (nl + ng), hipMemcpyHostToDevice, c->stream);
+  if (!c->job_ev[slot]) c->job_ev[slot] = get_event(c, false);
+  if (e == hipSuccess) e = hipEventRecord(c->job_ev[slot], c->stream);
+  const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
+  TimedPair tp{nullptr, nullptr};
+  if (timed) {
+    tp.a = get_event(c, true);
+    tp.b = get_event(c, true);
+    if (e == hipSuccess) e = hipEventRecord(tp.a, c->stream);
+  }
+  if (e == hipSuccess) e = launch_reduce(dj, (int)nl, true, lds_need, c->stream);
+  if (e == hipSuccess) e = launch_reduce(dj + nl, (int)ng, false, 0, c->stream);
+  if (timed && e == hipSuccess) {
+    e = hipEventRecord(tp.b, c->stream);
+    c->reduce_timing.push_back(tp);
+  }
+  if (e != hipSuccess) fail_all(c, LTI_EDEVICE);
+}
+
+void launch(lti_ctx* c) {
+  if (c->live.empty() || c->free_slots.empty()) return;
+  const int slot = c->free_slots.back();
+  TileDesc* ht = c->h_tiles + (size_t)slot * c->batch_tiles;
+  TileDesc* dt = c->d_tiles + (size_t)slot * c->batch_tiles;
+  std::vector<std::vector<TileDesc>> per(kNumSweepClasses);
+  Batch b;
+  int total = 0;
+  for (Request* r : c->live) {
+    if (total >= c->batch_tiles) break;
+    if (r->state != RState::kLive || r->next_tile >= r->ntiles) continue;
+    int took = 0;
+    while (r->next_tile < r->ntiles && total < c->batch_tiles) {
+      const int64_t t = r->next_tile++;
+      TileDesc td;
+      td.rd = r->d_desc;
+      td.start = (uint32_t)(t * r->F);
+      td.count = (uint32_t)std::min<int64_t>(r->F, r->K - t * r->F);
+      per[r->kclass].push_back(td);
+      ++took;
+      ++total;
+    }
+    b.credit.emplace_back(r, took);
+    if (r->res.t_first_launch_us == 0.0) r->res.t_first_launch_us = c->now_us();
+  }
+  if (total == 0) return;
+  c->free_slots.pop_back();
+  b.slot = slot;
+  std::vector<std::pair<int, int>> ranges;  // (class, offset)
+  int off = 0;
+  for (int k = 0; k < kNumSweepClasses; ++k) {
+    if (per[k].empty()) continue;
+    std::copy(per[k].begin(), per[k].end(), ht + off);
+    ranges.emplace_back(k, off);
+    off += (int)per[k].size();
+  }
+  hipError_t e = hipMemcpyAsync(dt, ht, sizeof(TileDesc) * total, hipMemcpyHostToDevice, c->stream);
+  b.timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
+  if (b.timed) {
+    b.t0 = get_event(c, true);
+    b.t1 = get_event(c, true);
+    if (e == hipSuccess) e = hipEventRecord(b.t0, c->stream);
+  }
+  for (auto& kr : ranges) {
+    if (e != hipSuccess) break;
+    e = launch_sweep(kr.first, dt + kr.second, (int)per[kr.first].size(), c->stream);
+    c->stats.sweep_launches++;
+  }
+  if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, c->stream);
+  b.done = get_event(c, false);
+  if (e == hipSuccess) e = hipEventRecord(b.done, c->stream);
+  c->stats.tiles_launched += total;
+  if (e != hipSuccess) {
+    fail_all(c, LTI_EDEVICE);
+    return;
+  }
+  c->inflight.push_back(std::move(b));
+}
+
+void complete_request(lti_ctx* c, Request* r) {
+  const lti_request& q = r->req;
+  r->res.status = LTI_OK;
+  r->res.n_points = q.n_omega;
+  if (q.mem == LTI_MEM_HOST) {
+    HostStage& hs = r->hs;
+    std::memcpy(q.G_out, hs.base + hs.offG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
+    if (q.info_out) {
+      std::memcpy(q.info_out, hs.base + hs.offInfo, sizeof(lti_point_info) * q.n_omega);
+      for (int64_t k = 0; k < q.n_omega; ++k) {
+        const lti_point_info& pi = q.info_out[k];
+        if (pi.path == LTI_PATH_REFINED) r->res.n_refined++;
+        if (pi.path == LTI_PATH_FALLBACK) r->res.n_fallback++;
+        if (pi.path == LTI_PATH_SINGULAR) r->res.n_singular++;
+        r->res.max_est_rel_err = std::max(r->res.max_est_rel_err, (double)pi.est_rel_err);
+      }
+    }
+  }
+  release_stage(c, r->hs);
+  r->res.t_done_us = c->now_us();
+  r->state = RState::kDone;
+  c->stats.requests_done++;
+  c->stats.points_done += q.n_omega;
+  release_request_memory(c, r);
+}
+
+void finish_tiles(lti_ctx* c, Request* r) {
+  const lti_request& q = r->req;
+  if (q.mem == LTI_MEM_DEVICE) {
+    // results are already in the caller's device buffers; the batch event
+    // that credited the last tile orders them
+    complete_request(c, r);
+    return;
+  }
+  HostStage& hs = r->hs;
+  char* b = static_cast<char*>(r->block);
+  hipError_t e = hipMemcpyAsync(hs.base + hs.offG, b + r->dOffG,
+                                sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu, hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess && q.info_out)
+    e = hipMemcpyAsync(hs.base + hs.offInfo, b + r->dOffInfo, sizeof(lti_point_info) * q.n_omega,
+                       hipMemcpyDeviceToHost, c->stream);
+  r->d2h_ev = get_event(c, false);
+  if (e == hipSuccess) e = hipEventRecord(r->d2h_ev, c->stream);
+  if (e != hipSuccess) {
+    fail_all(c, LTI_EDEVICE);
+    return;
+  }
+  r->state = RState::kFinishing;
+}
+
+bool retire(lti_ctx* c) {
+  bool progressed = false;
+  while (!c->reduce_timing.empty()) {
+    TimedPair& tp = c->reduce_timing.front();
+    const hipError_t q = hipEventQuery(tp.b);
+    if (q == hipErrorNotReady) break;
+    float ms = 0.f;
+    if (q == hipSuccess && hipEventElapsedTime(&ms, tp.a, tp.b) == hipSuccess) {
+      c->stats.reduce_kernel_ms += ms;
+      c->stats.timed_reduce_launches++;
+    }
+    put_event(c, tp.a, true);
+    put_event(c, tp.b, true);
+    c->reduce_timing.pop_front();
+  }
+  while (!c->inflight.empty()) {
+    Batch& b = c->inflight.front();
+    const hipError_t q = hipEventQuery(b.done);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) {
+      fail_all(c, LTI_EDEVICE);
+      return true;
+    }
+    if (b.timed) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, b.t0, b.t1) == hipSuccess) {
+        c->stats.sweep_kernel_ms += ms;
+        c->stats.timed_sweep_launches++;
+      }
+      put_event(c, b.t0, true);
+      put_event(c, b.t1, true);
+    }
+    for (auto& cr : b.credit) {
+      Request* r = cr.first;
+      r->tiles_done += cr.second;
+      if (r->tiles_done == r->ntiles && r->state == RState::kLive) finish_tiles(c, r);
+      if (c->device_error) return true;
+    }
+    put_event(c, b.done, false);
+    c->free_slots.push_back(b.slot);
+    c->inflight.pop_front();
+    progressed = true;
+  }
+  for (auto it = c->live.begin(); it != c->live.end();) {
+    Request* r = *it;
+    if (r->state == RState::kFinishing) {
+      const hipError_t q = hipEventQuery(r->d2h_ev);
+      if (q == hipErrorNotReady) {
+        ++it;
+        continue;
+      }
+      put_event(c, r->d2h_ev, false);
+      r->d2h_ev = nullptr;
+      if (q != hipSuccess) {
+        fail_all(c, LTI_EDEVICE);
+        return true;
+      }
+      complete_request(c, r);
+    }
+    if (r->state == RState::kDone || r->state == RState::kFailed) {
+      it = c->live.erase(it);
+      progressed = true;
+      c->cv_done.notify_all();
+    } else {
+      ++it;
+    }
+  }
+  return progressed;
+}
+
+void scheduler(lti_ctx* c) {
+  (void)hipSetDevice(c->device);
+  std::unique_lock<std::mutex> lk(c->mu);
+  while (!c->stop) {
+    if (c->device_error) {
+      c->cv_work.wait(lk, [&] { return c->stop; });
+      break;
+    }
+    bool progressed = retire(c);
+    const size_t pending_before = c->pending.size();
+    admit(c);
+    progressed |= c->pending.size() != pending_before;
+    const size_t inflight_before = c->inflight.size();
+    while ((int)c->inflight.size() < kInflight && !c->device_error) {
+      const size_t sz = c->inflight.size();
+      launch(c);
+      if (c->inflight.size() == sz) break;
+    }
+    progressed |= c->inflight.size() != inflight_before;
+    if (progressed) continue;
+    const bool busy = !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty();
+    if (busy) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    } else {
+      c->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    }
+  }
+}
+
+int validate(const lti_request* q) {
+  if (!q) return LTI_EINVAL;
+  if (q->nx <= 0 || q->nu <= 0 || q->ny <= 0 || q->n_omega <= 0) return LTI_EINVAL;
+  if (!q->A || !q->B || !q->C || !q->omega || !q->G_out) return LTI_EINVAL;
+  if (q->mem != LTI_MEM_HOST && q->mem != LTI_MEM_DEVICE) return LTI_EINVAL;
+  if (q->precision != LTI_PREC_FP64 && q->precision != LTI_PREC_REFINED) return LTI_EINVAL;
+  if (q->reserved0 != 0) return LTI_EINVAL;
+  if (q->n_omega > (int64_t)UINT32_MAX) return LTI_EINVAL;
+  if (std::isnan(q->rtol) || q->rtol >= 1.0) return LTI_EINVAL;
+  if (sweep_class(q->precision, q->nx, q->nu) < 0 || q->ny > kMaxRhs) return LTI_EUNSUPPORTED;
+  return LTI_OK;
+}
+
+// Stage a host-memory request's inputs (and room for its outputs).
+int stage_inputs(lti_ctx* c, Request* r) {
+  const lti_request& q = r->req;
+  const int n = q.nx, m = q.nu, p = q.ny;
+  HostStage& hs = r->hs;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  hs.offA = take(sizeof(double) * n * n);
+  hs.offB = take(sizeof(double) * n * m);
+  hs.offC = take(sizeof(double) * p * n);
+  hs.offD = take(sizeof(double) * p * m);
+  hs.offW = take(sizeof(double) * q.n_omega);
+  hs.offDesc = take(sizeof(ReqDesc));
+  hs.offG = take(sizeof(double) * 2 * (size_t)q.n_omega * p * m);
+  hs.offInfo = take(q.info_out ? sizeof(lti_point_info) * q.n_omega : 0);
+  hs.bytes = off;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    hs.base = static_cast<char*>(c->staging.alloc(hs.bytes));
+  }
+  hs.pinned = hs.base != nullptr;
+  if (!hs.pinned) {
+    try {
+      hs.fallback.resize(hs.bytes);
+    } catch (...) {
+      return LTI_ENOMEM;
+    }
+    hs.base = hs.fallback.data();
+  }
+  // A..D must be contiguous in this order (one H2D copy)
+  std::memcpy(hs.base + hs.offA, q.A, sizeof(double) * n * n);
+  std::memcpy(hs.base + hs.offB, q.B, sizeof(double) * n * m);
+  std::memcpy(hs.base + hs.offC, q.C, sizeof(double) * p * n);
+  if (q.D)
+    std::memcpy(hs.base + hs.offD, q.D, sizeof(double) * p * m);
+  else
+    std::memset(hs.base + hs.offD, 0, sizeof(double) * p * m);
+  std::memcpy(hs.base + hs.offW, q.omega, sizeof(double) * q.n_omega);
+  uint64_t h = 1469598103934665603ull;
+  const int dims[3] = {n, m, p};
+  h = fnv1a(dims, sizeof(dims), h);
+  h = fnv1a(hs.base + hs.offA, hs.offW - hs.offA, h);
+  r->hash = h;
+  return LTI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t lti_freqresp_abi_version(void) { return LTI_ABI_VERSION; }
+
+const char* lti_freqresp_strerror(int code) {
+  switch (code) {
+    case LTI_OK: return "ok";
+    case LTI_PENDING: return "request still pending";
+    case LTI_EINVAL: return "invalid argument";
+    case LTI_ENOSPC: return "request can never fit in the arena";
+    case LTI_EAGAIN: return "pending queue full";
+    case LTI_ENOENT: return "unknown or already collected request";
+    case LTI_EDEVICE: return "HIP device error; context unusable";
+    case LTI_ENOMEM: return "host allocation failed";
+    case LTI_EUNSUPPORTED: return "dimensions not supported by the kernels";
+    default: return "unknown error code";
+  }
+}
+
+int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
+  if (!cfg || !out) return LTI_EINVAL;
+  *out = nullptr;
+  if (cfg->abi_version != LTI_ABI_VERSION) return LTI_EINVAL;
+  if (!cfg->arena || cfg->arena_bytes < (size_t(1) << 20)) return LTI_EINVAL;
+  if (reinterpret_cast<uintptr_t>(cfg->arena) % kAlign) return LTI_EINVAL;
+  std::unique_ptr<lti_ctx> c(new (std::nothrow) lti_ctx());
+  if (!c) return LTI_ENOMEM;
+  c->device = cfg->device;
+  c->flags = cfg->flags;
+  c->max_pending = cfg->max_pending > 0 ? cfg->max_pending : kDefaultMaxPending;
+  c->tile_points = cfg->tile_points > 0 ? cfg->tile_points : 0;
+  c->batch_tiles = cfg->max_batch_tiles > 0 ? cfg->max_batch_tiles : kDefaultBatchTiles;
+  c->t0 = Clock::now();
+  if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
+  c->arena.init(static_cast<char*>(cfg->arena), cfg->arena_bytes);
+  const size_t tiles_bytes = align_up(sizeof(TileDesc) * (size_t)c->batch_tiles * kInflight);
+  const size_t jobs_bytes = align_up(sizeof(ReduceJob) * (size_t)kMaxJobs * kJobSlots);
+  c->fixed_bytes = tiles_bytes + jobs_bytes;
+  void* dt = c->arena.alloc(tiles_bytes);
+  void* dj = c->arena.alloc(jobs_bytes);
+  if (!dt || !dj) return LTI_EINVAL;  // arena too small for the descriptor rings
+  c->d_tiles = static_cast<TileDesc*>(dt);
+  c->d_jobs = static_cast<ReduceJob*>(dj);
+  const size_t staging = cfg->host_staging_bytes ? cfg->host_staging_bytes : kDefaultStaging;
+  void* hp = nullptr;
+  if (hipHostMalloc(&hp, tiles_bytes + jobs_bytes + staging, hipHostMallocDefault) != hipSuccess) return LTI_EDEVICE;
+  c->h_tiles = static_cast<TileDesc*>(hp);
+  c->h_jobs = reinterpret_cast<ReduceJob*>(static_cast<char*>(hp) + tiles_bytes);
+  c->staging_base = static_cast<char*>(hp) + tiles_bytes + jobs_bytes;
+  c->staging.init(c->staging_base, staging);
+  if (cfg->stream) {
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipHostFree(hp);
+      return LTI_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  for (int s = 0; s < kInflight; ++s) c->free_slots.push_back(s);
+  try {
+    c->thread = std::thread(scheduler, c.get());
+  } catch (...) {
+    (void)hipHostFree(hp);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    return LTI_ENOMEM;
+  }
+  *out = c.release();
+  return LTI_OK;
+}
+
+int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
+  if (!c || !out_id) return LTI_EINVAL;
+  const int v = validate(q);
+  if (v != LTI_OK) return v;
+  const int n = q->nx, m = q->nu, p = q->ny;
+  if (q->mem == LTI_MEM_HOST) {
+    if (!all_finite(q->A, (size_t)n * n) || !all_finite(q->B, (size_t)n * m) || !all_finite(q->C, (size_t)p * n) ||
+        (q->D && !all_finite(q->D, (size_t)p * m)) || !all_finite(q->omega, (size_t)q->n_omega))
+      return LTI_EINVAL;
+  }
+  std::unique_ptr<Request> r(new (std::nothrow) Request());
+  if (!r) return LTI_ENOMEM;
+  r->req = *q;
+  if (q->rtol <= 0.0) r->req.rtol = 1e-10;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->device_error) return LTI_EDEVICE;
+    const Need nd = request_need(r->req, true);
+    if (!c->arena.can_ever_fit(nd.block() + nd.model + c->fixed_bytes)) return LTI_ENOSPC;
+    if ((int)c->all.size() >= c->max_pending) return LTI_EAGAIN;
+  }
+  if (q->mem == LTI_MEM_HOST) {
+    const int s = stage_inputs(c, r.get());
+    if (s != LTI_OK) return s;
+  } else {
+    // only the descriptor needs staging
+    HostStage& hs = r->hs;
+    hs.offDesc = 0;
+    hs.bytes = align_up(sizeof(ReqDesc));
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      hs.base = static_cast<char*>(c->staging.alloc(hs.bytes));
+    }
+    hs.pinned = hs.base != nullptr;
+    if (!hs.pinned) {
+      hs.fallback.resize(hs.bytes);
+      hs.base = hs.fallback.data();
+    }
+    r->hash = 0;  // device inputs: the key and dimensions identify the model
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->device_error) {
+    release_stage(c, r->hs);
+    return LTI_EDEVICE;
+  }
+  if ((int)c->all.size() >= c->max_pending) {
+    release_stage(c, r->hs);
+    return LTI_EAGAIN;
+  }
+  r->id = c->next_id++;
+  r->res.t_submit_us = c->now_us();
+  Request* raw = r.get();
+  c->all.emplace(raw->id, std::move(r));
+  c->pending.push_back(raw);
+  c->stats.requests_submitted++;
+  *out_id = raw->id;
+  c->cv_work.notify_one();
+  return LTI_OK;
+}
+
+int lti_freqresp_poll(lti_ctx* c, uint64_t id, int32_t timeout_us, lti_result* out) {
+  if (!c) return LTI_EINVAL;
+  std::unique_lock<std::mutex> lk(c->mu);
+  auto it = c->all.find(id);
+  if (it == c->all.end()) return LTI_ENOENT;
+  Request* r = it->second.get();
+  auto finished = [&] { return r->state == RState::kDone || r->state == RState::kFailed; };
+  if (!finished() && timeout_us != 0) {
+    if (timeout_us < 0)
+      c->cv_done.wait(lk, finished);
+    else
+      c->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), finished);
+  }
+  if (!finished()) return LTI_PENDING;
+  const int status = r->state == RState::kDone ? LTI_OK : r->status;
+  r->res.status = status;
+  if (out) *out = r->res;
+  release_stage(c, r->hs);
+  c->all.erase(it);
+  return status;
+}
+
+int lti_freqresp_destroy(lti_ctx* c) {
+  if (!c) return LTI_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->stop = true;
+  }
+  c->cv_work.notify_all();
+  c->cv_done.notify_all();
+  if (c->thread.joinable()) c->thread.join();
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& b : c->inflight) {
+    put_event(c, b.done, false);
+    put_event(c, b.t0, true);
+    put_event(c, b.t1, true);
+  }
+  for (auto& tp : c->reduce_timing) {
+    put_event(c, tp.a, true);
+    put_event(c, tp.b, true);
+  }
+  for (auto& kv : c->all)
+    if (kv.second->d2h_ev) put_event(c, kv.second->d2h_ev, false);
+  for (int s = 0; s < kJobSlots; ++s) put_event(c, c->job_ev[s], false);
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->timing_pool) (void)hipEventDestroy(e);
+  if (c->h_tiles) (void)hipHostFree(c->h_tiles);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return LTI_OK;
+}
+
+int lti_freqresp_get_reduced(lti_ctx* c, uint64_t key, int32_t nx, int32_t nu, int32_t ny, double* H, double* Bt,
+                             double* Ct) {
+  if (!c || key == 0 || nx <= 0 || nu <= 0 || ny <= 0) return LTI_EINVAL;
+  ReducedModel rm{};
+  Resident* held = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->device_error) return LTI_EDEVICE;
+    for (auto& up : c->residents)
+      if (up->key == key && up->n == nx && up->m == nu && up->p == ny) held = up.get();
+    if (!held) return LTI_ENOENT;
+    rm = held->rm;
+    held->refs++;
+  }
+  const int n = nx, m = nu, p = ny;
+  std::vector<double> hp((size_t)hlen(n)), bt((size_t)n * m), ct((size_t)n * p);
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(hp.data(), rm.H, hp.size() * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(bt.data(), rm.Bt, bt.size() * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(ct.data(), rm.Ct, ct.size() * 8, hipMemcpyDeviceToHost);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    held->refs--;
+  }
+  if (e != hipSuccess) return LTI_EDEVICE;
+  if (H) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) H[(size_t)i * n + j] = (i <= j + 1) ? hp[hoff(j) + i] : 0.0;
+  }
+  if (Bt) std::memcpy(Bt, bt.data(), bt.size() * 8);
+  if (Ct) {
+    for (int a = 0; a < p; ++a)
+      for (int i = 0; i < n; ++i) Ct[(size_t)a * n + i] = ct[(size_t)i * p + a];
+  }
+  return LTI_OK;
+}
+
+int lti_freqresp_stats(lti_ctx* c, lti_stats* out) {
+  if (!c || !out) return LTI_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  *out = c->stats;
+  out->arena_bytes_in_use = c->arena.used();
+  out->arena_peak_bytes = c->arena.peak();
+  return LTI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+"""CPU checks of the boundary: the library loads and exports every symbol the
+header declares, and the ctypes structs have the header's layout."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2401_04068_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lti_freqresp.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lti_freqresp_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("lti_freqresp_create", "lti_freqresp_submit", "lti_freqresp_poll",
+                     "lti_freqresp_destroy"):
+        assert required in names
+    assert sorted(binding.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.lti_freqresp_abi_version() == binding.ABI_VERSION
+    assert binding.strerror(binding.LTI_ENOSPC) == "request can never fit in the arena"
+    assert binding.strerror(12345) == "unknown error code"
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text(
+        '#include "lti_freqresp.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lti_config), "
+        "sizeof(lti_request), sizeof(lti_result), sizeof(lti_stats), sizeof(lti_point_info), "
+        "offsetof(lti_request, G_out), offsetof(lti_config, host_staging_bytes));return 0;}\n"
+    )
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", f"-I{os.path.dirname(HEADER)}", str(prog), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    got = [int(x) for x in out]
+    want = [
+        ctypes.sizeof(binding.LtiConfig),
+        ctypes.sizeof(binding.LtiRequest),
+        ctypes.sizeof(binding.LtiResult),
+        ctypes.sizeof(binding.LtiStats),
+        binding.POINT_INFO_DTYPE.itemsize,
+        binding.LtiRequest.G_out.offset,
+        binding.LtiConfig.host_staging_bytes.offset,
+    ]
+    assert got == want
+
+
+def test_create_rejects_bad_config_without_touching_the_gpu():
+    lib = binding.load()
+    ctx = ctypes.c_void_p()
+    cfg = binding.LtiConfig()
+    cfg.abi_version = 999
+    assert lib.lti_freqresp_create(ctypes.byref(cfg), ctypes.byref(ctx)) == binding.LTI_EINVAL
+    cfg.abi_version = binding.ABI_VERSION
+    cfg.arena = None
+    cfg.arena_bytes = 1 << 30
+    assert lib.lti_freqresp_create(ctypes.byref(cfg), ctypes.byref(ctx)) == binding.LTI_EINVAL
+    cfg.arena = 0x1000 + 8  # misaligned, never dereferenced
+    assert lib.lti_freqresp_create(ctypes.byref(cfg), ctypes.byref(ctx)) == binding.LTI_EINVAL
+    assert lib.lti_freqresp_create(None, ctypes.byref(ctx)) == binding.LTI_EINVAL
+    assert lib.lti_freqresp_destroy(None) == binding.LTI_EINVAL
+    assert lib.lti_freqresp_submit(None, None, None) == binding.LTI_EINVAL
+    assert lib.lti_freqresp_poll(None, 1, 0, None) == binding.LTI_EINVAL
