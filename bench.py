@@ -1,0 +1,309 @@
+"""Frequency-response benchmark on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mimo64]
+
+A step is one pass of the whole path over one synthetic model: submit the
+model with its frequency grid already resident in HBM (a device-memory
+request), let the library reduce A to Hessenberg form, run every per-frequency
+solve, and poll the result.  The default workload is the 64-state, 4-input,
+4-output model on 2000 log-spaced frequencies evaluated on the plain float64
+path; the same workload is also timed on the refined float32 path and
+reported beside it.
+
+Printed: one JSON line with points/s (counting only points whose relative
+error against the CPU oracle is <= 1e-10), per-step latency percentiles, the
+roofline of the dominant kernel (the per-frequency sweep, timed with HIP
+events inside the library on the stream it runs on) and the CPU oracle timed
+on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frequency-response points/sec at ≤1e-10 rel err (refined vs plain FP64); p50/p99 latency"
+TOL = 1e-10
+FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def sweep_flops_per_point(n: int, m: int, p: int) -> float:
+    """Algorithmic flops of one frequency on the float64 path: the column
+    rotations (14 flops per row per step, 7 n^2), the fused back-substitution
+    (8 flops per row, step and right-hand side, 4 m n^2) and G = Ct^T X
+    (4 n m p); O(n m) terms are left out."""
+    return 7.0 * n * n + 4.0 * m * n * n + 4.0 * n * m * p
+
+
+def _source_digest() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2401_04068_amd", "csrc", "sweep.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_record(workload: str):
+    """HBM bytes per sweep launch from committed rocprofv3 counter runs, used
+    only while the kernel source is the one the counters were taken on."""
+    path = os.path.join(PROFILES, f"sweep_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("sweep_source_sha256_16") != _source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+# ------------------------------------------------------------------ CPU leg
+
+def _oracle_chunk(args):
+    A, B, C, D, w = args
+    import oracle
+
+    return oracle.freqresp(A, B, C, D, w)
+
+
+def cpu_baseline(mdl, target_s: float = 12.0):
+    """The oracle on this host's cores: frequencies split over a process pool
+    (one single-threaded-BLAS worker per core, at most 16), repeated until
+    about target_s seconds of wall time.  Returns (record, G_ref)."""
+    cores = min(16, os.cpu_count() or 1)
+    K = mdl.K
+    chunks = np.array_split(np.arange(K), cores)
+    jobs = [(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[c]) for c in chunks if len(c)]
+    ctx = mp.get_context("spawn")
+    saved = {k: os.environ.get(k) for k in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS")}
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"  # inherited by the spawned workers only
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        pool = ctx.Pool(len(jobs))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    with pool:
+        pool.map(_oracle_chunk, jobs[:1])  # start-up
+        t0 = time.perf_counter()
+        reps = 0
+        G_ref = None
+        while True:
+            parts = pool.map(_oracle_chunk, jobs)
+            reps += 1
+            if G_ref is None:
+                G_ref = np.concatenate(parts)
+            if time.perf_counter() - t0 >= target_s:
+                break
+        dt = time.perf_counter() - t0
+    rec = {
+        "value": reps * K / dt,
+        "unit": "points/s",
+        "cores": len(jobs),
+        "kind": "oracle",
+        "sample": f"{reps} passes over the full {K}-point grid of the same model "
+                  f"(dense complex LU per frequency, {len(jobs)} worker processes)",
+    }
+    return rec, G_ref
+
+
+# ------------------------------------------------------------------ GPU leg
+
+def _make_model(workload: str):
+    from paper_2401_04068_amd import workloads as wl
+
+    if workload == "mimo64":
+        return wl.mimo64()
+    if workload == "siso8":
+        return wl.siso8()
+    if workload == "damped256":
+        return wl.damped256_model(0)
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def run_gpu(mdl, precision: int, steps: int, warmup: int):
+    import torch
+
+    from paper_2401_04068_amd import binding
+
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(mdl, k))).to(dev) for k in ("A", "B", "C", "D", "omega")}
+    G = torch.empty((mdl.K, mdl.p, mdl.m, 2), dtype=torch.float64, device=dev)
+    info = torch.empty((mdl.K * 8,), dtype=torch.uint8, device=dev)
+    eng = binding.Engine(arena_bytes=1 << 30, kernel_timing=True)
+    try:
+        def step():
+            h = eng.submit_device(t["A"], t["B"], t["C"], t["D"], t["omega"], G, info, precision=precision)
+            eng.wait(h)
+            return h
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        s0 = eng.stats()
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a = time.perf_counter()
+            step()
+            lat.append(time.perf_counter() - a)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s1 = eng.stats()
+        Gh = G.cpu().numpy()
+        Gh = Gh[..., 0] + 1j * Gh[..., 1]
+        infoh = info.cpu().numpy().view(binding.POINT_INFO_DTYPE)
+    finally:
+        eng.close()
+    launches = s1["timed_sweep_launches"] - s0["timed_sweep_launches"]
+    sweep_ms = (s1["sweep_kernel_ms"] - s0["sweep_kernel_ms"]) / max(launches, 1)
+    rlaunch = s1["timed_reduce_launches"] - s0["timed_reduce_launches"]
+    reduce_ms = (s1["reduce_kernel_ms"] - s0["reduce_kernel_ms"]) / max(rlaunch, 1)
+    return {
+        "seconds": dt,
+        "lat": np.array(lat),
+        "sweep_ms_per_launch": sweep_ms,
+        "sweep_launches_per_step": launches / steps,
+        "reduce_ms_per_launch": reduce_ms,
+        "G": Gh,
+        "info": infoh,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="mimo64", choices=["mimo64", "siso8", "damped256"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--paths", default="both", choices=["both", "fp64", "refined"],
+                    help="which precision paths to time (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this engine's work units are independent "
+              "and its multi-GPU sharding is not built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    mdl = _make_model(args.workload)
+    n, m, p, K = mdl.n, mdl.m, mdl.p, mdl.K
+
+    # The CPU leg runs first, before anything touches the GPU, so that its
+    # worker processes start from a process with no device state.
+    if args.no_cpu:
+        import oracle
+
+        G_ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+        cpu = None
+    else:
+        cpu, G_ref = cpu_baseline(mdl)
+
+    import torch
+
+    from paper_2401_04068_amd import binding
+
+    binding.load()
+    if args.copy_calibration:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    fp64 = ref = None
+    if args.paths in ("both", "fp64"):
+        fp64 = run_gpu(mdl, binding.PREC_FP64, args.steps, args.warmup)
+    if args.paths in ("both", "refined"):
+        ref = run_gpu(mdl, binding.PREC_REFINED, args.steps, args.warmup)
+    if fp64 is None or ref is None:
+        done = fp64 or ref
+        print(json.dumps({"profiling_run": args.paths, "ms_per_step": 1e3 * done["seconds"] / args.steps,
+                          "sweep_ms_per_launch": done["sweep_ms_per_launch"]}), flush=True)
+        return
+
+    import oracle
+
+    err64 = oracle.rel_err(fp64["G"], G_ref)
+    err32 = oracle.rel_err(ref["G"], G_ref)
+    ok64 = float(np.mean(err64 <= TOL))
+    ok32 = float(np.mean(err32 <= TOL))
+
+    pts64 = K * args.steps / fp64["seconds"]
+    pts32 = K * args.steps / ref["seconds"]
+    value = pts64 * ok64
+    flops_launch = sweep_flops_per_point(n, m, p) * K / max(fp64["sweep_launches_per_step"], 1)
+    achieved = flops_launch / (fp64["sweep_ms_per_launch"] * 1e-3) / 1e12
+    traffic = _traffic_record(args.workload)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * fp64["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: n={n}, m={m}, p={p}, K={K} log-spaced frequencies, "
+                        "one model per step, inputs resident in HBM, float64 path",
+            "n": n, "m": m, "p": p, "points_per_step": K,
+        },
+        "latency_ms": {
+            "p50": float(np.percentile(fp64["lat"], 50) * 1e3),
+            "p99": float(np.percentile(fp64["lat"], 99) * 1e3),
+        },
+        "accuracy": {"max_rel_err": float(err64.max()), "frac_within_1e-10": ok64},
+        "refined": {
+            "points_per_s": pts32 * ok32,
+            "points_per_s_raw": pts32,
+            "max_rel_err": float(err32.max()),
+            "frac_within_1e-10": ok32,
+            "ms_per_step": 1e3 * ref["seconds"] / args.steps,
+            "latency_ms": {"p50": float(np.percentile(ref["lat"], 50) * 1e3),
+                           "p99": float(np.percentile(ref["lat"], 99) * 1e3)},
+            "mean_fp32_solves": float(np.mean(ref["info"]["iters"])),
+            "sweep_ms_per_launch": ref["sweep_ms_per_launch"],
+            "vs_fp64": (pts32 * ok32) / value if value else None,
+        },
+        "kernels": {
+            "sweep_ms_per_launch": fp64["sweep_ms_per_launch"],
+            "sweep_launches_per_step": fp64["sweep_launches_per_step"],
+            "reduce_ms_per_launch": fp64["reduce_ms_per_launch"],
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": "sweep_kernel<fp64> (per-frequency Givens sweep)",
+            "flops_per_launch": flops_launch,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,11 +75,14 @@ struct ReqDesc {
 };
 
 // A tile: `count` consecutive frequencies of one request, solved by one
-// wavefront.
+// wavefront for the right-hand-side columns j0 .. j0 + mc - 1 (a request's
+// columns may be split over several tiles to expose more parallelism).
 struct TileDesc {
   const ReqDesc* rd;
   uint32_t start;
-  uint32_t count;
+  uint16_t count;
+  uint8_t j0;
+  uint8_t mc;
 };
 static_assert(sizeof(TileDesc) == 16, "TileDesc must stay 16 bytes");
 
@@ -91,6 +94,44 @@ constexpr int kNumSweepClasses = 2 * kNumRowClasses * kNumRhsClasses;
 constexpr int kMaxN = 256;
 constexpr int kMaxRhs = 16;
 int sweep_class(int precision, int n, int m);
-hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, hipStream_t s);
+
+// LDS staging of one request's reduced model by a sweep workgroup: H, Bt and
+// Ct in float64, plus H and Bt in float32 for the refined path, each block
+// 16-byte aligned, in that order.  A workgroup stages when its four tiles
+// belong to one request and the model fits in kStageLimit bytes; otherwise
+// it reads the model from global memory.
+constexpr size_t kStageLimit = 64 * 1024;
+struct StageLayout {
+  size_t H, Bt, Ct, H32, Bt32, bytes;
+};
+__host__ __device__ inline size_t stage_align(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline StageLayout stage_layout(int precision, int n, int m, int p) {
+  StageLayout L;
+  const size_t hl = (size_t)hlen(n);
+  size_t o = 0;
+  L.H = o;
+  o += stage_align(hl * 8);
+  L.Bt = o;
+  o += stage_align((size_t)n * m * 8);
+  L.Ct = o;
+  o += stage_align((size_t)n * p * 8);
+  L.H32 = o;
+  L.Bt32 = o;
+  if (precision == LTI_PREC_REFINED) {
+    o += stage_align(hl * 4);
+    L.Bt32 = o;
+    o += stage_align((size_t)n * m * 4);
+  }
+  L.bytes = o;
+  return L;
+}
+// Staging bytes of a request, 0 when it does not fit kStageLimit.
+__host__ __device__ inline size_t stage_bytes(int precision, int n, int m, int p) {
+  const size_t b = stage_layout(precision, n, m, p).bytes;
+  return b <= kStageLimit ? b : 0;
+}
+// lds_bytes: dynamic LDS for staging (the largest stage_bytes() of the
+// launch's requests; 0 disables staging).
+hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, size_t lds_bytes, hipStream_t s);
 
 }  // namespace lti

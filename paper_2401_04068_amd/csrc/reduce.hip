@@ -14,33 +14,28 @@
 // accesses of the right update spread over the LDS banks.
 //
 // Every reflector costs three workgroup barriers: build v (wave 0), left
-// update (groups of 16 lanes per column: dot product, then rank-1 update of
-// the same column), right update (groups of 16 lanes per row).
+// update (a group of G adjacent lanes per column: partial dot products over
+// interleaved rows, a log2(G)-step shuffle sum, then the rank-1 update of the
+// same column), right update (a group of G lanes per row, likewise).  Small
+// groups keep every column (row) of a 64..128-state model in one pass.
 #include "lti_kernels.h"
 
 namespace lti {
 
 namespace {
 
-constexpr int kGroup = 16;
-
-__device__ __forceinline__ double group_sum16(double x) {
-  x += __shfl_xor(x, 8, 64);
-  x += __shfl_xor(x, 4, 64);
-  x += __shfl_xor(x, 2, 64);
-  x += __shfl_xor(x, 1, 64);
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+  for (int d = G / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
   return x;
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-  x += __shfl_xor(x, 32, 64);
-  x += __shfl_xor(x, 16, 64);
-  return group_sum16(x);
-}
+__device__ __forceinline__ double wave_sum(double x) { return group_sum<64>(x); }
 
 __host__ __device__ inline int ld_of(int n, int p) { return (n + p) | 1; }
 
-template <int NT, bool kLds>
+template <int NT, int G, bool kLds>
 __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ jobs) {
   extern __shared__ double smem[];
   const ReduceJob job = jobs[blockIdx.x];
@@ -75,9 +70,9 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
   }
   __syncthreads();
 
-  const int lane16 = tid & (kGroup - 1);
-  const int group = tid / kGroup;
-  constexpr int kGroups = NT / kGroup;
+  const int lg = tid & (G - 1);
+  const int group = tid / G;
+  constexpr int kGroups = NT / G;
 
   for (int k = 0; k + 2 < n; ++k) {
     double* colk = W + (size_t)ldw * k;
@@ -115,18 +110,18 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
     for (int c = k + 1 + group; c < ncol; c += kGroups) {
       double* col = W + (size_t)ldw * c;
       double s = 0.0;
-      for (int i = k + 1 + lane16; i < n; i += kGroup) s = fma(v[i], col[i], s);
-      s = group_sum16(s) * tau;
-      for (int i = k + 1 + lane16; i < n; i += kGroup) col[i] = fma(-v[i], s, col[i]);
+      for (int i = k + 1 + lg; i < n; i += G) s = fma(v[i], col[i], s);
+      s = group_sum<G>(s) * tau;
+      for (int i = k + 1 + lg; i < n; i += G) col[i] = fma(-v[i], s, col[i]);
     }
     __syncthreads();
 
     // right: rows 0..n+p-1 (A and C), columns k+1..n-1
     for (int r = group; r < nrow; r += kGroups) {
       double s = 0.0;
-      for (int c = k + 1 + lane16; c < n; c += kGroup) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
-      s = group_sum16(s) * tau;
-      for (int c = k + 1 + lane16; c < n; c += kGroup) {
+      for (int c = k + 1 + lg; c < n; c += G) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
+      s = group_sum<G>(s) * tau;
+      for (int c = k + 1 + lg; c < n; c += G) {
         double* x = W + (size_t)r + (size_t)ldw * c;
         *x = fma(-s, v[c], *x);
       }
@@ -161,7 +156,9 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
 }
 
 constexpr int kLdsThreads = 512;
+constexpr int kLdsGroup = 4;
 constexpr int kGlobalThreads = 1024;
+constexpr int kGlobalGroup = 8;
 constexpr size_t kLdsLimit = 160 * 1024;
 
 size_t lds_bytes(int n, int m, int p) {
@@ -217,16 +214,16 @@ hipError_t launch_reduce(const ReduceJob* jobs, int njobs, bool lds, size_t lds_
   if (lds) {
     static bool attr_set = false;
     if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hess_kernel<kLdsThreads, true>),
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hess_kernel<kLdsThreads, kLdsGroup, true>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
       if (e != hipSuccess) return e;
       attr_set = true;
     }
-    hess_kernel<kLdsThreads, true><<<njobs, kLdsThreads, lds_need, s>>>(jobs);
+    hess_kernel<kLdsThreads, kLdsGroup, true><<<njobs, kLdsThreads, lds_need, s>>>(jobs);
   } else {
     // v (n <= 1024 doubles) plus scalars
     const size_t sh = (kMaxReduceN + 8) * sizeof(double);
-    hess_kernel<kGlobalThreads, false><<<njobs, kGlobalThreads, sh, s>>>(jobs);
+    hess_kernel<kGlobalThreads, kGlobalGroup, false><<<njobs, kGlobalThreads, sh, s>>>(jobs);
   }
   return hipGetLastError();
 }

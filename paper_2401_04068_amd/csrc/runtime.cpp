@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -47,6 +48,9 @@ constexpr int kMaxJobs = 1024;
 constexpr int kDefaultMaxPending = 8192;
 constexpr int kDefaultBatchTiles = 16384;
 constexpr size_t kDefaultStaging = size_t(256) << 20;
+// Tiles (wavefronts) one request should offer before its columns are split:
+// 256 CUs x 4 SIMDs x 4 resident waves.
+constexpr int64_t kTargetTiles = 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -146,7 +150,10 @@ struct Request {
   ReqDesc* d_desc = nullptr;
   int kclass = -1;
   int64_t K = 0;
-  int F = 1;
+  int F = 1;        // frequencies per tile
+  int S = 1;        // right-hand-side column groups per frequency block
+  int mc = 1;       // columns per group
+  size_t stage = 0; // LDS bytes a sweep workgroup needs to stage the model
   int64_t ntiles = 0, next_tile = 0, tiles_done = 0;
   hipEvent_t d2h_ev = nullptr;
   lti_result res{};
@@ -192,6 +199,9 @@ struct lti_ctx {
   int max_pending = kDefaultMaxPending;
   int tile_points = 0;
   int batch_tiles = kDefaultBatchTiles;
+  int rhs_split = 0;        // 0: automatic
+  bool stage_lds = true;    // LDS staging of reduced models in the sweep
+  int64_t target_tiles = kTargetTiles;
   Arena arena;
   Arena staging;  // pinned host pool
   char* staging_base = nullptr;
@@ -461,12 +471,21 @@ bool admit_one(lti_ctx* c, Request* r, std::vector<ReduceJob>& jobs_lds, std::ve
     fail_all(c, LTI_EDEVICE);
     return true;
   }
-  r->kclass = sweep_class(q.precision, n, m);
   r->K = q.n_omega;
   int F = c->tile_points;
   if (F <= 0) F = (int)std::min<int64_t>(8, std::max<int64_t>(1, r->K / 2048));
   r->F = F;
-  r->ntiles = (r->K + F - 1) / F;
+  // Split the right-hand-side columns over several tiles when the request
+  // alone has too few frequency blocks to fill the device.
+  const int64_t fblocks = (r->K + F - 1) / F;
+  int S = c->rhs_split;
+  if (S <= 0) S = (fblocks >= c->target_tiles) ? 1 : (int)((c->target_tiles + fblocks - 1) / fblocks);
+  S = std::max(1, std::min(S, m));
+  r->mc = (m + S - 1) / S;
+  r->S = (m + r->mc - 1) / r->mc;
+  r->kclass = sweep_class(q.precision, n, r->mc);
+  r->stage = stage_bytes(q.precision, n, m, p);
+  r->ntiles = fblocks * r->S;
   r->next_tile = 0;
   r->tiles_done = 0;
   r->state = RState::kLive;
@@ -518,6 +537,7 @@ void launch(lti_ctx* c) {
   TileDesc* ht = c->h_tiles + (size_t)slot * c->batch_tiles;
   TileDesc* dt = c->d_tiles + (size_t)slot * c->batch_tiles;
   std::vector<std::vector<TileDesc>> per(kNumSweepClasses);
+  std::vector<size_t> lds(kNumSweepClasses, 0);
   Batch b;
   int total = 0;
   for (Request* r : c->live) {
@@ -526,11 +546,16 @@ void launch(lti_ctx* c) {
     int took = 0;
     while (r->next_tile < r->ntiles && total < c->batch_tiles) {
       const int64_t t = r->next_tile++;
+      const int64_t fb = t / r->S;
+      const int g = (int)(t % r->S);
       TileDesc td;
       td.rd = r->d_desc;
-      td.start = (uint32_t)(t * r->F);
-      td.count = (uint32_t)std::min<int64_t>(r->F, r->K - t * r->F);
+      td.start = (uint32_t)(fb * r->F);
+      td.count = (uint16_t)std::min<int64_t>(r->F, r->K - fb * r->F);
+      td.j0 = (uint8_t)(g * r->mc);
+      td.mc = (uint8_t)std::min(r->mc, r->req.nu - g * r->mc);
       per[r->kclass].push_back(td);
+      lds[r->kclass] = std::max(lds[r->kclass], r->stage);
       ++took;
       ++total;
     }
@@ -557,7 +582,8 @@ void launch(lti_ctx* c) {
   }
   for (auto& kr : ranges) {
     if (e != hipSuccess) break;
-    e = launch_sweep(kr.first, dt + kr.second, (int)per[kr.first].size(), c->stream);
+    e = launch_sweep(kr.first, dt + kr.second, (int)per[kr.first].size(), c->stage_lds ? lds[kr.first] : 0,
+                     c->stream);
     c->stats.sweep_launches++;
   }
   if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, c->stream);
@@ -820,6 +846,10 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   c->max_pending = cfg->max_pending > 0 ? cfg->max_pending : kDefaultMaxPending;
   c->tile_points = cfg->tile_points > 0 ? cfg->tile_points : 0;
   c->batch_tiles = cfg->max_batch_tiles > 0 ? cfg->max_batch_tiles : kDefaultBatchTiles;
+  // debug knobs for tuning sweeps (not part of the ABI)
+  if (const char* e = std::getenv("LTI_FREQRESP_RHS_SPLIT")) c->rhs_split = std::atoi(e);
+  if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES")) c->target_tiles = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("LTI_FREQRESP_STAGE_LDS")) c->stage_lds = std::atoi(e) != 0;
   c->t0 = Clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
   c->arena.init(static_cast<char*>(cfg->arena), cfg->arena_bytes);

@@ -1,5 +1,5 @@
 // Per-frequency shifted Hessenberg solves: one wavefront per tile of
-// frequencies of one request.
+// frequencies (and right-hand-side columns) of one request.
 //
 // For one frequency w, M = j w I - H is upper Hessenberg with a complex
 // diagonal and real off-diagonal entries.  Columns are rotated right to left,
@@ -13,9 +13,9 @@
 // R(k, k) = r real and positive (Golub & Van Loan, sec. 5.1.8, complex
 // Givens rotations; Laub 1981 for the per-frequency Hessenberg solve).  As
 // soon as column k of R is final, the back-substitution for R y = B takes
-// its step: y_k = b_k / r, b_{0..k-1} -= R(0..k-1, k) y_k.  R is never
-// stored.  Then X = Z y is formed by applying the rotations in increasing
-// order, which is the first-order linear recurrence
+// its step: b_{0..k-1} -= (R(0..k-1, k) / r) b_k, and y_k = b_k / r.  R is
+// never stored.  Then X = Z y is formed by applying the rotations in
+// increasing order, which is the first-order linear recurrence
 //
 //     t_0 = y_0,  t_k = -c_k t_{k-1} + conj(s_k) y_k,
 //     x_{k-1} = s_k t_{k-1} + c_k y_k,  x_{n-1} = t_{n-1} ,
@@ -24,12 +24,14 @@
 // reduce-scatter over the 64 lanes.
 //
 // Lane layout: row i lives on lane i % 64 in register slice i / 64 (R slices,
-// n <= 64 R); each lane holds its rows' carry entry (column being rotated),
-// right-hand-side rows (m <= MM complex) and, after the sweep, its rows' y
-// and rotation parameters.  The sweep reads H one column per step, right to
-// left, straight from the packed column-major layout (the next column is
-// loaded while the current one is used); every frequency of a request reads
-// the same H, which stays in L2.
+// n <= 64 R); each lane holds its rows' carry entry (the column being
+// rotated) and right-hand-side rows (MM complex columns); row k keeps b_k,
+// the rotation and 1/r after its step.  Per step the pivot row's carry and
+// the subdiagonal entry reach every lane as scalars (readlane and a scalar
+// load issued two steps ahead), b_k through an LDS broadcast; the column of
+// H (real, read once per step, right to left from the packed column-major
+// layout) is loaded one step ahead.  Every frequency of a request reads the
+// same H, which stays in L1/L2.
 #include <cfloat>
 #include <cmath>
 
@@ -40,6 +42,39 @@ namespace lti {
 namespace {
 
 constexpr int kWaves = 4;  // wavefronts per workgroup, one tile each
+
+template <typename T>
+using gptr = const T __attribute__((address_space(1)))*;  // global
+template <typename T>
+using cptr = const T __attribute__((address_space(4)))*;  // constant (scalar loads)
+template <typename T>
+using lptr = const T __attribute__((address_space(3)))*;  // LDS
+
+// Read-only view of one array of the reduced model, staged in LDS (kLds) or
+// read from global memory.
+template <typename T, bool kLds>
+struct Src {
+  const T* p;
+  __device__ __forceinline__ T operator[](int i) const {
+    if constexpr (kLds)
+      return ((lptr<T>)p)[i];
+    else
+      return ((gptr<T>)p)[i];
+  }
+  // an entry every lane reads at once (a scalar load from global memory)
+  __device__ __forceinline__ T uniform(int i) const {
+    if constexpr (kLds)
+      return ((lptr<T>)p)[i];
+    else
+      return ((cptr<T>)p)[i];
+  }
+};
+
+template <bool kLds>
+struct ModelSrc {
+  Src<double, kLds> H, Bt, Ct;
+  Src<float, kLds> H32, Bt32;
+};
 
 __device__ __forceinline__ double readlane(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -52,58 +87,55 @@ __device__ __forceinline__ float readlane(float v, int l) {
 
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
-__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
-__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 
-template <typename T>
-struct Limits;
-template <>
-struct Limits<double> {
-  static constexpr double eps = DBL_EPSILON / 2;
-};
+__device__ __forceinline__ int hoff32(int j) { return j * (j + 3) / 2; }
 
 // Register state of one frequency's solve.
 template <typename T, int R, int MM>
 struct Sweep {
-  T cr[R], ci[R];            // carry column (real, imag)
-  T br[R][MM], bi[R][MM];    // right-hand side, then y, then x
-  T rc[R], rsr[R], rsi[R];   // rotation k stored on row k (row 0: unused)
-  T dmin, dmax;              // extreme |R(k,k)|
+  T cr[R], ci[R];           // carry column (real, imag)
+  T br[R][MM], bi[R][MM];   // right-hand side; after the sweep y; after apply_rotations x
+  T rc[R], rsr[R], rsi[R];  // rotation k stored on row k (row 0 unused)
+  T rinv[R];                // 1 / R(k, k) on row k (row 0 unused)
   bool singular;
 };
 
 // Givens RQ sweep fused with back-substitution.  On entry br/bi hold the
-// right-hand side rows; on exit they hold y.
-template <typename T, int R, int MM>
-__device__ __forceinline__ void givens_sweep(const T* __restrict__ H, int n, T w, Sweep<T, R, MM>& st) {
+// right-hand-side rows; on exit they hold y.  `bcast` is this wavefront's
+// 2 * MM values of LDS.
+template <typename T, int R, int MM, bool kLds>
+__device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T w, Sweep<T, R, MM>& st, T* bcast) {
   const int lane = threadIdx.x & 63;
-  st.dmin = (T)INFINITY;
-  st.dmax = (T)0;
   st.singular = false;
   {
-    const T* col = H + hoff(n - 1);
+    const int off = hoff32(n - 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = lane + 64 * r;
-      const T h = (i < n) ? col[i] : (T)0;
+      const T h = (i < n) ? H[off + i] : (T)0;
       st.cr[r] = -h;
       st.ci[r] = (i == n - 1) ? w : (T)0;
       st.rc[r] = (T)0;
       st.rsr[r] = (T)1;
       st.rsi[r] = (T)0;
+      st.rinv[r] = (T)1;
     }
   }
+  // column n-2 (rows 0..n-1) for the first step
   T hc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) hc[r] = (T)0;
   if (n >= 2) {
-    const T* col = H + hoff(n - 2);
+    const int off = hoff32(n - 2);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = lane + 64 * r;
-      if (i <= n - 1) hc[r] = col[i];
+      if (i <= n - 1) hc[r] = H[off + i];
     }
   }
+  // subdiagonal H(k, k-1) for the next two steps (scalar loads)
+  T sub0 = (n >= 2) ? H.uniform(hoff32(n - 2) + n - 1) : (T)0;
+  T sub1 = (n >= 3) ? H.uniform(hoff32(n - 3) + n - 2) : (T)0;
 
 #pragma unroll
   for (int s = R - 1; s >= 0; --s) {
@@ -112,100 +144,156 @@ __device__ __forceinline__ void givens_sweep(const T* __restrict__ H, int n, T w
     const int klo = (64 * s > 1) ? 64 * s : 1;
     for (int k = khi; k >= klo; --k) {
       const int kl = k - 64 * s;
-      // prefetch column k-2, rows 0..k-1, for the next step
+      // b_k to LDS (lane kl), read back below as a broadcast
+      if (lane == kl) {
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          bcast[2 * j] = st.br[s][j];
+          bcast[2 * j + 1] = st.bi[s][j];
+        }
+      }
+      // prefetch: column k-2 (rows 0..k-1) and subdiagonal H(k-2, k-3)
       T hn[R];
 #pragma unroll
       for (int t = 0; t < R; ++t) hn[t] = (T)0;
       if (k >= 2) {
-        const T* coln = H + hoff(k - 2);
+        const int off = hoff32(k - 2);
 #pragma unroll
         for (int t = 0; t <= s; ++t) {
           const int i = lane + 64 * t;
-          if (i <= k - 1) hn[t] = coln[i];
+          if (i <= k - 1) hn[t] = H[off + i];
         }
       }
+      const T sub2 = (k >= 3) ? H.uniform(hoff32(k - 3) + k - 2) : (T)0;
+
       const T ar = readlane(st.cr[s], kl);
       const T ai = readlane(st.ci[s], kl);
-      const T beta = -readlane(hc[s], kl);
+      const T beta = -sub0;
       const T nrm2 = ar * ar + ai * ai + beta * beta;
-      T rinv, c, sr, si, rkk;
+      T rinv, c, sr, si;
       if (nrm2 > (T)0) {
         rinv = rsqrt_t(nrm2);
         c = beta * rinv;
         sr = ar * rinv;
         si = ai * rinv;
-        rkk = nrm2 * rinv;
       } else {  // column already zero: identity rotation, R(k,k) = 0
         rinv = (T)INFINITY;
         c = (T)0;
         sr = (T)1;
         si = (T)0;
-        rkk = (T)0;
         st.singular = true;
       }
-      st.dmin = fmin(st.dmin, rkk);
-      st.dmax = fmax(st.dmax, rkk);
-      T yr[MM], yi[MM];
+      // the LDS write above must land before any lane reads it back
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      T bkr[MM], bki[MM];
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
-        yr[j] = readlane(st.br[s][j], kl) * rinv;
-        yi[j] = readlane(st.bi[s][j], kl) * rinv;
+        bkr[j] = bcast[2 * j];
+        bki[j] = bcast[2 * j + 1];
       }
 #pragma unroll
       for (int t = 0; t <= s; ++t) {
+        const int i = lane + 64 * t;
         if (t < s || lane < kl) {
-          const int i = lane + 64 * t;
           const T cr_ = st.cr[t], ci_ = st.ci[t];
-          const T orr = -hc[t];
-          const T oi = (i == k - 1) ? w : (T)0;
-          // new column k (final R(i, k)) and new carry (column k-1)
-          const T nkr = c * orr + sr * cr_ + si * ci_;
-          const T nki = c * oi + sr * ci_ - si * cr_;
-          st.cr[t] = sr * orr - si * oi - c * cr_;
-          st.ci[t] = sr * oi + si * orr - c * ci_;
+          const T o = -hc[t];  // M(i, k-1), real off the diagonal
+          T nkr = c * o + sr * cr_ + si * ci_;
+          T nki = sr * ci_ - si * cr_;
+          T n1r = sr * o - c * cr_;
+          T n1i = si * o - c * ci_;
+          if (i == k - 1) {  // diagonal entry: M(k-1, k-1) also holds j w
+            nki += c * w;
+            n1r -= si * w;
+            n1i += sr * w;
+          }
+          st.cr[t] = n1r;
+          st.ci[t] = n1i;
+          nkr *= rinv;  // R(i, k) / R(k, k)
+          nki *= rinv;
 #pragma unroll
           for (int j = 0; j < MM; ++j) {
-            st.br[t][j] -= nkr * yr[j] - nki * yi[j];
-            st.bi[t][j] -= nkr * yi[j] + nki * yr[j];
+            st.br[t][j] = fma(-nkr, bkr[j], st.br[t][j]);
+            st.br[t][j] = fma(nki, bki[j], st.br[t][j]);
+            st.bi[t][j] = fma(-nkr, bki[j], st.bi[t][j]);
+            st.bi[t][j] = fma(-nki, bkr[j], st.bi[t][j]);
           }
         }
       }
       if (lane == kl) {
-#pragma unroll
-        for (int j = 0; j < MM; ++j) {
-          st.br[s][j] = yr[j];
-          st.bi[s][j] = yi[j];
-        }
         st.rc[s] = c;
         st.rsr[s] = sr;
         st.rsi[s] = si;
+        st.rinv[s] = rinv;
       }
+      // the next step's LDS write must not overtake this step's reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int t = 0; t < R; ++t) hc[t] = hn[t];
+      sub0 = sub1;
+      sub1 = sub2;
     }
   }
-  // row 0: R(0,0) is the carry entry itself (complex)
-  {
-    const T ar = readlane(st.cr[0], 0);
-    const T ai = readlane(st.ci[0], 0);
-    const T d = ar * ar + ai * ai;
-    const T dinv = (T)1 / d;  // inf when singular
-    if (!(d > (T)0)) st.singular = true;
-    const T r0 = sqrt_t(d);
-    st.dmin = fmin(st.dmin, r0);
-    st.dmax = fmax(st.dmax, r0);
-    if (lane == 0) {
+  // y_k = b_k / R(k,k); row 0: R(0,0) is the final carry entry (complex)
+  const T ar = readlane(st.cr[0], 0);
+  const T ai = readlane(st.ci[0], 0);
+  const T d = ar * ar + ai * ai;
+  if (!(d > (T)0)) st.singular = true;
+  const T dinv = (T)1 / d;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = lane + 64 * r;
+    if (i == 0) {
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
         const T xr = st.br[0][j], xi = st.bi[0][j];
         st.br[0][j] = (xr * ar + xi * ai) * dinv;
         st.bi[0][j] = (xi * ar - xr * ai) * dinv;
       }
+    } else {
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        st.br[r][j] *= st.rinv[r];
+        st.bi[r][j] *= st.rinv[r];
+      }
     }
   }
 }
 
+// Ratio of the largest to the smallest |R(k,k)| (a lower bound on the
+// condition number of R), from the per-row 1/R(k,k) and R(0,0).
+template <typename T, int R, int MM>
+__device__ __forceinline__ double diag_ratio(int n, const Sweep<T, R, MM>& st) {
+  const int lane = threadIdx.x & 63;
+  double lo = INFINITY, hi = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = lane + 64 * r;
+    if (i >= 1 && i < n) {
+      const double ri = (double)st.rinv[r];
+      lo = fmin(lo, ri);  // 1 / largest
+      hi = fmax(hi, ri);  // 1 / smallest
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, d, 64));
+    hi = fmax(hi, __shfl_xor(hi, d, 64));
+  }
+  const double ar = (double)readlane(st.cr[0], 0);
+  const double ai = (double)readlane(st.ci[0], 0);
+  const double r0 = sqrt(ar * ar + ai * ai);
+  const double rmax = fmax(1.0 / lo, r0);
+  const double rmin = fmin(1.0 / hi, r0);
+  return rmax / rmin;
+}
+
 // x := Z y, in place in br/bi (see the recurrence at the top of the file).
+// The scan's multipliers depend only on the rotations, so they are computed
+// once and the right-hand-side columns are then scanned one at a time.
 template <typename T, int R, int MM>
 __device__ __forceinline__ void apply_rotations(int n, Sweep<T, R, MM>& st) {
   const int lane = threadIdx.x & 63;
@@ -216,96 +304,74 @@ __device__ __forceinline__ void apply_rotations(int n, Sweep<T, R, MM>& st) {
   for (int s = 0; s < R; ++s) {
     if (64 * s >= n) break;
     const int i = lane + 64 * s;
-    // element i: t -> a t + u
-    T a;
-    T ur[MM], ui[MM];
-    if (i == 0 || i >= n) {
-      a = (T)0;
+    const bool inner = (i > 0 && i < n);
+    // element i is t -> a t + u; a = -c_i (0 for row 0 and past the end)
+    T a = inner ? -st.rc[s] : (T)0;
+    T am[6];  // multiplier of the shifted partial sum at each scan stage
 #pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        ur[j] = (i == 0) ? st.br[s][j] : (T)0;
-        ui[j] = (i == 0) ? st.bi[s][j] : (T)0;
-      }
-    } else {
-      a = -st.rc[s];
-      const T sr = st.rsr[s], si = st.rsi[s];
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {  // conj(s) * y
-        ur[j] = sr * st.br[s][j] + si * st.bi[s][j];
-        ui[j] = sr * st.bi[s][j] - si * st.br[s][j];
-      }
-    }
-    // inclusive scan: (a, u) o (a', u') = (a a', a u' + u)
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
+    for (int q = 0; q < 6; ++q) {
+      const int d = 1 << q;
       const T ap = __shfl_up(a, d, 64);
-      T upr[MM], upi[MM];
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        upr[j] = __shfl_up(ur[j], d, 64);
-        upi[j] = __shfl_up(ui[j], d, 64);
-      }
-      if (lane >= d) {
-#pragma unroll
-        for (int j = 0; j < MM; ++j) {
-          ur[j] = a * upr[j] + ur[j];
-          ui[j] = a * upi[j] + ui[j];
-        }
-        a = a * ap;
-      }
+      am[q] = (lane >= d) ? a : (T)0;
+      if (lane >= d) a = a * ap;
     }
-    T tr[MM], ti[MM];
-#pragma unroll
-    for (int j = 0; j < MM; ++j) {
-      tr[j] = a * tinr[j] + ur[j];
-      ti[j] = a * tini[j] + ui[j];
-    }
-    // rotation and y of row i+1
+    // rotation of row i+1 (lane 63 takes row 64(s+1) from the next slice)
     T nc = __shfl_down(st.rc[s], 1, 64);
     T nsr = __shfl_down(st.rsr[s], 1, 64);
     T nsi = __shfl_down(st.rsi[s], 1, 64);
-    T nyr[MM], nyi[MM];
-#pragma unroll
-    for (int j = 0; j < MM; ++j) {
-      nyr[j] = __shfl_down(st.br[s][j], 1, 64);
-      nyi[j] = __shfl_down(st.bi[s][j], 1, 64);
-    }
+    const int sn = (s + 1 < R) ? s + 1 : s;
     if (s + 1 < R) {
-      // lane 63 takes row 64(s+1) from the next slice
-      const T c0 = readlane(st.rc[s + 1 < R ? s + 1 : s], 0);
-      const T s0r = readlane(st.rsr[s + 1 < R ? s + 1 : s], 0);
-      const T s0i = readlane(st.rsi[s + 1 < R ? s + 1 : s], 0);
+      const T c0 = readlane(st.rc[sn], 0);
+      const T s0r = readlane(st.rsr[sn], 0);
+      const T s0i = readlane(st.rsi[sn], 0);
       if (lane == 63) {
         nc = c0;
         nsr = s0r;
         nsi = s0i;
       }
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        const T y0r = readlane(st.br[s + 1 < R ? s + 1 : s][j], 0);
-        const T y0i = readlane(st.bi[s + 1 < R ? s + 1 : s][j], 0);
-        if (lane == 63) {
-          nyr[j] = y0r;
-          nyi[j] = y0i;
-        }
-      }
     }
+    const T sr = st.rsr[s], si = st.rsi[s];
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
-      tinr[j] = readlane(tr[j], 63);
-      tini[j] = readlane(ti[j], 63);
-    }
-    if (i < n - 1) {
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {  // x_i = s_{i+1} t_i + c_{i+1} y_{i+1}
-        st.br[s][j] = nsr * tr[j] - nsi * ti[j] + nc * nyr[j];
-        st.bi[s][j] = nsr * ti[j] + nsi * tr[j] + nc * nyi[j];
+      const T yr = st.br[s][j], yi = st.bi[s][j];
+      T ur, ui;
+      if (inner) {  // conj(s_i) y_i
+        ur = sr * yr + si * yi;
+        ui = sr * yi - si * yr;
+      } else {
+        ur = (i == 0) ? yr : (T)0;
+        ui = (i == 0) ? yi : (T)0;
       }
-    } else if (i == n - 1) {
 #pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        st.br[s][j] = tr[j];
-        st.bi[s][j] = ti[j];
+      for (int q = 0; q < 6; ++q) {
+        const int d = 1 << q;
+        const T upr = __shfl_up(ur, d, 64);
+        const T upi = __shfl_up(ui, d, 64);
+        if (lane >= d) {
+          ur = fma(am[q], upr, ur);
+          ui = fma(am[q], upi, ui);
+        }
+      }
+      const T tr = fma(a, tinr[j], ur);
+      const T ti = fma(a, tini[j], ui);
+      T nyr = __shfl_down(yr, 1, 64);
+      T nyi = __shfl_down(yi, 1, 64);
+      if (s + 1 < R) {
+        const T y0r = readlane(st.br[sn][j], 0);
+        const T y0i = readlane(st.bi[sn][j], 0);
+        if (lane == 63) {
+          nyr = y0r;
+          nyi = y0i;
+        }
+      }
+      tinr[j] = readlane(tr, 63);
+      tini[j] = readlane(ti, 63);
+      if (i < n - 1) {  // x_i = s_{i+1} t_i + c_{i+1} y_{i+1}
+        st.br[s][j] = nsr * tr - nsi * ti + nc * nyr;
+        st.bi[s][j] = nsr * ti + nsi * tr + nc * nyi;
+      } else if (i == n - 1) {
+        st.br[s][j] = tr;
+        st.bi[s][j] = ti;
       }
     }
   }
@@ -313,8 +379,8 @@ __device__ __forceinline__ void apply_rotations(int n, Sweep<T, R, MM>& st) {
 
 // One halving stage of the reduce-scatter: lanes whose bit D is set keep the
 // upper H entries and send the lower ones to their partner (and vice versa).
-template <int H, int D>
-__device__ __forceinline__ void rs_stage(double (&vr)[16], double (&vi)[16]) {
+template <int V, int H, int D>
+__device__ __forceinline__ void rs_stage(double (&vr)[V], double (&vi)[V]) {
   const bool upper = ((threadIdx.x & 63) & D) != 0;
 #pragma unroll
   for (int q = 0; q < H; ++q) {
@@ -327,56 +393,63 @@ __device__ __forceinline__ void rs_stage(double (&vr)[16], double (&vi)[16]) {
   }
 }
 
-// Sum of v over the 64 lanes for 16 complex values at once: after the call
-// lane l holds the total of index l >> 2 in vr[0], vi[0].
-__device__ __forceinline__ void reduce_scatter16(double (&vr)[16], double (&vi)[16]) {
-  rs_stage<8, 32>(vr, vi);
-  rs_stage<4, 16>(vr, vi);
-  rs_stage<2, 8>(vr, vi);
-  rs_stage<1, 4>(vr, vi);
-  vr[0] += __shfl_xor(vr[0], 2, 64);
-  vi[0] += __shfl_xor(vi[0], 2, 64);
-  vr[0] += __shfl_xor(vr[0], 1, 64);
-  vi[0] += __shfl_xor(vi[0], 1, 64);
+// Sum over the 64 lanes of kV = 8 complex values at once: after the call
+// lane l holds the total of index l >> 3 in vr[0], vi[0].
+constexpr int kV = 8;
+__device__ __forceinline__ void reduce_scatter8(double (&vr)[kV], double (&vi)[kV]) {
+  rs_stage<kV, 4, 32>(vr, vi);
+  rs_stage<kV, 2, 16>(vr, vi);
+  rs_stage<kV, 1, 8>(vr, vi);
+#pragma unroll
+  for (int d = 4; d >= 1; d >>= 1) {
+    vr[0] += __shfl_xor(vr[0], d, 64);
+    vi[0] += __shfl_xor(vi[0], d, 64);
+  }
 }
 
-// G = Ct^T X + D for one frequency, X in xr/xi (rows lane + 64 r).
-template <int R, int MM>
-__device__ __forceinline__ void write_output(const ReqDesc& rd, const double (&xr)[R][MM],
-                                             const double (&xi)[R][MM], double* __restrict__ G) {
+// G(:, j0 .. j0+mc-1) = Ct^T X + D for one frequency, X in xr/xi.
+template <int R, int MM, bool kLds>
+__device__ __forceinline__ void write_output(const ReqDesc& rd, Src<double, kLds> Ct, int j0, int mc,
+                                             const double (&xr)[R][MM], const double (&xi)[R][MM],
+                                             double* __restrict__ G) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m, p = rd.p;
-  constexpr int PC = 16 / MM;  // rows of G per pass
+  constexpr int PC = (kV / MM > 0) ? kV / MM : 1;  // rows of G per pass
+  constexpr int MC = (MM < kV) ? MM : kV;           // columns of G per pass
   for (int a0 = 0; a0 < p; a0 += PC) {
-    double vr[16], vi[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) vr[q] = vi[q] = 0.0;
+    for (int jb = 0; jb < MM; jb += MC) {
+      if (jb >= mc) break;
+      double vr[kV], vi[kV];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = lane + 64 * r;
-      if (i < n) {
+      for (int q = 0; q < kV; ++q) vr[q] = vi[q] = 0.0;
 #pragma unroll
-        for (int q = 0; q < PC; ++q) {
-          const int a = a0 + q;
-          const double cq = (a < p) ? rd.Ct[(size_t)i * p + a] : 0.0;
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        if (i < n) {
 #pragma unroll
-          for (int j = 0; j < MM; ++j) {
-            vr[q * MM + j] += cq * xr[r][j];
-            vi[q * MM + j] += cq * xi[r][j];
+          for (int q = 0; q < PC; ++q) {
+            const int a = a0 + q;
+            const double cq = (a < p) ? Ct[i * p + a] : 0.0;
+#pragma unroll
+            for (int j = 0; j < MC; ++j) {
+              vr[q * MC + j] = fma(cq, xr[r][jb + j], vr[q * MC + j]);
+              vi[q * MC + j] = fma(cq, xi[r][jb + j], vi[q * MC + j]);
+            }
           }
         }
       }
-    }
-    reduce_scatter16(vr, vi);
-    if ((lane & 3) == 0) {
-      const int idx = lane >> 2;
-      const int a = a0 + idx / MM;
-      const int j = idx % MM;
-      if (a < p && j < m) {
-        double2 g;
-        g.x = vr[0] + rd.D[(size_t)a * m + j];
-        g.y = vi[0];
-        reinterpret_cast<double2*>(G)[(size_t)a * m + j] = g;
+      reduce_scatter8(vr, vi);
+      if ((lane & 7) == 0) {
+        const int idx = lane >> 3;
+        const int a = a0 + idx / MC;
+        const int j = jb + idx % MC;
+        if (a < p && j < mc) {
+          double2 g;
+          g.x = vr[0] + rd.D[a * m + j0 + j];
+          g.y = vi[0];
+          reinterpret_cast<double2*>(G)[a * m + j0 + j] = g;
+        }
       }
     }
   }
@@ -391,28 +464,31 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
   return (xcd < rem) ? xcd * (per + 1) + pos : rem * (per + 1) + (xcd - rem) * per + pos;
 }
 
-template <int R, int MM>
-__device__ void solve_fp64(const ReqDesc& rd, int64_t k) {
+template <int R, int MM, bool kLds>
+__device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t k, int j0, int mc,
+                           double* bcast) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m;
   const double w = rd.omega[k];
+  const Src<double, kLds> Bt = md.Bt;
   Sweep<double, R, MM> st;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = lane + 64 * r;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
-      st.br[r][j] = (i < n && j < m) ? rd.Bt[(size_t)i * m + j] : 0.0;
+      st.br[r][j] = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
       st.bi[r][j] = 0.0;
     }
   }
-  givens_sweep<double, R, MM>(rd.H, n, w, st);
+  givens_sweep<double, R, MM, kLds>(md.H, n, w, st, bcast);
+  const double ratio = rd.info ? diag_ratio<double, R, MM>(n, st) : 0.0;
   apply_rotations<double, R, MM>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
-  write_output<R, MM>(rd, st.br, st.bi, G);
-  if (rd.info && lane == 0) {
+  write_output<R, MM, kLds>(rd, md.Ct, j0, mc, st.br, st.bi, G);
+  if (rd.info && lane == 0 && j0 == 0) {
     lti_point_info inf;
-    inf.est_rel_err = (float)(Limits<double>::eps * (st.dmax / st.dmin));
+    inf.est_rel_err = (float)(0.5 * DBL_EPSILON * ratio);
     inf.iters = 1;
     inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
     inf.reserved = 0;
@@ -422,7 +498,6 @@ __device__ void solve_fp64(const ReqDesc& rd, int64_t k) {
 
 // ---------------------------------------------------------------- refined
 
-// Wave-wide sum and max.
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
@@ -434,19 +509,21 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
-// r = Bt - (j w X - H X), float64, rows lane + 64 t.
-template <int R, int MM>
-__device__ __forceinline__ void residual64(const ReqDesc& rd, double w, const double (&xr)[R][MM],
-                                           const double (&xi)[R][MM], double (&rr)[R][MM],
-                                           double (&ri)[R][MM]) {
+// r = Bt - (j w X - H X), float64, rows lane + 64 t, columns j0 .. j0+MM-1.
+template <int R, int MM, bool kLds>
+__device__ __forceinline__ void residual64(const ReqDesc& rd, const ModelSrc<kLds>& md, double w, int j0,
+                                           int mc, const double (&xr)[R][MM], const double (&xi)[R][MM],
+                                           double (&rr)[R][MM], double (&ri)[R][MM]) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m;
+  const Src<double, kLds> Bt = md.Bt;
+  const Src<double, kLds> H = md.H;
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const int i = lane + 64 * t;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
-      const double b = (i < n && j < m) ? rd.Bt[(size_t)i * m + j] : 0.0;
+      const double b = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
       rr[t][j] = b + w * xi[t][j];
       ri[t][j] = -w * xr[t][j];
     }
@@ -457,7 +534,7 @@ __device__ __forceinline__ void residual64(const ReqDesc& rd, double w, const do
     const int jend = (n - 64 * sj < 64) ? n - 64 * sj : 64;
     for (int jl = 0; jl < jend; ++jl) {
       const int jc = 64 * sj + jl;  // column of H
-      const double* col = rd.H + hoff(jc);
+      const int off = hoff32(jc);
       const int len = (jc + 2 < n) ? jc + 2 : n;
       double xjr[MM], xji[MM];
 #pragma unroll
@@ -469,11 +546,11 @@ __device__ __forceinline__ void residual64(const ReqDesc& rd, double w, const do
       for (int t = 0; t < R; ++t) {
         const int i = lane + 64 * t;
         if (i < len) {
-          const double h = col[i];
+          const double h = H[off + i];
 #pragma unroll
           for (int j = 0; j < MM; ++j) {
-            rr[t][j] += h * xjr[j];
-            ri[t][j] += h * xji[j];
+            rr[t][j] = fma(h, xjr[j], rr[t][j]);
+            ri[t][j] = fma(h, xji[j], ri[t][j]);
           }
         }
       }
@@ -481,14 +558,17 @@ __device__ __forceinline__ void residual64(const ReqDesc& rd, double w, const do
   }
 }
 
-template <int R, int MM>
-__device__ void solve_refined(const ReqDesc& rd, int64_t k) {
+template <int R, int MM, bool kLds>
+__device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t k, int j0, int mc,
+                              double* bcast64) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m;
   const double w = rd.omega[k];
   const float wf = (float)w;
   const double tol = 0.1 * ((rd.rtol > 0.0) ? rd.rtol : 1e-10);
   constexpr int kMaxIters = 6;
+  float* bcast = reinterpret_cast<float*>(bcast64);
+  const Src<float, kLds> Bt32 = md.Bt32;
 
   double xr[R][MM], xi[R][MM];
   Sweep<float, R, MM> st;
@@ -497,11 +577,11 @@ __device__ void solve_refined(const ReqDesc& rd, int64_t k) {
     const int i = lane + 64 * r;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
-      st.br[r][j] = (i < n && j < m) ? rd.Bt32[(size_t)i * m + j] : 0.0f;
+      st.br[r][j] = (i < n && j < mc) ? Bt32[i * m + j0 + j] : 0.0f;
       st.bi[r][j] = 0.0f;
     }
   }
-  givens_sweep<float, R, MM>(rd.H32, n, wf, st);
+  givens_sweep<float, R, MM, kLds>(md.H32, n, wf, st, bcast);
   apply_rotations<float, R, MM>(n, st);
   double dprev = 0.0;
   {
@@ -525,7 +605,7 @@ __device__ void solve_refined(const ReqDesc& rd, int64_t k) {
   } else {
     for (int it = 0; it < kMaxIters; ++it) {
       double rr[R][MM], ri[R][MM];
-      residual64<R, MM>(rd, w, xr, xi, rr, ri);
+      residual64<R, MM, kLds>(rd, md, w, j0, mc, xr, xi, rr, ri);
       double amax = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -545,7 +625,7 @@ __device__ void solve_refined(const ReqDesc& rd, int64_t k) {
           st.br[r][j] = (float)(rr[r][j] * scale);
           st.bi[r][j] = (float)(ri[r][j] * scale);
         }
-      givens_sweep<float, R, MM>(rd.H32, n, wf, st);
+      givens_sweep<float, R, MM, kLds>(md.H32, n, wf, st, bcast);
       apply_rotations<float, R, MM>(n, st);
       ++iters;
       double d2 = 0.0, x2 = 0.0;
@@ -576,19 +656,20 @@ __device__ void solve_refined(const ReqDesc& rd, int64_t k) {
     }
     if (!ok) path = LTI_PATH_FALLBACK;
   }
-  bool singular = false;
   if (path == LTI_PATH_FALLBACK) {
+    const Src<double, kLds> Bt = md.Bt;
     Sweep<double, R, MM> sd;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = lane + 64 * r;
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
-        sd.br[r][j] = (i < n && j < m) ? rd.Bt[(size_t)i * m + j] : 0.0;
+        sd.br[r][j] = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
         sd.bi[r][j] = 0.0;
       }
     }
-    givens_sweep<double, R, MM>(rd.H, n, w, sd);
+    givens_sweep<double, R, MM, kLds>(md.H, n, w, sd, bcast64);
+    est = 0.5 * DBL_EPSILON * diag_ratio<double, R, MM>(n, sd);
     apply_rotations<double, R, MM>(n, sd);
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -597,13 +678,13 @@ __device__ void solve_refined(const ReqDesc& rd, int64_t k) {
         xr[r][j] = sd.br[r][j];
         xi[r][j] = sd.bi[r][j];
       }
-    singular = sd.singular;
-    est = Limits<double>::eps * (sd.dmax / sd.dmin);
-    if (singular) path = LTI_PATH_SINGULAR;
+    if (sd.singular) path = LTI_PATH_SINGULAR;
   }
   double* G = rd.G + (size_t)k * rd.p * m * 2;
-  write_output<R, MM>(rd, xr, xi, G);
-  if (rd.info && lane == 0) {
+  write_output<R, MM, kLds>(rd, md.Ct, j0, mc, xr, xi, G);
+  // with the columns split over several tiles, the tile holding column 0
+  // reports the point
+  if (rd.info && lane == 0 && j0 == 0) {
     lti_point_info inf;
     inf.est_rel_err = (float)est;
     inf.iters = (uint8_t)iters;
@@ -613,25 +694,86 @@ __device__ void solve_refined(const ReqDesc& rd, int64_t k) {
   }
 }
 
-template <int PREC, int R, int MM>
-__global__ __launch_bounds__(64 * kWaves) void sweep_kernel(const TileDesc* __restrict__ tiles, int ntiles) {
-  // the tile index is uniform per wavefront; say so, so that the descriptor
-  // loads become scalar loads
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int tile = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves + wave;
-  if (tile >= ntiles) return;
-  const TileDesc td = tiles[tile];
-  const ReqDesc rd = *td.rd;
+template <int PREC, int R, int MM, bool kLds>
+__device__ __forceinline__ void run_tile(const TileDesc& td, const ReqDesc& rd, const ModelSrc<kLds>& md,
+                                         double* bcast) {
   for (uint32_t f = 0; f < td.count; ++f) {
     const int64_t k = (int64_t)td.start + f;
     if (PREC == LTI_PREC_FP64)
-      solve_fp64<R, MM>(rd, k);
+      solve_fp64<R, MM, kLds>(rd, md, k, td.j0, td.mc, bcast);
     else
-      solve_refined<R, MM>(rd, k);
+      solve_refined<R, MM, kLds>(rd, md, k, td.j0, td.mc, bcast);
   }
 }
 
-using KernelFn = void (*)(const TileDesc*, int);
+template <int PREC, int R, int MM>
+__global__ __launch_bounds__(64 * kWaves) void sweep_kernel(const TileDesc* __restrict__ tiles, int ntiles,
+                                                            uint32_t lds_bytes) {
+  extern __shared__ __align__(16) char stage[];
+  __shared__ double bcast_all[kWaves][2 * MM];
+  __shared__ const ReqDesc* block_rd[kWaves];
+  // the tile index is uniform per wavefront; say so, so that the descriptor
+  // loads become scalar loads
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves + wave;
+  if (lane == 0) block_rd[wave] = (tile < ntiles) ? tiles[tile].rd : nullptr;
+  __syncthreads();
+  // stage the model in LDS when the whole workgroup works on one request
+  const ReqDesc* r0 = block_rd[0];
+  bool same = true;
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) same = same && (block_rd[w] == nullptr || block_rd[w] == r0);
+  const ReqDesc rd0 = *r0;
+  const StageLayout L = stage_layout(PREC, rd0.n, rd0.m, rd0.p);
+  // (a model with more than 128 states never fits the staging limit)
+  constexpr bool kCanStage = (R <= 2);
+  const bool staged = kCanStage && same && lds_bytes > 0 && L.bytes <= lds_bytes && L.bytes <= kStageLimit;
+  if (kCanStage && staged) {
+    const int nh = (int)hlen(rd0.n);
+    const int nb = rd0.n * rd0.m, nc = rd0.n * rd0.p;
+    double* sH = reinterpret_cast<double*>(stage + L.H);
+    double* sB = reinterpret_cast<double*>(stage + L.Bt);
+    double* sC = reinterpret_cast<double*>(stage + L.Ct);
+    for (int i = threadIdx.x; i < nh; i += 64 * kWaves) sH[i] = rd0.H[i];
+    for (int i = threadIdx.x; i < nb; i += 64 * kWaves) sB[i] = rd0.Bt[i];
+    for (int i = threadIdx.x; i < nc; i += 64 * kWaves) sC[i] = rd0.Ct[i];
+    if (PREC == LTI_PREC_REFINED) {
+      float* sH32 = reinterpret_cast<float*>(stage + L.H32);
+      float* sB32 = reinterpret_cast<float*>(stage + L.Bt32);
+      for (int i = threadIdx.x; i < nh; i += 64 * kWaves) sH32[i] = rd0.H32[i];
+      for (int i = threadIdx.x; i < nb; i += 64 * kWaves) sB32[i] = rd0.Bt32[i];
+    }
+    __syncthreads();
+  }
+  if (tile >= ntiles) return;
+  const TileDesc td = tiles[tile];
+  const ReqDesc rd = *td.rd;
+  double* bcast = bcast_all[wave];
+  if constexpr (kCanStage) {
+    if (staged) {
+      ModelSrc<true> md;
+      md.H.p = reinterpret_cast<const double*>(stage + L.H);
+      md.Bt.p = reinterpret_cast<const double*>(stage + L.Bt);
+      md.Ct.p = reinterpret_cast<const double*>(stage + L.Ct);
+      md.H32.p = reinterpret_cast<const float*>(stage + L.H32);
+      md.Bt32.p = reinterpret_cast<const float*>(stage + L.Bt32);
+      run_tile<PREC, R, MM, true>(td, rd, md, bcast);
+      return;
+    }
+  }
+  {
+    ModelSrc<false> md;
+    md.H.p = rd.H;
+    md.Bt.p = rd.Bt;
+    md.Ct.p = rd.Ct;
+    md.H32.p = rd.H32;
+    md.Bt32.p = rd.Bt32;
+    run_tile<PREC, R, MM, false>(td, rd, md, bcast);
+  }
+}
+
+using KernelFn = void (*)(const TileDesc*, int, uint32_t);
 
 template <int PREC, int R>
 constexpr KernelFn pick_mm(int mi) {
@@ -667,7 +809,7 @@ int sweep_class(int precision, int n, int m) {
   return (precision * kNumRowClasses + ri) * kNumRhsClasses + mi;
 }
 
-hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, hipStream_t s) {
+hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, size_t lds_bytes, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (kclass < 0 || kclass >= kNumSweepClasses) return hipErrorInvalidValue;
   const int mi = kclass % kNumRhsClasses;
@@ -675,7 +817,8 @@ hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, hipStream
   const int prec = kclass / (kNumRhsClasses * kNumRowClasses);
   const KernelFn fn = prec == LTI_PREC_FP64 ? pick<LTI_PREC_FP64>(ri, mi) : pick<LTI_PREC_REFINED>(ri, mi);
   const int blocks = (ntiles + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves), 0, s, tiles, ntiles);
+  if (lds_bytes > kStageLimit) lds_bytes = 0;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves), lds_bytes, s, tiles, ntiles, (uint32_t)lds_bytes);
   return hipGetLastError();
 }
 

@@ -227,3 +227,26 @@ def test_error_codes(eng):
     with pytest.raises(binding.LtiError) as ei:
         eng.poll(bogus, 0)
     assert ei.value.code == binding.LTI_ENOENT
+
+
+@pytest.mark.parametrize("split", ["1", "2", "3"])
+def test_rhs_split_policies_agree(split, monkeypatch):
+    """Splitting a request's right-hand-side columns over several tiles (a
+    scheduling choice that depends only on the request) changes the order of
+    the final lane reduction, not the result beyond rounding."""
+    from paper_2401_04068_amd import binding
+
+    mdl = wl.mixed_pole_model(np.random.default_rng(5), 70, 5, 3, wl.logspace_grid(1e-2, 1e2, 300))
+    outs = {}
+    for knob in ("1", split):
+        monkeypatch.setenv("LTI_FREQRESP_RHS_SPLIT", knob)
+        with binding.Engine(arena_bytes=256 << 20) as e:
+            for prec in ("fp64", "refined"):
+                h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=_prec(prec))
+                assert e.poll(h, -1)
+                outs[(knob, prec)] = h.G
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    assert oracle.rel_err(outs[(split, "fp64")], outs[("1", "fp64")]).max() <= 1e-14
+    for knob in ("1", split):
+        assert oracle.rel_err(outs[(knob, "fp64")], ref).max() <= TOL_FP64
+        assert oracle.rel_err(outs[(knob, "refined")], ref).max() <= TOL_REFINED
