@@ -183,12 +183,85 @@ def run_gpu(mdl, precision: int, steps: int, warmup: int):
     }
 
 
+def serving(args):
+    """Serving replay: the mixed-size request stream (n ~ U{4..128},
+    m, p ~ U{1..8}, K ~ U{256..4096}) submitted from host memory on the refined
+    path.  Open loop: each request is submitted at its Poisson arrival time
+    (2000 requests/s) and its latency runs from that arrival to the moment its
+    results are visible to poll().  Closed loop: all requests submitted at
+    once; throughput = points / (first submit -> last result)."""
+    import torch  # noqa: F401  (device memory for the arena)
+
+    import oracle
+    from paper_2401_04068_amd import binding
+    from paper_2401_04068_amd import workloads as wl
+
+    nreq = args.requests
+    reqs = wl.serving_requests(nreq)
+    arrivals = wl.serving_arrivals(nreq)
+    total_points = sum(r.K for r in reqs)
+    out = {"metric": METRIC, "workload": f"serving: {nreq} requests, Poisson 2000/s, refined path, host memory",
+           "requests": nreq, "points": total_points}
+    with binding.Engine(arena_bytes=8 << 30, host_staging_bytes=1 << 30) as eng:
+        # warm-up (kernel loading, pools)
+        for r in reqs[:8]:
+            eng.wait(eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED))
+        # open loop
+        handles = []
+        t0 = time.perf_counter()
+        for r, ta in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            lag = max(0.0, time.perf_counter() - t0 - ta)  # submission behind the arrival
+            handles.append((eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED), lag))
+        lat = []
+        for h, _ in handles:
+            eng.wait(h)
+        for h, lag in handles:
+            # arrival -> results visible: submission lag plus the library's
+            # submit -> done interval (both stamps on the library clock)
+            lat.append(lag + (h.result["t_done_us"] - h.result["t_submit_us"]) * 1e-6)
+        t_open = time.perf_counter() - t0
+        out["open_loop"] = {
+            "wall_s": t_open,
+            "points_per_s": total_points / t_open,
+            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                           "max": float(np.max(lat) * 1e3)},
+        }
+        open_handles = [h for h, _ in handles]
+        # closed loop
+        t0 = time.perf_counter()
+        hs = [eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED) for r in reqs]
+        for h in hs:
+            eng.wait(h)
+        t_closed = time.perf_counter() - t0
+        st = eng.stats()
+    # accuracy on a sample: every 64th request, every 61st point, against the oracle
+    worst = 0.0
+    n_fb = 0
+    for idx in range(0, nreq, 64):
+        r = reqs[idx]
+        sub = slice(None, None, 61)
+        ref = oracle.freqresp(r.A, r.B, r.C, r.D, r.omega[sub])
+        for G in (open_handles[idx].G, hs[idx].G):
+            worst = max(worst, float(oracle.rel_err(G[sub], ref).max()))
+    for h in hs:
+        n_fb += int(h.result["n_fallback"])
+    out["closed_loop"] = {"wall_s": t_closed, "points_per_s": total_points / t_closed}
+    out["accuracy_sample_max_rel_err"] = worst
+    out["fallback_points"] = n_fb
+    out["stats"] = {k: st[k] for k in ("reductions", "sweep_launches", "tiles_launched", "arena_peak_bytes")}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="mimo64", choices=["mimo64", "siso8", "damped256"])
+    ap.add_argument("--workload", default="mimo64", choices=["mimo64", "siso8", "damped256", "serving"])
+    ap.add_argument("--requests", type=int, default=4096, help="serving replay: number of requests")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--paths", default="both", choices=["both", "fp64", "refined"],
                     help="which precision paths to time (profiling runs)")
@@ -200,6 +273,9 @@ def main():
               "and its multi-GPU sharding is not built; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serving":
+        serving(args)
+        return
     mdl = _make_model(args.workload)
     n, m, p, K = mdl.n, mdl.m, mdl.p, mdl.K
 

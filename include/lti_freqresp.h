@@ -172,7 +172,9 @@ int lti_freqresp_create(const lti_config* config, lti_ctx** out);
 /* Queue one request and return without waiting for the GPU.
  * LTI_EINVAL: NULL pointers, dims <= 0, n_omega <= 0, unknown precision or
  *             mem, non-finite host input.
- * LTI_EUNSUPPORTED: nx > 256, or nu or ny > 16.
+ * LTI_EUNSUPPORTED: nx > 1024, or nu or ny > 16.  (Refined-precision
+ *             requests with nx > 256 run the float64 path; their points
+ *             report LTI_PATH_FP64.)
  * LTI_ENOSPC: the request alone needs more than the whole arena.
  * LTI_EAGAIN: max_pending requests are outstanding.
  * LTI_EDEVICE: the context saw a HIP error.

@@ -48,15 +48,19 @@ struct ReduceJob {
 };
 
 constexpr int kMaxReduceN = 1024;
+// Reduction kernel classes: 0..3 keep the working matrix in LDS (n <= 16, 32,
+// 64, 128); kReduceGlobal keeps it in a global scratch area.
+constexpr int kReduceGlobal = 4;
+constexpr int kNumReduceClasses = 5;
+int reduce_class(int n, int m, int p);
 // Whether the working matrix of an (n, m, p) model fits in LDS, the LDS bytes
 // that kernel needs, and the global scratch bytes the other kernel needs.
 bool reduce_fits_lds(int n, int m, int p);
 size_t reduce_lds_bytes(int n, int m, int p);
 size_t reduce_work_bytes(int n, int m, int p);
-// Launch jobs[0..njobs) (device array) of one kind (lds or global);
-// lds_bytes is the largest reduce_lds_bytes() among LDS jobs.
-hipError_t launch_reduce(const ReduceJob* jobs, int njobs, bool lds, size_t lds_bytes,
-                         hipStream_t s);
+// Launch jobs[0..njobs) (device array) of one reduction class; lds_bytes is
+// the largest reduce_lds_bytes() among them (ignored for kReduceGlobal).
+hipError_t launch_reduce(const ReduceJob* jobs, int njobs, int rclass, size_t lds_bytes, hipStream_t s);
 
 // Per-request descriptor, resident in device memory while the request lives.
 struct ReqDesc {
@@ -94,6 +98,20 @@ constexpr int kNumSweepClasses = 2 * kNumRowClasses * kNumRhsClasses;
 constexpr int kMaxN = 256;
 constexpr int kMaxRhs = 16;
 int sweep_class(int precision, int n, int m);
+
+// Four-frequencies-per-wavefront kernels (sweep16.hip), both precisions,
+// n <= 64 and at most 4 right-hand-side columns per tile; -1 when the request
+// is not covered.  Their tiles should hold a multiple of 4 frequencies.
+constexpr int kNumSweep16Classes = 18;
+int sweep16_class(int precision, int n, int mc);
+hipError_t launch_sweep16(int cls, const TileDesc* tiles, int ntiles, hipStream_t s);
+
+// Workgroup-per-frequency kernels (sweepwg.hip): float64 path, 256 < n <= 1024,
+// at most 4 right-hand-side columns per tile; -1 when not covered.
+constexpr int kMaxNWG = 1024;
+constexpr int kNumSweepWGClasses = 3;
+int sweep_wg_class(int precision, int n, int mc);
+hipError_t launch_sweep_wg(int cls, const TileDesc* tiles, int ntiles, hipStream_t s);
 
 // LDS staging of one request's reduced model by a sweep workgroup: H, Bt and
 // Ct in float64, plus H and Bt in float32 for the refined path, each block

@@ -13,29 +13,22 @@
 // W is column-major with an odd leading dimension so that the row-strided
 // accesses of the right update spread over the LDS banks.
 //
-// Every reflector costs three workgroup barriers: build v (wave 0), left
-// update (a group of G adjacent lanes per column: partial dot products over
-// interleaved rows, a log2(G)-step shuffle sum, then the rank-1 update of the
-// same column), right update (a group of G lanes per row, likewise).  Small
-// groups keep every column (row) of a 64..128-state model in one pass.
+// Every reflector costs three workgroup barriers: build v (wave 0, DPP wave
+// sum of squares), left update (a group of G adjacent lanes per column:
+// partial dot products over Q interleaved rows, a DPP sum within the group,
+// then the rank-1 update of the same column), right update (a group of G
+// lanes per row, likewise).  The Q-element inner loops are unrolled and
+// predicated so that their LDS loads issue back to back.
+#include "dpp.h"
 #include "lti_kernels.h"
 
 namespace lti {
 
 namespace {
 
-template <int G>
-__device__ __forceinline__ double group_sum(double x) {
-#pragma unroll
-  for (int d = G / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
-}
-
-__device__ __forceinline__ double wave_sum(double x) { return group_sum<64>(x); }
-
 __host__ __device__ inline int ld_of(int n, int p) { return (n + p) | 1; }
 
-template <int NT, int G, bool kLds>
+template <int NT, int G, int Q, bool kLds>
 __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ jobs) {
   extern __shared__ double smem[];
   const ReduceJob job = jobs[blockIdx.x];
@@ -83,7 +76,7 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
         const double x = colk[i];
         ss = fma(x, x, ss);
       }
-      ss = wave_sum(ss);
+      ss = wave_sum_dpp(ss);
       double tau = 0.0, beta = alpha, scale = 0.0;
       if (ss != 0.0) {
         const double nrm = sqrt(fma(alpha, alpha, ss));
@@ -107,23 +100,76 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
     const double tau = sc[0];
 
     // left: rows k+1..n-1, columns k+1..n+m-1 (A and B)
-    for (int c = k + 1 + group; c < ncol; c += kGroups) {
-      double* col = W + (size_t)ldw * c;
-      double s = 0.0;
-      for (int i = k + 1 + lg; i < n; i += G) s = fma(v[i], col[i], s);
-      s = group_sum<G>(s) * tau;
-      for (int i = k + 1 + lg; i < n; i += G) col[i] = fma(-v[i], s, col[i]);
+    if constexpr (Q == 0) {
+      for (int c = k + 1 + group; c < ncol; c += kGroups) {
+        double* col = W + (size_t)ldw * c;
+        double s = 0.0;
+        for (int i = k + 1 + lg; i < n; i += G) s = fma(v[i], col[i], s);
+        s = group_sum_dpp<G>(s) * tau;
+        for (int i = k + 1 + lg; i < n; i += G) col[i] = fma(-v[i], s, col[i]);
+      }
+    } else {
+      double vv[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int i = k + 1 + lg + G * q;
+        vv[q] = (i < n) ? v[i] : 0.0;
+      }
+      for (int c = k + 1 + group; c < ncol; c += kGroups) {
+        double* col = W + (size_t)ldw * c;
+        double xx[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int i = k + 1 + lg + G * q;
+          xx[q] = (i < n) ? col[i] : 0.0;
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s = fma(vv[q], xx[q], s);
+        s = group_sum_dpp<G>(s) * tau;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int i = k + 1 + lg + G * q;
+          if (i < n) col[i] = fma(-vv[q], s, xx[q]);
+        }
+      }
     }
     __syncthreads();
 
     // right: rows 0..n+p-1 (A and C), columns k+1..n-1
-    for (int r = group; r < nrow; r += kGroups) {
-      double s = 0.0;
-      for (int c = k + 1 + lg; c < n; c += G) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
-      s = group_sum<G>(s) * tau;
-      for (int c = k + 1 + lg; c < n; c += G) {
-        double* x = W + (size_t)r + (size_t)ldw * c;
-        *x = fma(-s, v[c], *x);
+    if constexpr (Q == 0) {
+      for (int r = group; r < nrow; r += kGroups) {
+        double s = 0.0;
+        for (int c = k + 1 + lg; c < n; c += G) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
+        s = group_sum_dpp<G>(s) * tau;
+        for (int c = k + 1 + lg; c < n; c += G) {
+          double* x = W + (size_t)r + (size_t)ldw * c;
+          *x = fma(-s, v[c], *x);
+        }
+      }
+    } else {
+      double vv[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int c = k + 1 + lg + G * q;
+        vv[q] = (c < n) ? v[c] : 0.0;
+      }
+      for (int r = group; r < nrow; r += kGroups) {
+        double xx[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int c = k + 1 + lg + G * q;
+          xx[q] = (c < n) ? W[(size_t)r + (size_t)ldw * c] : 0.0;
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s = fma(xx[q], vv[q], s);
+        s = group_sum_dpp<G>(s) * tau;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int c = k + 1 + lg + G * q;
+          if (c < n) W[(size_t)r + (size_t)ldw * c] = fma(-s, vv[q], xx[q]);
+        }
       }
     }
     __syncthreads();
@@ -155,8 +201,9 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
   for (int idx = tid; idx < p * m; idx += NT) o.D[idx] = job.D ? job.D[idx] : 0.0;
 }
 
-constexpr int kLdsThreads = 512;
-constexpr int kLdsGroup = 4;
+// LDS kernel: 1024 threads; a column (row) is shared by G lanes holding Q
+// interleaved rows (columns) each: G = 16 up to 64 states, 8 up to 128.
+constexpr int kLdsThreads = 1024;
 constexpr int kGlobalThreads = 1024;
 constexpr int kGlobalGroup = 8;
 constexpr size_t kLdsLimit = 160 * 1024;
@@ -167,14 +214,34 @@ size_t lds_bytes(int n, int m, int p) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+using ReduceFn = void (*)(const ReduceJob*);
+
+template <int G, int Q>
+hipError_t launch_lds(const ReduceJob* jobs, int njobs, size_t lds_need, hipStream_t s) {
+  static bool attr_set = false;  // launches come from one scheduler thread
+  const void* fn = reinterpret_cast<const void*>(&hess_kernel<kLdsThreads, G, Q, true>);
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hess_kernel<kLdsThreads, G, Q, true><<<njobs, kLdsThreads, lds_need, s>>>(jobs);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 bool reduce_fits_lds(int n, int m, int p) { return lds_bytes(n, m, p) <= kLdsLimit; }
 
 size_t reduce_lds_bytes(int n, int m, int p) { return lds_bytes(n, m, p); }
 
+int reduce_class(int n, int m, int p) {
+  if (!reduce_fits_lds(n, m, p) || n > 128) return kReduceGlobal;
+  return (n <= 16) ? 0 : (n <= 32) ? 1 : (n <= 64) ? 2 : 3;
+}
+
 size_t reduce_work_bytes(int n, int m, int p) {
-  if (reduce_fits_lds(n, m, p)) return 0;
+  if (reduce_class(n, m, p) != kReduceGlobal) return 0;
   return align256((size_t)ld_of(n, p) * (size_t)(n + m) * sizeof(double));
 }
 
@@ -207,25 +274,22 @@ void reduced_layout(void* base, int n, int m, int p, ReducedModel* o) {
   o->pad = 0;
 }
 
-hipError_t launch_reduce(const ReduceJob* jobs, int njobs, bool lds, size_t lds_need,
-                         hipStream_t s) {
+hipError_t launch_reduce(const ReduceJob* jobs, int njobs, int rclass, size_t lds_need, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  if (lds && lds_need > kLdsLimit) return hipErrorInvalidValue;
-  if (lds) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&hess_kernel<kLdsThreads, kLdsGroup, true>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-    hess_kernel<kLdsThreads, kLdsGroup, true><<<njobs, kLdsThreads, lds_need, s>>>(jobs);
-  } else {
-    // v (n <= 1024 doubles) plus scalars
+  if (rclass == kReduceGlobal) {
+    // v (n <= kMaxReduceN doubles) plus scalars
     const size_t sh = (kMaxReduceN + 8) * sizeof(double);
-    hess_kernel<kGlobalThreads, kGlobalGroup, false><<<njobs, kGlobalThreads, sh, s>>>(jobs);
+    hess_kernel<kGlobalThreads, kGlobalGroup, 0, false><<<njobs, kGlobalThreads, sh, s>>>(jobs);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  if (lds_need > kLdsLimit) return hipErrorInvalidValue;
+  switch (rclass) {
+    case 0: return launch_lds<16, 1>(jobs, njobs, lds_need, s);
+    case 1: return launch_lds<16, 2>(jobs, njobs, lds_need, s);
+    case 2: return launch_lds<16, 4>(jobs, njobs, lds_need, s);
+    case 3: return launch_lds<8, 16>(jobs, njobs, lds_need, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace lti

@@ -20,6 +20,7 @@
 // library, so every H2D and D2H copy is a true asynchronous DMA that never
 // stalls the scheduler behind queued kernels.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -51,6 +52,8 @@ constexpr size_t kDefaultStaging = size_t(256) << 20;
 // Tiles (wavefronts) one request should offer before its columns are split:
 // 256 CUs x 4 SIMDs x 4 resident waves.
 constexpr int64_t kTargetTiles = 4096;
+// The same for four-frequency tiles (each already carries four solves).
+constexpr int64_t kTargetTiles16 = 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -201,6 +204,8 @@ struct lti_ctx {
   int batch_tiles = kDefaultBatchTiles;
   int rhs_split = 0;        // 0: automatic
   bool stage_lds = true;    // LDS staging of reduced models in the sweep
+  bool use_sweep16 = true;  // four-frequencies-per-wavefront kernels where they apply
+  int64_t target_tiles16 = kTargetTiles16;
   int64_t target_tiles = kTargetTiles;
   Arena arena;
   Arena staging;  // pinned host pool
@@ -360,13 +365,22 @@ bool job_slot_free(lti_ctx* c) {
 }
 
 // Try to admit one request.  Returns false when it has to wait for memory.
-bool admit_one(lti_ctx* c, Request* r, std::vector<ReduceJob>& jobs_lds, std::vector<ReduceJob>& jobs_glb,
-               size_t& lds_need, bool jobs_allowed) {
+struct JobLists {
+  std::vector<ReduceJob> jobs[kNumReduceClasses];
+  size_t lds[kNumReduceClasses] = {};
+  size_t total() const {
+    size_t t = 0;
+    for (const auto& v : jobs) t += v.size();
+    return t;
+  }
+};
+
+bool admit_one(lti_ctx* c, Request* r, JobLists& jl, bool jobs_allowed) {
   const lti_request& q = r->req;
   const int n = q.nx, m = q.nu, p = q.ny;
   Resident* res = find_resident(c, *r);
   const bool needs_model = (res == nullptr);
-  if (needs_model && (!jobs_allowed || (int)(jobs_lds.size() + jobs_glb.size()) >= kMaxJobs)) return false;
+  if (needs_model && (!jobs_allowed || (int)jl.total() >= kMaxJobs)) return false;
   const Need nd = request_need(q, needs_model);
   void* mblock = nullptr;
   if (needs_model) {
@@ -441,12 +455,9 @@ bool admit_one(lti_ctx* c, Request* r, std::vector<ReduceJob>& jobs_lds, std::ve
     job.out = res->rm;
     job.work = nd.work ? reinterpret_cast<double*>(b) : nullptr;
     b += nd.work;
-    if (reduce_fits_lds(n, m, p)) {
-      jobs_lds.push_back(job);
-      lds_need = std::max(lds_need, reduce_lds_bytes(n, m, p));
-    } else {
-      jobs_glb.push_back(job);
-    }
+    const int rc = reduce_class(n, m, p);
+    jl.jobs[rc].push_back(job);
+    if (rc != kReduceGlobal) jl.lds[rc] = std::max(jl.lds[rc], reduce_lds_bytes(n, m, p));
   }
   ReqDesc* desc = reinterpret_cast<ReqDesc*>(hs.base + hs.offDesc);
   *desc = ReqDesc{};
@@ -472,19 +483,41 @@ bool admit_one(lti_ctx* c, Request* r, std::vector<ReduceJob>& jobs_lds, std::ve
     return true;
   }
   r->K = q.n_omega;
+  // Kernel family: four frequencies per wavefront (n <= 64, at most four
+  // right-hand-side columns per tile), one frequency per wavefront
+  // (n <= 256), or one frequency per workgroup (n <= 1024, float64; refined
+  // requests of that size run the float64 path and report it per point).
+  const bool wg = n > kMaxN;
+  const bool four = !wg && c->use_sweep16 && sweep16_class(q.precision, n, std::min(m, 4)) >= 0;
   int F = c->tile_points;
-  if (F <= 0) F = (int)std::min<int64_t>(8, std::max<int64_t>(1, r->K / 2048));
+  if (F <= 0) F = four ? 4 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, r->K / 2048));
+  if (four) F = (F + 3) & ~3;
   r->F = F;
   // Split the right-hand-side columns over several tiles when the request
   // alone has too few frequency blocks to fill the device.
   const int64_t fblocks = (r->K + F - 1) / F;
+  const int64_t target = four ? c->target_tiles16 : c->target_tiles;
   int S = c->rhs_split;
-  if (S <= 0) S = (fblocks >= c->target_tiles) ? 1 : (int)((c->target_tiles + fblocks - 1) / fblocks);
+  if (S <= 0) S = (fblocks >= target) ? 1 : (int)((target + fblocks - 1) / fblocks);
   S = std::max(1, std::min(S, m));
+  if (four || wg) S = std::max(S, (m + 3) / 4);
   r->mc = (m + S - 1) / S;
   r->S = (m + r->mc - 1) / r->mc;
-  r->kclass = sweep_class(q.precision, n, r->mc);
-  r->stage = stage_bytes(q.precision, n, m, p);
+  if (wg)
+    r->kclass = kNumSweepClasses + kNumSweep16Classes + sweep_wg_class(LTI_PREC_FP64, n, r->mc);
+  else if (four)
+    r->kclass = kNumSweepClasses + sweep16_class(q.precision, n, r->mc);
+  else {
+    // one-frequency kernels keep R * MM <= 32 (R = 1, 2, 4 row slices):
+    // split further until the column count fits
+    while (sweep_class(q.precision, n, r->mc) < 0 && r->mc > 1) {
+      ++S;
+      r->mc = (m + S - 1) / S;
+      r->S = (m + r->mc - 1) / r->mc;
+    }
+    r->kclass = sweep_class(q.precision, n, r->mc);
+  }
+  r->stage = (four || wg) ? 0 : stage_bytes(q.precision, n, m, p);
   r->ntiles = fblocks * r->S;
   r->next_tile = 0;
   r->tiles_done = 0;
@@ -495,24 +528,28 @@ bool admit_one(lti_ctx* c, Request* r, std::vector<ReduceJob>& jobs_lds, std::ve
 }
 
 void admit(lti_ctx* c) {
-  std::vector<ReduceJob> jobs_lds, jobs_glb;
-  size_t lds_need = 0;
+  JobLists jl;
   const bool jobs_allowed = job_slot_free(c);
   while (!c->pending.empty() && !c->device_error) {
     Request* r = c->pending.front();
-    if (!admit_one(c, r, jobs_lds, jobs_glb, lds_need, jobs_allowed)) break;
+    if (!admit_one(c, r, jl, jobs_allowed)) break;
     c->pending.pop_front();
     if (r->state == RState::kLive) c->live.push_back(r);
   }
-  if (c->device_error || (jobs_lds.empty() && jobs_glb.empty())) return;
-  const size_t nl = jobs_lds.size(), ng = jobs_glb.size();
+  const size_t njobs = jl.total();
+  if (c->device_error || njobs == 0) return;
   const int slot = c->job_next;
   c->job_next = (c->job_next + 1) % kJobSlots;
   ReduceJob* hj = c->h_jobs + (size_t)slot * kMaxJobs;
   ReduceJob* dj = c->d_jobs + (size_t)slot * kMaxJobs;
-  std::copy(jobs_lds.begin(), jobs_lds.end(), hj);
-  std::copy(jobs_glb.begin(), jobs_glb.end(), hj + nl);
-  hipError_t e = hipMemcpyAsync(dj, hj, sizeof(ReduceJob) * (nl + ng), hipMemcpyHostToDevice, c->stream);
+  size_t off[kNumReduceClasses];
+  size_t o = 0;
+  for (int rc = 0; rc < kNumReduceClasses; ++rc) {
+    off[rc] = o;
+    std::copy(jl.jobs[rc].begin(), jl.jobs[rc].end(), hj + o);
+    o += jl.jobs[rc].size();
+  }
+  hipError_t e = hipMemcpyAsync(dj, hj, sizeof(ReduceJob) * njobs, hipMemcpyHostToDevice, c->stream);
   if (!c->job_ev[slot]) c->job_ev[slot] = get_event(c, false);
   if (e == hipSuccess) e = hipEventRecord(c->job_ev[slot], c->stream);
   const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
@@ -522,8 +559,8 @@ void admit(lti_ctx* c) {
     tp.b = get_event(c, true);
     if (e == hipSuccess) e = hipEventRecord(tp.a, c->stream);
   }
-  if (e == hipSuccess) e = launch_reduce(dj, (int)nl, true, lds_need, c->stream);
-  if (e == hipSuccess) e = launch_reduce(dj + nl, (int)ng, false, 0, c->stream);
+  for (int rc = 0; rc < kNumReduceClasses && e == hipSuccess; ++rc)
+    e = launch_reduce(dj + off[rc], (int)jl.jobs[rc].size(), rc, jl.lds[rc], c->stream);
   if (timed && e == hipSuccess) {
     e = hipEventRecord(tp.b, c->stream);
     c->reduce_timing.push_back(tp);
@@ -536,8 +573,9 @@ void launch(lti_ctx* c) {
   const int slot = c->free_slots.back();
   TileDesc* ht = c->h_tiles + (size_t)slot * c->batch_tiles;
   TileDesc* dt = c->d_tiles + (size_t)slot * c->batch_tiles;
-  std::vector<std::vector<TileDesc>> per(kNumSweepClasses);
-  std::vector<size_t> lds(kNumSweepClasses, 0);
+  constexpr int kAllClasses = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
+  std::vector<std::vector<TileDesc>> per(kAllClasses);
+  std::vector<size_t> lds(kAllClasses, 0);
   Batch b;
   int total = 0;
   for (Request* r : c->live) {
@@ -567,7 +605,7 @@ void launch(lti_ctx* c) {
   b.slot = slot;
   std::vector<std::pair<int, int>> ranges;  // (class, offset)
   int off = 0;
-  for (int k = 0; k < kNumSweepClasses; ++k) {
+  for (int k = 0; k < kAllClasses; ++k) {
     if (per[k].empty()) continue;
     std::copy(per[k].begin(), per[k].end(), ht + off);
     ranges.emplace_back(k, off);
@@ -582,8 +620,14 @@ void launch(lti_ctx* c) {
   }
   for (auto& kr : ranges) {
     if (e != hipSuccess) break;
-    e = launch_sweep(kr.first, dt + kr.second, (int)per[kr.first].size(), c->stage_lds ? lds[kr.first] : 0,
-                     c->stream);
+    if (kr.first >= kNumSweepClasses + kNumSweep16Classes)
+      e = launch_sweep_wg(kr.first - kNumSweepClasses - kNumSweep16Classes, dt + kr.second,
+                          (int)per[kr.first].size(), c->stream);
+    else if (kr.first >= kNumSweepClasses)
+      e = launch_sweep16(kr.first - kNumSweepClasses, dt + kr.second, (int)per[kr.first].size(), c->stream);
+    else
+      e = launch_sweep(kr.first, dt + kr.second, (int)per[kr.first].size(), c->stage_lds ? lds[kr.first] : 0,
+                       c->stream);
     c->stats.sweep_launches++;
   }
   if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, c->stream);
@@ -720,7 +764,10 @@ bool retire(lti_ctx* c) {
 
 void scheduler(lti_ctx* c) {
   (void)hipSetDevice(c->device);
+  // short sleeps below must stay short: 1 us timer slack for this thread
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
   std::unique_lock<std::mutex> lk(c->mu);
+  Clock::time_point idle_since = Clock::now();
   while (!c->stop) {
     if (c->device_error) {
       c->cv_work.wait(lk, [&] { return c->stop; });
@@ -737,14 +784,23 @@ void scheduler(lti_ctx* c) {
       if (c->inflight.size() == sz) break;
     }
     progressed |= c->inflight.size() != inflight_before;
-    if (progressed) continue;
+    if (progressed) {
+      idle_since = Clock::now();
+      continue;
+    }
     const bool busy = !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty();
     if (busy) {
+      // device work outstanding: poll its events, spinning (yield) for the
+      // first 200 us so that short requests complete without sleep latency
       lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      if (Clock::now() - idle_since < std::chrono::microseconds(200))
+        std::this_thread::yield();
+      else
+        std::this_thread::sleep_for(std::chrono::microseconds(10));
       lk.lock();
     } else {
       c->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+      idle_since = Clock::now();
     }
   }
 }
@@ -758,7 +814,7 @@ int validate(const lti_request* q) {
   if (q->reserved0 != 0) return LTI_EINVAL;
   if (q->n_omega > (int64_t)UINT32_MAX) return LTI_EINVAL;
   if (std::isnan(q->rtol) || q->rtol >= 1.0) return LTI_EINVAL;
-  if (sweep_class(q->precision, q->nx, q->nu) < 0 || q->ny > kMaxRhs) return LTI_EUNSUPPORTED;
+  if (q->nx > kMaxNWG || q->nu > kMaxRhs || q->ny > kMaxRhs) return LTI_EUNSUPPORTED;
   return LTI_OK;
 }
 
@@ -850,6 +906,8 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   if (const char* e = std::getenv("LTI_FREQRESP_RHS_SPLIT")) c->rhs_split = std::atoi(e);
   if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES")) c->target_tiles = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("LTI_FREQRESP_STAGE_LDS")) c->stage_lds = std::atoi(e) != 0;
+  if (const char* e = std::getenv("LTI_FREQRESP_SWEEP16")) c->use_sweep16 = std::atoi(e) != 0;
+  if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES16")) c->target_tiles16 = std::max(1, std::atoi(e));
   c->t0 = Clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
   c->arena.init(static_cast<char*>(cfg->arena), cfg->arena_bytes);

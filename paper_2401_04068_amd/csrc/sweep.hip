@@ -36,59 +36,13 @@
 #include <cmath>
 
 #include "lti_kernels.h"
+#include "sweep_common.h"
 
 namespace lti {
 
 namespace {
 
-constexpr int kWaves = 4;  // wavefronts per workgroup, one tile each
-
-template <typename T>
-using gptr = const T __attribute__((address_space(1)))*;  // global
-template <typename T>
-using cptr = const T __attribute__((address_space(4)))*;  // constant (scalar loads)
-template <typename T>
-using lptr = const T __attribute__((address_space(3)))*;  // LDS
-
-// Read-only view of one array of the reduced model, staged in LDS (kLds) or
-// read from global memory.
-template <typename T, bool kLds>
-struct Src {
-  const T* p;
-  __device__ __forceinline__ T operator[](int i) const {
-    if constexpr (kLds)
-      return ((lptr<T>)p)[i];
-    else
-      return ((gptr<T>)p)[i];
-  }
-  // an entry every lane reads at once (a scalar load from global memory)
-  __device__ __forceinline__ T uniform(int i) const {
-    if constexpr (kLds)
-      return ((lptr<T>)p)[i];
-    else
-      return ((cptr<T>)p)[i];
-  }
-};
-
-template <bool kLds>
-struct ModelSrc {
-  Src<double, kLds> H, Bt, Ct;
-  Src<float, kLds> H32, Bt32;
-};
-
-__device__ __forceinline__ double readlane(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ float readlane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-__device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
-__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
-
-__device__ __forceinline__ int hoff32(int j) { return j * (j + 3) / 2; }
+using namespace sweep_detail;
 
 // Register state of one frequency's solve.
 template <typename T, int R, int MM>
@@ -455,15 +409,6 @@ __device__ __forceinline__ void write_output(const ReqDesc& rd, Src<double, kLds
   }
 }
 
-__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
-  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
-  // XCD works on a contiguous range of tiles (tiles of one request share H in
-  // that XCD's L2).
-  const int per = nb / 8, rem = nb % 8;
-  const int xcd = b % 8, pos = b / 8;
-  return (xcd < rem) ? xcd * (per + 1) + pos : rem * (per + 1) + (xcd - rem) * per + pos;
-}
-
 template <int R, int MM, bool kLds>
 __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t k, int j0, int mc,
                            double* bcast) {
@@ -497,17 +442,6 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
 }
 
 // ---------------------------------------------------------------- refined
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
-}
-__device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = fmax(x, __shfl_xor(x, d, 64));
-  return x;
-}
 
 // r = Bt - (j w X - H X), float64, rows lane + 64 t, columns j0 .. j0+MM-1.
 template <int R, int MM, bool kLds>

@@ -1,0 +1,694 @@
+// Shifted Hessenberg solves for models of at most 64 states: four
+// frequencies per wavefront.
+//
+// The arithmetic is the one of sweep.hip (right-to-left complex Givens column
+// rotations fused with back-substitution, then X = Z y by a scan of the
+// rotation recurrence, then G = (CQ) X + D; see the comments there).  Only
+// the mapping differs: frequency g = lane / 16 of the wavefront owns one
+// 16-lane DPP row, and row i of its system lives on lane 16 g + i % 16 in
+// register slice i / 16 (R <= 4 slices).  The four frequencies (consecutive
+// grid points of one request, so they share H, Q^T B and (CQ)^T) advance in
+// lockstep, which
+//   * shares the per-step scalar chain (pivot broadcast, rsqrt, rotation) and
+//     the column load of H among four solves,
+//   * keeps idle lanes to the pivot's own 16-row slice (slices above the
+//     pivot are skipped, not masked), and
+//   * keeps the cross-lane moves inside the row: the scan uses row_shr DPP
+//     with identity `old` values and the output reduce-scatter pairs lanes by
+//     row mirrors.
+// The pivot row's carry entry and right-hand side reach the other lanes of
+// its row through a small LDS slot per frequency, which lets the 16 steps of
+// a slice run as a loop (a fully unrolled step sequence does not fit the
+// instruction cache).
+#include <cfloat>
+#include <cmath>
+#include <type_traits>
+
+#include "dpp.h"
+#include "lti_kernels.h"
+#include "sweep_common.h"
+
+namespace lti {
+
+namespace {
+
+using namespace sweep_detail;
+
+constexpr int kWaves16 = 4;  // wavefronts per workgroup, one tile each
+
+template <int T0, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (T0 < N) {
+    f(std::integral_constant<int, T0>{});
+    static_for<T0 + 1, N>(f);
+  }
+}
+
+template <typename T, int R, int MM>
+struct S16 {
+  T cr[R], ci[R];           // carry column
+  T br[R][MM], bi[R][MM];   // right-hand side -> y -> x
+  T rc[R], rsr[R], rsi[R];  // rotation k on row k (row 0 unused)
+  T rinv[R];                // 1 / R(k, k) on row k
+  bool singular;            // this lane's frequency
+};
+
+template <typename T>
+__device__ __forceinline__ T group_min16(T x) {
+  x = fmin(x, dpp<kDppQuadSwap1>(x));
+  x = fmin(x, dpp<kDppQuadSwap2>(x));
+  x = fmin(x, dpp<kDppRowHalfMirror>(x));
+  return fmin(x, dpp<kDppRowMirror>(x));
+}
+template <typename T>
+__device__ __forceinline__ T group_max16(T x) {
+  x = fmax(x, dpp<kDppQuadSwap1>(x));
+  x = fmax(x, dpp<kDppQuadSwap2>(x));
+  x = fmax(x, dpp<kDppRowHalfMirror>(x));
+  return fmax(x, dpp<kDppRowMirror>(x));
+}
+
+// Sweep and back-substitution for the four frequencies of the wavefront.  On
+// entry br/bi hold the right-hand sides, on exit y.  bcast: this wavefront's
+// 4 x (2 + 2 MM) values of LDS, one slot per frequency for the pivot row's
+// carry entry and right-hand side.  Slices are unrolled at compile time; the
+// 16 steps inside a slice are a loop, so the code stays small.
+template <typename T, int R, int MM>
+__device__ __forceinline__ void sweep16(const T* Hg, int n, T w, S16<T, R, MM>& st, T* bcast) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, gl = lane & 15;
+  const gptr<T> H = (gptr<T>)Hg;
+  const cptr<T> Hs = (cptr<T>)Hg;
+  T* mine = bcast + g * (2 + 2 * MM);
+  st.singular = false;
+  {
+    const int off = hoff32(n - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = gl + 16 * r;
+      const T h = (i < n) ? H[off + i] : (T)0;
+      st.cr[r] = -h;
+      st.ci[r] = (i == n - 1) ? w : (T)0;
+      st.rc[r] = (T)0;
+      st.rsr[r] = (T)1;
+      st.rsi[r] = (T)0;
+      st.rinv[r] = (T)1;
+    }
+  }
+  T hc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) hc[r] = (T)0;
+  if (n >= 2) {
+    const int off = hoff32(n - 2);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = gl + 16 * r;
+      if (i <= n - 1) hc[r] = H[off + i];
+    }
+  }
+  T sub0 = (n >= 2) ? Hs[hoff32(n - 2) + n - 1] : (T)0;
+  T sub1 = (n >= 3) ? Hs[hoff32(n - 3) + n - 2] : (T)0;
+
+  static_for<0, R>([&](auto sc) {
+    constexpr int s = R - 1 - decltype(sc)::value;
+    if (16 * s > n - 1) return;  // no pivot row in this slice (uniform)
+    const int jhi = (n - 1 - 16 * s < 15) ? n - 1 - 16 * s : 15;
+    const int jlo = (s == 0) ? 1 : 0;
+    for (int jl = jhi; jl >= jlo; --jl) {
+      const int k = 16 * s + jl;
+      // the pivot row publishes its carry entry and right-hand side
+      if (gl == jl) {
+        mine[0] = st.cr[s];
+        mine[1] = st.ci[s];
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          mine[2 + 2 * j] = st.br[s][j];
+          mine[3 + 2 * j] = st.bi[s][j];
+        }
+      }
+      // prefetch column k-2 (rows 0..k-1) and the subdiagonal two steps ahead
+      T hn[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) hn[t] = (T)0;
+      if (k >= 2) {
+        const int off = hoff32(k - 2);
+#pragma unroll
+        for (int t = 0; t <= s; ++t) {
+          const int i = gl + 16 * t;
+          if (i <= k - 1) hn[t] = H[off + i];
+        }
+      }
+      const T sub2 = (k >= 3) ? Hs[hoff32(k - 3) + k - 2] : (T)0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const T ar = mine[0];
+      const T ai = mine[1];
+      T bkr[MM], bki[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        bkr[j] = mine[2 + 2 * j];
+        bki[j] = mine[3 + 2 * j];
+      }
+      const T beta = -sub0;
+      const T nrm2 = ar * ar + ai * ai + beta * beta;
+      const bool ok = nrm2 > (T)0;
+      const T rq = rsqrt_t(ok ? nrm2 : (T)1);
+      // zero column (ok false): identity rotation and R(k,k) = 0
+      const T rinv = ok ? rq : (T)INFINITY;
+      const T c = ok ? beta * rq : (T)0;
+      const T sr = ok ? ar * rq : (T)1;
+      const T si = ok ? ai * rq : (T)0;
+      st.singular = st.singular || !ok;
+#pragma unroll
+      for (int t = 0; t <= s; ++t) {
+        const int i = gl + 16 * t;
+        if (t < s || gl < jl) {
+          const T cr_ = st.cr[t], ci_ = st.ci[t];
+          const T o = -hc[t];
+          T nkr = c * o + sr * cr_ + si * ci_;
+          T nki = sr * ci_ - si * cr_;
+          T n1r = sr * o - c * cr_;
+          T n1i = si * o - c * ci_;
+          if (i == k - 1) {  // the diagonal entry of column k-1 also holds j w
+            nki += c * w;
+            n1r -= si * w;
+            n1i += sr * w;
+          }
+          st.cr[t] = n1r;
+          st.ci[t] = n1i;
+          nkr *= rinv;
+          nki *= rinv;
+#pragma unroll
+          for (int j = 0; j < MM; ++j) {
+            st.br[t][j] = fma(-nkr, bkr[j], st.br[t][j]);
+            st.br[t][j] = fma(nki, bki[j], st.br[t][j]);
+            st.bi[t][j] = fma(-nkr, bki[j], st.bi[t][j]);
+            st.bi[t][j] = fma(-nki, bkr[j], st.bi[t][j]);
+          }
+        }
+      }
+      if (gl == jl) {
+        st.rc[s] = c;
+        st.rsr[s] = sr;
+        st.rsi[s] = si;
+        st.rinv[s] = rinv;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int t = 0; t < R; ++t) hc[t] = hn[t];
+      sub0 = sub1;
+      sub1 = sub2;
+    }
+  });
+  // y_k = b_k / R(k,k); R(0,0) is the final carry entry of row 0
+  const T ar = dpp<dpp_row_newbcast(0)>(st.cr[0]);
+  const T ai = dpp<dpp_row_newbcast(0)>(st.ci[0]);
+  const T d = ar * ar + ai * ai;
+  st.singular = st.singular || !(d > (T)0);
+  const T dinv = (T)1 / d;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = gl + 16 * r;
+    if (i == 0) {
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        const T xr = st.br[0][j], xi = st.bi[0][j];
+        st.br[0][j] = (xr * ar + xi * ai) * dinv;
+        st.bi[0][j] = (xi * ar - xr * ai) * dinv;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        st.br[r][j] *= st.rinv[r];
+        st.bi[r][j] *= st.rinv[r];
+      }
+    }
+  }
+}
+
+// Largest over smallest |R(k,k)| for this lane's frequency.
+template <typename T, int R, int MM>
+__device__ __forceinline__ double diag_ratio16(int n, const S16<T, R, MM>& st) {
+  const int gl = threadIdx.x & 15;
+  double lo = INFINITY, hi = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = gl + 16 * r;
+    if (i >= 1 && i < n) {
+      lo = fmin(lo, (double)st.rinv[r]);
+      hi = fmax(hi, (double)st.rinv[r]);
+    }
+  }
+  lo = group_min16(lo);
+  hi = group_max16(hi);
+  const double ar = (double)dpp<dpp_row_newbcast(0)>(st.cr[0]);
+  const double ai = (double)dpp<dpp_row_newbcast(0)>(st.ci[0]);
+  const double r0 = sqrt(ar * ar + ai * ai);
+  return fmax(1.0 / lo, r0) / fmin(1.0 / hi, r0);
+}
+
+// x := Z y in place (scan of t_k = -c_k t_{k-1} + conj(s_k) y_k within each
+// 16-lane row, slice by slice).
+template <typename T, int R, int MM>
+__device__ __forceinline__ void apply_rotations16(int n, S16<T, R, MM>& st) {
+  const int gl = threadIdx.x & 15;
+  T tinr[MM], tini[MM];
+#pragma unroll
+  for (int j = 0; j < MM; ++j) tinr[j] = tini[j] = (T)0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (16 * r >= n) break;
+    const int i = gl + 16 * r;
+    const bool inner = (i > 0 && i < n);
+    T a = inner ? -st.rc[r] : (T)0;
+    T am[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      am[q] = a;
+      T ap;
+      if (q == 0) ap = dpp<dpp_row_shr(1)>(a, (T)1);
+      if (q == 1) ap = dpp<dpp_row_shr(2)>(a, (T)1);
+      if (q == 2) ap = dpp<dpp_row_shr(4)>(a, (T)1);
+      if (q == 3) ap = dpp<dpp_row_shr(8)>(a, (T)1);
+      a = a * ap;
+    }
+    // rotation of row i+1 (row 16(r+1) for the last lane of the row)
+    T nc = dpp<dpp_row_shl(1)>(st.rc[r]);
+    T nsr = dpp<dpp_row_shl(1)>(st.rsr[r]);
+    T nsi = dpp<dpp_row_shl(1)>(st.rsi[r]);
+    const int rn = (r + 1 < R) ? r + 1 : r;
+    if (r + 1 < R) {
+      const T c0 = dpp<dpp_row_newbcast(0)>(st.rc[rn]);
+      const T s0r = dpp<dpp_row_newbcast(0)>(st.rsr[rn]);
+      const T s0i = dpp<dpp_row_newbcast(0)>(st.rsi[rn]);
+      if (gl == 15) {
+        nc = c0;
+        nsr = s0r;
+        nsi = s0i;
+      }
+    }
+    const T sr = st.rsr[r], si = st.rsi[r];
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      const T yr = st.br[r][j], yi = st.bi[r][j];
+      T ur, ui;
+      if (inner) {
+        ur = sr * yr + si * yi;
+        ui = sr * yi - si * yr;
+      } else {
+        ur = (i == 0) ? yr : (T)0;
+        ui = (i == 0) ? yi : (T)0;
+      }
+      ur = fma(am[0], dpp<dpp_row_shr(1)>(ur, (T)0), ur);
+      ui = fma(am[0], dpp<dpp_row_shr(1)>(ui, (T)0), ui);
+      ur = fma(am[1], dpp<dpp_row_shr(2)>(ur, (T)0), ur);
+      ui = fma(am[1], dpp<dpp_row_shr(2)>(ui, (T)0), ui);
+      ur = fma(am[2], dpp<dpp_row_shr(4)>(ur, (T)0), ur);
+      ui = fma(am[2], dpp<dpp_row_shr(4)>(ui, (T)0), ui);
+      ur = fma(am[3], dpp<dpp_row_shr(8)>(ur, (T)0), ur);
+      ui = fma(am[3], dpp<dpp_row_shr(8)>(ui, (T)0), ui);
+      const T tr = fma(a, tinr[j], ur);
+      const T ti = fma(a, tini[j], ui);
+      T nyr = dpp<dpp_row_shl(1)>(yr);
+      T nyi = dpp<dpp_row_shl(1)>(yi);
+      if (r + 1 < R) {
+        const T y0r = dpp<dpp_row_newbcast(0)>(st.br[rn][j]);
+        const T y0i = dpp<dpp_row_newbcast(0)>(st.bi[rn][j]);
+        if (gl == 15) {
+          nyr = y0r;
+          nyi = y0i;
+        }
+      }
+      tinr[j] = dpp<dpp_row_newbcast(15)>(tr);
+      tini[j] = dpp<dpp_row_newbcast(15)>(ti);
+      if (i < n - 1) {
+        st.br[r][j] = nsr * tr - nsi * ti + nc * nyr;
+        st.bi[r][j] = nsr * ti + nsi * tr + nc * nyi;
+      } else if (i == n - 1) {
+        st.br[r][j] = tr;
+        st.bi[r][j] = ti;
+      }
+    }
+  }
+}
+
+// One halving stage of the 16-lane reduce-scatter; CTRL pairs the lanes,
+// `upper` marks the half that keeps the upper H entries.
+template <int CTRL, int H>
+__device__ __forceinline__ void rs16_stage(double (&vr)[8], double (&vi)[8], bool upper) {
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    const double sr = upper ? vr[q] : vr[q + H];
+    const double si = upper ? vi[q] : vi[q + H];
+    const double kr = upper ? vr[q + H] : vr[q];
+    const double ki = upper ? vi[q + H] : vi[q];
+    vr[q] = kr + dpp<CTRL>(sr);
+    vi[q] = ki + dpp<CTRL>(si);
+  }
+}
+
+// G(:, j0 .. j0+mc-1) of this lane's frequency = (CQ) X + D; the sum over the
+// row's 16 lanes is a reduce-scatter of 8 complex values, after which lane gl
+// holds entry gl / 2.
+template <int R, int MM>
+__device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc, bool valid,
+                                               const double (&xr)[R][MM], const double (&xi)[R][MM],
+                                               double* __restrict__ G) {
+  const int gl = threadIdx.x & 15;
+  const int n = rd.n, m = rd.m, p = rd.p;
+  const gptr<double> Ct = (gptr<double>)rd.Ct;
+  constexpr int PC = (8 / MM > 0) ? 8 / MM : 1;
+  constexpr int MC = (MM < 8) ? MM : 8;
+  const bool up8 = gl >= 8, up4 = (gl & 7) >= 4, up2 = (gl & 3) >= 2;
+  for (int a0 = 0; a0 < p; a0 += PC) {
+#pragma unroll
+    for (int jb = 0; jb < MM; jb += MC) {
+      if (jb >= mc) break;
+      double vr[8], vi[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) vr[q] = vi[q] = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = gl + 16 * r;
+        if (i < n) {
+#pragma unroll
+          for (int q = 0; q < PC; ++q) {
+            const int a = a0 + q;
+            const double cq = (a < p) ? Ct[i * p + a] : 0.0;
+#pragma unroll
+            for (int j = 0; j < MC; ++j) {
+              vr[q * MC + j] = fma(cq, xr[r][jb + j], vr[q * MC + j]);
+              vi[q * MC + j] = fma(cq, xi[r][jb + j], vi[q * MC + j]);
+            }
+          }
+        }
+      }
+      rs16_stage<kDppRowMirror, 4>(vr, vi, up8);
+      rs16_stage<kDppRowHalfMirror, 2>(vr, vi, up4);
+      rs16_stage<0x1B, 1>(vr, vi, up2);  // quad_perm [3,2,1,0]
+      vr[0] += dpp<kDppQuadSwap1>(vr[0]);
+      vi[0] += dpp<kDppQuadSwap1>(vi[0]);
+      if (valid && (gl & 1) == 0) {
+        const int idx = gl >> 1;
+        const int a = a0 + idx / MC;
+        const int j = jb + idx % MC;
+        if (a < p && j < mc) {
+          double2 gv;
+          gv.x = vr[0] + rd.D[a * m + j0 + j];
+          gv.y = vi[0];
+          reinterpret_cast<double2*>(G)[a * m + j0 + j] = gv;
+        }
+      }
+    }
+  }
+}
+
+template <int R, int MM>
+__device__ void solve16_fp64(const ReqDesc& rd, int64_t k, bool valid, int j0, int mc, double* bcast) {
+  const int gl = threadIdx.x & 15;
+  const int n = rd.n, m = rd.m;
+  const double w = rd.omega[k];
+  const gptr<double> Bt = (gptr<double>)rd.Bt;
+  S16<double, R, MM> st;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = gl + 16 * r;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      st.br[r][j] = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
+      st.bi[r][j] = 0.0;
+    }
+  }
+  sweep16<double, R, MM>(rd.H, n, w, st, bcast);
+  const double ratio = rd.info ? diag_ratio16<double, R, MM>(n, st) : 0.0;
+  apply_rotations16<double, R, MM>(n, st);
+  double* G = rd.G + (size_t)k * rd.p * m * 2;
+  write_output16<R, MM>(rd, j0, mc, valid, st.br, st.bi, G);
+  if (rd.info && valid && gl == 0 && j0 == 0) {
+    lti_point_info inf;
+    inf.est_rel_err = (float)(0.5 * DBL_EPSILON * ratio);
+    inf.iters = 1;
+    inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
+    inf.reserved = 0;
+    rd.info[k] = inf;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T group_sum16(T x) {
+  return group_sum_dpp<16>(x);
+}
+
+__device__ __forceinline__ double bperm_d(int addr, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// r = Q^T B - (j w X - H X) in float64 for this lane's frequency; the row
+// X(j, :) reaches the other lanes of its 16-lane row through ds_bpermute.
+template <int R, int MM>
+__device__ __forceinline__ void residual16(const ReqDesc& rd, double w, int j0, int mc, const double (&xr)[R][MM],
+                                           const double (&xi)[R][MM], double (&rr)[R][MM], double (&ri)[R][MM]) {
+  const int lane = threadIdx.x & 63, gl = lane & 15;
+  const int n = rd.n, m = rd.m;
+  const gptr<double> Bt = (gptr<double>)rd.Bt;
+  const gptr<double> H = (gptr<double>)rd.H;
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = gl + 16 * t;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      const double b = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
+      rr[t][j] = b + w * xi[t][j];
+      ri[t][j] = -w * xr[t][j];
+    }
+  }
+  static_for<0, R>([&](auto sc) {
+    constexpr int sj = decltype(sc)::value;
+    if (16 * sj >= n) return;
+    const int jend = (n - 16 * sj < 16) ? n - 16 * sj : 16;
+    for (int jl = 0; jl < jend; ++jl) {
+      const int jc = 16 * sj + jl;  // column of H
+      const int off = hoff32(jc);
+      const int len = (jc + 2 < n) ? jc + 2 : n;
+      const int addr = ((lane & 48) | jl) << 2;
+      double xjr[MM], xji[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        xjr[j] = bperm_d(addr, xr[sj][j]);
+        xji[j] = bperm_d(addr, xi[sj][j]);
+      }
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int i = gl + 16 * t;
+        if (i < len) {
+          const double h = H[off + i];
+#pragma unroll
+          for (int j = 0; j < MM; ++j) {
+            rr[t][j] = fma(h, xjr[j], rr[t][j]);
+            ri[t][j] = fma(h, xji[j], ri[t][j]);
+          }
+        }
+      }
+    }
+  });
+}
+
+// Refined path: complex-float32 solves, float64 residuals and accumulation,
+// float64 fallback (see solve_refined in sweep.hip).  The four frequencies of
+// the wavefront iterate in lockstep until all have stopped.
+template <int R, int MM>
+__device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0, int mc, double* bcast64) {
+  const int gl = threadIdx.x & 15;
+  const int n = rd.n, m = rd.m;
+  const double w = rd.omega[k];
+  const float wf = (float)w;
+  const double tol = 0.1 * ((rd.rtol > 0.0) ? rd.rtol : 1e-10);
+  constexpr int kMaxIters = 6;
+  float* bcast = reinterpret_cast<float*>(bcast64);
+  const gptr<float> Bt32 = (gptr<float>)rd.Bt32;
+
+  double xr[R][MM], xi[R][MM];
+  S16<float, R, MM> st;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = gl + 16 * r;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      st.br[r][j] = (i < n && j < mc) ? Bt32[i * m + j0 + j] : 0.0f;
+      st.bi[r][j] = 0.0f;
+    }
+  }
+  sweep16<float, R, MM>(rd.H32, n, wf, st, bcast);
+  apply_rotations16<float, R, MM>(n, st);
+  double s2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      xr[r][j] = (double)st.br[r][j];
+      xi[r][j] = (double)st.bi[r][j];
+      s2 += xr[r][j] * xr[r][j] + xi[r][j] * xi[r][j];
+    }
+  double dprev = sqrt(group_sum16(s2));
+  int iters = 1;
+  double est = 1.0;
+  bool done = false, ok = false;
+  if (st.singular || !(dprev < INFINITY)) done = true;  // -> float64 fallback
+  for (int it = 0; it < kMaxIters; ++it) {
+    if (__all(done)) break;
+    double rr[R][MM], ri[R][MM];
+    residual16<R, MM>(rd, w, j0, mc, xr, xi, rr, ri);
+    double amax = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < MM; ++j) amax = fmax(amax, fmax(fabs(rr[r][j]), fabs(ri[r][j])));
+    amax = group_max16(amax);
+    if (!done && amax == 0.0) {  // X solves the float64 system exactly
+      est = 0.0;
+      ok = true;
+      done = true;
+    }
+    const double scale = (amax > 0.0) ? 1.0 / amax : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        st.br[r][j] = (float)(rr[r][j] * scale);
+        st.bi[r][j] = (float)(ri[r][j] * scale);
+      }
+    sweep16<float, R, MM>(rd.H32, n, wf, st, bcast);
+    apply_rotations16<float, R, MM>(n, st);
+    double d2 = 0.0, x2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        const double dr = done ? 0.0 : (double)st.br[r][j] * amax;
+        const double di = done ? 0.0 : (double)st.bi[r][j] * amax;
+        xr[r][j] += dr;
+        xi[r][j] += di;
+        d2 += dr * dr + di * di;
+        x2 += xr[r][j] * xr[r][j] + xi[r][j] * xi[r][j];
+      }
+    const double dn = sqrt(group_sum16(d2));
+    const double xn = sqrt(group_sum16(x2));
+    if (!done) {
+      ++iters;
+      if (!(dn < INFINITY) || !(xn > 0.0)) {
+        done = true;  // non-finite: fall back
+      } else {
+        const double rel = dn / xn;
+        const double pred = rel * (dn / dprev);
+        est = (pred < rel) ? pred : rel;
+        if (rel <= tol || pred <= tol) {
+          ok = true;
+          done = true;
+        } else if (dn > 0.5 * dprev || it + 1 == kMaxIters) {
+          done = true;  // stalled
+        }
+        dprev = dn;
+      }
+    }
+  }
+  int path = ok ? LTI_PATH_REFINED : LTI_PATH_FALLBACK;
+  if (__any(!ok)) {
+    const gptr<double> Bt = (gptr<double>)rd.Bt;
+    S16<double, R, MM> sd;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = gl + 16 * r;
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        sd.br[r][j] = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
+        sd.bi[r][j] = 0.0;
+      }
+    }
+    sweep16<double, R, MM>(rd.H, n, w, sd, bcast64);
+    const double ratio = diag_ratio16<double, R, MM>(n, sd);
+    apply_rotations16<double, R, MM>(n, sd);
+    if (!ok) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          xr[r][j] = sd.br[r][j];
+          xi[r][j] = sd.bi[r][j];
+        }
+      est = 0.5 * DBL_EPSILON * ratio;
+      if (sd.singular) path = LTI_PATH_SINGULAR;
+    }
+  }
+  double* G = rd.G + (size_t)k * rd.p * m * 2;
+  write_output16<R, MM>(rd, j0, mc, valid, xr, xi, G);
+  if (rd.info && valid && gl == 0 && j0 == 0) {
+    lti_point_info inf;
+    inf.est_rel_err = (float)est;
+    inf.iters = (uint8_t)iters;
+    inf.path = (uint8_t)path;
+    inf.reserved = 0;
+    rd.info[k] = inf;
+  }
+}
+
+template <int PREC, int R, int MM>
+__global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const TileDesc* __restrict__ tiles, int ntiles) {
+  __shared__ double bcast_all[kWaves16][4 * (2 + 2 * MM)];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves16 + wave;
+  if (tile >= ntiles) return;
+  const TileDesc td = tiles[tile];
+  const ReqDesc rd = *td.rd;
+  const int g = (threadIdx.x & 63) >> 4;
+  double* bcast = bcast_all[wave];
+  for (uint32_t f0 = 0; f0 < td.count; f0 += 4) {
+    // group g solves frequency f0 + g; past the tile's end it repeats the
+    // last frequency and writes nothing
+    const uint32_t f = f0 + g;
+    const bool valid = f < td.count;
+    const int64_t k = (int64_t)td.start + (valid ? f : td.count - 1);
+    if (PREC == LTI_PREC_FP64)
+      solve16_fp64<R, MM>(rd, k, valid, td.j0, td.mc, bcast);
+    else
+      solve16_refined<R, MM>(rd, k, valid, td.j0, td.mc, bcast);
+  }
+}
+
+using Kernel16Fn = void (*)(const TileDesc*, int);
+
+template <int PREC, int R>
+Kernel16Fn pick16_mm(int mi) {
+  return mi == 0 ? sweep16_kernel<PREC, R, 1> : mi == 1 ? sweep16_kernel<PREC, R, 2> : sweep16_kernel<PREC, R, 4>;
+}
+
+template <int PREC>
+Kernel16Fn pick16(int ri, int mi) {
+  return ri == 0 ? pick16_mm<PREC, 1>(mi) : ri == 1 ? pick16_mm<PREC, 2>(mi) : pick16_mm<PREC, 4>(mi);
+}
+
+}  // namespace
+
+int sweep16_class(int precision, int n, int mc) {
+  if (precision != LTI_PREC_FP64 && precision != LTI_PREC_REFINED) return -1;
+  if (n < 1 || n > 64 || mc < 1 || mc > 4) return -1;
+  const int ri = (n <= 16) ? 0 : (n <= 32) ? 1 : 2;
+  const int mi = (mc <= 1) ? 0 : (mc <= 2) ? 1 : 2;
+  return (precision * 3 + ri) * 3 + mi;
+}
+
+hipError_t launch_sweep16(int cls, const TileDesc* tiles, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (cls < 0 || cls >= kNumSweep16Classes) return hipErrorInvalidValue;
+  const int prec = cls / 9, ri = (cls / 3) % 3, mi = cls % 3;
+  const Kernel16Fn fn = prec == LTI_PREC_FP64 ? pick16<LTI_PREC_FP64>(ri, mi) : pick16<LTI_PREC_REFINED>(ri, mi);
+  const int blocks = (ntiles + kWaves16 - 1) / kWaves16;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves16), 0, s, tiles, ntiles);
+  return hipGetLastError();
+}
+
+}  // namespace lti

@@ -215,9 +215,9 @@ def test_error_codes(eng):
     with pytest.raises(binding.LtiError) as ei:
         eng.submit(A, mdl.B, mdl.C, mdl.D, mdl.omega)
     assert ei.value.code == binding.LTI_EINVAL
-    big = np.eye(257)
+    big = np.eye(1025)
     with pytest.raises(binding.LtiError) as ei:
-        eng.submit(-big, np.ones((257, 1)), np.ones((1, 257)), None, [1.0])
+        eng.submit(-big, np.ones((1025, 1)), np.ones((1, 1025)), None, [1.0])
     assert ei.value.code == binding.LTI_EUNSUPPORTED
     # 16 x 16 outputs: 4 KiB of G per frequency, 600k frequencies > the 2 GiB arena
     with pytest.raises(binding.LtiError) as ei:
@@ -250,3 +250,40 @@ def test_rhs_split_policies_agree(split, monkeypatch):
     for knob in ("1", split):
         assert oracle.rel_err(outs[(knob, "fp64")], ref).max() <= TOL_FP64
         assert oracle.rel_err(outs[(knob, "refined")], ref).max() <= TOL_REFINED
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 17, 31, 33, 48, 63, 64])
+def test_four_frequency_kernel_matches_single(n, monkeypatch):
+    """The four-frequencies-per-wavefront float64 kernel (models up to 64
+    states) against the one-frequency-per-wavefront kernel and the oracle;
+    grid sizes that leave partly filled groups of four."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(9000 + n)
+    w = np.concatenate([[0.0, -1.25], wl.logspace_grid(1e-2, 1e2, 27)])  # 29 points
+    mdl = wl.mixed_pole_model(rng, n, 3, 2, w)
+    outs = {}
+    for knob in ("0", "1"):
+        monkeypatch.setenv("LTI_FREQRESP_SWEEP16", knob)
+        with binding.Engine(arena_bytes=256 << 20) as e:
+            h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+            assert e.poll(h, -1)
+            outs[knob] = (h.G, h.info.copy())
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    assert oracle.rel_err(outs["1"][0], ref).max() <= TOL_FP64
+    assert oracle.rel_err(outs["1"][0], outs["0"][0]).max() <= 1e-13
+    assert np.array_equal(outs["1"][1]["path"], outs["0"][1]["path"])
+
+
+@pytest.mark.parametrize("n,m,p", [(257, 3, 2), (300, 5, 4), (512, 2, 3), (1024, 16, 16)])
+def test_large_state_dimensions(eng, n, m, p):
+    """Models above 256 states (one workgroup per frequency), float64 path."""
+    rng = np.random.default_rng(12000 + n)
+    w = np.concatenate([[0.0, -3.0], wl.logspace_grid(1e-2, 1e2, 7)])
+    mdl = wl.mixed_pole_model(rng, n, m, p, w)
+    print(f"case large n={n} m={m} p={p}", flush=True)
+    h = _run(eng, mdl, _prec("fp64"))
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    err = oracle.rel_err(h.G, ref)
+    assert err.max() <= TOL_FP64, (n, err.max(), int(err.argmax()))
+    assert np.all(h.info["path"] == 0)
