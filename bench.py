@@ -12,8 +12,8 @@ reported beside it.
 
 Printed: one JSON line with points/s (counting only points whose relative
 error against the CPU oracle is <= 1e-10), per-step latency percentiles, the
-roofline of the dominant kernel (the per-frequency sweep, timed with HIP
-events inside the library on the stream it runs on) and the CPU oracle timed
+roofline of the per-frequency sweep kernel (timed with HIP events inside
+the library on the stream it runs on) and the CPU oracle timed
 on this host's cores.
 """
 from __future__ import annotations
@@ -46,22 +46,34 @@ def sweep_flops_per_point(n: int, m: int, p: int) -> float:
     return 7.0 * n * n + 4.0 * m * n * n + 4.0 * n * m * p
 
 
-def _source_digest() -> str:
+def sweep_kernel_family(n: int) -> tuple[str, list[str]]:
+    """The sweep kernel the library launches for an n-state float64 request
+    (with its default tiling) and the source files that define it."""
+    common = ["sweep_common.h", "dpp.h", "lti_kernels.h"]
+    if n <= 64:
+        return "sweep16_kernel", ["sweep16.hip"] + common
+    if n <= 256:
+        return "sweep_kernel", ["sweep.hip"] + common
+    return "sweep_wg_kernel", ["sweepwg.hip"] + common
+
+
+def _source_digest(files: list[str]) -> str:
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2401_04068_amd", "csrc", "sweep.hip"), "rb") as f:
-        h.update(f.read())
+    for name in files:
+        with open(os.path.join(ROOT, "paper_2401_04068_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def _traffic_record(workload: str):
+def _traffic_record(workload: str, files: list[str]):
     """HBM bytes per sweep launch from committed rocprofv3 counter runs, used
-    only while the kernel source is the one the counters were taken on."""
+    only while the kernel sources are the ones the counters were taken on."""
     path = os.path.join(PROFILES, f"sweep_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("sweep_source_sha256_16") != _source_digest():
+    if rec.get("source_sha256_16") != _source_digest(files):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -324,7 +336,8 @@ def main():
     value = pts64 * ok64
     flops_launch = sweep_flops_per_point(n, m, p) * K / max(fp64["sweep_launches_per_step"], 1)
     achieved = flops_launch / (fp64["sweep_ms_per_launch"] * 1e-3) / 1e12
-    traffic = _traffic_record(args.workload)
+    kname, kfiles = sweep_kernel_family(n)
+    traffic = _traffic_record(args.workload, kfiles)
 
     out = {
         "metric": METRIC,
@@ -373,7 +386,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VALU_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": "sweep_kernel<fp64> (per-frequency Givens sweep)",
+            "kernel": f"{kname}<fp64> (per-frequency Givens sweep)",
+            "kernel_source_sha256_16": _source_digest(kfiles),
             "flops_per_launch": flops_launch,
         },
         "cpu_baseline": cpu,

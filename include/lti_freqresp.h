@@ -169,12 +169,14 @@ typedef struct lti_ctx lti_ctx;
  * Returns LTI_OK and *out, or LTI_EINVAL / LTI_EDEVICE / LTI_ENOMEM. */
 int lti_freqresp_create(const lti_config* config, lti_ctx** out);
 
-/* Queue one request and return without waiting for the GPU.
+/* Queue one request and return without waiting for the GPU.  When the
+ * request can start at once, its first kernels are launched from the calling
+ * thread (on the context's stream) before submit returns.
  * LTI_EINVAL: NULL pointers, dims <= 0, n_omega <= 0, unknown precision or
  *             mem, non-finite host input.
- * LTI_EUNSUPPORTED: nx > 1024, or nu or ny > 16.  (Refined-precision
- *             requests with nx > 256 run the float64 path; their points
- *             report LTI_PATH_FP64.)
+ * LTI_EUNSUPPORTED: nx > 1024, or nu or ny > 16, or n_omega * nu > 2^32 - 1.
+ *             (Refined-precision requests with nx > 256 run the float64
+ *             path; their points report LTI_PATH_FP64.)
  * LTI_ENOSPC: the request alone needs more than the whole arena.
  * LTI_EAGAIN: max_pending requests are outstanding.
  * LTI_EDEVICE: the context saw a HIP error.
@@ -185,7 +187,9 @@ int lti_freqresp_submit(lti_ctx* ctx, const lti_request* req, uint64_t* out_id);
  * request id.  Returns LTI_OK with *out filled once the request is done (the
  * id is then collected: a second poll gives LTI_ENOENT), LTI_PENDING if it is
  * still running, LTI_ENOENT for an unknown id, or the request's own error
- * (also reported in out->status) if it failed. */
+ * (also reported in out->status) if it failed.  A waiting poll drives the
+ * scheduling itself (retire, admit, launch) for up to 2 ms before it sleeps
+ * on the completion signal. */
 int lti_freqresp_poll(lti_ctx* ctx, uint64_t id, int32_t timeout_us, lti_result* out);
 
 /* Stop the scheduler, wait for the device work already launched, release

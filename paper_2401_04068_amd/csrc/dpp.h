@@ -63,6 +63,24 @@ __device__ __forceinline__ float readlane_d(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// Exchanges between 16-lane rows (gfx950 v_permlane16_swap / 32_swap, VALU
+// operations): with both operands x, permlane16_swap returns (even row's x,
+// odd row's x) at each position of a row pair, permlane32_swap returns (low
+// half's x, high half's x).  Summing the pair gives every lane
+// x[l] + x[l ^ 16] (resp. x[l ^ 32]), added in the same order on both sides.
+__device__ __forceinline__ double xor16_sum(double x) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double xor32_sum(double x) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
 // Sum over the whole wavefront, returned to every lane (read from lane 63).
 template <typename T>
 __device__ __forceinline__ T wave_sum_dpp(T x) {

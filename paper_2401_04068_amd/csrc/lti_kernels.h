@@ -37,7 +37,7 @@ void reduced_layout(void* base, int n, int m, int p, ReducedModel* out);
 
 // One reduction job: read A, B, C, D (device pointers, row-major; D may be
 // null), write the reduced model.  `work` is a scratch area of
-// reduce_work_bytes(n, m, p) bytes (unused when the model fits in LDS).
+// reduce_work_bytes(n, m, p) bytes (null for the register kernel).
 struct ReduceJob {
   const double* A;
   const double* B;
@@ -48,21 +48,28 @@ struct ReduceJob {
 };
 
 constexpr int kMaxReduceN = 1024;
-// Reduction kernel classes: 0..3 keep the working matrix in LDS (n <= 16, 32,
-// 64, 128); kReduceGlobal keeps it in a global scratch area.
-constexpr int kReduceGlobal = 4;
-constexpr int kNumReduceClasses = 5;
+// Reduction kernel classes: 0 .. kNumRegClasses-1 keep the working matrix in
+// registers (class S-1 for S = ceil(max(n+p, n+m) / 16) <= 9, n <= 128);
+// kReduceGlobal keeps it in a global scratch area.
+constexpr int kMaxRegReduceN = 128;
+constexpr int kNumRegClasses = 9;
+constexpr int kReduceGlobal = kNumRegClasses;
+constexpr int kNumReduceClasses = kNumRegClasses + 1;
 int reduce_class(int n, int m, int p);
-// Whether the working matrix of an (n, m, p) model fits in LDS, the LDS bytes
-// that kernel needs, and the global scratch bytes the other kernel needs.
-bool reduce_fits_lds(int n, int m, int p);
-size_t reduce_lds_bytes(int n, int m, int p);
+// Global scratch bytes a job of this shape needs (0 for register classes).
 size_t reduce_work_bytes(int n, int m, int p);
-// Launch jobs[0..njobs) (device array) of one reduction class; lds_bytes is
-// the largest reduce_lds_bytes() among them (ignored for kReduceGlobal).
-hipError_t launch_reduce(const ReduceJob* jobs, int njobs, int rclass, size_t lds_bytes, hipStream_t s);
+// Up to kMaxInlineJobs reduction jobs of one class, passed to the kernel by
+// value; one workgroup per job.
+constexpr int kMaxInlineJobs = 24;
+struct ReduceLaunch {
+  int njobs;
+  ReduceJob job[kMaxInlineJobs];
+};
+static_assert(sizeof(ReduceLaunch) <= 3072, "reduction launch arguments must stay small");
+hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s);
 
-// Per-request descriptor, resident in device memory while the request lives.
+// Per-request descriptor, handed to the sweep kernels in their launch
+// arguments.
 struct ReqDesc {
   const double* H;
   const double* Bt;
@@ -78,17 +85,28 @@ struct ReqDesc {
   double rtol;
 };
 
-// A tile: `count` consecutive frequencies of one request, solved by one
-// wavefront for the right-hand-side columns j0 .. j0 + mc - 1 (a request's
-// columns may be split over several tiles to expose more parallelism).
-struct TileDesc {
-  const ReqDesc* rd;
-  uint32_t start;
-  uint16_t count;
-  uint8_t j0;
+// A sweep launch covers tiles of up to kMaxSegs requests and is passed to the
+// kernel by value (kernel arguments: no copy, no descriptor in memory).
+// Tile t of a request holds frequencies [F (t / S), F (t / S) + F) (clipped
+// to K) and right-hand-side columns [mc (t % S), mc (t % S) + mc) (clipped to
+// m); segment s gives launch tiles [tile0, next segment's tile0) to the
+// request's tiles first, first + 1, ...
+struct SweepSeg {
+  ReqDesc rd;
+  uint32_t tile0;
+  uint32_t first;
+  uint32_t K;
+  uint16_t F;
+  uint8_t S;
   uint8_t mc;
 };
-static_assert(sizeof(TileDesc) == 16, "TileDesc must stay 16 bytes");
+constexpr int kMaxSegs = 16;
+struct SweepLaunch {
+  int nseg;
+  int ntiles;
+  SweepSeg seg[kMaxSegs];
+};
+static_assert(sizeof(SweepLaunch) <= 2048, "sweep launch arguments must stay small");
 
 // Sweep kernel classes: precision x rows-per-lane (1, 2, 4 -> n <= 64, 128,
 // 256) x right-hand-side capacity (1, 2, 4, 8, 16).
@@ -104,14 +122,14 @@ int sweep_class(int precision, int n, int m);
 // is not covered.  Their tiles should hold a multiple of 4 frequencies.
 constexpr int kNumSweep16Classes = 18;
 int sweep16_class(int precision, int n, int mc);
-hipError_t launch_sweep16(int cls, const TileDesc* tiles, int ntiles, hipStream_t s);
+hipError_t launch_sweep16(int cls, const SweepLaunch& L, hipStream_t s);
 
 // Workgroup-per-frequency kernels (sweepwg.hip): float64 path, 256 < n <= 1024,
 // at most 4 right-hand-side columns per tile; -1 when not covered.
 constexpr int kMaxNWG = 1024;
 constexpr int kNumSweepWGClasses = 3;
 int sweep_wg_class(int precision, int n, int mc);
-hipError_t launch_sweep_wg(int cls, const TileDesc* tiles, int ntiles, hipStream_t s);
+hipError_t launch_sweep_wg(int cls, const SweepLaunch& L, hipStream_t s);
 
 // LDS staging of one request's reduced model by a sweep workgroup: H, Bt and
 // Ct in float64, plus H and Bt in float32 for the refined path, each block
@@ -150,6 +168,6 @@ __host__ __device__ inline size_t stage_bytes(int precision, int n, int m, int p
 }
 // lds_bytes: dynamic LDS for staging (the largest stage_bytes() of the
 // launch's requests; 0 disables staging).
-hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, size_t lds_bytes, hipStream_t s);
+hipError_t launch_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s);
 
 }  // namespace lti

@@ -7,18 +7,25 @@
 // [A ; C] (Golub & Van Loan, Matrix Computations, 4th ed., Algorithm 7.4.2).
 // At the end the working matrix holds H = Q^T A Q, Q^T B and C Q.
 //
-// The augmented (n+p) x (n+m) working matrix W = [[A, B], [C, *]] lives in
-// LDS when it fits (n <= 128 with m, p <= 8 does: at most 149 KB of the
-// 160 KB per CU), otherwise in a global scratch area that stays hot in L2.
-// W is column-major with an odd leading dimension so that the row-strided
-// accesses of the right update spread over the LDS banks.
+// Two kernels work on the augmented (n+p) x (n+m) matrix W = [[A, B], [C, *]]:
 //
-// Every reflector costs three workgroup barriers: build v (wave 0, DPP wave
-// sum of squares), left update (a group of G adjacent lanes per column:
-// partial dot products over Q interleaved rows, a DPP sum within the group,
-// then the rank-1 update of the same column), right update (a group of G
-// lanes per row, likewise).  The Q-element inner loops are unrolled and
-// predicated so that their LDS loads issue back to back.
+// * Register kernel (n <= 128).  256 threads form a 16 x 16 grid; thread
+//   (r, c) holds W(i, j) for i = r (mod 16), j = c (mod 16) in an S x S
+//   register array, S = ceil(max(n+p, n+m) / 16).  The two one-sided updates
+//   of a step are applied together as one rank-2 update computed from the old
+//   matrix,
+//       P W P = W - v (tau W^T v)^T - tau (q - tau gamma v) v^T,
+//       q = W v,  gamma = v^T W v,
+//   so a step needs two exchanges: the row sums q (a DPP sum inside each
+//   16-lane row) with the column sums W^T v (over the 16 thread rows: two
+//   lane shuffles inside the wavefront, then LDS across the four), and the
+//   next pivot column with its norm.  Two barriers per reflector; the step
+//   is straight-line code over all S x S slots.
+// * Global kernel (n > 128): W in a global scratch area that stays hot in
+//   L2, three barriers per reflector (build v, left update, right update),
+//   a group of G adjacent lanes per column or row with DPP group sums.
+#include <algorithm>
+
 #include "dpp.h"
 #include "lti_kernels.h"
 
@@ -26,30 +33,219 @@ namespace lti {
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Register kernel
+
+constexpr int kRegThreads = 256;
+
+// Sum over the four 16-lane rows of the wavefront (same column position).
+__device__ __forceinline__ double sum_thread_rows(double x) { return xor32_sum(xor16_sum(x)); }
+
+template <int S>
+__global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunch L) {
+  constexpr int kPad = 16 * S;
+  __shared__ double xcol[kPad];   // pivot column, rows k+1 .. n-1
+  __shared__ double pw[4][kPad];  // column sums W^T v, one partial per wavefront
+  __shared__ double ssw[4];       // pivot column sum of squares below row k+1
+  __shared__ double gw[4];        // v^T W v partials
+
+  const ReduceJob job = L.job[blockIdx.x];
+  const int n = job.out.n, m = job.out.m, p = job.out.p;
+  const int nrow = n + p, ncol = n + m;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int tc = lane & 15;
+  const int tr = (wv << 2) | (lane >> 4);
+
+  // Row a of the register block is one vector, so that reading the column
+  // slot kb (uniform, known at run time) is an indexed register move, not a
+  // trip through scratch memory.
+  using Row = double __attribute__((ext_vector_type(S < 2 ? 2 : S)));
+  Row W[S];
+#pragma unroll
+  for (int a = 0; a < S; ++a) {
+    const int i = tr + 16 * a;
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      const int c = tc + 16 * b;
+      double x = 0.0;
+      if (i < n) {
+        if (c < n)
+          x = job.A[(size_t)i * n + c];
+        else if (c < ncol)
+          x = job.B[(size_t)i * m + (c - n)];
+      } else if (i < nrow && c < n) {
+        x = job.C[(size_t)(i - n) * n + c];
+      }
+      W[a][b] = x;
+    }
+  }
+
+  // Publish column kc (rows kc+1 .. n-1) and its sum of squares below row
+  // kc+1; only the 16 threads of thread column kc % 16 hold it.
+  auto publish = [&](int kc) {
+    const int kb = kc >> 4;
+    const bool mine = tc == (kc & 15);
+    double x[S];
+#pragma unroll
+    for (int a = 0; a < S; ++a) x[a] = W[a][kb];
+    double ss = 0.0;
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      const int i = tr + 16 * a;
+      if (mine && i > kc && i < n) xcol[i] = x[a];
+      const double x2 = (i > kc + 1 && i < n) ? x[a] : 0.0;
+      ss = fma(x2, x2, ss);
+    }
+    ss = sum_thread_rows(mine ? ss : 0.0);
+    if (lane == (kc & 15)) ssw[wv] = ss;
+  };
+
+  if (n > 2) publish(0);
+  __syncthreads();
+
+  // Every step runs the same straight-line code over all S x S slots: slots
+  // outside the active rows and columns meet exact zeros of v (a taken branch
+  // costs more than the few fused multiply-adds it would skip).  Column k is
+  // not reset to beta e_{k+1} explicitly: the update itself leaves beta (to
+  // rounding) on the subdiagonal and rounding-level values below it, which
+  // are never read again (H is stored up to the subdiagonal, and later
+  // reflectors only touch those rows through their own rounding-level
+  // column sums).
+  for (int k = 0; k + 2 < n; ++k) {
+    // reflector of column k, computed by every thread
+    double xr[S], xc[S];
+#pragma unroll
+    for (int a = 0; a < S; ++a) xr[a] = xcol[tr + 16 * a];
+#pragma unroll
+    for (int b = 0; b < S; ++b) xc[b] = xcol[tc + 16 * b];
+    const double ss = (ssw[0] + ssw[1]) + (ssw[2] + ssw[3]);
+    const double alpha = xcol[k + 1];
+    double tau = 0.0, scale = 0.0;
+    if (ss != 0.0) {
+      const double nrm = sqrt(fma(alpha, alpha, ss));
+      const double beta = (alpha >= 0.0) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // v on this thread's rows and columns (stale or unwritten entries of
+    // xcol are never selected)
+    double vr[S], vc[S];
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      const int i = tr + 16 * a;
+      const double t = xr[a] * scale;
+      vr[a] = (i == k + 1) ? 1.0 : ((i > k + 1 && i < n) ? t : 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      const int c = tc + 16 * b;
+      const double t = xc[b] * scale;
+      vc[b] = (c == k + 1) ? 1.0 : ((c > k + 1 && c < n) ? t : 0.0);
+    }
+    // partial W^T v over this thread's rows, partial W v over its columns
+    double pp[S], qq[S];
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      pp[b] = 0.0;
+#pragma unroll
+      for (int a = 0; a < S; ++a) pp[b] = fma(vr[a], W[a][b], pp[b]);
+    }
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      qq[a] = 0.0;
+#pragma unroll
+      for (int b = 0; b < S; ++b) qq[a] = fma(W[a][b], vc[b], qq[a]);
+      qq[a] = group_sum_dpp<16>(qq[a]);  // row sum over the 16 thread columns
+    }
+    double g = 0.0;
+#pragma unroll
+    for (int a = 0; a < S; ++a) g = fma(vr[a], qq[a], g);
+    g = sum_thread_rows(g);
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      pp[b] = sum_thread_rows(pp[b]);
+      if (lane < 16) pw[wv][tc + 16 * b] = pp[b];
+    }
+    if (lane == 0) gw[wv] = g;
+    __syncthreads();
+
+    double pr[4][S];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int b = 0; b < S; ++b) pr[w][b] = pw[w][tc + 16 * b];
+    const double gamma = (gw[0] + gw[1]) + (gw[2] + gw[3]);
+    const double tg = tau * gamma;
+#pragma unroll
+    for (int b = 0; b < S; ++b) pp[b] = tau * ((pr[0][b] + pr[1][b]) + (pr[2][b] + pr[3][b]));
+#pragma unroll
+    for (int a = 0; a < S; ++a) qq[a] = tau * fma(-tg, vr[a], qq[a]);
+    // W -= v (tau W^T v)^T + tau (q - tau gamma v) v^T
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) {
+        W[a][b] = fma(-vr[a], pp[b], W[a][b]);
+        W[a][b] = fma(-qq[a], vc[b], W[a][b]);
+      }
+    if (k + 3 < n) publish(k + 1);
+    __syncthreads();
+  }
+
+  // write the reduced model
+  const ReducedModel& o = job.out;
+#pragma unroll
+  for (int a = 0; a < S; ++a) {
+    const int i = tr + 16 * a;
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      const int c = tc + 16 * b;
+      const double x = W[a][b];
+      if (i < n) {
+        if (c < n) {
+          if (i <= c + 1) {
+            const int64_t off = hoff(c) + i;
+            o.H[off] = x;
+            o.H32[off] = (float)x;
+          }
+        } else if (c < ncol) {
+          const int idx = i * m + (c - n);
+          o.Bt[idx] = x;
+          o.Bt32[idx] = (float)x;
+        }
+      } else if (i < nrow && c < n) {
+        const int idx = c * p + (i - n);
+        o.Ct[idx] = x;
+        o.Ct32[idx] = (float)x;
+      }
+    }
+  }
+  for (int idx = threadIdx.x; idx < p * m; idx += kRegThreads) o.D[idx] = job.D ? job.D[idx] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Global kernel
+
+constexpr int kGlobalThreads = 1024;
+constexpr int kGlobalGroup = 8;
+
 __host__ __device__ inline int ld_of(int n, int p) { return (n + p) | 1; }
 
-template <int NT, int G, int Q, bool kLds>
-__global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ jobs) {
-  extern __shared__ double smem[];
-  const ReduceJob job = jobs[blockIdx.x];
+// W column-major in job.work with an odd leading dimension, so that the
+// row-strided accesses of the right update spread over the channels.
+template <int NT, int G>
+__global__ __launch_bounds__(NT) void hess_global_kernel(const ReduceLaunch L) {
+  __shared__ double v[kMaxReduceN];
+  __shared__ double sc[1];
+  const ReduceJob job = L.job[blockIdx.x];
   const int n = job.out.n, m = job.out.m, p = job.out.p;
   const int ldw = ld_of(n, p);
   const int ncol = n + m;
   const int nrow = n + p;
   const int tid = threadIdx.x;
-  double* W;
-  double* v;
-  double* sc;
-  if (kLds) {
-    W = smem;
-    v = smem + (size_t)ldw * ncol;
-  } else {
-    W = job.work;
-    v = smem;
-  }
-  sc = v + n;
+  double* W = job.work;
 
-  // load [[A, B], [C, *]] column-major
   for (int idx = tid; idx < nrow * ncol; idx += NT) {
     const int i = idx % nrow;
     const int c = idx / nrow;
@@ -100,82 +296,28 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
     const double tau = sc[0];
 
     // left: rows k+1..n-1, columns k+1..n+m-1 (A and B)
-    if constexpr (Q == 0) {
-      for (int c = k + 1 + group; c < ncol; c += kGroups) {
-        double* col = W + (size_t)ldw * c;
-        double s = 0.0;
-        for (int i = k + 1 + lg; i < n; i += G) s = fma(v[i], col[i], s);
-        s = group_sum_dpp<G>(s) * tau;
-        for (int i = k + 1 + lg; i < n; i += G) col[i] = fma(-v[i], s, col[i]);
-      }
-    } else {
-      double vv[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int i = k + 1 + lg + G * q;
-        vv[q] = (i < n) ? v[i] : 0.0;
-      }
-      for (int c = k + 1 + group; c < ncol; c += kGroups) {
-        double* col = W + (size_t)ldw * c;
-        double xx[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int i = k + 1 + lg + G * q;
-          xx[q] = (i < n) ? col[i] : 0.0;
-        }
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) s = fma(vv[q], xx[q], s);
-        s = group_sum_dpp<G>(s) * tau;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int i = k + 1 + lg + G * q;
-          if (i < n) col[i] = fma(-vv[q], s, xx[q]);
-        }
-      }
+    for (int c = k + 1 + group; c < ncol; c += kGroups) {
+      double* col = W + (size_t)ldw * c;
+      double s = 0.0;
+      for (int i = k + 1 + lg; i < n; i += G) s = fma(v[i], col[i], s);
+      s = group_sum_dpp<G>(s) * tau;
+      for (int i = k + 1 + lg; i < n; i += G) col[i] = fma(-v[i], s, col[i]);
     }
     __syncthreads();
 
     // right: rows 0..n+p-1 (A and C), columns k+1..n-1
-    if constexpr (Q == 0) {
-      for (int r = group; r < nrow; r += kGroups) {
-        double s = 0.0;
-        for (int c = k + 1 + lg; c < n; c += G) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
-        s = group_sum_dpp<G>(s) * tau;
-        for (int c = k + 1 + lg; c < n; c += G) {
-          double* x = W + (size_t)r + (size_t)ldw * c;
-          *x = fma(-s, v[c], *x);
-        }
-      }
-    } else {
-      double vv[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int c = k + 1 + lg + G * q;
-        vv[q] = (c < n) ? v[c] : 0.0;
-      }
-      for (int r = group; r < nrow; r += kGroups) {
-        double xx[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int c = k + 1 + lg + G * q;
-          xx[q] = (c < n) ? W[(size_t)r + (size_t)ldw * c] : 0.0;
-        }
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) s = fma(xx[q], vv[q], s);
-        s = group_sum_dpp<G>(s) * tau;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int c = k + 1 + lg + G * q;
-          if (c < n) W[(size_t)r + (size_t)ldw * c] = fma(-s, vv[q], xx[q]);
-        }
+    for (int r = group; r < nrow; r += kGroups) {
+      double s = 0.0;
+      for (int c = k + 1 + lg; c < n; c += G) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
+      s = group_sum_dpp<G>(s) * tau;
+      for (int c = k + 1 + lg; c < n; c += G) {
+        double* x = W + (size_t)r + (size_t)ldw * c;
+        *x = fma(-s, v[c], *x);
       }
     }
     __syncthreads();
   }
 
-  // write the reduced model
   const ReducedModel& o = job.out;
   for (int j = 0; j < n; ++j) {
     const int len = (j + 2 < n) ? j + 2 : n;
@@ -201,43 +343,20 @@ __global__ __launch_bounds__(NT) void hess_kernel(const ReduceJob* __restrict__ 
   for (int idx = tid; idx < p * m; idx += NT) o.D[idx] = job.D ? job.D[idx] : 0.0;
 }
 
-// LDS kernel: 1024 threads; a column (row) is shared by G lanes holding Q
-// interleaved rows (columns) each: G = 16 up to 64 states, 8 up to 128.
-constexpr int kLdsThreads = 1024;
-constexpr int kGlobalThreads = 1024;
-constexpr int kGlobalGroup = 8;
-constexpr size_t kLdsLimit = 160 * 1024;
-
-size_t lds_bytes(int n, int m, int p) {
-  return ((size_t)ld_of(n, p) * (size_t)(n + m) + (size_t)n + 8) * sizeof(double);
-}
-
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-using ReduceFn = void (*)(const ReduceJob*);
-
-template <int G, int Q>
-hipError_t launch_lds(const ReduceJob* jobs, int njobs, size_t lds_need, hipStream_t s) {
-  static bool attr_set = false;  // launches come from one scheduler thread
-  const void* fn = reinterpret_cast<const void*>(&hess_kernel<kLdsThreads, G, Q, true>);
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hess_kernel<kLdsThreads, G, Q, true><<<njobs, kLdsThreads, lds_need, s>>>(jobs);
+template <int S>
+hipError_t launch_reg(const ReduceLaunch& L, hipStream_t s) {
+  hess_reg_kernel<S><<<L.njobs, kRegThreads, 0, s>>>(L);
   return hipGetLastError();
 }
 
 }  // namespace
 
-bool reduce_fits_lds(int n, int m, int p) { return lds_bytes(n, m, p) <= kLdsLimit; }
-
-size_t reduce_lds_bytes(int n, int m, int p) { return lds_bytes(n, m, p); }
-
 int reduce_class(int n, int m, int p) {
-  if (!reduce_fits_lds(n, m, p) || n > 128) return kReduceGlobal;
-  return (n <= 16) ? 0 : (n <= 32) ? 1 : (n <= 64) ? 2 : 3;
+  const int s = (std::max(n + p, n + m) + 15) / 16;
+  if (n <= kMaxRegReduceN && s <= kNumRegClasses) return s - 1;
+  return kReduceGlobal;
 }
 
 size_t reduce_work_bytes(int n, int m, int p) {
@@ -274,20 +393,22 @@ void reduced_layout(void* base, int n, int m, int p, ReducedModel* o) {
   o->pad = 0;
 }
 
-hipError_t launch_reduce(const ReduceJob* jobs, int njobs, int rclass, size_t lds_need, hipStream_t s) {
-  if (njobs <= 0) return hipSuccess;
-  if (rclass == kReduceGlobal) {
-    // v (n <= kMaxReduceN doubles) plus scalars
-    const size_t sh = (kMaxReduceN + 8) * sizeof(double);
-    hess_kernel<kGlobalThreads, kGlobalGroup, 0, false><<<njobs, kGlobalThreads, sh, s>>>(jobs);
-    return hipGetLastError();
-  }
-  if (lds_need > kLdsLimit) return hipErrorInvalidValue;
+hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s) {
+  if (L.njobs <= 0) return hipSuccess;
+  if (L.njobs > kMaxInlineJobs) return hipErrorInvalidValue;
   switch (rclass) {
-    case 0: return launch_lds<16, 1>(jobs, njobs, lds_need, s);
-    case 1: return launch_lds<16, 2>(jobs, njobs, lds_need, s);
-    case 2: return launch_lds<16, 4>(jobs, njobs, lds_need, s);
-    case 3: return launch_lds<8, 16>(jobs, njobs, lds_need, s);
+    case 0: return launch_reg<1>(L, s);
+    case 1: return launch_reg<2>(L, s);
+    case 2: return launch_reg<3>(L, s);
+    case 3: return launch_reg<4>(L, s);
+    case 4: return launch_reg<5>(L, s);
+    case 5: return launch_reg<6>(L, s);
+    case 6: return launch_reg<7>(L, s);
+    case 7: return launch_reg<8>(L, s);
+    case 8: return launch_reg<9>(L, s);
+    case kReduceGlobal:
+      hess_global_kernel<kGlobalThreads, kGlobalGroup><<<L.njobs, kGlobalThreads, 0, s>>>(L);
+      return hipGetLastError();
     default: return hipErrorInvalidValue;
   }
 }

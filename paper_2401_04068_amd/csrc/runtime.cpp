@@ -2,8 +2,10 @@
 // models, admission by memory budget, and continuous batching of the
 // per-frequency solves of every live request into shared kernel launches.
 //
-// One scheduler thread per context owns all device work, issued in order on
-// one stream:
+// All device work is issued in order on one stream by a scheduling pass
+// (pump) that runs under the context lock: on the context's scheduler thread,
+// and inline on the caller's thread in submit() and in a waiting poll(), so a
+// lone request starts and completes without a thread hand-off.  A pass:
 //
 //   admit    pending requests in arrival order while their memory fits:
 //            upload inputs, reuse a resident reduced model or queue a
@@ -18,7 +20,9 @@
 //
 // Host inputs are copied at submit() into pinned staging owned by the
 // library, so every H2D and D2H copy is a true asynchronous DMA that never
-// stalls the scheduler behind queued kernels.
+// stalls the scheduler behind queued kernels.  The descriptors the kernels
+// need (reduction jobs, per-request descriptors and tile ranges) travel in
+// the kernel arguments: nothing but the inputs and results is ever copied.
 #include <hip/hip_runtime.h>
 #include <sys/prctl.h>
 
@@ -44,11 +48,13 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kInflight = 3;
-constexpr int kJobSlots = 4;
+// Reduction jobs queued by one admission pass (bounds one pass's work).
 constexpr int kMaxJobs = 1024;
 constexpr int kDefaultMaxPending = 8192;
 constexpr int kDefaultBatchTiles = 16384;
 constexpr size_t kDefaultStaging = size_t(256) << 20;
+// A waiting poll() runs scheduling passes itself for up to this long.
+constexpr int64_t kPollSpinUs = 2000;
 // Tiles (wavefronts) one request should offer before its columns are split:
 // 256 CUs x 4 SIMDs x 4 resident waves.
 constexpr int64_t kTargetTiles = 4096;
@@ -128,14 +134,14 @@ struct Resident {
 
 enum class RState { kPending, kLive, kFinishing, kDone, kFailed };
 
-// Host-side staging of one request: A, B, C, D, omega, the ReqDesc and (at
+// Host-side staging of a host-memory request: A, B, C, D, omega and (at
 // completion) G and info, in one pinned block when the pool has room.
 struct HostStage {
   char* base = nullptr;  // pinned block, or fallback.data()
   size_t bytes = 0;
   bool pinned = false;
   std::vector<char> fallback;
-  size_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0, offDesc = 0, offG = 0, offInfo = 0;
+  size_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0, offG = 0, offInfo = 0;
 };
 
 struct Request {
@@ -147,10 +153,10 @@ struct Request {
   HostStage hs;
   Resident* model = nullptr;
   bool reused = false;
-  void* block = nullptr;  // device: omega, G, info, ReqDesc, A..D, reduction scratch
+  void* block = nullptr;  // device: A..D, omega, G, info, reduction scratch
   size_t block_bytes = 0;
-  size_t dOffG = 0, dOffInfo = 0;
-  ReqDesc* d_desc = nullptr;
+  size_t dOffG = 0;
+  ReqDesc desc{};         // handed to the sweep kernels in their arguments
   int kclass = -1;
   int64_t K = 0;
   int F = 1;        // frequencies per tile
@@ -166,8 +172,7 @@ struct Batch {
   hipEvent_t done = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   bool timed = false;
-  int slot = 0;
-  std::vector<std::pair<Request*, int>> credit;
+  std::vector<std::pair<Request*, int64_t>> credit;
 };
 
 struct TimedPair {
@@ -209,7 +214,6 @@ struct lti_ctx {
   int64_t target_tiles = kTargetTiles;
   Arena arena;
   Arena staging;  // pinned host pool
-  char* staging_base = nullptr;
   Clock::time_point t0;
 
   std::mutex mu;
@@ -228,14 +232,7 @@ struct lti_ctx {
   std::deque<Batch> inflight;
   std::deque<TimedPair> reduce_timing;
 
-  TileDesc* h_tiles = nullptr;  // pinned, kInflight slots
-  TileDesc* d_tiles = nullptr;  // arena
-  std::vector<int> free_slots;
-  ReduceJob* h_jobs = nullptr;  // pinned, kJobSlots slots of kMaxJobs
-  ReduceJob* d_jobs = nullptr;
-  hipEvent_t job_ev[kJobSlots] = {};
-  int job_next = 0;
-  size_t fixed_bytes = 0;
+  char* staging_block = nullptr;  // the pinned allocation behind `staging`
   std::vector<hipEvent_t> event_pool, timing_pool;
 
   lti_stats stats{};
@@ -287,10 +284,11 @@ void release_stage(lti_ctx* c, HostStage& hs) {
   hs.fallback.shrink_to_fit();
 }
 
-// Device bytes of a request (besides a shared resident model).
+// Device bytes of a request (besides a shared resident model); the block holds
+// [A..D | omega | G | info] (host-memory requests), then the reduction scratch.
 struct Need {
-  size_t omega = 0, G = 0, info = 0, desc = 0, inputs = 0, work = 0, model = 0;
-  size_t block() const { return omega + G + info + desc + inputs + work; }
+  size_t omega = 0, G = 0, info = 0, inputs = 0, work = 0, model = 0;
+  size_t block() const { return omega + G + info + inputs + work; }
 };
 
 Need request_need(const lti_request& q, bool needs_model) {
@@ -301,7 +299,6 @@ Need request_need(const lti_request& q, bool needs_model) {
     nd.G = align_up(sizeof(double) * 2 * (size_t)q.n_omega * p * m);
     nd.info = q.info_out ? align_up(sizeof(lti_point_info) * q.n_omega) : 0;
   }
-  nd.desc = align_up(sizeof(ReqDesc));
   if (needs_model) {
     if (q.mem == LTI_MEM_HOST)  // same per-matrix alignment as the host staging
       nd.inputs = align_up(sizeof(double) * n * n) + align_up(sizeof(double) * n * m) +
@@ -359,15 +356,9 @@ void release_request_memory(lti_ctx* c, Request* r) {
   }
 }
 
-bool job_slot_free(lti_ctx* c) {
-  hipEvent_t e = c->job_ev[c->job_next];
-  return !e || hipEventQuery(e) != hipErrorNotReady;
-}
-
 // Try to admit one request.  Returns false when it has to wait for memory.
 struct JobLists {
   std::vector<ReduceJob> jobs[kNumReduceClasses];
-  size_t lds[kNumReduceClasses] = {};
   size_t total() const {
     size_t t = 0;
     for (const auto& v : jobs) t += v.size();
@@ -375,12 +366,12 @@ struct JobLists {
   }
 };
 
-bool admit_one(lti_ctx* c, Request* r, JobLists& jl, bool jobs_allowed) {
+bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   const lti_request& q = r->req;
   const int n = q.nx, m = q.nu, p = q.ny;
   Resident* res = find_resident(c, *r);
   const bool needs_model = (res == nullptr);
-  if (needs_model && (!jobs_allowed || (int)jl.total() >= kMaxJobs)) return false;
+  if (needs_model && (int)jl.total() >= kMaxJobs) return false;
   const Need nd = request_need(q, needs_model);
   void* mblock = nullptr;
   if (needs_model) {
@@ -422,62 +413,57 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl, bool jobs_allowed) {
   double* d_G = q.G_out;
   lti_point_info* d_info = q.info_out;
   hipError_t e = hipSuccess;
+  ReduceJob job{};
+  if (needs_model) {
+    job.A = q.A;
+    job.B = q.B;
+    job.C = q.C;
+    job.D = q.D;
+  }
   if (host) {
+    // A..D (when this request reduces its model) and omega sit back to back
+    // in staging; the block mirrors that layout, so one H2D copy moves them
+    const size_t src0 = needs_model ? hs.offA : hs.offW;
+    const size_t bytes = hs.offW - src0 + sizeof(double) * q.n_omega;
+    e = hipMemcpyAsync(b, hs.base + src0, bytes, hipMemcpyHostToDevice, c->stream);
+    if (needs_model) {
+      job.A = reinterpret_cast<const double*>(b);
+      job.B = reinterpret_cast<const double*>(b + (hs.offB - hs.offA));
+      job.C = reinterpret_cast<const double*>(b + (hs.offC - hs.offA));
+      job.D = reinterpret_cast<const double*>(b + (hs.offD - hs.offA));
+    }
+    b += nd.inputs;
     d_omega = reinterpret_cast<const double*>(b);
-    e = hipMemcpyAsync(b, hs.base + hs.offW, sizeof(double) * q.n_omega, hipMemcpyHostToDevice, c->stream);
     b += nd.omega;
-    r->dOffG = nd.omega;
+    r->dOffG = (size_t)(b - static_cast<char*>(block));
     d_G = reinterpret_cast<double*>(b);
     b += nd.G;
-    r->dOffInfo = nd.omega + nd.G;
     d_info = nd.info ? reinterpret_cast<lti_point_info*>(b) : nullptr;
     b += nd.info;
   }
-  ReqDesc* d_desc = reinterpret_cast<ReqDesc*>(b);
-  b += nd.desc;
   if (needs_model) {
-    ReduceJob job{};
-    if (host) {
-      char* dIn = b;
-      const size_t bytes = (size_t)(hs.offW - hs.offA);  // A, B, C, D are contiguous in staging
-      if (e == hipSuccess) e = hipMemcpyAsync(dIn, hs.base + hs.offA, bytes, hipMemcpyHostToDevice, c->stream);
-      job.A = reinterpret_cast<const double*>(dIn);
-      job.B = reinterpret_cast<const double*>(dIn + (hs.offB - hs.offA));
-      job.C = reinterpret_cast<const double*>(dIn + (hs.offC - hs.offA));
-      job.D = reinterpret_cast<const double*>(dIn + (hs.offD - hs.offA));
-      b += nd.inputs;
-    } else {
-      job.A = q.A;
-      job.B = q.B;
-      job.C = q.C;
-      job.D = q.D;
-    }
     job.out = res->rm;
     job.work = nd.work ? reinterpret_cast<double*>(b) : nullptr;
     b += nd.work;
-    const int rc = reduce_class(n, m, p);
-    jl.jobs[rc].push_back(job);
-    if (rc != kReduceGlobal) jl.lds[rc] = std::max(jl.lds[rc], reduce_lds_bytes(n, m, p));
+    jl.jobs[reduce_class(n, m, p)].push_back(job);
   }
-  ReqDesc* desc = reinterpret_cast<ReqDesc*>(hs.base + hs.offDesc);
-  *desc = ReqDesc{};
-  desc->H = res->rm.H;
-  desc->Bt = res->rm.Bt;
-  desc->Ct = res->rm.Ct;
-  desc->D = res->rm.D;
-  desc->H32 = res->rm.H32;
-  desc->Bt32 = res->rm.Bt32;
-  desc->Ct32 = res->rm.Ct32;
-  desc->omega = d_omega;
-  desc->G = d_G;
-  desc->info = d_info;
-  desc->n = n;
-  desc->m = m;
-  desc->p = p;
-  desc->precision = q.precision;
-  desc->rtol = q.rtol;
-  r->d_desc = d_desc;
-  if (e == hipSuccess) e = hipMemcpyAsync(d_desc, desc, sizeof(ReqDesc), hipMemcpyHostToDevice, c->stream);
+  ReqDesc& desc = r->desc;
+  desc = ReqDesc{};
+  desc.H = res->rm.H;
+  desc.Bt = res->rm.Bt;
+  desc.Ct = res->rm.Ct;
+  desc.D = res->rm.D;
+  desc.H32 = res->rm.H32;
+  desc.Bt32 = res->rm.Bt32;
+  desc.Ct32 = res->rm.Ct32;
+  desc.omega = d_omega;
+  desc.G = d_G;
+  desc.info = d_info;
+  desc.n = n;
+  desc.m = m;
+  desc.p = p;
+  desc.precision = q.precision;
+  desc.rtol = q.rtol;
   if (e != hipSuccess) {
     fail_all(c, LTI_EDEVICE);
     return true;
@@ -529,38 +515,31 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl, bool jobs_allowed) {
 
 void admit(lti_ctx* c) {
   JobLists jl;
-  const bool jobs_allowed = job_slot_free(c);
   while (!c->pending.empty() && !c->device_error) {
     Request* r = c->pending.front();
-    if (!admit_one(c, r, jl, jobs_allowed)) break;
+    if (!admit_one(c, r, jl)) break;
     c->pending.pop_front();
     if (r->state == RState::kLive) c->live.push_back(r);
   }
-  const size_t njobs = jl.total();
-  if (c->device_error || njobs == 0) return;
-  const int slot = c->job_next;
-  c->job_next = (c->job_next + 1) % kJobSlots;
-  ReduceJob* hj = c->h_jobs + (size_t)slot * kMaxJobs;
-  ReduceJob* dj = c->d_jobs + (size_t)slot * kMaxJobs;
-  size_t off[kNumReduceClasses];
-  size_t o = 0;
-  for (int rc = 0; rc < kNumReduceClasses; ++rc) {
-    off[rc] = o;
-    std::copy(jl.jobs[rc].begin(), jl.jobs[rc].end(), hj + o);
-    o += jl.jobs[rc].size();
-  }
-  hipError_t e = hipMemcpyAsync(dj, hj, sizeof(ReduceJob) * njobs, hipMemcpyHostToDevice, c->stream);
-  if (!c->job_ev[slot]) c->job_ev[slot] = get_event(c, false);
-  if (e == hipSuccess) e = hipEventRecord(c->job_ev[slot], c->stream);
+  if (c->device_error || jl.total() == 0) return;
   const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
   TimedPair tp{nullptr, nullptr};
+  hipError_t e = hipSuccess;
   if (timed) {
     tp.a = get_event(c, true);
     tp.b = get_event(c, true);
-    if (e == hipSuccess) e = hipEventRecord(tp.a, c->stream);
+    e = hipEventRecord(tp.a, c->stream);
   }
-  for (int rc = 0; rc < kNumReduceClasses && e == hipSuccess; ++rc)
-    e = launch_reduce(dj + off[rc], (int)jl.jobs[rc].size(), rc, jl.lds[rc], c->stream);
+  // the jobs travel in the kernel arguments, kMaxInlineJobs per launch
+  ReduceLaunch L;
+  for (int rc = 0; rc < kNumReduceClasses && e == hipSuccess; ++rc) {
+    const std::vector<ReduceJob>& v = jl.jobs[rc];
+    for (size_t i0 = 0; i0 < v.size() && e == hipSuccess; i0 += kMaxInlineJobs) {
+      L.njobs = (int)std::min<size_t>(kMaxInlineJobs, v.size() - i0);
+      std::copy(v.begin() + i0, v.begin() + i0 + L.njobs, L.job);
+      e = launch_reduce(L, rc, c->stream);
+    }
+  }
   if (timed && e == hipSuccess) {
     e = hipEventRecord(tp.b, c->stream);
     c->reduce_timing.push_back(tp);
@@ -568,67 +547,66 @@ void admit(lti_ctx* c) {
   if (e != hipSuccess) fail_all(c, LTI_EDEVICE);
 }
 
+// Gather up to batch_tiles tiles from the live requests (oldest first) into
+// one batch: one launch per kernel class and kMaxSegs requests, each request
+// a contiguous range of its tiles.
 void launch(lti_ctx* c) {
-  if (c->live.empty() || c->free_slots.empty()) return;
-  const int slot = c->free_slots.back();
-  TileDesc* ht = c->h_tiles + (size_t)slot * c->batch_tiles;
-  TileDesc* dt = c->d_tiles + (size_t)slot * c->batch_tiles;
+  if (c->live.empty() || (int)c->inflight.size() >= kInflight) return;
   constexpr int kAllClasses = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
-  std::vector<std::vector<TileDesc>> per(kAllClasses);
+  struct Piece {
+    Request* r;
+    int64_t first, count;
+  };
+  std::vector<std::vector<Piece>> per(kAllClasses);
   std::vector<size_t> lds(kAllClasses, 0);
   Batch b;
-  int total = 0;
+  int64_t total = 0;
   for (Request* r : c->live) {
     if (total >= c->batch_tiles) break;
     if (r->state != RState::kLive || r->next_tile >= r->ntiles) continue;
-    int took = 0;
-    while (r->next_tile < r->ntiles && total < c->batch_tiles) {
-      const int64_t t = r->next_tile++;
-      const int64_t fb = t / r->S;
-      const int g = (int)(t % r->S);
-      TileDesc td;
-      td.rd = r->d_desc;
-      td.start = (uint32_t)(fb * r->F);
-      td.count = (uint16_t)std::min<int64_t>(r->F, r->K - fb * r->F);
-      td.j0 = (uint8_t)(g * r->mc);
-      td.mc = (uint8_t)std::min(r->mc, r->req.nu - g * r->mc);
-      per[r->kclass].push_back(td);
-      lds[r->kclass] = std::max(lds[r->kclass], r->stage);
-      ++took;
-      ++total;
-    }
-    b.credit.emplace_back(r, took);
+    const int64_t take = std::min<int64_t>(r->ntiles - r->next_tile, c->batch_tiles - total);
+    per[r->kclass].push_back(Piece{r, r->next_tile, take});
+    lds[r->kclass] = std::max(lds[r->kclass], r->stage);
+    r->next_tile += take;
+    total += take;
+    b.credit.emplace_back(r, take);
     if (r->res.t_first_launch_us == 0.0) r->res.t_first_launch_us = c->now_us();
   }
   if (total == 0) return;
-  c->free_slots.pop_back();
-  b.slot = slot;
-  std::vector<std::pair<int, int>> ranges;  // (class, offset)
-  int off = 0;
-  for (int k = 0; k < kAllClasses; ++k) {
-    if (per[k].empty()) continue;
-    std::copy(per[k].begin(), per[k].end(), ht + off);
-    ranges.emplace_back(k, off);
-    off += (int)per[k].size();
-  }
-  hipError_t e = hipMemcpyAsync(dt, ht, sizeof(TileDesc) * total, hipMemcpyHostToDevice, c->stream);
+  hipError_t e = hipSuccess;
   b.timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
   if (b.timed) {
     b.t0 = get_event(c, true);
     b.t1 = get_event(c, true);
-    if (e == hipSuccess) e = hipEventRecord(b.t0, c->stream);
+    e = hipEventRecord(b.t0, c->stream);
   }
-  for (auto& kr : ranges) {
-    if (e != hipSuccess) break;
-    if (kr.first >= kNumSweepClasses + kNumSweep16Classes)
-      e = launch_sweep_wg(kr.first - kNumSweepClasses - kNumSweep16Classes, dt + kr.second,
-                          (int)per[kr.first].size(), c->stream);
-    else if (kr.first >= kNumSweepClasses)
-      e = launch_sweep16(kr.first - kNumSweepClasses, dt + kr.second, (int)per[kr.first].size(), c->stream);
-    else
-      e = launch_sweep(kr.first, dt + kr.second, (int)per[kr.first].size(), c->stage_lds ? lds[kr.first] : 0,
-                       c->stream);
-    c->stats.sweep_launches++;
+  SweepLaunch L;
+  for (int k = 0; k < kAllClasses && e == hipSuccess; ++k) {
+    const std::vector<Piece>& v = per[k];
+    for (size_t i0 = 0; i0 < v.size() && e == hipSuccess; i0 += kMaxSegs) {
+      L.nseg = (int)std::min<size_t>(kMaxSegs, v.size() - i0);
+      uint32_t t = 0;
+      for (int sgi = 0; sgi < L.nseg; ++sgi) {
+        const Piece& pc = v[i0 + sgi];
+        SweepSeg& sg = L.seg[sgi];
+        sg.rd = pc.r->desc;
+        sg.tile0 = t;
+        sg.first = (uint32_t)pc.first;
+        sg.K = (uint32_t)pc.r->K;
+        sg.F = (uint16_t)pc.r->F;
+        sg.S = (uint8_t)pc.r->S;
+        sg.mc = (uint8_t)pc.r->mc;
+        t += (uint32_t)pc.count;
+      }
+      L.ntiles = (int)t;
+      if (k >= kNumSweepClasses + kNumSweep16Classes)
+        e = launch_sweep_wg(k - kNumSweepClasses - kNumSweep16Classes, L, c->stream);
+      else if (k >= kNumSweepClasses)
+        e = launch_sweep16(k - kNumSweepClasses, L, c->stream);
+      else
+        e = launch_sweep(k, L, c->stage_lds ? lds[k] : 0, c->stream);
+      c->stats.sweep_launches++;
+    }
   }
   if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, c->stream);
   b.done = get_event(c, false);
@@ -677,12 +655,11 @@ void finish_tiles(lti_ctx* c, Request* r) {
   }
   HostStage& hs = r->hs;
   char* b = static_cast<char*>(r->block);
-  hipError_t e = hipMemcpyAsync(hs.base + hs.offG, b + r->dOffG,
-                                sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu, hipMemcpyDeviceToHost,
-                                c->stream);
-  if (e == hipSuccess && q.info_out)
-    e = hipMemcpyAsync(hs.base + hs.offInfo, b + r->dOffInfo, sizeof(lti_point_info) * q.n_omega,
-                       hipMemcpyDeviceToHost, c->stream);
+  // G and info are back to back in the block and in staging (same aligned
+  // offsets): one D2H copy
+  const size_t gbytes = sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu;
+  const size_t bytes = q.info_out ? (hs.offInfo - hs.offG) + sizeof(lti_point_info) * q.n_omega : gbytes;
+  hipError_t e = hipMemcpyAsync(hs.base + hs.offG, b + r->dOffG, bytes, hipMemcpyDeviceToHost, c->stream);
   r->d2h_ev = get_event(c, false);
   if (e == hipSuccess) e = hipEventRecord(r->d2h_ev, c->stream);
   if (e != hipSuccess) {
@@ -731,7 +708,6 @@ bool retire(lti_ctx* c) {
       if (c->device_error) return true;
     }
     put_event(c, b.done, false);
-    c->free_slots.push_back(b.slot);
     c->inflight.pop_front();
     progressed = true;
   }
@@ -762,6 +738,42 @@ bool retire(lti_ctx* c) {
   return progressed;
 }
 
+// One scheduling pass (c->mu held, c->device current): retire finished work,
+// admit pending requests, launch tiles.  Returns whether anything changed.
+bool pump(lti_ctx* c) {
+  if (c->device_error) return false;
+  bool progressed = retire(c);
+  const size_t pending_before = c->pending.size();
+  admit(c);
+  progressed |= c->pending.size() != pending_before;
+  const size_t inflight_before = c->inflight.size();
+  while ((int)c->inflight.size() < kInflight && !c->device_error) {
+    const size_t sz = c->inflight.size();
+    launch(c);
+    if (c->inflight.size() == sz) break;
+  }
+  progressed |= c->inflight.size() != inflight_before;
+  return progressed;
+}
+
+bool busy(const lti_ctx* c) { return !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty(); }
+
+// Makes the context's device current on the calling thread for a scope and
+// restores the caller's device afterwards.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  DeviceScope(const DeviceScope&) = delete;
+  DeviceScope& operator=(const DeviceScope&) = delete;
+  ~DeviceScope() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
 void scheduler(lti_ctx* c) {
   (void)hipSetDevice(c->device);
   // short sleeps below must stay short: 1 us timer slack for this thread
@@ -773,23 +785,11 @@ void scheduler(lti_ctx* c) {
       c->cv_work.wait(lk, [&] { return c->stop; });
       break;
     }
-    bool progressed = retire(c);
-    const size_t pending_before = c->pending.size();
-    admit(c);
-    progressed |= c->pending.size() != pending_before;
-    const size_t inflight_before = c->inflight.size();
-    while ((int)c->inflight.size() < kInflight && !c->device_error) {
-      const size_t sz = c->inflight.size();
-      launch(c);
-      if (c->inflight.size() == sz) break;
-    }
-    progressed |= c->inflight.size() != inflight_before;
-    if (progressed) {
+    if (pump(c)) {
       idle_since = Clock::now();
       continue;
     }
-    const bool busy = !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty();
-    if (busy) {
+    if (busy(c)) {
       // device work outstanding: poll its events, spinning (yield) for the
       // first 200 us so that short requests complete without sleep latency
       lk.unlock();
@@ -815,6 +815,8 @@ int validate(const lti_request* q) {
   if (q->n_omega > (int64_t)UINT32_MAX) return LTI_EINVAL;
   if (std::isnan(q->rtol) || q->rtol >= 1.0) return LTI_EINVAL;
   if (q->nx > kMaxNWG || q->nu > kMaxRhs || q->ny > kMaxRhs) return LTI_EUNSUPPORTED;
+  // tile indices (at most n_omega x nu per request) are 32-bit
+  if (q->n_omega * q->nu > (int64_t)UINT32_MAX) return LTI_EUNSUPPORTED;
   return LTI_OK;
 }
 
@@ -834,7 +836,6 @@ int stage_inputs(lti_ctx* c, Request* r) {
   hs.offC = take(sizeof(double) * p * n);
   hs.offD = take(sizeof(double) * p * m);
   hs.offW = take(sizeof(double) * q.n_omega);
-  hs.offDesc = take(sizeof(ReqDesc));
   hs.offG = take(sizeof(double) * 2 * (size_t)q.n_omega * p * m);
   hs.offInfo = take(q.info_out ? sizeof(lti_point_info) * q.n_omega : 0);
   hs.bytes = off;
@@ -911,21 +912,11 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   c->t0 = Clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
   c->arena.init(static_cast<char*>(cfg->arena), cfg->arena_bytes);
-  const size_t tiles_bytes = align_up(sizeof(TileDesc) * (size_t)c->batch_tiles * kInflight);
-  const size_t jobs_bytes = align_up(sizeof(ReduceJob) * (size_t)kMaxJobs * kJobSlots);
-  c->fixed_bytes = tiles_bytes + jobs_bytes;
-  void* dt = c->arena.alloc(tiles_bytes);
-  void* dj = c->arena.alloc(jobs_bytes);
-  if (!dt || !dj) return LTI_EINVAL;  // arena too small for the descriptor rings
-  c->d_tiles = static_cast<TileDesc*>(dt);
-  c->d_jobs = static_cast<ReduceJob*>(dj);
   const size_t staging = cfg->host_staging_bytes ? cfg->host_staging_bytes : kDefaultStaging;
   void* hp = nullptr;
-  if (hipHostMalloc(&hp, tiles_bytes + jobs_bytes + staging, hipHostMallocDefault) != hipSuccess) return LTI_EDEVICE;
-  c->h_tiles = static_cast<TileDesc*>(hp);
-  c->h_jobs = reinterpret_cast<ReduceJob*>(static_cast<char*>(hp) + tiles_bytes);
-  c->staging_base = static_cast<char*>(hp) + tiles_bytes + jobs_bytes;
-  c->staging.init(c->staging_base, staging);
+  if (hipHostMalloc(&hp, staging, hipHostMallocDefault) != hipSuccess) return LTI_EDEVICE;
+  c->staging_block = static_cast<char*>(hp);
+  c->staging.init(c->staging_block, staging);
   if (cfg->stream) {
     c->stream = static_cast<hipStream_t>(cfg->stream);
   } else {
@@ -935,7 +926,6 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
     }
     c->own_stream = true;
   }
-  for (int s = 0; s < kInflight; ++s) c->free_slots.push_back(s);
   try {
     c->thread = std::thread(scheduler, c.get());
   } catch (...) {
@@ -965,26 +955,13 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->device_error) return LTI_EDEVICE;
     const Need nd = request_need(r->req, true);
-    if (!c->arena.can_ever_fit(nd.block() + nd.model + c->fixed_bytes)) return LTI_ENOSPC;
+    if (!c->arena.can_ever_fit(nd.block() + nd.model)) return LTI_ENOSPC;
     if ((int)c->all.size() >= c->max_pending) return LTI_EAGAIN;
   }
   if (q->mem == LTI_MEM_HOST) {
     const int s = stage_inputs(c, r.get());
     if (s != LTI_OK) return s;
   } else {
-    // only the descriptor needs staging
-    HostStage& hs = r->hs;
-    hs.offDesc = 0;
-    hs.bytes = align_up(sizeof(ReqDesc));
-    {
-      std::lock_guard<std::mutex> lk(c->mu);
-      hs.base = static_cast<char*>(c->staging.alloc(hs.bytes));
-    }
-    hs.pinned = hs.base != nullptr;
-    if (!hs.pinned) {
-      hs.fallback.resize(hs.bytes);
-      hs.base = hs.fallback.data();
-    }
     r->hash = 0;  // device inputs: the key and dimensions identify the model
   }
   std::lock_guard<std::mutex> lk(c->mu);
@@ -1003,6 +980,11 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
   c->pending.push_back(raw);
   c->stats.requests_submitted++;
   *out_id = raw->id;
+  {
+    // start it from this thread when it can start now
+    DeviceScope ds(c->device);
+    pump(c);
+  }
   c->cv_work.notify_one();
   return LTI_OK;
 }
@@ -1015,10 +997,29 @@ int lti_freqresp_poll(lti_ctx* c, uint64_t id, int32_t timeout_us, lti_result* o
   Request* r = it->second.get();
   auto finished = [&] { return r->state == RState::kDone || r->state == RState::kFailed; };
   if (!finished() && timeout_us != 0) {
-    if (timeout_us < 0)
-      c->cv_done.wait(lk, finished);
-    else
-      c->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), finished);
+    // drive the scheduling passes from this thread for a while (a short
+    // request completes without a thread hand-off), then sleep on the
+    // completion signal
+    const Clock::time_point t_start = Clock::now();
+    const auto limit = std::chrono::microseconds(
+        timeout_us < 0 ? kPollSpinUs : std::min<int64_t>(timeout_us, kPollSpinUs));
+    {
+      DeviceScope ds(c->device);
+      while (!finished() && !c->device_error && Clock::now() - t_start < limit) {
+        if (pump(c)) continue;
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+      }
+    }
+    if (!finished()) {
+      if (timeout_us < 0) {
+        c->cv_done.wait(lk, finished);
+      } else {
+        const auto left = std::chrono::microseconds(timeout_us) - (Clock::now() - t_start);
+        if (left > Clock::duration::zero()) c->cv_done.wait_for(lk, left, finished);
+      }
+    }
   }
   if (!finished()) return LTI_PENDING;
   const int status = r->state == RState::kDone ? LTI_OK : r->status;
@@ -1051,10 +1052,9 @@ int lti_freqresp_destroy(lti_ctx* c) {
   }
   for (auto& kv : c->all)
     if (kv.second->d2h_ev) put_event(c, kv.second->d2h_ev, false);
-  for (int s = 0; s < kJobSlots; ++s) put_event(c, c->job_ev[s], false);
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->timing_pool) (void)hipEventDestroy(e);
-  if (c->h_tiles) (void)hipHostFree(c->h_tiles);
+  if (c->staging_block) (void)hipHostFree(c->staging_block);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return LTI_OK;

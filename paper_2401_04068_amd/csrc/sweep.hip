@@ -400,9 +400,9 @@ __device__ __forceinline__ void write_output(const ReqDesc& rd, Src<double, kLds
         const int j = jb + idx % MC;
         if (a < p && j < mc) {
           double2 g;
-          g.x = vr[0] + rd.D[a * m + j0 + j];
+          g.x = vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
           g.y = vi[0];
-          reinterpret_cast<double2*>(G)[a * m + j0 + j] = g;
+          store_c(G, a * m + j0 + j, g);
         }
       }
     }
@@ -414,7 +414,7 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
                            double* bcast) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m;
-  const double w = rd.omega[k];
+  const double w = ((gptr<double>)rd.omega)[k];
   const Src<double, kLds> Bt = md.Bt;
   Sweep<double, R, MM> st;
 #pragma unroll
@@ -437,7 +437,7 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
     inf.iters = 1;
     inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
     inf.reserved = 0;
-    rd.info[k] = inf;
+    store_info(rd.info, k, inf);
   }
 }
 
@@ -497,7 +497,7 @@ __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64
                               double* bcast64) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m;
-  const double w = rd.omega[k];
+  const double w = ((gptr<double>)rd.omega)[k];
   const float wf = (float)w;
   const double tol = 0.1 * ((rd.rtol > 0.0) ? rd.rtol : 1e-10);
   constexpr int kMaxIters = 6;
@@ -624,12 +624,12 @@ __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64
     inf.iters = (uint8_t)iters;
     inf.path = (uint8_t)path;
     inf.reserved = 0;
-    rd.info[k] = inf;
+    store_info(rd.info, k, inf);
   }
 }
 
 template <int PREC, int R, int MM, bool kLds>
-__device__ __forceinline__ void run_tile(const TileDesc& td, const ReqDesc& rd, const ModelSrc<kLds>& md,
+__device__ __forceinline__ void run_tile(const Tile& td, const ReqDesc& rd, const ModelSrc<kLds>& md,
                                          double* bcast) {
   for (uint32_t f = 0; f < td.count; ++f) {
     const int64_t k = (int64_t)td.start + f;
@@ -641,57 +641,52 @@ __device__ __forceinline__ void run_tile(const TileDesc& td, const ReqDesc& rd, 
 }
 
 template <int PREC, int R, int MM>
-__global__ __launch_bounds__(64 * kWaves) void sweep_kernel(const TileDesc* __restrict__ tiles, int ntiles,
-                                                            uint32_t lds_bytes) {
+__global__ __launch_bounds__(64 * kWaves) void sweep_kernel(const SweepLaunch L, uint32_t lds_bytes) {
   extern __shared__ __align__(16) char stage[];
   __shared__ double bcast_all[kWaves][2 * MM];
-  __shared__ const ReqDesc* block_rd[kWaves];
-  // the tile index is uniform per wavefront; say so, so that the descriptor
-  // loads become scalar loads
+  // the tile index is uniform per wavefront; say so, so that everything
+  // derived from it stays in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int tile = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves + wave;
-  if (lane == 0) block_rd[wave] = (tile < ntiles) ? tiles[tile].rd : nullptr;
-  __syncthreads();
+  const int tb = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves;  // < ntiles
+  const int tile = tb + wave;
   // stage the model in LDS when the whole workgroup works on one request
-  const ReqDesc* r0 = block_rd[0];
-  bool same = true;
-#pragma unroll
-  for (int w = 1; w < kWaves; ++w) same = same && (block_rd[w] == nullptr || block_rd[w] == r0);
-  const ReqDesc rd0 = *r0;
-  const StageLayout L = stage_layout(PREC, rd0.n, rd0.m, rd0.p);
+  const int s0 = seg_of(L, tb);
+  const bool same = seg_of(L, min(tb + kWaves, L.ntiles) - 1) == s0;
+  const ReqDesc rd0 = L.seg[s0].rd;
+  const StageLayout SL = stage_layout(PREC, rd0.n, rd0.m, rd0.p);
   // (a model with more than 128 states never fits the staging limit)
   constexpr bool kCanStage = (R <= 2);
-  const bool staged = kCanStage && same && lds_bytes > 0 && L.bytes <= lds_bytes && L.bytes <= kStageLimit;
+  const bool staged = kCanStage && same && lds_bytes > 0 && SL.bytes <= lds_bytes && SL.bytes <= kStageLimit;
   if (kCanStage && staged) {
     const int nh = (int)hlen(rd0.n);
     const int nb = rd0.n * rd0.m, nc = rd0.n * rd0.p;
-    double* sH = reinterpret_cast<double*>(stage + L.H);
-    double* sB = reinterpret_cast<double*>(stage + L.Bt);
-    double* sC = reinterpret_cast<double*>(stage + L.Ct);
+    double* sH = reinterpret_cast<double*>(stage + SL.H);
+    double* sB = reinterpret_cast<double*>(stage + SL.Bt);
+    double* sC = reinterpret_cast<double*>(stage + SL.Ct);
     for (int i = threadIdx.x; i < nh; i += 64 * kWaves) sH[i] = rd0.H[i];
     for (int i = threadIdx.x; i < nb; i += 64 * kWaves) sB[i] = rd0.Bt[i];
     for (int i = threadIdx.x; i < nc; i += 64 * kWaves) sC[i] = rd0.Ct[i];
     if (PREC == LTI_PREC_REFINED) {
-      float* sH32 = reinterpret_cast<float*>(stage + L.H32);
-      float* sB32 = reinterpret_cast<float*>(stage + L.Bt32);
+      float* sH32 = reinterpret_cast<float*>(stage + SL.H32);
+      float* sB32 = reinterpret_cast<float*>(stage + SL.Bt32);
       for (int i = threadIdx.x; i < nh; i += 64 * kWaves) sH32[i] = rd0.H32[i];
       for (int i = threadIdx.x; i < nb; i += 64 * kWaves) sB32[i] = rd0.Bt32[i];
     }
     __syncthreads();
   }
-  if (tile >= ntiles) return;
-  const TileDesc td = tiles[tile];
-  const ReqDesc rd = *td.rd;
+  if (tile >= L.ntiles) return;
+  const int s = seg_of(L, tile);
+  const ReqDesc rd = L.seg[s].rd;
+  const Tile td = tile_of(L.seg[s], tile);
   double* bcast = bcast_all[wave];
   if constexpr (kCanStage) {
     if (staged) {
       ModelSrc<true> md;
-      md.H.p = reinterpret_cast<const double*>(stage + L.H);
-      md.Bt.p = reinterpret_cast<const double*>(stage + L.Bt);
-      md.Ct.p = reinterpret_cast<const double*>(stage + L.Ct);
-      md.H32.p = reinterpret_cast<const float*>(stage + L.H32);
-      md.Bt32.p = reinterpret_cast<const float*>(stage + L.Bt32);
+      md.H.p = reinterpret_cast<const double*>(stage + SL.H);
+      md.Bt.p = reinterpret_cast<const double*>(stage + SL.Bt);
+      md.Ct.p = reinterpret_cast<const double*>(stage + SL.Ct);
+      md.H32.p = reinterpret_cast<const float*>(stage + SL.H32);
+      md.Bt32.p = reinterpret_cast<const float*>(stage + SL.Bt32);
       run_tile<PREC, R, MM, true>(td, rd, md, bcast);
       return;
     }
@@ -707,7 +702,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(const TileDesc* __re
   }
 }
 
-using KernelFn = void (*)(const TileDesc*, int, uint32_t);
+using KernelFn = void (*)(const SweepLaunch, uint32_t);
 
 template <int PREC, int R>
 constexpr KernelFn pick_mm(int mi) {
@@ -743,16 +738,16 @@ int sweep_class(int precision, int n, int m) {
   return (precision * kNumRowClasses + ri) * kNumRhsClasses + mi;
 }
 
-hipError_t launch_sweep(int kclass, const TileDesc* tiles, int ntiles, size_t lds_bytes, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s) {
+  if (L.ntiles <= 0) return hipSuccess;
   if (kclass < 0 || kclass >= kNumSweepClasses) return hipErrorInvalidValue;
   const int mi = kclass % kNumRhsClasses;
   const int ri = (kclass / kNumRhsClasses) % kNumRowClasses;
   const int prec = kclass / (kNumRhsClasses * kNumRowClasses);
   const KernelFn fn = prec == LTI_PREC_FP64 ? pick<LTI_PREC_FP64>(ri, mi) : pick<LTI_PREC_REFINED>(ri, mi);
-  const int blocks = (ntiles + kWaves - 1) / kWaves;
+  const int blocks = (L.ntiles + kWaves - 1) / kWaves;
   if (lds_bytes > kStageLimit) lds_bytes = 0;
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves), lds_bytes, s, tiles, ntiles, (uint32_t)lds_bytes);
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves), lds_bytes, s, L, (uint32_t)lds_bytes);
   return hipGetLastError();
 }
 

@@ -397,9 +397,9 @@ __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc
         const int j = jb + idx % MC;
         if (a < p && j < mc) {
           double2 gv;
-          gv.x = vr[0] + rd.D[a * m + j0 + j];
+          gv.x = vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
           gv.y = vi[0];
-          reinterpret_cast<double2*>(G)[a * m + j0 + j] = gv;
+          store_c(G, a * m + j0 + j, gv);
         }
       }
     }
@@ -410,7 +410,7 @@ template <int R, int MM>
 __device__ void solve16_fp64(const ReqDesc& rd, int64_t k, bool valid, int j0, int mc, double* bcast) {
   const int gl = threadIdx.x & 15;
   const int n = rd.n, m = rd.m;
-  const double w = rd.omega[k];
+  const double w = ((gptr<double>)rd.omega)[k];
   const gptr<double> Bt = (gptr<double>)rd.Bt;
   S16<double, R, MM> st;
 #pragma unroll
@@ -433,7 +433,7 @@ __device__ void solve16_fp64(const ReqDesc& rd, int64_t k, bool valid, int j0, i
     inf.iters = 1;
     inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
     inf.reserved = 0;
-    rd.info[k] = inf;
+    store_info(rd.info, k, inf);
   }
 }
 
@@ -505,7 +505,7 @@ template <int R, int MM>
 __device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0, int mc, double* bcast64) {
   const int gl = threadIdx.x & 15;
   const int n = rd.n, m = rd.m;
-  const double w = rd.omega[k];
+  const double w = ((gptr<double>)rd.omega)[k];
   const float wf = (float)w;
   const double tol = 0.1 * ((rd.rtol > 0.0) ? rd.rtol : 1e-10);
   constexpr int kMaxIters = 6;
@@ -632,18 +632,19 @@ __device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0
     inf.iters = (uint8_t)iters;
     inf.path = (uint8_t)path;
     inf.reserved = 0;
-    rd.info[k] = inf;
+    store_info(rd.info, k, inf);
   }
 }
 
 template <int PREC, int R, int MM>
-__global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const TileDesc* __restrict__ tiles, int ntiles) {
+__global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const SweepLaunch L) {
   __shared__ double bcast_all[kWaves16][4 * (2 + 2 * MM)];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves16 + wave;
-  if (tile >= ntiles) return;
-  const TileDesc td = tiles[tile];
-  const ReqDesc rd = *td.rd;
+  if (tile >= L.ntiles) return;
+  const int s = seg_of(L, tile);
+  const ReqDesc rd = L.seg[s].rd;
+  const Tile td = tile_of(L.seg[s], tile);
   const int g = (threadIdx.x & 63) >> 4;
   double* bcast = bcast_all[wave];
   for (uint32_t f0 = 0; f0 < td.count; f0 += 4) {
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const TileDesc* 
   }
 }
 
-using Kernel16Fn = void (*)(const TileDesc*, int);
+using Kernel16Fn = void (*)(const SweepLaunch);
 
 template <int PREC, int R>
 Kernel16Fn pick16_mm(int mi) {
@@ -681,13 +682,13 @@ int sweep16_class(int precision, int n, int mc) {
   return (precision * 3 + ri) * 3 + mi;
 }
 
-hipError_t launch_sweep16(int cls, const TileDesc* tiles, int ntiles, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_sweep16(int cls, const SweepLaunch& L, hipStream_t s) {
+  if (L.ntiles <= 0) return hipSuccess;
   if (cls < 0 || cls >= kNumSweep16Classes) return hipErrorInvalidValue;
   const int prec = cls / 9, ri = (cls / 3) % 3, mi = cls % 3;
   const Kernel16Fn fn = prec == LTI_PREC_FP64 ? pick16<LTI_PREC_FP64>(ri, mi) : pick16<LTI_PREC_REFINED>(ri, mi);
-  const int blocks = (ntiles + kWaves16 - 1) / kWaves16;
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves16), 0, s, tiles, ntiles);
+  const int blocks = (L.ntiles + kWaves16 - 1) / kWaves16;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves16), 0, s, L);
   return hipGetLastError();
 }
 

@@ -17,6 +17,47 @@ template <typename T>
 using cptr = const T __attribute__((address_space(4)))*;  // constant (scalar loads)
 template <typename T>
 using lptr = const T __attribute__((address_space(3)))*;  // LDS
+template <typename T>
+using gmut = T __attribute__((address_space(1)))*;  // global, written
+
+// Stores through the global address space (a generic store also counts
+// against the LDS wait counter).
+__device__ __forceinline__ void store_c(double* G, int idx, double2 v) {
+  gmut<double> g = (gmut<double>)G + 2 * idx;
+  g[0] = v.x;
+  g[1] = v.y;
+}
+__device__ __forceinline__ void store_info(lti_point_info* info, int64_t k, const lti_point_info& v) {
+  uint64_t bits;
+  __builtin_memcpy(&bits, &v, sizeof(bits));
+  ((gmut<uint64_t>)info)[k] = bits;
+}
+
+// Launch tile t (wave-uniform) of a sweep launch: its segment, and the
+// frequencies and columns it covers.
+struct Tile {
+  uint32_t start, count;
+  int j0, mc;
+};
+
+__device__ __forceinline__ int seg_of(const SweepLaunch& L, int t) {
+  int s = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxSegs; ++i)
+    if (i < L.nseg && t >= (int)L.seg[i].tile0) s = i;
+  return s;
+}
+
+__device__ __forceinline__ Tile tile_of(const SweepSeg& g, int t) {
+  const uint32_t local = g.first + (uint32_t)(t - (int)g.tile0);
+  const uint32_t fb = local / g.S, grp = local % g.S;
+  Tile x;
+  x.start = fb * g.F;
+  x.count = min((uint32_t)g.F, g.K - x.start);
+  x.j0 = (int)grp * g.mc;
+  x.mc = min((int)g.mc, g.rd.m - x.j0);
+  return x;
+}
 
 // Read-only view of one array of the reduced model, staged in LDS (kLds) or
 // read from global memory.

@@ -88,18 +88,29 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T w, SWG<T, MM>& st
     const int tk = k % kThreadsWG, rk = k / kThreadsWG;
     double* slot = sh.piv[k & 1];
     if (tid == tk) {
-      sfor<0, kRWG>([&](auto rc_) {
-        constexpr int r = decltype(rc_)::value;
-        if (r == rk) {
-          slot[0] = (double)st.cr[r];
-          slot[1] = (double)st.ci[r];
+      // select the pivot slice's values (selects, not a branch per slice:
+      // merged branches turn into pointer phis that keep st in memory)
+      T pv[2 + 2 * MM];
+      pv[0] = st.cr[0];
+      pv[1] = st.ci[0];
 #pragma unroll
-          for (int j = 0; j < MM; ++j) {
-            slot[2 + 2 * j] = (double)st.br[r][j];
-            slot[3 + 2 * j] = (double)st.bi[r][j];
-          }
+      for (int j = 0; j < MM; ++j) {
+        pv[2 + 2 * j] = st.br[0][j];
+        pv[3 + 2 * j] = st.bi[0][j];
+      }
+#pragma unroll
+      for (int r = 1; r < kRWG; ++r) {
+        const bool here = r == rk;
+        pv[0] = here ? st.cr[r] : pv[0];
+        pv[1] = here ? st.ci[r] : pv[1];
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          pv[2 + 2 * j] = here ? st.br[r][j] : pv[2 + 2 * j];
+          pv[3 + 2 * j] = here ? st.bi[r][j] : pv[3 + 2 * j];
         }
-      });
+      }
+#pragma unroll
+      for (int q = 0; q < 2 + 2 * MM; ++q) slot[q] = (double)pv[q];
     }
     T hn[kRWG];
 #pragma unroll
@@ -158,16 +169,13 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T w, SWG<T, MM>& st
         }
       }
     }
-    if (tid == tk) {
-      sfor<0, kRWG>([&](auto rc_) {
-        constexpr int r = decltype(rc_)::value;
-        if (r == rk) {
-          st.rc[r] = c;
-          st.rsr[r] = sr;
-          st.rsi[r] = si;
-          st.rinv[r] = rinv;
-        }
-      });
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      const bool here = tid == tk && r == rk;
+      st.rc[r] = here ? c : st.rc[r];
+      st.rsr[r] = here ? sr : st.rsr[r];
+      st.rsi[r] = here ? si : st.rsi[r];
+      st.rinv[r] = here ? rinv : st.rinv[r];
     }
 #pragma unroll
     for (int r = 0; r < kRWG; ++r) hc[r] = hn[r];
@@ -207,8 +215,8 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T w, SWG<T, MM>& st
 
 // Local scan of one slice's 64-row segment: on return `a` is the product of
 // the segment's multipliers up to this row and u[j] the partial sum.
-template <typename T, int MM>
-__device__ __forceinline__ void segment_scan(int n, int r, const SWG<T, MM>& st, T& a, T (&u_r)[MM], T (&u_i)[MM]) {
+template <int r, typename T, int MM>
+__device__ __forceinline__ void segment_scan(int n, const SWG<T, MM>& st, T& a, T (&u_r)[MM], T (&u_i)[MM]) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int i = tid + kThreadsWG * r;
   const bool inner = (i > 0 && i < n);
@@ -255,11 +263,11 @@ template <typename T, int MM>
 __device__ __forceinline__ void apply_rotations_wg(int n, SWG<T, MM>& st, ShWG& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NS = 4 * kRWG;
-#pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
+  sfor<0, kRWG>([&](auto rc_) {
+    constexpr int r = decltype(rc_)::value;
     const int sg = 4 * r + wv;
     T a, ur[MM], ui[MM];
-    segment_scan<T, MM>(n, r, st, a, ur, ui);
+    segment_scan<r>(n, st, a, ur, ui);
     if (lane == 63) {
       sh.segA[sg] = (double)a;
 #pragma unroll
@@ -278,7 +286,7 @@ __device__ __forceinline__ void apply_rotations_wg(int n, SWG<T, MM>& st, ShWG& 
         sh.first[sg][4 + 2 * j] = (double)st.bi[r][j];
       }
     }
-  }
+  });
   __syncthreads();
   if (tid < MM) {  // link the segments: t_in(sg + 1) = A(sg) t_in(sg) + U(sg)
     double tr = 0.0, ti = 0.0;
@@ -293,12 +301,12 @@ __device__ __forceinline__ void apply_rotations_wg(int n, SWG<T, MM>& st, ShWG& 
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
+  sfor<0, kRWG>([&](auto rc_) {
+    constexpr int r = decltype(rc_)::value;
     const int i = tid + kThreadsWG * r;
     const int sg = 4 * r + wv;
     T a, ur[MM], ui[MM];
-    segment_scan<T, MM>(n, r, st, a, ur, ui);
+    segment_scan<r>(n, st, a, ur, ui);
     T nc = __shfl_down(st.rc[r], 1, 64);
     T nsr = __shfl_down(st.rsr[r], 1, 64);
     T nsi = __shfl_down(st.rsi[r], 1, 64);
@@ -329,7 +337,7 @@ __device__ __forceinline__ void apply_rotations_wg(int n, SWG<T, MM>& st, ShWG& 
         st.bi[r][j] = ti;
       }
     }
-  }
+  });
   __syncthreads();
 }
 
@@ -381,9 +389,9 @@ __device__ __forceinline__ void write_output_wg(const ReqDesc& rd, int j0, int m
         gi += sh.red[q][j][1];
       }
       double2 g;
-      g.x = gr + rd.D[a * m + j0 + j];
+      g.x = gr + ((gptr<double>)rd.D)[a * m + j0 + j];
       g.y = gi;
-      reinterpret_cast<double2*>(G)[a * m + j0 + j] = g;
+      store_c(G, a * m + j0 + j, g);
     }
     __syncthreads();
   }
@@ -393,7 +401,7 @@ template <int MM>
 __device__ void solve_wg_fp64(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG& sh) {
   const int tid = threadIdx.x;
   const int n = rd.n, m = rd.m;
-  const double w = rd.omega[k];
+  const double w = ((gptr<double>)rd.omega)[k];
   const gptr<double> Bt = (gptr<double>)rd.Bt;
   SWG<double, MM> st;
 #pragma unroll
@@ -415,17 +423,18 @@ __device__ void solve_wg_fp64(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG
     inf.iters = 1;
     inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
     inf.reserved = 0;
-    rd.info[k] = inf;
+    store_info(rd.info, k, inf);
   }
 }
 
 template <int MM>
-__global__ __launch_bounds__(kThreadsWG) void sweep_wg_kernel(const TileDesc* __restrict__ tiles, int ntiles) {
+__global__ __launch_bounds__(kThreadsWG) void sweep_wg_kernel(const SweepLaunch L) {
   __shared__ ShWG sh;
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
-  if (tile >= ntiles) return;
-  const TileDesc td = tiles[tile];
-  const ReqDesc rd = *td.rd;
+  if (tile >= L.ntiles) return;
+  const int s = seg_of(L, tile);
+  const ReqDesc rd = L.seg[s].rd;
+  const Tile td = tile_of(L.seg[s], tile);
   for (uint32_t f = 0; f < td.count; ++f) solve_wg_fp64<MM>(rd, (int64_t)td.start + f, td.j0, td.mc, sh);
 }
 
@@ -437,12 +446,12 @@ int sweep_wg_class(int precision, int n, int mc) {
   return (mc <= 1) ? 0 : (mc <= 2) ? 1 : 2;
 }
 
-hipError_t launch_sweep_wg(int cls, const TileDesc* tiles, int ntiles, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  using Fn = void (*)(const TileDesc*, int);
-  const Fn fn = cls == 0 ? sweep_wg_kernel<1> : cls == 1 ? sweep_wg_kernel<2> : sweep_wg_kernel<4>;
+hipError_t launch_sweep_wg(int cls, const SweepLaunch& L, hipStream_t s) {
+  if (L.ntiles <= 0) return hipSuccess;
   if (cls < 0 || cls > 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(ntiles), dim3(kThreadsWG), 0, s, tiles, ntiles);
+  using Fn = void (*)(const SweepLaunch);
+  const Fn fn = cls == 0 ? sweep_wg_kernel<1> : cls == 1 ? sweep_wg_kernel<2> : sweep_wg_kernel<4>;
+  hipLaunchKernelGGL(fn, dim3(L.ntiles), dim3(kThreadsWG), 0, s, L);
   return hipGetLastError();
 }
 
