@@ -5,7 +5,9 @@
 A step is one pass of the whole path over one synthetic model: submit the
 model with its frequency grid already resident in HBM (a device-memory
 request), let the library reduce A to Hessenberg form, run every per-frequency
-solve, and poll the result.  The default workload is the 64-state, 4-input,
+solve, and poll the result.  The throughput run keeps up to --window requests
+in flight (each is still a full step with its own reduction); the latency
+percentiles come from a second run with one request at a time.  The default workload is the 64-state, 4-input,
 4-output model on 2000 log-spaced frequencies evaluated on the plain float64
 path; the same workload is also timed on the refined float32 path and
 reported beside it.
@@ -145,39 +147,56 @@ def _make_model(workload: str):
     raise SystemExit(f"unknown workload {workload}")
 
 
-def run_gpu(mdl, precision: int, steps: int, warmup: int):
+def run_gpu(mdl, precision: int, steps: int, warmup: int, window: int):
+    """Time `steps` device-memory requests of one model (each its own
+    reduction and all its solves).  Throughput run: up to `window` requests
+    in flight (each has its own output buffers; a new one is submitted as the
+    oldest completes).  Latency run: the same number of requests one at a
+    time, submit -> results visible."""
     import torch
 
     from paper_2401_04068_amd import binding
 
     dev = torch.device("cuda:0")
     t = {k: torch.from_numpy(np.ascontiguousarray(getattr(mdl, k))).to(dev) for k in ("A", "B", "C", "D", "omega")}
-    G = torch.empty((mdl.K, mdl.p, mdl.m, 2), dtype=torch.float64, device=dev)
-    info = torch.empty((mdl.K * 8,), dtype=torch.uint8, device=dev)
+    W = max(1, window)
+    Gs = [torch.empty((mdl.K, mdl.p, mdl.m, 2), dtype=torch.float64, device=dev) for _ in range(W)]
+    infos = [torch.empty((mdl.K * 8,), dtype=torch.uint8, device=dev) for _ in range(W)]
     eng = binding.Engine(arena_bytes=1 << 30, kernel_timing=True)
     try:
-        def step():
-            h = eng.submit_device(t["A"], t["B"], t["C"], t["D"], t["omega"], G, info, precision=precision)
-            eng.wait(h)
-            return h
+        def submit(slot):
+            return eng.submit_device(t["A"], t["B"], t["C"], t["D"], t["omega"], Gs[slot], infos[slot],
+                                     precision=precision)
 
-        for _ in range(warmup):
-            step()
+        def pipelined(n):
+            inflight = []
+            for i in range(n):
+                if len(inflight) == W:
+                    eng.wait(inflight.pop(0))
+                inflight.append(submit(i % W))
+            for h in inflight:
+                eng.wait(h)
+
+        pipelined(warmup)
         torch.cuda.synchronize()
         s0 = eng.stats()
-        lat = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            a = time.perf_counter()
-            step()
-            lat.append(time.perf_counter() - a)
+        pipelined(steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         s1 = eng.stats()
-        Gh = G.cpu().numpy()
+        lat = []
+        for _ in range(steps):
+            a = time.perf_counter()
+            eng.wait(submit(0))
+            lat.append(time.perf_counter() - a)
+        torch.cuda.synchronize()
+        Gh = Gs[0].cpu().numpy()
         Gh = Gh[..., 0] + 1j * Gh[..., 1]
-        infoh = info.cpu().numpy().view(binding.POINT_INFO_DTYPE)
+        infoh = infos[0].cpu().numpy().view(binding.POINT_INFO_DTYPE)
+        # every buffer of the throughput run holds the same (deterministic) result
+        same = all(torch.equal(Gs[0], g) for g in Gs[1:min(W, steps)])
     finally:
         eng.close()
     launches = s1["timed_sweep_launches"] - s0["timed_sweep_launches"]
@@ -190,6 +209,8 @@ def run_gpu(mdl, precision: int, steps: int, warmup: int):
         "sweep_ms_per_launch": sweep_ms,
         "sweep_launches_per_step": launches / steps,
         "reduce_ms_per_launch": reduce_ms,
+        "reductions_per_step": (s1["reductions"] - s0["reductions"]) / steps,
+        "outputs_identical": bool(same),
         "G": Gh,
         "info": infoh,
     }
@@ -274,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="mimo64", choices=["mimo64", "siso8", "damped256", "serving"])
     ap.add_argument("--requests", type=int, default=4096, help="serving replay: number of requests")
+    ap.add_argument("--window", type=int, default=8,
+                    help="requests in flight in the throughput run (each step is still one full request)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--paths", default="both", choices=["both", "fp64", "refined"],
                     help="which precision paths to time (profiling runs)")
@@ -315,9 +338,9 @@ def main():
 
     fp64 = ref = None
     if args.paths in ("both", "fp64"):
-        fp64 = run_gpu(mdl, binding.PREC_FP64, args.steps, args.warmup)
+        fp64 = run_gpu(mdl, binding.PREC_FP64, args.steps, args.warmup, args.window)
     if args.paths in ("both", "refined"):
-        ref = run_gpu(mdl, binding.PREC_REFINED, args.steps, args.warmup)
+        ref = run_gpu(mdl, binding.PREC_REFINED, args.steps, args.warmup, args.window)
     if fp64 is None or ref is None:
         done = fp64 or ref
         print(json.dumps({"profiling_run": args.paths, "ms_per_step": 1e3 * done["seconds"] / args.steps,
@@ -333,6 +356,8 @@ def main():
 
     pts64 = K * args.steps / fp64["seconds"]
     pts32 = K * args.steps / ref["seconds"]
+    if fp64["reductions_per_step"] != 1.0 or not fp64["outputs_identical"]:
+        raise RuntimeError("every step must reduce its model once and produce the same result")
     value = pts64 * ok64
     flops_launch = sweep_flops_per_point(n, m, p) * K / max(fp64["sweep_launches_per_step"], 1)
     achieved = flops_launch / (fp64["sweep_ms_per_launch"] * 1e-3) / 1e12
@@ -354,10 +379,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: n={n}, m={m}, p={p}, K={K} log-spaced frequencies, "
-                        "one model per step, inputs resident in HBM, float64 path",
-            "n": n, "m": m, "p": p, "points_per_step": K,
+                        f"one model per step (its own reduction), up to {args.window} requests in flight, "
+                        "inputs resident in HBM, float64 path",
+            "n": n, "m": m, "p": p, "points_per_step": K, "requests_in_flight": args.window,
+            "reductions_per_step": fp64["reductions_per_step"],
         },
-        "latency_ms": {
+        "latency_ms": {  # one request alone: submit -> results visible
             "p50": float(np.percentile(fp64["lat"], 50) * 1e3),
             "p99": float(np.percentile(fp64["lat"], 99) * 1e3),
         },

@@ -2,14 +2,20 @@
 // models, admission by memory budget, and continuous batching of the
 // per-frequency solves of every live request into shared kernel launches.
 //
-// All device work is issued in order on one stream by a scheduling pass
+// Device work is issued on two streams by a scheduling pass
 // (pump) that runs under the context lock: on the context's scheduler thread,
 // and inline on the caller's thread in submit() and in a waiting poll(), so a
 // lone request starts and completes without a thread hand-off.  A pass:
 //
 //   admit    pending requests in arrival order while their memory fits:
 //            upload inputs, reuse a resident reduced model or queue a
-//            reduction job (all reduction jobs of one pass share one launch);
+//            reduction job (the jobs of one pass share a launch per kernel
+//            class).  Uploads and reductions go to one of kAdmitStreams
+//            admission streams (round robin over passes); the sweep stream
+//            then waits on an event recorded after them, so the reductions of
+//            newly admitted requests run beside the sweeps already queued and
+//            beside the reductions of the previous passes (one reduction
+//            occupies a single CU);
 //   launch   gather up to max_batch_tiles tiles from the live requests
 //            (oldest first), group them by kernel class and launch; at most
 //            kInflight batches are outstanding, so requests that arrive
@@ -47,7 +53,8 @@ namespace lti {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kInflight = 3;
+constexpr int kInflight = 8;
+constexpr int kAdmitStreams = 4;
 // Reduction jobs queued by one admission pass (bounds one pass's work).
 constexpr int kMaxJobs = 1024;
 constexpr int kDefaultMaxPending = 8192;
@@ -201,7 +208,11 @@ using namespace lti;
 
 struct lti_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // sweeps and result copies
+  hipStream_t rstreams[kAdmitStreams] = {};  // uploads and reductions
+  hipEvent_t admit_ev[kAdmitStreams] = {};   // end of the last pass on each
+  int next_rstream = 0;
+  hipStream_t rstream = nullptr;             // the current pass's stream
   bool own_stream = false;
   uint32_t flags = 0;
   int max_pending = kDefaultMaxPending;
@@ -359,6 +370,7 @@ void release_request_memory(lti_ctx* c, Request* r) {
 // Try to admit one request.  Returns false when it has to wait for memory.
 struct JobLists {
   std::vector<ReduceJob> jobs[kNumReduceClasses];
+  bool copies = false;  // uploads were issued on the admission stream
   size_t total() const {
     size_t t = 0;
     for (const auto& v : jobs) t += v.size();
@@ -425,7 +437,8 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
     // in staging; the block mirrors that layout, so one H2D copy moves them
     const size_t src0 = needs_model ? hs.offA : hs.offW;
     const size_t bytes = hs.offW - src0 + sizeof(double) * q.n_omega;
-    e = hipMemcpyAsync(b, hs.base + src0, bytes, hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpyAsync(b, hs.base + src0, bytes, hipMemcpyHostToDevice, c->rstream);
+    jl.copies = true;
     if (needs_model) {
       job.A = reinterpret_cast<const double*>(b);
       job.B = reinterpret_cast<const double*>(b + (hs.offB - hs.offA));
@@ -515,20 +528,23 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
 
 void admit(lti_ctx* c) {
   JobLists jl;
+  const int rs = c->next_rstream;
+  c->rstream = c->rstreams[rs];
   while (!c->pending.empty() && !c->device_error) {
     Request* r = c->pending.front();
     if (!admit_one(c, r, jl)) break;
     c->pending.pop_front();
     if (r->state == RState::kLive) c->live.push_back(r);
   }
-  if (c->device_error || jl.total() == 0) return;
-  const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
+  if (c->device_error || (jl.total() == 0 && !jl.copies)) return;
+  c->next_rstream = (rs + 1) % kAdmitStreams;
+  const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0 && jl.total() > 0;
   TimedPair tp{nullptr, nullptr};
   hipError_t e = hipSuccess;
   if (timed) {
     tp.a = get_event(c, true);
     tp.b = get_event(c, true);
-    e = hipEventRecord(tp.a, c->stream);
+    e = hipEventRecord(tp.a, c->rstream);
   }
   // the jobs travel in the kernel arguments, kMaxInlineJobs per launch
   ReduceLaunch L;
@@ -537,13 +553,16 @@ void admit(lti_ctx* c) {
     for (size_t i0 = 0; i0 < v.size() && e == hipSuccess; i0 += kMaxInlineJobs) {
       L.njobs = (int)std::min<size_t>(kMaxInlineJobs, v.size() - i0);
       std::copy(v.begin() + i0, v.begin() + i0 + L.njobs, L.job);
-      e = launch_reduce(L, rc, c->stream);
+      e = launch_reduce(L, rc, c->rstream);
     }
   }
   if (timed && e == hipSuccess) {
-    e = hipEventRecord(tp.b, c->stream);
+    e = hipEventRecord(tp.b, c->rstream);
     c->reduce_timing.push_back(tp);
   }
+  // sweeps queued from now on see this pass's uploads and reductions
+  if (e == hipSuccess) e = hipEventRecord(c->admit_ev[rs], c->rstream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->admit_ev[rs], 0);
   if (e != hipSuccess) fail_all(c, LTI_EDEVICE);
 }
 
@@ -756,6 +775,15 @@ bool pump(lti_ctx* c) {
   return progressed;
 }
 
+void destroy_admit_streams(lti_ctx* c) {
+  for (int i = 0; i < kAdmitStreams; ++i) {
+    if (c->admit_ev[i]) (void)hipEventDestroy(c->admit_ev[i]);
+    if (c->rstreams[i]) (void)hipStreamDestroy(c->rstreams[i]);
+    c->admit_ev[i] = nullptr;
+    c->rstreams[i] = nullptr;
+  }
+}
+
 bool busy(const lti_ctx* c) { return !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty(); }
 
 // Makes the context's device current on the calling thread for a scope and
@@ -926,10 +954,21 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
     }
     c->own_stream = true;
   }
+  bool ok = true;
+  for (int i = 0; i < kAdmitStreams && ok; ++i)
+    ok = hipStreamCreateWithFlags(&c->rstreams[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&c->admit_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    destroy_admit_streams(c.get());
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    (void)hipHostFree(hp);
+    return LTI_EDEVICE;
+  }
   try {
     c->thread = std::thread(scheduler, c.get());
   } catch (...) {
     (void)hipHostFree(hp);
+    destroy_admit_streams(c.get());
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     return LTI_ENOMEM;
   }
@@ -1040,6 +1079,8 @@ int lti_freqresp_destroy(lti_ctx* c) {
   c->cv_done.notify_all();
   if (c->thread.joinable()) c->thread.join();
   (void)hipSetDevice(c->device);
+  for (hipStream_t rs : c->rstreams)
+    if (rs) (void)hipStreamSynchronize(rs);
   (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->inflight) {
     put_event(c, b.done, false);
@@ -1055,6 +1096,7 @@ int lti_freqresp_destroy(lti_ctx* c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->timing_pool) (void)hipEventDestroy(e);
   if (c->staging_block) (void)hipHostFree(c->staging_block);
+  destroy_admit_streams(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return LTI_OK;
@@ -1077,6 +1119,8 @@ int lti_freqresp_get_reduced(lti_ctx* c, uint64_t key, int32_t nx, int32_t nu, i
   const int n = nx, m = nu, p = ny;
   std::vector<double> hp((size_t)hlen(n)), bt((size_t)n * m), ct((size_t)n * p);
   hipError_t e = hipSetDevice(c->device);
+  for (hipStream_t rs : c->rstreams)
+    if (e == hipSuccess) e = hipStreamSynchronize(rs);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = hipMemcpy(hp.data(), rm.H, hp.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(bt.data(), rm.Bt, bt.size() * 8, hipMemcpyDeviceToHost);
