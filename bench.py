@@ -67,15 +67,17 @@ def _source_digest(files: list[str]) -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic_record(workload: str, files: list[str]):
+def _traffic_record(workload: str, files: list[str], window: int):
     """HBM bytes per sweep launch from committed rocprofv3 counter runs, used
-    only while the kernel sources are the ones the counters were taken on."""
+    only while the kernel sources and the number of requests in flight (which
+    sets how many requests a launch carries) are the ones the counters were
+    taken with."""
     path = os.path.join(PROFILES, f"sweep_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha256_16") != _source_digest(files):
+    if rec.get("source_sha256_16") != _source_digest(files) or rec.get("window") != window:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -295,7 +297,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="mimo64", choices=["mimo64", "siso8", "damped256", "serving"])
     ap.add_argument("--requests", type=int, default=4096, help="serving replay: number of requests")
-    ap.add_argument("--window", type=int, default=8,
+    ap.add_argument("--window", type=int, default=16,
                     help="requests in flight in the throughput run (each step is still one full request)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--paths", default="both", choices=["both", "fp64", "refined"],
@@ -359,10 +361,12 @@ def main():
     if fp64["reductions_per_step"] != 1.0 or not fp64["outputs_identical"]:
         raise RuntimeError("every step must reduce its model once and produce the same result")
     value = pts64 * ok64
-    flops_launch = sweep_flops_per_point(n, m, p) * K / max(fp64["sweep_launches_per_step"], 1)
+    # a launch (one batch of the sweep stream) may carry the tiles of several
+    # requests in flight
+    flops_launch = sweep_flops_per_point(n, m, p) * K / max(fp64["sweep_launches_per_step"], 1e-9)
     achieved = flops_launch / (fp64["sweep_ms_per_launch"] * 1e-3) / 1e12
     kname, kfiles = sweep_kernel_family(n)
-    traffic = _traffic_record(args.workload, kfiles)
+    traffic = _traffic_record(args.workload, kfiles, args.window)
 
     out = {
         "metric": METRIC,

@@ -10,14 +10,18 @@
 //   admit    pending requests in arrival order while their memory fits:
 //            upload inputs, reuse a resident reduced model or queue a
 //            reduction job (the jobs of one pass share a launch per kernel
-//            class).  Uploads and reductions go to one of kAdmitStreams
-//            admission streams (round robin over passes); the sweep stream
-//            then waits on an event recorded after them, so the reductions of
-//            newly admitted requests run beside the sweeps already queued and
-//            beside the reductions of the previous passes (one reduction
+//            class).  Uploads and reductions go to an idle one of
+//            kAdmitStreams admission streams and end with an event that the
+//            requests of the pass (and the models it reduced) keep; a sweep
+//            launch first waits on the events of its requests, so reductions
+//            run beside sweeps.  While every admission stream is still busy,
+//            new requests wait, and are then admitted together: their
+//            reductions share launches and run side by side (one reduction
 //            occupies a single CU);
 //   launch   gather up to max_batch_tiles tiles from the live requests
-//            (oldest first), group them by kernel class and launch; at most
+//            (oldest first), group them by kernel class and launch on the
+//            next of kSweepStreams sweep streams (round robin, so the
+//            latency-bound sweeps of different batches overlap); at most
 //            kInflight batches are outstanding, so requests that arrive
 //            meanwhile join the next batch;
 //   retire   when a batch's event has fired, credit its tiles; a request
@@ -54,7 +58,13 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kInflight = 8;
-constexpr int kAdmitStreams = 4;
+// Streams: one admission stream and one sweep stream by default (a process
+// gets few hardware queues, four by default, and streams that share one run
+// in order).  With one admission stream, requests that arrive during a
+// reduction are admitted together afterwards, so their reductions and their
+// sweeps share launches; more streams (a tuning knob) measured slower.
+constexpr int kAdmitStreams = 2;
+constexpr int kSweepStreams = 2;
 // Reduction jobs queued by one admission pass (bounds one pass's work).
 constexpr int kMaxJobs = 1024;
 constexpr int kDefaultMaxPending = 8192;
@@ -128,7 +138,15 @@ class Arena {
   size_t used_ = 0, peak_ = 0;
 };
 
+// The end of one admission pass on its stream (uploads and reductions),
+// shared by the requests admitted in it and by the models it reduced.
+struct PassEvent {
+  hipEvent_t ev = nullptr;
+  int refs = 0;
+};
+
 struct Resident {
+  PassEvent* ready = nullptr;  // pass that reduced it, until a user completed
   uint64_t key = 0;
   uint64_t hash = 0;
   int n = 0, m = 0, p = 0;
@@ -160,6 +178,8 @@ struct Request {
   HostStage hs;
   Resident* model = nullptr;
   bool reused = false;
+  PassEvent* ready = nullptr;        // its own admission pass
+  PassEvent* model_ready = nullptr;  // the pass that reduced a reused model
   void* block = nullptr;  // device: A..D, omega, G, info, reduction scratch
   size_t block_bytes = 0;
   size_t dOffG = 0;
@@ -171,11 +191,13 @@ struct Request {
   int mc = 1;       // columns per group
   size_t stage = 0; // LDS bytes a sweep workgroup needs to stage the model
   int64_t ntiles = 0, next_tile = 0, tiles_done = 0;
+  int waves_per_tile = 1;
   hipEvent_t d2h_ev = nullptr;
   lti_result res{};
 };
 
 struct Batch {
+  hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   bool timed = false;
@@ -208,11 +230,17 @@ using namespace lti;
 
 struct lti_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;   // sweeps and result copies
+  hipStream_t stream = nullptr;               // first sweep stream; result copies
+  hipStream_t sstreams[kSweepStreams] = {};  // sweeps ([0] = stream)
+  int next_sstream = 0;
+  int n_sstreams = 1;
   hipStream_t rstreams[kAdmitStreams] = {};  // uploads and reductions
-  hipEvent_t admit_ev[kAdmitStreams] = {};   // end of the last pass on each
   int next_rstream = 0;
+  int n_rstreams = 1;
   hipStream_t rstream = nullptr;             // the current pass's stream
+  PassEvent* last_pass[kAdmitStreams] = {};  // the last pass on each
+  PassEvent* pass = nullptr;                 // the current pass's event
+  std::vector<PassEvent*> pass_events;       // all live ones
   bool own_stream = false;
   uint32_t flags = 0;
   int max_pending = kDefaultMaxPending;
@@ -223,6 +251,7 @@ struct lti_ctx {
   bool use_sweep16 = true;  // four-frequencies-per-wavefront kernels where they apply
   int64_t target_tiles16 = kTargetTiles16;
   int64_t target_tiles = kTargetTiles;
+  int64_t outstanding_waves = 0;  // waves of admitted tiles not yet retired
   Arena arena;
   Arena staging;  // pinned host pool
   Clock::time_point t0;
@@ -269,6 +298,21 @@ hipEvent_t get_event(lti_ctx* c, bool timing) {
 
 void put_event(lti_ctx* c, hipEvent_t e, bool timing) {
   if (e) (timing ? c->timing_pool : c->event_pool).push_back(e);
+}
+
+PassEvent* pass_ref(PassEvent* pe) {
+  if (pe) pe->refs++;
+  return pe;
+}
+
+void pass_release(lti_ctx* c, PassEvent*& pe) {
+  if (!pe) return;
+  if (--pe->refs == 0) {
+    put_event(c, pe->ev, false);
+    c->pass_events.erase(std::find(c->pass_events.begin(), c->pass_events.end(), pe));
+    delete pe;
+  }
+  pe = nullptr;
 }
 
 void fail_all(lti_ctx* c, int code) {
@@ -332,6 +376,7 @@ Resident* find_resident(lti_ctx* c, const Request& r) {
 }
 
 void drop_resident(lti_ctx* c, Resident* res) {
+  pass_release(c, res->ready);
   c->arena.release(res->block, res->bytes);
   for (auto it = c->residents.begin(); it != c->residents.end(); ++it) {
     if (it->get() == res) {
@@ -359,8 +404,12 @@ void* alloc_evicting(lti_ctx* c, size_t bytes) {
 void release_request_memory(lti_ctx* c, Request* r) {
   if (r->block) c->arena.release(r->block, r->block_bytes);
   r->block = nullptr;
+  pass_release(c, r->ready);
+  pass_release(c, r->model_ready);
   if (r->model) {
     Resident* res = r->model;
+    // a user of the model has completed, so its reduction has too
+    if (r->state == RState::kDone) pass_release(c, res->ready);
     res->refs--;
     r->model = nullptr;
     if (res->key == 0 && res->refs == 0) drop_resident(c, res);
@@ -415,6 +464,10 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   res->last_use = ++c->use_clock;
   r->model = res;
   r->reused = !needs_model;
+  // what the request's sweeps have to wait for
+  if (needs_model) res->ready = pass_ref(c->pass);
+  if (needs_model || q.mem == LTI_MEM_HOST) r->ready = pass_ref(c->pass);
+  if (!needs_model) r->model_ready = pass_ref(res->ready);
   r->block = block;
   r->block_bytes = nd.block();
 
@@ -492,12 +545,14 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   if (F <= 0) F = four ? 4 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, r->K / 2048));
   if (four) F = (F + 3) & ~3;
   r->F = F;
-  // Split the right-hand-side columns over several tiles when the request
-  // alone has too few frequency blocks to fill the device.
+  // Split the right-hand-side columns over several tiles (each split
+  // repeats the rotations) only while the device would otherwise be short of
+  // wavefronts: the target counts the waves of tiles already outstanding.
   const int64_t fblocks = (r->K + F - 1) / F;
   const int64_t target = four ? c->target_tiles16 : c->target_tiles;
+  const int64_t avail = std::max<int64_t>(0, target - c->outstanding_waves);
   int S = c->rhs_split;
-  if (S <= 0) S = (fblocks >= target) ? 1 : (int)((target + fblocks - 1) / fblocks);
+  if (S <= 0) S = (fblocks >= avail) ? 1 : (int)((avail + fblocks - 1) / fblocks);
   S = std::max(1, std::min(S, m));
   if (four || wg) S = std::max(S, (m + 3) / 4);
   r->mc = (m + S - 1) / S;
@@ -518,6 +573,8 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   }
   r->stage = (four || wg) ? 0 : stage_bytes(q.precision, n, m, p);
   r->ntiles = fblocks * r->S;
+  r->waves_per_tile = wg ? 4 : 1;
+  c->outstanding_waves += r->ntiles * r->waves_per_tile;
   r->next_tile = 0;
   r->tiles_done = 0;
   r->state = RState::kLive;
@@ -527,9 +584,33 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
 }
 
 void admit(lti_ctx* c) {
+  if (c->pending.empty()) return;
+  // an idle admission stream, or wait for one
+  int rs = -1;
+  for (int i = 0; i < c->n_rstreams && rs < 0; ++i) {
+    const int cand = (c->next_rstream + i) % c->n_rstreams;
+    PassEvent*& lp = c->last_pass[cand];
+    if (!lp || hipEventQuery(lp->ev) != hipErrorNotReady) {
+      pass_release(c, lp);
+      rs = cand;
+    }
+  }
+  if (rs < 0) return;
   JobLists jl;
-  const int rs = c->next_rstream;
   c->rstream = c->rstreams[rs];
+  PassEvent* pe = new PassEvent{};
+  pe->ev = get_event(c, false);
+  pe->refs = 1;  // this pass's own reference, dropped below
+  c->pass_events.push_back(pe);
+  c->pass = pe;
+  struct Drop {
+    lti_ctx* c;
+    PassEvent* pe;
+    ~Drop() {
+      c->pass = nullptr;
+      pass_release(c, pe);
+    }
+  } drop{c, pe};
   while (!c->pending.empty() && !c->device_error) {
     Request* r = c->pending.front();
     if (!admit_one(c, r, jl)) break;
@@ -537,7 +618,7 @@ void admit(lti_ctx* c) {
     if (r->state == RState::kLive) c->live.push_back(r);
   }
   if (c->device_error || (jl.total() == 0 && !jl.copies)) return;
-  c->next_rstream = (rs + 1) % kAdmitStreams;
+  c->next_rstream = (rs + 1) % c->n_rstreams;
   const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0 && jl.total() > 0;
   TimedPair tp{nullptr, nullptr};
   hipError_t e = hipSuccess;
@@ -560,10 +641,13 @@ void admit(lti_ctx* c) {
     e = hipEventRecord(tp.b, c->rstream);
     c->reduce_timing.push_back(tp);
   }
-  // sweeps queued from now on see this pass's uploads and reductions
-  if (e == hipSuccess) e = hipEventRecord(c->admit_ev[rs], c->rstream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->admit_ev[rs], 0);
-  if (e != hipSuccess) fail_all(c, LTI_EDEVICE);
+  // the sweeps of this pass's requests wait on this
+  if (e == hipSuccess) e = (pe->ev ? hipEventRecord(pe->ev, c->rstream) : hipErrorOutOfMemory);
+  if (e != hipSuccess) {
+    fail_all(c, LTI_EDEVICE);
+    return;
+  }
+  c->last_pass[rs] = pass_ref(pe);
 }
 
 // Gather up to batch_tiles tiles from the live requests (oldest first) into
@@ -593,11 +677,22 @@ void launch(lti_ctx* c) {
   }
   if (total == 0) return;
   hipError_t e = hipSuccess;
+  hipStream_t ss = c->sstreams[c->next_sstream];
+  c->next_sstream = (c->next_sstream + 1) % c->n_sstreams;
+  b.stream = ss;
+  // wait for the uploads and reductions the batch's requests depend on
+  std::vector<PassEvent*> waited;
+  for (auto& cr : b.credit)
+    for (PassEvent* pe : {cr.first->ready, cr.first->model_ready})
+      if (pe && std::find(waited.begin(), waited.end(), pe) == waited.end()) {
+        waited.push_back(pe);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ss, pe->ev, 0);
+      }
   b.timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
   if (b.timed) {
     b.t0 = get_event(c, true);
     b.t1 = get_event(c, true);
-    e = hipEventRecord(b.t0, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(b.t0, ss);
   }
   SweepLaunch L;
   for (int k = 0; k < kAllClasses && e == hipSuccess; ++k) {
@@ -619,17 +714,17 @@ void launch(lti_ctx* c) {
       }
       L.ntiles = (int)t;
       if (k >= kNumSweepClasses + kNumSweep16Classes)
-        e = launch_sweep_wg(k - kNumSweepClasses - kNumSweep16Classes, L, c->stream);
+        e = launch_sweep_wg(k - kNumSweepClasses - kNumSweep16Classes, L, ss);
       else if (k >= kNumSweepClasses)
-        e = launch_sweep16(k - kNumSweepClasses, L, c->stream);
+        e = launch_sweep16(k - kNumSweepClasses, L, ss);
       else
-        e = launch_sweep(k, L, c->stage_lds ? lds[k] : 0, c->stream);
+        e = launch_sweep(k, L, c->stage_lds ? lds[k] : 0, ss);
       c->stats.sweep_launches++;
     }
   }
-  if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, c->stream);
+  if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, ss);
   b.done = get_event(c, false);
-  if (e == hipSuccess) e = hipEventRecord(b.done, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(b.done, ss);
   c->stats.tiles_launched += total;
   if (e != hipSuccess) {
     fail_all(c, LTI_EDEVICE);
@@ -703,10 +798,14 @@ bool retire(lti_ctx* c) {
     put_event(c, tp.b, true);
     c->reduce_timing.pop_front();
   }
-  while (!c->inflight.empty()) {
-    Batch& b = c->inflight.front();
+  // batches on different sweep streams may finish in any order
+  for (auto bit = c->inflight.begin(); bit != c->inflight.end();) {
+    Batch& b = *bit;
     const hipError_t q = hipEventQuery(b.done);
-    if (q == hipErrorNotReady) break;
+    if (q == hipErrorNotReady) {
+      ++bit;
+      continue;
+    }
     if (q != hipSuccess) {
       fail_all(c, LTI_EDEVICE);
       return true;
@@ -723,11 +822,12 @@ bool retire(lti_ctx* c) {
     for (auto& cr : b.credit) {
       Request* r = cr.first;
       r->tiles_done += cr.second;
+      c->outstanding_waves -= cr.second * r->waves_per_tile;
       if (r->tiles_done == r->ntiles && r->state == RState::kLive) finish_tiles(c, r);
       if (c->device_error) return true;
     }
     put_event(c, b.done, false);
-    c->inflight.pop_front();
+    bit = c->inflight.erase(bit);
     progressed = true;
   }
   for (auto it = c->live.begin(); it != c->live.end();) {
@@ -777,14 +877,18 @@ bool pump(lti_ctx* c) {
 
 void destroy_admit_streams(lti_ctx* c) {
   for (int i = 0; i < kAdmitStreams; ++i) {
-    if (c->admit_ev[i]) (void)hipEventDestroy(c->admit_ev[i]);
     if (c->rstreams[i]) (void)hipStreamDestroy(c->rstreams[i]);
-    c->admit_ev[i] = nullptr;
     c->rstreams[i] = nullptr;
+  }
+  for (int i = 1; i < kSweepStreams; ++i) {  // [0] is c->stream
+    if (c->sstreams[i]) (void)hipStreamDestroy(c->sstreams[i]);
+    c->sstreams[i] = nullptr;
   }
 }
 
-bool busy(const lti_ctx* c) { return !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty(); }
+bool busy(const lti_ctx* c) {
+  return !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty() || !c->pending.empty();
+}
 
 // Makes the context's device current on the calling thread for a scope and
 // restores the caller's device afterwards.
@@ -937,6 +1041,10 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   if (const char* e = std::getenv("LTI_FREQRESP_STAGE_LDS")) c->stage_lds = std::atoi(e) != 0;
   if (const char* e = std::getenv("LTI_FREQRESP_SWEEP16")) c->use_sweep16 = std::atoi(e) != 0;
   if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES16")) c->target_tiles16 = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("LTI_FREQRESP_ADMIT_STREAMS"))
+    c->n_rstreams = std::max(1, std::min(kAdmitStreams, std::atoi(e)));
+  if (const char* e = std::getenv("LTI_FREQRESP_SWEEP_STREAMS"))
+    c->n_sstreams = std::max(1, std::min(kSweepStreams, std::atoi(e)));
   c->t0 = Clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
   c->arena.init(static_cast<char*>(cfg->arena), cfg->arena_bytes);
@@ -955,9 +1063,11 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
     c->own_stream = true;
   }
   bool ok = true;
-  for (int i = 0; i < kAdmitStreams && ok; ++i)
-    ok = hipStreamCreateWithFlags(&c->rstreams[i], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&c->admit_ev[i], hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < c->n_rstreams && ok; ++i)
+    ok = hipStreamCreateWithFlags(&c->rstreams[i], hipStreamNonBlocking) == hipSuccess;
+  c->sstreams[0] = c->stream;
+  for (int i = 1; i < c->n_sstreams && ok; ++i)
+    ok = hipStreamCreateWithFlags(&c->sstreams[i], hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     destroy_admit_streams(c.get());
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -1081,7 +1191,8 @@ int lti_freqresp_destroy(lti_ctx* c) {
   (void)hipSetDevice(c->device);
   for (hipStream_t rs : c->rstreams)
     if (rs) (void)hipStreamSynchronize(rs);
-  (void)hipStreamSynchronize(c->stream);
+  for (hipStream_t ss : c->sstreams)
+    if (ss) (void)hipStreamSynchronize(ss);
   for (auto& b : c->inflight) {
     put_event(c, b.done, false);
     put_event(c, b.t0, true);
@@ -1093,6 +1204,12 @@ int lti_freqresp_destroy(lti_ctx* c) {
   }
   for (auto& kv : c->all)
     if (kv.second->d2h_ev) put_event(c, kv.second->d2h_ev, false);
+  for (PassEvent*& lp : c->last_pass) lp = nullptr;
+  for (PassEvent* pe : c->pass_events) {
+    put_event(c, pe->ev, false);
+    delete pe;
+  }
+  c->pass_events.clear();
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->timing_pool) (void)hipEventDestroy(e);
   if (c->staging_block) (void)hipHostFree(c->staging_block);
@@ -1121,7 +1238,8 @@ int lti_freqresp_get_reduced(lti_ctx* c, uint64_t key, int32_t nx, int32_t nu, i
   hipError_t e = hipSetDevice(c->device);
   for (hipStream_t rs : c->rstreams)
     if (e == hipSuccess) e = hipStreamSynchronize(rs);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  for (hipStream_t ss : c->sstreams)
+    if (e == hipSuccess) e = hipStreamSynchronize(ss);
   if (e == hipSuccess) e = hipMemcpy(hp.data(), rm.H, hp.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(bt.data(), rm.Bt, bt.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(ct.data(), rm.Ct, ct.size() * 8, hipMemcpyDeviceToHost);

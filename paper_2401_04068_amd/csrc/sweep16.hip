@@ -73,12 +73,10 @@ __device__ __forceinline__ T group_max16(T x) {
 // 4 x (2 + 2 MM) values of LDS, one slot per frequency for the pivot row's
 // carry entry and right-hand side.  Slices are unrolled at compile time; the
 // 16 steps inside a slice are a loop, so the code stays small.
-template <typename T, int R, int MM>
-__device__ __forceinline__ void sweep16(const T* Hg, int n, T w, S16<T, R, MM>& st, T* bcast) {
+template <typename T, int R, int MM, bool kLds>
+__device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM>& st, T* bcast) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, gl = lane & 15;
-  const gptr<T> H = (gptr<T>)Hg;
-  const cptr<T> Hs = (cptr<T>)Hg;
   T* mine = bcast + g * (2 + 2 * MM);
   st.singular = false;
   {
@@ -106,8 +104,8 @@ __device__ __forceinline__ void sweep16(const T* Hg, int n, T w, S16<T, R, MM>& 
       if (i <= n - 1) hc[r] = H[off + i];
     }
   }
-  T sub0 = (n >= 2) ? Hs[hoff32(n - 2) + n - 1] : (T)0;
-  T sub1 = (n >= 3) ? Hs[hoff32(n - 3) + n - 2] : (T)0;
+  T sub0 = (n >= 2) ? H.uniform(hoff32(n - 2) + n - 1) : (T)0;
+  T sub1 = (n >= 3) ? H.uniform(hoff32(n - 3) + n - 2) : (T)0;
 
   static_for<0, R>([&](auto sc) {
     constexpr int s = R - 1 - decltype(sc)::value;
@@ -138,7 +136,7 @@ __device__ __forceinline__ void sweep16(const T* Hg, int n, T w, S16<T, R, MM>& 
           if (i <= k - 1) hn[t] = H[off + i];
         }
       }
-      const T sub2 = (k >= 3) ? Hs[hoff32(k - 3) + k - 2] : (T)0;
+      const T sub2 = (k >= 3) ? H.uniform(hoff32(k - 3) + k - 2) : (T)0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -406,8 +404,9 @@ __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc
   }
 }
 
-template <int R, int MM>
-__device__ void solve16_fp64(const ReqDesc& rd, int64_t k, bool valid, int j0, int mc, double* bcast) {
+template <int R, int MM, bool kLds>
+__device__ void solve16_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, bool valid, int j0, int mc,
+                             double* bcast) {
   const int gl = threadIdx.x & 15;
   const int n = rd.n, m = rd.m;
   const double w = ((gptr<double>)rd.omega)[k];
@@ -422,7 +421,7 @@ __device__ void solve16_fp64(const ReqDesc& rd, int64_t k, bool valid, int j0, i
       st.bi[r][j] = 0.0;
     }
   }
-  sweep16<double, R, MM>(rd.H, n, w, st, bcast);
+  sweep16<double, R, MM, kLds>(H, n, w, st, bcast);
   const double ratio = rd.info ? diag_ratio16<double, R, MM>(n, st) : 0.0;
   apply_rotations16<double, R, MM>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
@@ -450,13 +449,13 @@ __device__ __forceinline__ double bperm_d(int addr, double v) {
 
 // r = Q^T B - (j w X - H X) in float64 for this lane's frequency; the row
 // X(j, :) reaches the other lanes of its 16-lane row through ds_bpermute.
-template <int R, int MM>
-__device__ __forceinline__ void residual16(const ReqDesc& rd, double w, int j0, int mc, const double (&xr)[R][MM],
-                                           const double (&xi)[R][MM], double (&rr)[R][MM], double (&ri)[R][MM]) {
+template <int R, int MM, bool kLds>
+__device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> H, double w, int j0, int mc,
+                                           const double (&xr)[R][MM], const double (&xi)[R][MM],
+                                           double (&rr)[R][MM], double (&ri)[R][MM]) {
   const int lane = threadIdx.x & 63, gl = lane & 15;
   const int n = rd.n, m = rd.m;
   const gptr<double> Bt = (gptr<double>)rd.Bt;
-  const gptr<double> H = (gptr<double>)rd.H;
 #pragma unroll
   for (int t = 0; t < R; ++t) {
     const int i = gl + 16 * t;
@@ -501,8 +500,9 @@ __device__ __forceinline__ void residual16(const ReqDesc& rd, double w, int j0, 
 // Refined path: complex-float32 solves, float64 residuals and accumulation,
 // float64 fallback (see solve_refined in sweep.hip).  The four frequencies of
 // the wavefront iterate in lockstep until all have stopped.
-template <int R, int MM>
-__device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0, int mc, double* bcast64) {
+template <int R, int MM, bool kLds>
+__device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<float, kLds> H32, int64_t k, bool valid,
+                                int j0, int mc, double* bcast64) {
   const int gl = threadIdx.x & 15;
   const int n = rd.n, m = rd.m;
   const double w = ((gptr<double>)rd.omega)[k];
@@ -523,7 +523,7 @@ __device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0
       st.bi[r][j] = 0.0f;
     }
   }
-  sweep16<float, R, MM>(rd.H32, n, wf, st, bcast);
+  sweep16<float, R, MM, kLds>(H32, n, wf, st, bcast);
   apply_rotations16<float, R, MM>(n, st);
   double s2 = 0.0;
 #pragma unroll
@@ -542,7 +542,7 @@ __device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0
   for (int it = 0; it < kMaxIters; ++it) {
     if (__all(done)) break;
     double rr[R][MM], ri[R][MM];
-    residual16<R, MM>(rd, w, j0, mc, xr, xi, rr, ri);
+    residual16<R, MM, kLds>(rd, H, w, j0, mc, xr, xi, rr, ri);
     double amax = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -562,7 +562,7 @@ __device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0
         st.br[r][j] = (float)(rr[r][j] * scale);
         st.bi[r][j] = (float)(ri[r][j] * scale);
       }
-    sweep16<float, R, MM>(rd.H32, n, wf, st, bcast);
+    sweep16<float, R, MM, kLds>(H32, n, wf, st, bcast);
     apply_rotations16<float, R, MM>(n, st);
     double d2 = 0.0, x2 = 0.0;
 #pragma unroll
@@ -609,7 +609,7 @@ __device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0
         sd.bi[r][j] = 0.0;
       }
     }
-    sweep16<double, R, MM>(rd.H, n, w, sd, bcast64);
+    sweep16<double, R, MM, kLds>(H, n, w, sd, bcast64);
     const double ratio = diag_ratio16<double, R, MM>(n, sd);
     apply_rotations16<double, R, MM>(n, sd);
     if (!ok) {
@@ -636,17 +636,12 @@ __device__ void solve16_refined(const ReqDesc& rd, int64_t k, bool valid, int j0
   }
 }
 
-template <int PREC, int R, int MM>
-__global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const SweepLaunch L) {
-  __shared__ double bcast_all[kWaves16][4 * (2 + 2 * MM)];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int tile = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves16 + wave;
-  if (tile >= L.ntiles) return;
-  const int s = seg_of(L, tile);
-  const ReqDesc rd = L.seg[s].rd;
-  const Tile td = tile_of(L.seg[s], tile);
+constexpr int hlen_max(int R) { return (16 * R - 1) * (16 * R + 2) / 2 + 16 * R; }
+
+template <int PREC, int R, int MM, bool kLds>
+__device__ __forceinline__ void run_tile16(const ReqDesc& rd, const Tile& td, Src<double, kLds> H,
+                                           Src<float, kLds> H32, double* bcast) {
   const int g = (threadIdx.x & 63) >> 4;
-  double* bcast = bcast_all[wave];
   for (uint32_t f0 = 0; f0 < td.count; f0 += 4) {
     // group g solves frequency f0 + g; past the tile's end it repeats the
     // last frequency and writes nothing
@@ -654,9 +649,45 @@ __global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const SweepLaunc
     const bool valid = f < td.count;
     const int64_t k = (int64_t)td.start + (valid ? f : td.count - 1);
     if (PREC == LTI_PREC_FP64)
-      solve16_fp64<R, MM>(rd, k, valid, td.j0, td.mc, bcast);
+      solve16_fp64<R, MM, kLds>(rd, H, k, valid, td.j0, td.mc, bcast);
     else
-      solve16_refined<R, MM>(rd, k, valid, td.j0, td.mc, bcast);
+      solve16_refined<R, MM, kLds>(rd, H, H32, k, valid, td.j0, td.mc, bcast);
+  }
+}
+
+// The reduced model's H (and its float32 copy on the refined path) is staged
+// in LDS when the workgroup's four tiles belong to one request, which they do
+// except where two requests meet in a launch.
+template <int PREC, int R, int MM>
+__global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const SweepLaunch L) {
+  __shared__ double bcast_all[kWaves16][4 * (2 + 2 * MM)];
+  __shared__ double sH[hlen_max(R)];
+  __shared__ float sH32[PREC == LTI_PREC_FP64 ? 1 : hlen_max(R)];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tb = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves16;  // < ntiles
+  const int tile = tb + wave;
+  const int s0 = seg_of(L, tb);
+  const bool staged = seg_of(L, min(tb + kWaves16, L.ntiles) - 1) == s0;
+  if (staged) {
+    const ReqDesc& r0 = L.seg[s0].rd;
+    const int nh = (int)hlen(r0.n);
+    const gptr<double> gH = (gptr<double>)r0.H;
+    for (int i = threadIdx.x; i < nh; i += 64 * kWaves16) sH[i] = gH[i];
+    if (PREC != LTI_PREC_FP64) {
+      const gptr<float> gH32 = (gptr<float>)r0.H32;
+      for (int i = threadIdx.x; i < nh; i += 64 * kWaves16) sH32[i] = gH32[i];
+    }
+    __syncthreads();
+  }
+  if (tile >= L.ntiles) return;
+  const int s = seg_of(L, tile);
+  const ReqDesc rd = L.seg[s].rd;
+  const Tile td = tile_of(L.seg[s], tile);
+  double* bcast = bcast_all[wave];
+  if (staged) {
+    run_tile16<PREC, R, MM, true>(rd, td, Src<double, true>{sH}, Src<float, true>{sH32}, bcast);
+  } else {
+    run_tile16<PREC, R, MM, false>(rd, td, Src<double, false>{rd.H}, Src<float, false>{rd.H32}, bcast);
   }
 }
 
