@@ -50,14 +50,20 @@ struct ReduceJob {
 constexpr int kMaxReduceN = 1024;
 // Reduction kernel classes: 0 .. kNumRegClasses-1 keep the working matrix in
 // registers (class S-1 for S = ceil(max(n+p, n+m) / 16) <= 9, n <= 128);
-// kReduceGlobal keeps it in a global scratch area.
+// kReduceGlobal keeps it in a global scratch area (one workgroup per model);
+// kReduceBlocked runs the blocked reduction over the whole GPU, one model at a
+// time (reduce_blocked.hip).
 constexpr int kMaxRegReduceN = 128;
 constexpr int kNumRegClasses = 9;
-constexpr int kReduceGlobal = kNumRegClasses;
-constexpr int kNumReduceClasses = kNumRegClasses + 1;
+constexpr int kReduceGlobal = kNumRegClasses;       // 128 < n <= kMaxGlobalReduceN
+constexpr int kReduceBlocked = kNumRegClasses + 1;  // larger n: blocked, whole GPU
+constexpr int kNumReduceClasses = kNumRegClasses + 2;
+constexpr int kMaxGlobalReduceN = 256;
 int reduce_class(int n, int m, int p);
 // Global scratch bytes a job of this shape needs (0 for register classes).
 size_t reduce_work_bytes(int n, int m, int p);
+size_t reduce_blocked_work_bytes(int n, int m, int p);
+hipError_t launch_reduce_blocked(const ReduceJob& job, hipStream_t s);
 // Up to kMaxInlineJobs reduction jobs of one class, passed to the kernel by
 // value; one workgroup per job.
 constexpr int kMaxInlineJobs = 24;

@@ -21,9 +21,10 @@
 //   lane shuffles inside the wavefront, then LDS across the four), and the
 //   next pivot column with its norm.  Two barriers per reflector; the step
 //   is straight-line code over all S x S slots.
-// * Global kernel (n > 128): W in a global scratch area that stays hot in
-//   L2, three barriers per reflector (build v, left update, right update),
-//   a group of G adjacent lanes per column or row with DPP group sums.
+// * Global kernel (128 < n <= 256): W in a global scratch area that stays
+//   hot in L2, three barriers per reflector (build v, left update, right
+//   update), a group of G adjacent lanes per column or row with DPP group
+//   sums.  Larger models take the blocked reduction (reduce_blocked.hip).
 #include <algorithm>
 
 #include "dpp.h"
@@ -356,11 +357,13 @@ hipError_t launch_reg(const ReduceLaunch& L, hipStream_t s) {
 int reduce_class(int n, int m, int p) {
   const int s = (std::max(n + p, n + m) + 15) / 16;
   if (n <= kMaxRegReduceN && s <= kNumRegClasses) return s - 1;
-  return kReduceGlobal;
+  return n <= kMaxGlobalReduceN ? kReduceGlobal : kReduceBlocked;
 }
 
 size_t reduce_work_bytes(int n, int m, int p) {
-  if (reduce_class(n, m, p) != kReduceGlobal) return 0;
+  const int rc = reduce_class(n, m, p);
+  if (rc == kReduceBlocked) return align256(reduce_blocked_work_bytes(n, m, p));
+  if (rc != kReduceGlobal) return 0;
   return align256((size_t)ld_of(n, p) * (size_t)(n + m) * sizeof(double));
 }
 
@@ -409,6 +412,12 @@ hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s) {
     case kReduceGlobal:
       hess_global_kernel<kGlobalThreads, kGlobalGroup><<<L.njobs, kGlobalThreads, 0, s>>>(L);
       return hipGetLastError();
+    case kReduceBlocked:
+      for (int i = 0; i < L.njobs; ++i) {
+        const hipError_t e = launch_reduce_blocked(L.job[i], s);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
     default: return hipErrorInvalidValue;
   }
 }
