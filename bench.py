@@ -68,10 +68,10 @@ def _source_digest(files: list[str]) -> str:
 
 
 def _traffic_record(workload: str, files: list[str], window: int):
-    """HBM bytes per sweep launch from committed rocprofv3 counter runs, used
-    only while the kernel sources and the number of requests in flight (which
-    sets how many requests a launch carries) are the ones the counters were
-    taken with."""
+    """HBM bytes per point swept, from committed rocprofv3 counter runs over
+    every sweep dispatch of a bench run, used only while the kernel sources
+    and the number of requests in flight (which decides how launches are
+    formed) are the ones the counters were taken with."""
     path = os.path.join(PROFILES, f"sweep_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -79,7 +79,7 @@ def _traffic_record(workload: str, files: list[str], window: int):
         rec = json.load(f)
     if rec.get("source_sha256_16") != _source_digest(files) or rec.get("window") != window:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("hbm_bytes_per_point")
 
 
 # ------------------------------------------------------------------ CPU leg
@@ -383,7 +383,8 @@ def main():
     flops_launch = sweep_flops_per_point(n, m, p) * K / max(fp64["sweep_launches_per_step"], 1e-9)
     achieved = flops_launch / (fp64["sweep_ms_per_launch"] * 1e-3) / 1e12
     kname, kfiles = sweep_kernel_family(n)
-    traffic = _traffic_record(args.workload, kfiles, args.window)
+    bpp = _traffic_record(args.workload, kfiles, args.window)
+    traffic = None if bpp is None else bpp * K / max(fp64["sweep_launches_per_step"], 1e-9)
 
     out = {
         "metric": METRIC,
