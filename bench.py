@@ -204,19 +204,26 @@ def run_gpu(mdl, precision: int, steps: int, warmup: int, window: int):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         s1 = eng.stats()
-        lat = []
-        for _ in range(steps):
-            a = time.perf_counter()
-            eng.wait(submit(0))
-            lat.append(time.perf_counter() - a)
         torch.cuda.synchronize()
-        Gh = Gs[0].cpu().numpy()
-        Gh = Gh[..., 0] + 1j * Gh[..., 1]
+        # every output buffer of the throughput run (the last request of
+        # each slot), checked against the oracle in main()
+        Gall = []
+        for g in Gs[:min(W, steps)]:
+            gh = g.cpu().numpy()
+            Gall.append(gh[..., 0] + 1j * gh[..., 1])
         infoh = infos[0].cpu().numpy().view(binding.POINT_INFO_DTYPE)
-        # every buffer of the throughput run holds the same (deterministic) result
-        same = all(torch.equal(Gs[0], g) for g in Gs[1:min(W, steps)])
     finally:
         eng.close()
+    # latency: one request at a time, on an engine without kernel-timing
+    # events (a user's configuration)
+    lat = []
+    with binding.Engine(arena_bytes=1 << 30) as eng2:
+        for i in range(warmup + steps):
+            a = time.perf_counter()
+            eng2.wait(eng2.submit_device(t["A"], t["B"], t["C"], t["D"], t["omega"], Gs[0], infos[0],
+                                         precision=precision))
+            if i >= warmup:
+                lat.append(time.perf_counter() - a)
     launches = s1["timed_sweep_launches"] - s0["timed_sweep_launches"]
     sweep_ms = (s1["sweep_kernel_ms"] - s0["sweep_kernel_ms"]) / max(launches, 1)
     rlaunch = s1["timed_reduce_launches"] - s0["timed_reduce_launches"]
@@ -228,8 +235,8 @@ def run_gpu(mdl, precision: int, steps: int, warmup: int, window: int):
         "sweep_launches_per_step": launches / steps,
         "reduce_ms_per_launch": reduce_ms,
         "reductions_per_step": (s1["reductions"] - s0["reductions"]) / steps,
-        "outputs_identical": bool(same),
-        "G": Gh,
+        "G": Gall[0],
+        "G_all": Gall,
         "info": infoh,
     }
 
@@ -368,15 +375,16 @@ def main():
 
     import oracle
 
-    err64 = oracle.rel_err(fp64["G"][ref_idx], G_ref)
-    err32 = oracle.rel_err(ref["G"][ref_idx], G_ref)
+    # the worst point over every output buffer of the throughput run
+    err64 = np.max([oracle.rel_err(g[ref_idx], G_ref) for g in fp64["G_all"]], axis=0)
+    err32 = np.max([oracle.rel_err(g[ref_idx], G_ref) for g in ref["G_all"]], axis=0)
     ok64 = float(np.mean(err64 <= TOL))
     ok32 = float(np.mean(err32 <= TOL))
 
     pts64 = K * args.steps / fp64["seconds"]
     pts32 = K * args.steps / ref["seconds"]
-    if fp64["reductions_per_step"] != 1.0 or not fp64["outputs_identical"]:
-        raise RuntimeError("every step must reduce its model once and produce the same result")
+    if fp64["reductions_per_step"] != 1.0 or ref["reductions_per_step"] != 1.0:
+        raise RuntimeError("every step must reduce its own model exactly once")
     value = pts64 * ok64
     # a launch (one batch of the sweep stream) may carry the tiles of several
     # requests in flight

@@ -142,6 +142,7 @@ class Arena {
 // shared by the requests admitted in it and by the models it reduced.
 struct PassEvent {
   hipEvent_t ev = nullptr;
+  hipStream_t stream = nullptr;  // where the pass was issued
   int refs = 0;
 };
 
@@ -597,8 +598,11 @@ void admit(lti_ctx* c) {
   }
   if (rs < 0) return;
   JobLists jl;
-  c->rstream = c->rstreams[rs];
+  // with no sweeps outstanding the pass goes on the stream the next sweep
+  // batch will use, which orders the two without a cross-stream wait
+  c->rstream = c->inflight.empty() ? c->sstreams[c->next_sstream] : c->rstreams[rs];
   PassEvent* pe = new PassEvent{};
+  pe->stream = c->rstream;
   pe->ev = get_event(c, false);
   pe->refs = 1;  // this pass's own reference, dropped below
   c->pass_events.push_back(pe);
@@ -684,7 +688,7 @@ void launch(lti_ctx* c) {
   std::vector<PassEvent*> waited;
   for (auto& cr : b.credit)
     for (PassEvent* pe : {cr.first->ready, cr.first->model_ready})
-      if (pe && std::find(waited.begin(), waited.end(), pe) == waited.end()) {
+      if (pe && pe->stream != ss && std::find(waited.begin(), waited.end(), pe) == waited.end()) {
         waited.push_back(pe);
         if (e == hipSuccess) e = hipStreamWaitEvent(ss, pe->ev, 0);
       }
