@@ -158,6 +158,7 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
       const T sr = ok ? ar * rq : (T)1;
       const T si = ok ? ai * rq : (T)0;
       st.singular = st.singular || !ok;
+      const T cw = c * w, sw_r = sr * w, sw_i = si * w;
 #pragma unroll
       for (int t = 0; t <= s; ++t) {
         const int i = gl + 16 * t;
@@ -168,10 +169,13 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
           T nki = sr * ci_ - si * cr_;
           T n1r = sr * o - c * cr_;
           T n1i = si * o - c * ci_;
-          if (i == k - 1) {  // the diagonal entry of column k-1 also holds j w
-            nki += c * w;
-            n1r -= si * w;
-            n1i += sr * w;
+          // the diagonal entry of column k-1 also holds j w; row k-1 lies in
+          // slice s or s-1, so the other slices skip this at compile time
+          if (t + 1 >= s) {
+            const T d = (i == k - 1) ? (T)1 : (T)0;
+            nki = fma(d, cw, nki);
+            n1r = fma(-d, sw_i, n1r);
+            n1i = fma(d, sw_r, n1i);
           }
           st.cr[t] = n1r;
           st.ci[t] = n1i;
