@@ -281,11 +281,26 @@ def serving(args):
             # submit -> done interval (both stamps on the library clock)
             lat.append(lag + (h.result["t_done_us"] - h.result["t_submit_us"]) * 1e-6)
         t_open = time.perf_counter() - t0
+
+        def pct(x):
+            x = np.asarray(x) * 1e3
+            return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)), "max": float(x.max())}
+
+        res = [h.result for h, _ in handles]
+        work = np.array([r.K * r.n * r.n * (r.m + 2) for r in reqs], dtype=float)
+        small = work <= np.median(work)
+        lat_a = np.array(lat)
         out["open_loop"] = {
             "wall_s": t_open,
             "points_per_s": total_points / t_open,
-            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
-                           "max": float(np.max(lat) * 1e3)},
+            "latency_ms": pct(lat),
+            # where the time goes: waiting for admission, admission to first
+            # sweep launch, first launch to results visible
+            "queue_ms": pct([(x["t_admit_us"] - x["t_submit_us"]) * 1e-6 for x in res]),
+            "start_ms": pct([(x["t_first_launch_us"] - x["t_admit_us"]) * 1e-6 for x in res]),
+            "run_ms": pct([(x["t_done_us"] - x["t_first_launch_us"]) * 1e-6 for x in res]),
+            "latency_ms_smaller_half": pct(lat_a[small]),
+            "latency_ms_larger_half": pct(lat_a[~small]),
         }
         open_handles = [h for h, _ in handles]
         # closed loop
