@@ -28,7 +28,7 @@
 // next panel column's b = M(:, c+1) - Y V(c+1, :)^T there and its partial
 // V^T b, so that every row-parallel step runs on the whole GPU and each sum
 // has a fixed order).  Per panel: blk_right and blk_left, the rank-nb updates
-// of the trailing matrix.
+// of the trailing matrix, on the float64 matrix cores (v_mfma_f64_16x16x4f64).
 #include <algorithm>
 
 #include "dpp.h"
@@ -42,7 +42,7 @@ constexpr int kNB = 32;          // panel width
 constexpr int kPThreads = 1024;  // blk_panel: one workgroup
 constexpr int kRowBlock = 64;    // rows per workgroup (blk_right); row padding
 constexpr int kRows = 16;        // rows per workgroup (blk_rows)
-constexpr int kLeftCols = 8;     // columns per workgroup (blk_left)
+constexpr int kLeftCols = 16;    // columns per workgroup (blk_left)
 
 struct BlkLayout {
   int ldm, ldv;  // leading dimensions of M, Y, b (rows) and V
@@ -292,8 +292,13 @@ __global__ __launch_bounds__(256) void blk_rows(const BlkArgs a) {
   }
 }
 
-// M(:, k+nbk .. n-1) -= Y V(k+nbk .. n-1, :)^T.  A 64 x 64 tile per
-// workgroup.
+// M(:, k+nbk .. n-1) -= Y V(k+nbk .. n-1, :)^T on the float64 matrix cores.
+// A 64 x 64 tile per workgroup; wavefront w owns rows 16 w .. 16 w + 15 and
+// the tile's four 16 x 16 column blocks.  v_mfma_f64_16x16x4f64 (lane l,
+// checked on the device): A operand = A(l % 16, l / 16), B operand =
+// B(l / 16, l % 16), result element q = D((l / 16) + 4 q, l % 16).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void blk_right(const BlkArgs a) {
   __shared__ double sY[kNB][kRowBlock + 1];
   __shared__ double sV[kNB][kRowBlock + 1];
@@ -309,45 +314,50 @@ __global__ __launch_bounds__(256) void blk_right(const BlkArgs a) {
     sV[l][r] = (l < nbk && col < n) ? B.V[(size_t)l * ldv + col] : 0.0;
   }
   __syncthreads();
-  const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4] = {};
-  for (int l = 0; l < nbk; ++l) {
-    double yv[4], vv[4];
+  const int lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  dbl4 acc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      yv[q] = sY[l][ty + 16 * q];
-      vv[q] = sV[l][tx + 16 * q];
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < nbk; kk += 4) {  // rows of sY/sV past nbk are zero
+    const double av = sY[kk + lk][16 * wv + lr];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const double bv = sV[kk + lk][16 * cb + lr];
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[q][u] = fma(yv[q], vv[u], acc[q][u]);
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int col = cc0 + tx + 16 * u;
+  for (int cb = 0; cb < 4; ++cb) {
+    const int col = cc0 + 16 * cb + lr;
     if (col >= n) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = r0 + ty + 16 * q;
-      if (i < B.N) B.M[(size_t)col * ldm + i] -= acc[q][u];
+      const int i = r0 + 16 * wv + lk + 4 * q;
+      if (i < B.N) B.M[(size_t)col * ldm + i] -= acc[cb][q];
     }
   }
 }
 
-// M(k+1 .. n-1, cols) -= V T^T V^T M(k+1 .. n-1, cols) for kLeftCols
-// trailing columns (B's included) per workgroup.
+// M(k+1 .. n-1, cols) -= V T^T V^T M(k+1 .. n-1, cols) for kLeftCols = 16
+// trailing columns (B's included) per workgroup, both products on the
+// float64 matrix cores (layout as in blk_right):
+//   W = V^T M: 64-row blocks staged in LDS, each wavefront takes four of the
+//     block's sixteen 4-row steps, two 16-row halves of W (reflectors 0-15,
+//     16-31) per wavefront, partial W summed over the wavefronts in LDS;
+//   Z = T^T W on the vector unit;  M -= V Z: 16-row blocks, one wavefront
+//     each, the A operand read straight from V.
 __global__ __launch_bounds__(256) void blk_left(const BlkArgs a) {
   __shared__ double sV[kRowBlock][kNB + 1];
   __shared__ double sM[kRowBlock][kLeftCols + 1];
-  __shared__ double sW[kNB][kLeftCols + 1];
+  __shared__ double sW[4][kNB][kLeftCols + 1];
   const Blk B(a.job);
   const int n = B.n, C = B.C, ldm = B.L.ldm, ldv = B.L.ldv;
   const int nbk = a.nbk, k = a.k;
   const int col0 = k + nbk + blockIdx.x * kLeftCols;
-  const int tid = threadIdx.x;
-  const int l = tid >> 3, q = tid & 7;  // (reflector, column) of W
-  double wacc = 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
   for (int rb = k + 1; rb < n; rb += kRowBlock) {
     for (int idx = tid; idx < kRowBlock * kNB; idx += 256) {
       const int r = idx % kRowBlock, ll = idx / kRowBlock;
@@ -360,27 +370,58 @@ __global__ __launch_bounds__(256) void blk_left(const BlkArgs a) {
       sM[r][qq] = (i < n && col < C) ? B.M[(size_t)col * ldm + i] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int r = 0; r < kRowBlock; ++r) wacc = fma(sV[r][l], sM[r][q], wacc);
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int r = 16 * wv + 4 * st + lk;  // this lane's row of the K step
+      const double bm = sM[r][lr];
+#pragma unroll
+      for (int lb = 0; lb < 2; ++lb)
+        acc[lb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sV[r][16 * lb + lr], bm, acc[lb], 0, 0, 0);
+    }
     __syncthreads();
   }
-  sW[l][q] = wacc;
+  // acc[lb][q] = partial W(16 lb + lk + 4 q, lr)
+#pragma unroll
+  for (int lb = 0; lb < 2; ++lb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sW[wv][16 * lb + lk + 4 * q][lr] = acc[lb][q];
   __syncthreads();
-  // Z = T^T W
-  double z = 0.0;
-  if (l < nbk)
-    for (int l2 = 0; l2 <= l; ++l2) z = fma(B.T[l2 + l * kNB], sW[l2][q], z);
+  // Z = T^T W, written over sW[0]
+  double z[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + 256 * h, l = e >> 4, qq = e & 15;  // 512 entries of Z
+    double zv = 0.0;
+    if (l < nbk)
+      for (int l2 = 0; l2 <= l; ++l2) {
+        const double wsum = (sW[0][l2][qq] + sW[1][l2][qq]) + (sW[2][l2][qq] + sW[3][l2][qq]);
+        zv = fma(B.T[l2 + l * kNB], wsum, zv);
+      }
+    z[h] = zv;
+  }
   __syncthreads();
-  sW[l][q] = z;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + 256 * h;
+    sW[0][e >> 4][e & 15] = z[h];
+  }
   __syncthreads();
-  // M -= V Z
-  for (int idx = tid; idx < (n - k - 1) * kLeftCols; idx += 256) {
-    const int r = idx / kLeftCols, qq = idx % kLeftCols;
-    const int i = k + 1 + r, col = col0 + qq;
-    if (col >= C) continue;
-    double s = 0.0;
-    for (int ll = 0; ll < nbk; ++ll) s = fma(B.V[(size_t)ll * ldv + i], sW[ll][qq], s);
-    B.M[(size_t)col * ldm + i] -= s;
+  // M -= V Z, one 16-row block per wavefront at a time
+  for (int i0 = k + 1 + 16 * wv; i0 < n; i0 += 64) {
+    dbl4 d = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < nbk; kk += 4) {
+      const int i = i0 + lr, ll = kk + lk;
+      const double av = (i < n && ll < nbk) ? B.V[(size_t)ll * ldv + i] : 0.0;
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sW[0][ll][lr], d, 0, 0, 0);
+    }
+    const int col = col0 + lr;
+    if (col < C) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + lk + 4 * q;
+        if (i < n) B.M[(size_t)col * ldm + i] -= d[q];
+      }
+    }
   }
 }
 
