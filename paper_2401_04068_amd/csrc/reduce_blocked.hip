@@ -139,14 +139,16 @@ __global__ __launch_bounds__(kPThreads) void blk_panel(const BlkArgs a) {
 
   for (int i = tid; i < N; i += kPThreads) bv[i] = (j == 0) ? B.M[(size_t)c * ldm + i] : B.b[i];
   if (j > 0) {
-    if (tid < j) {  // u = V^T b: the row blocks' partial sums (fixed order)
-      double u4[4] = {0.0, 0.0, 0.0, 0.0};
-      int rb = 0;
-      for (; rb + 4 <= B.L.nrb; rb += 4)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) u4[q] += B.upart[(size_t)(rb + q) * kNB + tid];
-      for (; rb < B.L.nrb; ++rb) u4[0] += B.upart[(size_t)rb * kNB + tid];
-      red[tid] = (u4[0] + u4[1]) + (u4[2] + u4[3]);
+    {  // u = V^T b from the row blocks' partial sums: 32 threads per
+       // reflector (one half wavefront), each a fixed stride of blocks, then
+       // a fixed-order DPP sum over the 32
+      const int l = tid >> 5, t32 = tid & 31;
+      double u = 0.0;
+      if (l < j)
+        for (int rb = t32; rb < B.L.nrb; rb += 32) u += B.upart[(size_t)rb * kNB + l];
+      u = group_sum_dpp<16>(u);
+      u += dpp<kDppRowBcast15, 0xa>(u);  // rows 1, 3 add rows 0, 2
+      if (l < j && t32 == 31) red[l] = u;
     }
     __syncthreads();
     if (tid < j) {  // z = T^T u
@@ -244,14 +246,24 @@ __global__ __launch_bounds__(256) void blk_rows(const BlkArgs a) {
   const int tid = threadIdx.x, r = tid & (kRows - 1), cl = tid >> 4;  // row, column lane
   const int i = blockIdx.x * kRows + r;  // < ldm
   const double* vj = B.V + (size_t)j * ldv;
-  // eight independent partial sums keep eight loads in flight per lane
-  double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int col = c + 1 + cl;
-  for (; col + 7 * 16 < n; col += 8 * 16)
+  // sixteen independent partial sums keep sixteen loads in flight per lane
+  double s16[16];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s8[q] = fma(B.M[(size_t)(col + 16 * q) * ldm + i], vj[col + 16 * q], s8[q]);
-  for (; col < n; col += 16) s8[0] = fma(B.M[(size_t)col * ldm + i], vj[col], s8[0]);
-  red[cl][r] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  for (int q = 0; q < 16; ++q) s16[q] = 0.0;
+  int col = c + 1 + cl;
+  for (; col + 15 * 16 < n; col += 16 * 16)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s16[q] = fma(B.M[(size_t)(col + 16 * q) * ldm + i], vj[col + 16 * q], s16[q]);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {  // the remainder, still all loads at once
+    const int cq = col + 16 * q;
+    if (cq < n) s16[q] = fma(B.M[(size_t)cq * ldm + i], vj[cq], s16[q]);
+  }
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+    for (int q = 0; q < h; ++q) s16[q] += s16[q + h];
+  red[cl][r] = s16[0];
   __syncthreads();
   if (cl == 0) {
     // this row of Y (issued together: the loop bound is the panel width)
