@@ -50,6 +50,9 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
   __shared__ double ssw[4];       // pivot column sum of squares below row k+1
   __shared__ double gw[4];        // v^T W v partials
 
+  // a reduction is a chain of dependent steps that often shares its CU with
+  // sweep wavefronts: let the SIMDs issue its instructions first
+  __builtin_amdgcn_s_setprio(3);
   const ReduceJob job = L.job[blockIdx.x];
   const int n = job.out.n, m = job.out.m, p = job.out.p;
   const int nrow = n + p, ncol = n + m;

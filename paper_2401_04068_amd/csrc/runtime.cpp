@@ -20,10 +20,8 @@
 //            occupies a single CU);
 //   launch   gather up to max_batch_tiles tiles from the live requests
 //            (oldest first), group them by kernel class and launch on the
-//            next of kSweepStreams sweep streams (round robin, so the
-//            latency-bound sweeps of different batches overlap); at most
-//            kInflight batches are outstanding, so requests that arrive
-//            meanwhile join the next batch;
+//            sweep stream; at most kInflight batches are outstanding, so
+//            requests that arrive meanwhile join the next batch;
 //   retire   when a batch's event has fired, credit its tiles; a request
 //            whose tiles are all done gets its D2H copy and then becomes
 //            visible to poll().
@@ -57,7 +55,11 @@ namespace lti {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kInflight = 8;
+// Sweep batches outstanding: one.  A new batch is formed when the previous
+// one completes, so requests admitted meanwhile share it (bigger launches,
+// and new requests wait behind one batch instead of a queue of them); this
+// measured best for throughput and for serving latency.
+constexpr int kInflight = 1;
 // Streams: one admission stream and one sweep stream by default (a process
 // gets few hardware queues, four by default, and streams that share one run
 // in order).  With one admission stream, requests that arrive during a
@@ -238,6 +240,7 @@ struct lti_ctx {
   hipStream_t rstreams[kAdmitStreams] = {};  // uploads and reductions
   int next_rstream = 0;
   int n_rstreams = 1;
+  int max_inflight = kInflight;  // sweep batches outstanding
   hipStream_t rstream = nullptr;             // the current pass's stream
   PassEvent* last_pass[kAdmitStreams] = {};  // the last pass on each
   PassEvent* pass = nullptr;                 // the current pass's event
@@ -658,7 +661,7 @@ void admit(lti_ctx* c) {
 // one batch: one launch per kernel class and kMaxSegs requests, each request
 // a contiguous range of its tiles.
 void launch(lti_ctx* c) {
-  if (c->live.empty() || (int)c->inflight.size() >= kInflight) return;
+  if (c->live.empty() || (int)c->inflight.size() >= c->max_inflight) return;
   constexpr int kAllClasses = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
   struct Piece {
     Request* r;
@@ -870,7 +873,7 @@ bool pump(lti_ctx* c) {
   admit(c);
   progressed |= c->pending.size() != pending_before;
   const size_t inflight_before = c->inflight.size();
-  while ((int)c->inflight.size() < kInflight && !c->device_error) {
+  while ((int)c->inflight.size() < c->max_inflight && !c->device_error) {
     const size_t sz = c->inflight.size();
     launch(c);
     if (c->inflight.size() == sz) break;
@@ -1045,6 +1048,8 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   if (const char* e = std::getenv("LTI_FREQRESP_STAGE_LDS")) c->stage_lds = std::atoi(e) != 0;
   if (const char* e = std::getenv("LTI_FREQRESP_SWEEP16")) c->use_sweep16 = std::atoi(e) != 0;
   if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES16")) c->target_tiles16 = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("LTI_FREQRESP_MAX_INFLIGHT"))
+    c->max_inflight = std::max(1, std::min(64, std::atoi(e)));
   if (const char* e = std::getenv("LTI_FREQRESP_ADMIT_STREAMS"))
     c->n_rstreams = std::max(1, std::min(kAdmitStreams, std::atoi(e)));
   if (const char* e = std::getenv("LTI_FREQRESP_SWEEP_STREAMS"))
@@ -1057,10 +1062,25 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   if (hipHostMalloc(&hp, staging, hipHostMallocDefault) != hipSuccess) return LTI_EDEVICE;
   c->staging_block = static_cast<char*>(hp);
   c->staging.init(c->staging_block, staging);
+  // tuning knob (not part of the ABI): keep the sweeps off the first N CUs,
+  // so that reductions always find room beside them
+  int reserved_cus = 0;
+  if (const char* e = std::getenv("LTI_FREQRESP_RESERVED_CUS")) reserved_cus = std::max(0, std::atoi(e));
   if (cfg->stream) {
     c->stream = static_cast<hipStream_t>(cfg->stream);
   } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    hipError_t e = hipSuccess;
+    int ncu = 0;
+    if (reserved_cus > 0 &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        reserved_cus < ncu) {
+      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+      for (int cu = reserved_cus; cu < ncu; ++cu) mask[cu / 32] |= 1u << (cu % 32);
+      e = hipExtStreamCreateWithCUMask(&c->stream, (uint32_t)mask.size(), mask.data());
+    } else {
+      e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    }
+    if (e != hipSuccess) {
       (void)hipHostFree(hp);
       return LTI_EDEVICE;
     }
