@@ -54,6 +54,25 @@ __device__ __forceinline__ T group_sum_dpp(T x) {
   return x;
 }
 
+// Variant for code in which every lane of the wavefront is active and the
+// pattern has a source inside the row for every lane (quad_perm, mirrors):
+// the destination needs no initial value, which saves a move per half.
+template <int CTRL>
+__device__ __forceinline__ double dpp_full(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each 16-lane row, every lane active (same pairings and order as
+// group_sum_dpp<16>).
+__device__ __forceinline__ double row_sum16_full(double x) {
+  x += dpp_full<kDppQuadSwap1>(x);
+  x += dpp_full<kDppQuadSwap2>(x);
+  x += dpp_full<kDppRowHalfMirror>(x);
+  return x + dpp_full<kDppRowMirror>(x);
+}
+
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
@@ -80,6 +99,24 @@ __device__ __forceinline__ double xor32_sum(double x) {
   const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
   return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
 }
+
+// Reduce-scatter steps between halves (32 lanes) or row pairs (16 lanes):
+// the swap exchanges complementary parts of u and w, so u + w afterwards
+// holds, on half of the lanes, u's total over the two parts and, on the
+// other half, w's.  Which lanes get which is read off the same swap applied
+// to the tags 0 (u) and 1 (w): swap_tag32/16() return that tag per lane.
+__device__ __forceinline__ double rs32_sum(double u, double w) {
+  const auto a = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(u), (unsigned)__double2loint(w), false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(u), (unsigned)__double2hiint(w), false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double rs16_sum(double u, double w) {
+  const auto a = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(u), (unsigned)__double2loint(w), false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(u), (unsigned)__double2hiint(w), false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ int swap_tag32() { return (int)__builtin_amdgcn_permlane32_swap(0u, 1u, false, false)[0]; }
+__device__ __forceinline__ int swap_tag16() { return (int)__builtin_amdgcn_permlane16_swap(0u, 1u, false, false)[0]; }
 
 // Sum over the whole wavefront, returned to every lane (read from lane 63).
 template <typename T>

@@ -19,13 +19,16 @@
 //   so a step needs two exchanges: the row sums q (a DPP sum inside each
 //   16-lane row) with the column sums W^T v (over the 16 thread rows: two
 //   lane shuffles inside the wavefront, then LDS across the four), and the
-//   next pivot column with its norm.  Two barriers per reflector; the step
-//   is straight-line code over all S x S slots.
+//   next pivot column with its norm.  Two barriers per reflector; the steps
+//   of one 16-column slot block share straight-line code in which the block
+//   index is a compile-time constant, so the slots that v cannot reach are
+//   skipped without branches.
 // * Global kernel (128 < n <= 256): W in a global scratch area that stays
 //   hot in L2, three barriers per reflector (build v, left update, right
 //   update), a group of G adjacent lanes per column or row with DPP group
 //   sums.  Larger models take the blocked reduction (reduce_blocked.hip).
 #include <algorithm>
+#include <type_traits>
 
 #include "dpp.h"
 #include "lti_kernels.h"
@@ -42,13 +45,21 @@ constexpr int kRegThreads = 256;
 // Sum over the four 16-lane rows of the wavefront (same column position).
 __device__ __forceinline__ double sum_thread_rows(double x) { return xor32_sum(xor16_sum(x)); }
 
+template <int T0, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (T0 < N) {
+    f(std::integral_constant<int, T0>{});
+    static_for<T0 + 1, N>(f);
+  }
+}
+
 template <int S>
 __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunch L) {
   constexpr int kPad = 16 * S;
-  __shared__ double xcol[kPad];   // pivot column, rows k+1 .. n-1
-  __shared__ double pw[4][kPad];  // column sums W^T v, one partial per wavefront
-  __shared__ double ssw[4];       // pivot column sum of squares below row k+1
-  __shared__ double gw[4];        // v^T W v partials
+  __shared__ double xcol[kPad];  // pivot column kc below row kc, zero elsewhere
+  // per wavefront: column sums W^T v (slot blocks 0..S-1) and v^T W v (block S)
+  __shared__ double pw[4][kPad + 16];
+  __shared__ double ssw[4];  // pivot column sum of squares below row kc+1
 
   // a reduction is a chain of dependent steps that often shares its CU with
   // sweep wavefronts: let the SIMDs issue its instructions first
@@ -60,10 +71,13 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
   const int wv = threadIdx.x >> 6;
   const int tc = lane & 15;
   const int tr = (wv << 2) | (lane >> 4);
+  // slot, within a group of four (two) reduce-scattered values, whose total
+  // this lane holds after the exchanges over its wavefront's thread rows
+  const int t32 = swap_tag32();
+  const int pos4 = 2 * swap_tag16() + t32;
 
-  // Row a of the register block is one vector, so that reading the column
-  // slot kb (uniform, known at run time) is an indexed register move, not a
-  // trip through scratch memory.
+  // Row a of the register block is one vector (kept from the variant with a
+  // run-time column slot; every slot index is a compile-time constant now).
   using Row = double __attribute__((ext_vector_type(S < 2 ? 2 : S)));
   Row W[S];
 #pragma unroll
@@ -84,118 +98,150 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
       W[a][b] = x;
     }
   }
+  bool live[S];  // this thread's row a is a row of A
+#pragma unroll
+  for (int a = 0; a < S; ++a) live[a] = tr + 16 * a < n;
 
-  // Publish column kc (rows kc+1 .. n-1) and its sum of squares below row
-  // kc+1; only the 16 threads of thread column kc % 16 hold it.
-  auto publish = [&](int kc) {
-    const int kb = kc >> 4;
+  // Publish column kc (its slot block KB = kc / 16 is a compile-time
+  // constant): the 16 threads of thread column kc % 16 write every entry of
+  // xcol, the column below row kc and zeros elsewhere (so v needs no bounds
+  // tests), and the sum of squares below row kc+1.
+  auto publish = [&](auto KBc, int kc) {
+    constexpr int kb = decltype(KBc)::value;
     const bool mine = tc == (kc & 15);
-    double x[S];
-#pragma unroll
-    for (int a = 0; a < S; ++a) x[a] = W[a][kb];
     double ss = 0.0;
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
+    static_for<0, S>([&](auto A) {
+      constexpr int a = decltype(A)::value;
       const int i = tr + 16 * a;
-      if (mine && i > kc && i < n) xcol[i] = x[a];
-      const double x2 = (i > kc + 1 && i < n) ? x[a] : 0.0;
-      ss = fma(x2, x2, ss);
-    }
+      double x = 0.0;
+      // rows of slot blocks below kb lie above kc
+      if constexpr (a >= kb) x = (i > kc && live[a]) ? W[a][kb] : 0.0;
+      if (mine) xcol[i] = x;
+      if constexpr (a == kb || a == kb + 1) x = (i == kc + 1) ? 0.0 : x;
+      ss = fma(x, x, ss);
+    });
     ss = sum_thread_rows(mine ? ss : 0.0);
     if (lane == (kc & 15)) ssw[wv] = ss;
   };
 
-  if (n > 2) publish(0);
+  if (n > 2) publish(std::integral_constant<int, 0>{}, 0);
   __syncthreads();
 
-  // Every step runs the same straight-line code over all S x S slots: slots
-  // outside the active rows and columns meet exact zeros of v (a taken branch
-  // costs more than the few fused multiply-adds it would skip).  Column k is
-  // not reset to beta e_{k+1} explicitly: the update itself leaves beta (to
-  // rounding) on the subdiagonal and rounding-level values below it, which
-  // are never read again (H is stored up to the subdiagonal, and later
-  // reflectors only touch those rows through their own rounding-level
-  // column sums).
-  for (int k = 0; k + 2 < n; ++k) {
-    // reflector of column k, computed by every thread
-    double xr[S], xc[S];
+  // Steps k = 16 kb .. 16 kb + 15 run the same code with kb a compile-time
+  // constant: v vanishes on rows and columns of slot blocks below kb (they lie
+  // at or above k), so those products are skipped; the columns of those
+  // blocks hold, below the subdiagonal, rounding-level values that are never
+  // read again, and are left alone.  Column k is not reset to beta e_{k+1}
+  // explicitly: the update itself leaves beta (to rounding) on the
+  // subdiagonal and rounding-level values below it.
+  static_for<0, S>([&](auto KB) {
+    constexpr int kb = decltype(KB)::value;
+    const int kend = (16 * kb + 16 < n - 2) ? 16 * kb + 16 : n - 2;
+    for (int k = 16 * kb; k < kend; ++k) {
+      // reflector of column k, computed by every thread
+      double xr[S], xc[S];
 #pragma unroll
-    for (int a = 0; a < S; ++a) xr[a] = xcol[tr + 16 * a];
+      for (int a = kb; a < S; ++a) xr[a] = xcol[tr + 16 * a];
 #pragma unroll
-    for (int b = 0; b < S; ++b) xc[b] = xcol[tc + 16 * b];
-    const double ss = (ssw[0] + ssw[1]) + (ssw[2] + ssw[3]);
-    const double alpha = xcol[k + 1];
-    double tau = 0.0, scale = 0.0;
-    if (ss != 0.0) {
-      const double nrm = sqrt(fma(alpha, alpha, ss));
-      const double beta = (alpha >= 0.0) ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    // v on this thread's rows and columns (stale or unwritten entries of
-    // xcol are never selected)
-    double vr[S], vc[S];
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-      const int i = tr + 16 * a;
-      const double t = xr[a] * scale;
-      vr[a] = (i == k + 1) ? 1.0 : ((i > k + 1 && i < n) ? t : 0.0);
-    }
-#pragma unroll
-    for (int b = 0; b < S; ++b) {
-      const int c = tc + 16 * b;
-      const double t = xc[b] * scale;
-      vc[b] = (c == k + 1) ? 1.0 : ((c > k + 1 && c < n) ? t : 0.0);
-    }
-    // partial W^T v over this thread's rows, partial W v over its columns
-    double pp[S], qq[S];
-#pragma unroll
-    for (int b = 0; b < S; ++b) {
-      pp[b] = 0.0;
-#pragma unroll
-      for (int a = 0; a < S; ++a) pp[b] = fma(vr[a], W[a][b], pp[b]);
-    }
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-      qq[a] = 0.0;
-#pragma unroll
-      for (int b = 0; b < S; ++b) qq[a] = fma(W[a][b], vc[b], qq[a]);
-      qq[a] = group_sum_dpp<16>(qq[a]);  // row sum over the 16 thread columns
-    }
-    double g = 0.0;
-#pragma unroll
-    for (int a = 0; a < S; ++a) g = fma(vr[a], qq[a], g);
-    g = sum_thread_rows(g);
-#pragma unroll
-    for (int b = 0; b < S; ++b) {
-      pp[b] = sum_thread_rows(pp[b]);
-      if (lane < 16) pw[wv][tc + 16 * b] = pp[b];
-    }
-    if (lane == 0) gw[wv] = g;
-    __syncthreads();
-
-    double pr[4][S];
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-#pragma unroll
-      for (int b = 0; b < S; ++b) pr[w][b] = pw[w][tc + 16 * b];
-    const double gamma = (gw[0] + gw[1]) + (gw[2] + gw[3]);
-    const double tg = tau * gamma;
-#pragma unroll
-    for (int b = 0; b < S; ++b) pp[b] = tau * ((pr[0][b] + pr[1][b]) + (pr[2][b] + pr[3][b]));
-#pragma unroll
-    for (int a = 0; a < S; ++a) qq[a] = tau * fma(-tg, vr[a], qq[a]);
-    // W -= v (tau W^T v)^T + tau (q - tau gamma v) v^T
-#pragma unroll
-    for (int a = 0; a < S; ++a)
-#pragma unroll
-      for (int b = 0; b < S; ++b) {
-        W[a][b] = fma(-vr[a], pp[b], W[a][b]);
-        W[a][b] = fma(-qq[a], vc[b], W[a][b]);
+      for (int b = kb; b < S; ++b) xc[b] = xcol[tc + 16 * b];
+      const double ss = (ssw[0] + ssw[1]) + (ssw[2] + ssw[3]);
+      const double alpha = xcol[k + 1];
+      double tau = 0.0, scale = 0.0;
+      if (ss != 0.0) {
+        const double nrm = sqrt(fma(alpha, alpha, ss));
+        const double beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
       }
-    if (k + 3 < n) publish(k + 1);
-    __syncthreads();
-  }
+      // v: 1 on row k+1 (slot block kb or kb+1), the scaled column below it
+      double vr[S], vc[S];
+#pragma unroll
+      for (int a = kb; a < S; ++a) {
+        vr[a] = xr[a] * scale;
+        if (a <= kb + 1) vr[a] = (tr + 16 * a == k + 1) ? 1.0 : vr[a];
+      }
+#pragma unroll
+      for (int b = kb; b < S; ++b) {
+        vc[b] = xc[b] * scale;
+        if (b <= kb + 1) vc[b] = (tc + 16 * b == k + 1) ? 1.0 : vc[b];
+      }
+      // partial W^T v over this thread's rows, partial W v over its columns
+      double pp[S], qq[S];
+#pragma unroll
+      for (int b = kb; b < S; ++b) {
+        pp[b] = 0.0;
+#pragma unroll
+        for (int a = kb; a < S; ++a) pp[b] = fma(vr[a], W[a][b], pp[b]);
+      }
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        qq[a] = 0.0;
+#pragma unroll
+        for (int b = kb; b < S; ++b) qq[a] = fma(W[a][b], vc[b], qq[a]);
+        qq[a] = row_sum16_full(qq[a]);  // row sum over the 16 thread columns
+      }
+      double g = 0.0;
+#pragma unroll
+      for (int a = kb; a < S; ++a) g = fma(vr[a], qq[a], g);
+      // Sums over the wavefront's four thread rows of pp[kb..S-1] and g
+      // (value j goes to block kb + j of pw, g to block S): groups of four
+      // are reduce-scattered in two swaps, a remaining pair in one swap and
+      // one exchange, a remaining single value in two exchanges.
+      {
+        constexpr int cnt = S - kb + 1;
+        double val[cnt];
+#pragma unroll
+        for (int j = 0; j + 1 < cnt; ++j) val[j] = pp[kb + j];
+        val[cnt - 1] = g;
+        double* const dst = &pw[wv][tc + 16 * kb];
+#pragma unroll
+        for (int j = 0; j + 4 <= cnt; j += 4) {
+          const double x = rs16_sum(rs32_sum(val[j], val[j + 1]), rs32_sum(val[j + 2], val[j + 3]));
+          dst[16 * (j + pos4)] = x;
+        }
+        constexpr int j2 = cnt & ~3;
+        if constexpr ((cnt & 3) >= 2) {
+          const double x = xor16_sum(rs32_sum(val[j2], val[j2 + 1]));
+          if ((lane & 16) == 0) dst[16 * (j2 + t32)] = x;
+        }
+        if constexpr ((cnt & 1) == 1) {
+          constexpr int j1 = cnt - 1;
+          const double x = sum_thread_rows(val[j1]);
+          if (lane < 16) dst[16 * j1] = x;
+        }
+      }
+      __syncthreads();
+
+      const double gamma = (pw[0][tc + kPad] + pw[1][tc + kPad]) + (pw[2][tc + kPad] + pw[3][tc + kPad]);
+      const double tg = tau * gamma;
+#pragma unroll
+      for (int b = kb; b < S; ++b) {
+        const int c = tc + 16 * b;
+        pp[b] = tau * ((pw[0][c] + pw[1][c]) + (pw[2][c] + pw[3][c]));
+      }
+#pragma unroll
+      for (int a = 0; a < S; ++a) qq[a] = tau * (a >= kb ? fma(-tg, vr[a], qq[a]) : qq[a]);
+      // W -= v (tau W^T v)^T + tau (q - tau gamma v) v^T
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = kb; b < S; ++b) {
+          if (a >= kb) W[a][b] = fma(-vr[a], pp[b], W[a][b]);
+          W[a][b] = fma(-qq[a], vc[b], W[a][b]);
+        }
+      if (k + 3 < n) {
+        if constexpr (kb + 1 < S) {
+          if (((k + 1) & 15) == 0)
+            publish(std::integral_constant<int, kb + 1>{}, k + 1);
+          else
+            publish(KB, k + 1);
+        } else {
+          publish(KB, k + 1);
+        }
+      }
+      __syncthreads();
+    }
+  });
 
   // write the reduced model
   const ReducedModel& o = job.out;
