@@ -671,9 +671,30 @@ void launch(lti_ctx* c) {
   std::vector<size_t> lds(kAllClasses, 0);
   Batch b;
   int64_t total = 0;
+  // Requests whose uploads and reductions have finished go first; the others
+  // join only a batch that would otherwise be empty (its launch then waits
+  // for them on the device).  Otherwise a batch holding one just-admitted
+  // request would keep the sweep stream idle for that reduction while
+  // requests reduced earlier wait too.
+  std::vector<std::pair<const PassEvent*, bool>> seen;
+  auto pass_done = [&](const PassEvent* pe) {
+    if (!pe || !pe->ev) return true;
+    for (const auto& sd : seen)
+      if (sd.first == pe) return sd.second;
+    const bool done = hipEventQuery(pe->ev) != hipErrorNotReady;
+    seen.emplace_back(pe, done);
+    return done;
+  };
+  bool any_ready = false;
+  for (Request* r : c->live)
+    if (r->state == RState::kLive && r->next_tile < r->ntiles && pass_done(r->ready) && pass_done(r->model_ready)) {
+      any_ready = true;
+      break;
+    }
   for (Request* r : c->live) {
     if (total >= c->batch_tiles) break;
     if (r->state != RState::kLive || r->next_tile >= r->ntiles) continue;
+    if (any_ready && !(pass_done(r->ready) && pass_done(r->model_ready))) continue;
     const int64_t take = std::min<int64_t>(r->ntiles - r->next_tile, c->batch_tiles - total);
     per[r->kclass].push_back(Piece{r, r->next_tile, take});
     lds[r->kclass] = std::max(lds[r->kclass], r->stage);
