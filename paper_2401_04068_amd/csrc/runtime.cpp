@@ -671,11 +671,10 @@ void launch(lti_ctx* c) {
   std::vector<size_t> lds(kAllClasses, 0);
   Batch b;
   int64_t total = 0;
-  // Requests whose uploads and reductions have finished go first; the others
-  // join only a batch that would otherwise be empty (its launch then waits
-  // for them on the device).  Otherwise a batch holding one just-admitted
-  // request would keep the sweep stream idle for that reduction while
-  // requests reduced earlier wait too.
+  // Requests whose uploads and reductions have finished go first.  When none
+  // has, the batch takes the requests of the oldest unfinished admission
+  // pass only (its launch then waits for that pass on the device), so that a
+  // pass admitted later does not hold back the sweeps of an earlier one.
   std::vector<std::pair<const PassEvent*, bool>> seen;
   auto pass_done = [&](const PassEvent* pe) {
     if (!pe || !pe->ev) return true;
@@ -686,15 +685,25 @@ void launch(lti_ctx* c) {
     return done;
   };
   bool any_ready = false;
-  for (Request* r : c->live)
-    if (r->state == RState::kLive && r->next_tile < r->ntiles && pass_done(r->ready) && pass_done(r->model_ready)) {
+  const PassEvent* oldest = nullptr;
+  for (Request* r : c->live) {
+    if (r->state != RState::kLive || r->next_tile >= r->ntiles) continue;
+    const bool rd = pass_done(r->ready), md = pass_done(r->model_ready);
+    if (rd && md) {
       any_ready = true;
       break;
     }
+    if (!oldest) oldest = rd ? r->model_ready : r->ready;
+  }
+  auto eligible = [&](const Request* r) {
+    const bool rd = pass_done(r->ready), md = pass_done(r->model_ready);
+    if (any_ready) return rd && md;
+    return (rd || r->ready == oldest) && (md || r->model_ready == oldest);
+  };
   for (Request* r : c->live) {
     if (total >= c->batch_tiles) break;
     if (r->state != RState::kLive || r->next_tile >= r->ntiles) continue;
-    if (any_ready && !(pass_done(r->ready) && pass_done(r->model_ready))) continue;
+    if (!eligible(r)) continue;
     const int64_t take = std::min<int64_t>(r->ntiles - r->next_tile, c->batch_tiles - total);
     per[r->kclass].push_back(Piece{r, r->next_tile, take});
     lds[r->kclass] = std::max(lds[r->kclass], r->stage);
@@ -712,7 +721,7 @@ void launch(lti_ctx* c) {
   std::vector<PassEvent*> waited;
   for (auto& cr : b.credit)
     for (PassEvent* pe : {cr.first->ready, cr.first->model_ready})
-      if (pe && pe->stream != ss && std::find(waited.begin(), waited.end(), pe) == waited.end()) {
+      if (pe && pe->stream != ss && !pass_done(pe) && std::find(waited.begin(), waited.end(), pe) == waited.end()) {
         waited.push_back(pe);
         if (e == hipSuccess) e = hipStreamWaitEvent(ss, pe->ev, 0);
       }
@@ -890,15 +899,21 @@ bool retire(lti_ctx* c) {
 bool pump(lti_ctx* c) {
   if (c->device_error) return false;
   bool progressed = retire(c);
+  const size_t inflight_before = c->inflight.size();
+  auto fill = [&] {
+    while ((int)c->inflight.size() < c->max_inflight && !c->device_error) {
+      const size_t sz = c->inflight.size();
+      launch(c);
+      if (c->inflight.size() == sz) break;
+    }
+  };
+  // sweeps of requests already admitted go out before a new admission pass,
+  // so that the pass does not land on an idle sweep stream ahead of them
+  fill();
   const size_t pending_before = c->pending.size();
   admit(c);
   progressed |= c->pending.size() != pending_before;
-  const size_t inflight_before = c->inflight.size();
-  while ((int)c->inflight.size() < c->max_inflight && !c->device_error) {
-    const size_t sz = c->inflight.size();
-    launch(c);
-    if (c->inflight.size() == sz) break;
-  }
+  fill();
   progressed |= c->inflight.size() != inflight_before;
   return progressed;
 }

@@ -152,11 +152,12 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
       const T nrm2 = ar * ar + ai * ai + beta * beta;
       const bool ok = nrm2 > (T)0;
       const T rq = rsqrt_t(ok ? nrm2 : (T)1);
-      // zero column (ok false): identity rotation and R(k,k) = 0
+      // zero column (ok false, then ar = ai = beta = 0): a zero rotation and
+      // R(k,k) = 0; the frequency is flagged singular
       const T rinv = ok ? rq : (T)INFINITY;
-      const T c = ok ? beta * rq : (T)0;
-      const T sr = ok ? ar * rq : (T)1;
-      const T si = ok ? ai * rq : (T)0;
+      const T c = beta * rq;
+      const T sr = ar * rq;
+      const T si = ai * rq;
       st.singular = st.singular || !ok;
       const T cw = c * w, sw_r = sr * w, sw_i = si * w;
 #pragma unroll
