@@ -331,8 +331,8 @@ def serving(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="mimo64", choices=["mimo64", "siso8", "damped256", "large1024", "serving"])
     ap.add_argument("--requests", type=int, default=4096, help="serving replay: number of requests")
     ap.add_argument("--window", type=int, default=16,

@@ -124,17 +124,18 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
           mine[3 + 2 * j] = st.bi[s][j];
         }
       }
-      // prefetch column k-2 (rows 0..k-1) and the subdiagonal two steps ahead
+      // prefetch column k-2 (rows 0..k-1) and the subdiagonal two steps
+      // ahead.  The loads of the pivot slice run past row k-1 into the next
+      // packed column (at most 15 entries, which the packed array and its LDS
+      // copy hold); those rows are never used.
       T hn[R];
-#pragma unroll
-      for (int t = 0; t < R; ++t) hn[t] = (T)0;
       if (k >= 2) {
-        const int off = hoff32(k - 2);
+        const int off = hoff32(k - 2) + gl;
 #pragma unroll
-        for (int t = 0; t <= s; ++t) {
-          const int i = gl + 16 * t;
-          if (i <= k - 1) hn[t] = H[off + i];
-        }
+        for (int t = 0; t <= s; ++t) hn[t] = H[off + 16 * t];
+      } else {
+#pragma unroll
+        for (int t = 0; t <= s; ++t) hn[t] = (T)0;
       }
       const T sub2 = (k >= 3) ? H.uniform(hoff32(k - 3) + k - 2) : (T)0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -201,7 +202,7 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-      for (int t = 0; t < R; ++t) hc[t] = hn[t];
+      for (int t = 0; t <= s; ++t) hc[t] = hn[t];
       sub0 = sub1;
       sub1 = sub2;
     }
