@@ -33,6 +33,12 @@
 #include "dpp.h"
 #include "lti_kernels.h"
 
+// Issue priority of the register reduction's wavefronts (0 = the default of
+// the sweep wavefronts that share their CUs, 3 = highest).
+#ifndef LTI_REDUCE_PRIO
+#define LTI_REDUCE_PRIO 3
+#endif
+
 namespace lti {
 
 namespace {
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
 
   // a reduction is a chain of dependent steps that often shares its CU with
   // sweep wavefronts: let the SIMDs issue its instructions first
-  __builtin_amdgcn_s_setprio(3);
+  __builtin_amdgcn_s_setprio(LTI_REDUCE_PRIO);
   const ReduceJob job = L.job[blockIdx.x];
   const int n = job.out.n, m = job.out.m, p = job.out.p;
   const int nrow = n + p, ncol = n + m;

@@ -107,105 +107,137 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
   T sub0 = (n >= 2) ? H.uniform(hoff32(n - 2) + n - 1) : (T)0;
   T sub1 = (n >= 3) ? H.uniform(hoff32(n - 3) + n - 2) : (T)0;
 
+  // The pivot row's carry entry and right-hand side reach the other lanes of
+  // its 16-lane row through this wavefront's LDS slot.  Step k publishes the
+  // next pivot row k-1 as soon as the slice holding it is rotated: its carry
+  // entry is read back at once (the next step's rotation starts from it), its
+  // right-hand side after the other slices' back-substitution, which still
+  // needs row k's; the LDS round trip overlaps the other slices' work.  LDS
+  // operations of one wavefront complete in program order.
+  auto lds_order = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  T par, pai, pbr[MM], pbi[MM];
+  auto publish = [&](auto TT, int j) {
+    constexpr int t = decltype(TT)::value;
+    if (gl == j) {
+      mine[0] = st.cr[t];
+      mine[1] = st.ci[t];
+#pragma unroll
+      for (int jj = 0; jj < MM; ++jj) {
+        mine[2 + 2 * jj] = st.br[t][jj];
+        mine[3 + 2 * jj] = st.bi[t][jj];
+      }
+    }
+    lds_order();
+    par = mine[0];
+    pai = mine[1];
+  };
+  auto read_rhs = [&] {
+    lds_order();
+#pragma unroll
+    for (int jj = 0; jj < MM; ++jj) {
+      pbr[jj] = mine[2 + 2 * jj];
+      pbi[jj] = mine[3 + 2 * jj];
+    }
+  };
+  // row n-1 is the first pivot
+  static_for<0, R>([&](auto TT) {
+    constexpr int t = decltype(TT)::value;
+    if ((n - 1) >> 4 == t) publish(TT, (n - 1) & 15);
+  });
+  read_rhs();
+
+  // Step k = 16 s + jl; SP (compile-time) is the slice of row k-1: s for
+  // jl >= 1, s - 1 for jl = 0.
+  auto step = [&](auto SC, auto SP, int jl) {
+    constexpr int s = decltype(SC)::value;
+    constexpr int sp = decltype(SP)::value;
+    const int k = 16 * s + jl;
+    // prefetch column k-2 (rows 0..k-1) and the subdiagonal two steps
+    // ahead.  The loads of the pivot slice run past row k-1 into the next
+    // packed column (at most 15 entries, which the packed array and its LDS
+    // copy hold); those rows are never used.
+    T hn[R];
+    if (k >= 2) {
+      const int off = hoff32(k - 2) + gl;
+#pragma unroll
+      for (int t = 0; t <= s; ++t) hn[t] = H[off + 16 * t];
+    } else {
+#pragma unroll
+      for (int t = 0; t <= s; ++t) hn[t] = (T)0;
+    }
+    const T sub2 = (k >= 3) ? H.uniform(hoff32(k - 3) + k - 2) : (T)0;
+    const T beta = -sub0;
+    const T nrm2 = par * par + pai * pai + beta * beta;
+    const bool ok = nrm2 > (T)0;
+    const T rq = rsqrt_t(ok ? nrm2 : (T)1);
+    // zero column (ok false, then par = pai = beta = 0): a zero rotation and
+    // R(k,k) = 0; the frequency is flagged singular
+    const T rinv = ok ? rq : (T)INFINITY;
+    const T c = beta * rq;
+    const T sr = par * rq;
+    const T si = pai * rq;
+    st.singular = st.singular || !ok;
+    const T cw = c * w, sw_r = sr * w, sw_i = si * w;
+    // rows of slice t below k: rotate the carry column with column k-1, then
+    // b_i -= (R(i,k) / R(k,k)) b_k
+    auto rot = [&](auto TT) {
+      constexpr int t = decltype(TT)::value;
+      if (t < s || gl < jl) {
+        const T cr_ = st.cr[t], ci_ = st.ci[t];
+        const T o = -hc[t];
+        T nkr = c * o + sr * cr_ + si * ci_;
+        T nki = sr * ci_ - si * cr_;
+        T n1r = sr * o - c * cr_;
+        T n1i = si * o - c * ci_;
+        // the diagonal entry of column k-1 (row k-1, in slice sp) also
+        // holds j w
+        if constexpr (t == sp) {
+          const T d = (gl + 16 * t == k - 1) ? (T)1 : (T)0;
+          nki = fma(d, cw, nki);
+          n1r = fma(-d, sw_i, n1r);
+          n1i = fma(d, sw_r, n1i);
+        }
+        st.cr[t] = n1r;
+        st.ci[t] = n1i;
+        nkr *= rinv;
+        nki *= rinv;
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          st.br[t][j] = fma(-nkr, pbr[j], st.br[t][j]);
+          st.br[t][j] = fma(nki, pbi[j], st.br[t][j]);
+          st.bi[t][j] = fma(-nkr, pbi[j], st.bi[t][j]);
+          st.bi[t][j] = fma(-nki, pbr[j], st.bi[t][j]);
+        }
+      }
+    };
+    rot(SP);
+    publish(SP, (k - 1) & 15);
+    // the other slices (for jl = 0, slice s holds no row below k)
+    static_for<0, sp>([&](auto TT) { rot(TT); });
+    if (gl == jl) {
+      st.rc[s] = c;
+      st.rsr[s] = sr;
+      st.rsi[s] = si;
+      st.rinv[s] = rinv;
+    }
+    read_rhs();
+#pragma unroll
+    for (int t = 0; t <= s; ++t) hc[t] = hn[t];
+    sub0 = sub1;
+    sub1 = sub2;
+  };
+
   static_for<0, R>([&](auto sc) {
     constexpr int s = R - 1 - decltype(sc)::value;
     if (16 * s > n - 1) return;  // no pivot row in this slice (uniform)
     const int jhi = (n - 1 - 16 * s < 15) ? n - 1 - 16 * s : 15;
-    const int jlo = (s == 0) ? 1 : 0;
-    for (int jl = jhi; jl >= jlo; --jl) {
-      const int k = 16 * s + jl;
-      // the pivot row publishes its carry entry and right-hand side
-      if (gl == jl) {
-        mine[0] = st.cr[s];
-        mine[1] = st.ci[s];
-#pragma unroll
-        for (int j = 0; j < MM; ++j) {
-          mine[2 + 2 * j] = st.br[s][j];
-          mine[3 + 2 * j] = st.bi[s][j];
-        }
-      }
-      // prefetch column k-2 (rows 0..k-1) and the subdiagonal two steps
-      // ahead.  The loads of the pivot slice run past row k-1 into the next
-      // packed column (at most 15 entries, which the packed array and its LDS
-      // copy hold); those rows are never used.
-      T hn[R];
-      if (k >= 2) {
-        const int off = hoff32(k - 2) + gl;
-#pragma unroll
-        for (int t = 0; t <= s; ++t) hn[t] = H[off + 16 * t];
-      } else {
-#pragma unroll
-        for (int t = 0; t <= s; ++t) hn[t] = (T)0;
-      }
-      const T sub2 = (k >= 3) ? H.uniform(hoff32(k - 3) + k - 2) : (T)0;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const T ar = mine[0];
-      const T ai = mine[1];
-      T bkr[MM], bki[MM];
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        bkr[j] = mine[2 + 2 * j];
-        bki[j] = mine[3 + 2 * j];
-      }
-      const T beta = -sub0;
-      const T nrm2 = ar * ar + ai * ai + beta * beta;
-      const bool ok = nrm2 > (T)0;
-      const T rq = rsqrt_t(ok ? nrm2 : (T)1);
-      // zero column (ok false, then ar = ai = beta = 0): a zero rotation and
-      // R(k,k) = 0; the frequency is flagged singular
-      const T rinv = ok ? rq : (T)INFINITY;
-      const T c = beta * rq;
-      const T sr = ar * rq;
-      const T si = ai * rq;
-      st.singular = st.singular || !ok;
-      const T cw = c * w, sw_r = sr * w, sw_i = si * w;
-#pragma unroll
-      for (int t = 0; t <= s; ++t) {
-        const int i = gl + 16 * t;
-        if (t < s || gl < jl) {
-          const T cr_ = st.cr[t], ci_ = st.ci[t];
-          const T o = -hc[t];
-          T nkr = c * o + sr * cr_ + si * ci_;
-          T nki = sr * ci_ - si * cr_;
-          T n1r = sr * o - c * cr_;
-          T n1i = si * o - c * ci_;
-          // the diagonal entry of column k-1 also holds j w; row k-1 lies in
-          // slice s or s-1, so the other slices skip this at compile time
-          if (t + 1 >= s) {
-            const T d = (i == k - 1) ? (T)1 : (T)0;
-            nki = fma(d, cw, nki);
-            n1r = fma(-d, sw_i, n1r);
-            n1i = fma(d, sw_r, n1i);
-          }
-          st.cr[t] = n1r;
-          st.ci[t] = n1i;
-          nkr *= rinv;
-          nki *= rinv;
-#pragma unroll
-          for (int j = 0; j < MM; ++j) {
-            st.br[t][j] = fma(-nkr, bkr[j], st.br[t][j]);
-            st.br[t][j] = fma(nki, bki[j], st.br[t][j]);
-            st.bi[t][j] = fma(-nkr, bki[j], st.bi[t][j]);
-            st.bi[t][j] = fma(-nki, bkr[j], st.bi[t][j]);
-          }
-        }
-      }
-      if (gl == jl) {
-        st.rc[s] = c;
-        st.rsr[s] = sr;
-        st.rsi[s] = si;
-        st.rinv[s] = rinv;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int t = 0; t <= s; ++t) hc[t] = hn[t];
-      sub0 = sub1;
-      sub1 = sub2;
-    }
+    using SC = std::integral_constant<int, s>;
+    for (int jl = jhi; jl >= 1; --jl) step(SC{}, SC{}, jl);
+    if constexpr (s >= 1) step(SC{}, std::integral_constant<int, s - 1>{}, 0);
   });
   // y_k = b_k / R(k,k); R(0,0) is the final carry entry of row 0
   const T ar = dpp<dpp_row_newbcast(0)>(st.cr[0]);
