@@ -35,6 +35,7 @@
 #include <sys/prctl.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -74,6 +75,9 @@ constexpr int kDefaultBatchTiles = 16384;
 constexpr size_t kDefaultStaging = size_t(256) << 20;
 // A waiting poll() runs scheduling passes itself for up to this long.
 constexpr int64_t kPollSpinUs = 2000;
+// The scheduler thread backs off while a caller's thread has run a
+// scheduling pass within this window.
+constexpr double kClientActiveUs = 200.0;
 // Tiles (wavefronts) one request should offer before its columns are split:
 // 256 CUs x 4 SIMDs x 4 resident waves.
 constexpr int64_t kTargetTiles = 4096;
@@ -243,6 +247,7 @@ struct lti_ctx {
   int max_inflight = kInflight;  // sweep batches outstanding
   hipStream_t rstream = nullptr;             // the current pass's stream
   PassEvent* last_pass[kAdmitStreams] = {};  // the last pass on each
+  std::atomic<double> client_pump_us{-1e30};  // when a caller's thread last ran a pass
   PassEvent* pass = nullptr;                 // the current pass's event
   std::vector<PassEvent*> pass_events;       // all live ones
   bool own_stream = false;
@@ -589,7 +594,9 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
 
 void admit(lti_ctx* c) {
   if (c->pending.empty()) return;
-  // an idle admission stream, or wait for one
+  // an idle admission stream, or wait for one (requests that arrive
+  // meanwhile join the next pass; queueing a pass behind a running one split
+  // the passes and measured slower)
   int rs = -1;
   for (int i = 0; i < c->n_rstreams && rs < 0; ++i) {
     const int cand = (c->next_rstream + i) % c->n_rstreams;
@@ -966,9 +973,13 @@ void scheduler(lti_ctx* c) {
     }
     if (busy(c)) {
       // device work outstanding: poll its events, spinning (yield) for the
-      // first 200 us so that short requests complete without sleep latency
+      // first 200 us so that short requests complete without sleep latency;
+      // while a caller's thread runs the passes itself (submit, poll), step
+      // back so as not to contend with it for the lock
       lk.unlock();
-      if (Clock::now() - idle_since < std::chrono::microseconds(200))
+      if (c->now_us() - c->client_pump_us.load(std::memory_order_relaxed) < kClientActiveUs)
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      else if (Clock::now() - idle_since < std::chrono::microseconds(200))
         std::this_thread::yield();
       else
         std::this_thread::sleep_for(std::chrono::microseconds(10));
@@ -1160,7 +1171,9 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
   if (!r) return LTI_ENOMEM;
   r->req = *q;
   if (q->rtol <= 0.0) r->req.rtol = 1e-10;
-  {
+  if (q->mem == LTI_MEM_HOST) {
+    // checked before staging (the pinned pool is not taken for a request
+    // that can never run); device requests check under the lock below
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->device_error) return LTI_EDEVICE;
     const Need nd = request_need(r->req, true);
@@ -1178,6 +1191,10 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
     release_stage(c, r->hs);
     return LTI_EDEVICE;
   }
+  if (q->mem == LTI_MEM_DEVICE) {
+    const Need nd = request_need(r->req, true);
+    if (!c->arena.can_ever_fit(nd.block() + nd.model)) return LTI_ENOSPC;
+  }
   if ((int)c->all.size() >= c->max_pending) {
     release_stage(c, r->hs);
     return LTI_EAGAIN;
@@ -1193,6 +1210,7 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
     // start it from this thread when it can start now
     DeviceScope ds(c->device);
     pump(c);
+    c->client_pump_us.store(c->now_us(), std::memory_order_relaxed);
   }
   c->cv_work.notify_one();
   return LTI_OK;
@@ -1215,7 +1233,9 @@ int lti_freqresp_poll(lti_ctx* c, uint64_t id, int32_t timeout_us, lti_result* o
     {
       DeviceScope ds(c->device);
       while (!finished() && !c->device_error && Clock::now() - t_start < limit) {
-        if (pump(c)) continue;
+        const bool progressed = pump(c);
+        c->client_pump_us.store(c->now_us(), std::memory_order_relaxed);
+        if (progressed) continue;
         lk.unlock();
         std::this_thread::yield();
         lk.lock();
