@@ -152,13 +152,13 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
       for (int b = kb; b < S; ++b) xc[b] = xcol[tc + 16 * b];
       const double ss = (ssw[0] + ssw[1]) + (ssw[2] + ssw[3]);
       const double alpha = xcol[k + 1];
-      double tau = 0.0, scale = 0.0;
-      if (ss != 0.0) {
-        const double nrm = sqrt(fma(alpha, alpha, ss));
-        const double beta = (alpha >= 0.0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
+      // branch-free, so that the read of alpha joins the loads above; a
+      // column already reduced (ss = 0) takes tau = 0 (P = I)
+      const double nrm = sqrt(fma(alpha, alpha, ss));
+      const double beta = (alpha >= 0.0) ? -nrm : nrm;
+      const bool live = ss != 0.0;
+      const double tau = live ? (beta - alpha) / beta : 0.0;
+      const double scale = live ? 1.0 / (alpha - beta) : 0.0;
       // v: 1 on row k+1 (slot block kb or kb+1), the scaled column below it
       double vr[S], vc[S];
 #pragma unroll
