@@ -1047,10 +1047,16 @@ int stage_inputs(lti_ctx* c, Request* r) {
   else
     std::memset(hs.base + hs.offD, 0, sizeof(double) * p * m);
   std::memcpy(hs.base + hs.offW, q.omega, sizeof(double) * q.n_omega);
+  // the model's identity: its dimensions and the bytes of A, B, C, D (not
+  // the alignment gaps between them in staging, which hold whatever the
+  // pool held before)
   uint64_t h = 1469598103934665603ull;
   const int dims[3] = {n, m, p};
   h = fnv1a(dims, sizeof(dims), h);
-  h = fnv1a(hs.base + hs.offA, hs.offW - hs.offA, h);
+  h = fnv1a(hs.base + hs.offA, sizeof(double) * n * n, h);
+  h = fnv1a(hs.base + hs.offB, sizeof(double) * n * m, h);
+  h = fnv1a(hs.base + hs.offC, sizeof(double) * p * n, h);
+  h = fnv1a(hs.base + hs.offD, sizeof(double) * p * m, h);
   r->hash = h;
   return LTI_OK;
 }

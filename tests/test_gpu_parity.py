@@ -198,6 +198,28 @@ def test_repeat_query_reuses_reduction(eng):
     assert oracle.rel_err(h3.G, ref).max() <= TOL_REFINED
 
 
+def test_repeats_and_new_models_in_flight_together(eng):
+    """Repeat queries of one model, submitted while its first query (and the
+    reductions of new models between them) are still in flight, wait for that
+    reduction and all match the oracle."""
+    base = wl.mimo64(K=300)
+    others = wl.serving_requests(6, start=80)
+    p64 = _prec("fp64")
+    hs = [eng.submit(base.A, base.B, base.C, base.D, base.omega, precision=p64, model_key=501)]
+    reqs = [base]
+    for i, r in enumerate(others):
+        hs.append(eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=p64, model_key=600 + i))
+        hs.append(eng.submit(base.A, base.B, base.C, base.D, base.omega, precision=p64, model_key=501))
+        reqs += [r, base]
+    for h in hs:
+        assert eng.poll(h, -1)
+    sub = slice(None, None, 7)
+    for r, h in zip(reqs, hs):
+        ref = oracle.freqresp(r.A, r.B, r.C, r.D, r.omega[sub])
+        assert oracle.rel_err(h.G[sub], ref).max() <= TOL_FP64, (r.n, r.m, r.p, r.K)
+    assert sum(h.result["reduction_reused"] for h in hs[2::2]) == len(others)
+
+
 def _mix_vs_alone(eng, reqs):
     alone = [_run(eng, r, _prec("refined")).G for r in reqs]
     handles = [eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=_prec("refined")) for r in reqs]
