@@ -215,9 +215,18 @@ struct TimedPair {
   hipEvent_t a, b;
 };
 
+// FNV-1a over 64-bit words (the arrays hashed here are doubles), then any
+// remaining bytes.
 uint64_t fnv1a(const void* data, size_t bytes, uint64_t h) {
   const unsigned char* p = static_cast<const unsigned char*>(data);
-  for (size_t i = 0; i < bytes; ++i) {
+  size_t i = 0;
+  for (; i + 8 <= bytes; i += 8) {
+    uint64_t w;
+    std::memcpy(&w, p + i, 8);
+    h ^= w;
+    h *= 1099511628211ull;
+  }
+  for (; i < bytes; ++i) {
     h ^= p[i];
     h *= 1099511628211ull;
   }
@@ -1049,7 +1058,9 @@ int stage_inputs(lti_ctx* c, Request* r) {
   std::memcpy(hs.base + hs.offW, q.omega, sizeof(double) * q.n_omega);
   // the model's identity: its dimensions and the bytes of A, B, C, D (not
   // the alignment gaps between them in staging, which hold whatever the
-  // pool held before)
+  // pool held before); only keyed requests are ever matched
+  r->hash = 0;
+  if (q.model_key == 0) return LTI_OK;
   uint64_t h = 1469598103934665603ull;
   const int dims[3] = {n, m, p};
   h = fnv1a(dims, sizeof(dims), h);
