@@ -428,7 +428,12 @@ __device__ void solve_wg_fp64(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG
 }
 
 template <int MM>
-__global__ __launch_bounds__(kThreadsWG) void sweep_wg_kernel(const SweepLaunch L) {
+// At most 256 registers per lane, so that two workgroups share a CU (the
+// step loop is latency-bound: one barrier and one LDS round trip per step);
+// the four-column kernel then keeps a few values of its set-up and output
+// phases in scratch memory, none in the step loop.
+__global__ __launch_bounds__(kThreadsWG) __attribute__((amdgpu_waves_per_eu(2))) void sweep_wg_kernel(
+    const SweepLaunch L) {
   __shared__ ShWG sh;
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
   if (tile >= L.ntiles) return;
