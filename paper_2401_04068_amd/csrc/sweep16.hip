@@ -697,7 +697,12 @@ __device__ __forceinline__ void run_tile16(const ReqDesc& rd, const Tile& td, Sr
 // in LDS when the workgroup's four tiles belong to one request, which they do
 // except where two requests meet in a launch.
 template <int PREC, int R, int MM>
-__global__ __launch_bounds__(64 * kWaves16) void sweep16_kernel(const SweepLaunch L) {
+// At most 168 registers per lane (three wavefronts per SIMD): a launch that
+// carries several requests has more wavefronts than two per SIMD; the
+// four-column kernel then keeps a few values of its set-up, slice change and
+// output phases in scratch memory, none in the step loops.
+__global__ __launch_bounds__(64 * kWaves16) __attribute__((amdgpu_waves_per_eu(3))) void sweep16_kernel(
+    const SweepLaunch L) {
   __shared__ double bcast_all[kWaves16][4 * (2 + 2 * MM)];
   __shared__ double sH[hlen_max(R)];
   __shared__ float sH32[PREC == LTI_PREC_FP64 ? 1 : hlen_max(R)];
