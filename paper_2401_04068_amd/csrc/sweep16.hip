@@ -696,13 +696,17 @@ __device__ __forceinline__ void run_tile16(const ReqDesc& rd, const Tile& td, Sr
 // The reduced model's H (and its float32 copy on the refined path) is staged
 // in LDS when the workgroup's four tiles belong to one request, which they do
 // except where two requests meet in a launch.
+//
+// The float64 kernels use at most 168 registers per lane (three wavefronts
+// per SIMD, and room for a reduction workgroup beside two sweep wavefronts):
+// a launch that carries several requests has more wavefronts than two per
+// SIMD.  The four-column kernel then keeps a few values of its set-up, slice
+// change and output phases in scratch memory, none in the step loops.  The
+// refined kernels keep their full register sets (capped the same way, they
+// would spill up to 740 bytes per lane).
 template <int PREC, int R, int MM>
-// At most 168 registers per lane (three wavefronts per SIMD): a launch that
-// carries several requests has more wavefronts than two per SIMD; the
-// four-column kernel then keeps a few values of its set-up, slice change and
-// output phases in scratch memory, none in the step loops.
-__global__ __launch_bounds__(64 * kWaves16) __attribute__((amdgpu_waves_per_eu(3))) void sweep16_kernel(
-    const SweepLaunch L) {
+__global__ __launch_bounds__(64 * kWaves16)
+__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? 3 : 1))) void sweep16_kernel(const SweepLaunch L) {
   __shared__ double bcast_all[kWaves16][4 * (2 + 2 * MM)];
   __shared__ double sH[hlen_max(R)];
   __shared__ float sH32[PREC == LTI_PREC_FP64 ? 1 : hlen_max(R)];
