@@ -23,10 +23,13 @@
 //   of one 16-column slot block share straight-line code in which the block
 //   index is a compile-time constant, so the slots that v cannot reach are
 //   skipped without branches.
-// * Global kernel (128 < n <= 256): W in a global scratch area that stays
-//   hot in L2, three barriers per reflector (build v, left update, right
-//   update), a group of G adjacent lanes per column or row with DPP group
-//   sums.  Larger models take the blocked reduction (reduce_blocked.hip).
+// * Global kernel (128 < n <= 256): W (column-major) in a global scratch
+//   area that stays hot in L2, three barriers per reflector (build v, left
+//   update, right update).  The left update gives each column a group of G
+//   adjacent lanes (DPP group sums); the right update gives a wavefront 16
+//   consecutive rows and four interleaved quarters of the columns, so that
+//   both walk down columns.  Larger models take the blocked reduction
+//   (reduce_blocked.hip).
 #include <algorithm>
 #include <type_traits>
 
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
 // Global kernel
 
 constexpr int kGlobalThreads = 1024;
-constexpr int kGlobalGroup = 8;
+constexpr int kGlobalGroup = 16;
 
 __host__ __device__ inline int ld_of(int n, int p) { return (n + p) | 1; }
 
@@ -355,20 +358,39 @@ __global__ __launch_bounds__(NT) void hess_global_kernel(const ReduceLaunch L) {
     for (int c = k + 1 + group; c < ncol; c += kGroups) {
       double* col = W + (size_t)ldw * c;
       double s = 0.0;
+      // unrolled: several L2 loads in flight per lane instead of one
+#pragma unroll 8
       for (int i = k + 1 + lg; i < n; i += G) s = fma(v[i], col[i], s);
       s = group_sum_dpp<G>(s) * tau;
+#pragma unroll 8
       for (int i = k + 1 + lg; i < n; i += G) col[i] = fma(-v[i], s, col[i]);
     }
     __syncthreads();
 
-    // right: rows 0..n+p-1 (A and C), columns k+1..n-1
-    for (int r = group; r < nrow; r += kGroups) {
-      double s = 0.0;
-      for (int c = k + 1 + lg; c < n; c += G) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
-      s = group_sum_dpp<G>(s) * tau;
-      for (int c = k + 1 + lg; c < n; c += G) {
-        double* x = W + (size_t)r + (size_t)ldw * c;
-        *x = fma(-s, v[c], *x);
+    // right: rows 0..n+p-1 (A and C), columns k+1..n-1.  A wavefront covers
+    // 16 consecutive rows (lane % 16) and four interleaved quarters of the
+    // columns (lane / 16), so that each load reads 16 consecutive entries of
+    // a column (W is column-major); the four partial sums of a row meet
+    // through two lane exchanges.
+    {
+      const int lane = tid & 63, wv = tid >> 6;
+      const int lr = lane & 15, q = lane >> 4;
+      for (int r0 = 16 * wv; r0 < nrow; r0 += NT / 4) {
+        const int r = r0 + lr;
+        const bool live = r < nrow;
+        double s = 0.0;
+        if (live) {
+#pragma unroll 8
+          for (int c = k + 1 + q; c < n; c += 4) s = fma(W[(size_t)r + (size_t)ldw * c], v[c], s);
+        }
+        s = xor32_sum(xor16_sum(s)) * tau;
+        if (live) {
+#pragma unroll 8
+          for (int c = k + 1 + q; c < n; c += 4) {
+            double* x = W + (size_t)r + (size_t)ldw * c;
+            *x = fma(-s, v[c], *x);
+          }
+        }
       }
     }
     __syncthreads();
