@@ -696,7 +696,9 @@ void launch(lti_ctx* c) {
     if (!pe || !pe->ev) return true;
     for (const auto& sd : seen)
       if (sd.first == pe) return sd.second;
-    const bool done = hipEventQuery(pe->ev) != hipErrorNotReady;
+    // an event in error counts as not done: the launch then waits on it and
+    // the wait reports the error
+    const bool done = hipEventQuery(pe->ev) == hipSuccess;
     seen.emplace_back(pe, done);
     return done;
   };
