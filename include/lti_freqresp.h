@@ -20,8 +20,15 @@
  * rotation per subdiagonal entry) fused with column back-substitution.
  * Two precisions exist: plain float64, and complex-float32 solves with
  * float64 residual-based iterative refinement (Higham, *Accuracy and
- * Stability of Numerical Algorithms*, 2nd ed., ch. 12) whose stalled points
- * fall back to float64.
+ * Stability of Numerical Algorithms*, 2nd ed., ch. 12).  Points whose
+ * refinement stalls, and float64 points whose estimated error exceeds the
+ * request's tolerance, are refined once more with the residual of the
+ * original (A, B) in double-double arithmetic (Higham, sec. 12.1), since
+ * near an eigenvalue the rounding of the reduction itself dominates.
+ * With fewer outputs than inputs the transposed system (A^T, C^T, B^T, D^T)
+ * is solved (G^T = B^T (s I - A^T)^{-1} C^T + D^T), so every solve has
+ * min(nu, ny) right-hand sides.  The same solves evaluate G at any complex
+ * point s (request.points), including the discrete-time z = exp(j theta).
  *
  * Serving model: a context owns a scheduler thread.  submit() copies a
  * request's host inputs and returns at once; the scheduler admits requests
@@ -48,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LTI_ABI_VERSION 1u
+#define LTI_ABI_VERSION 2u
 
 /* ---------------------------------------------------------------- codes */
 #define LTI_OK            0
@@ -74,9 +81,20 @@ extern "C" {
 #define LTI_PATH_REFINED   1  /* float32 solves, float64 refinement converged  */
 #define LTI_PATH_FALLBACK  2  /* refinement stalled; float64 solve used        */
 #define LTI_PATH_SINGULAR  3  /* j w I - A singular to working precision       */
+#define LTI_PATH_FP64_DD   4  /* float64 solve, then double-double residual
+                                 refinement against A (estimated error > rtol) */
+
+/* request.points: what omega holds */
+#define LTI_POINTS_JW     0   /* real frequencies w_k in rad/s: s_k = j w_k            */
+#define LTI_POINTS_S      1   /* complex points: omega[2k] + j omega[2k+1] = s_k       */
+#define LTI_POINTS_Z      2   /* discrete time: theta_k = w_k T in rad/sample,
+                                 z_k = exp(j theta_k); the solves use s_k = z_k     */
 
 /* config.flags */
 #define LTI_CFG_KERNEL_TIMING 1u  /* bracket every kernel launch with HIP events */
+#define LTI_CFG_FORCE_DD      2u  /* testing: every point takes the double-double
+                                     refinement (path FALLBACK / FP64_DD)        */
+#define LTI_CFG_NO_TRANSPOSE  4u  /* never solve the transposed system           */
 
 /* Per-frequency result information, 8 bytes. */
 typedef struct lti_point_info {
@@ -85,10 +103,15 @@ typedef struct lti_point_info {
   uint8_t path;         /* LTI_PATH_*                                        */
   uint16_t reserved;
 } lti_point_info;
-/* est_rel_err: for LTI_PATH_REFINED the last correction norm
- * ||dX||_F / ||X||_F; for LTI_PATH_FP64 / _FALLBACK the product of the
- * float64 unit roundoff and the ratio of the largest to the smallest
- * diagonal entry of the triangular factor (a lower bound on kappa). */
+/* est_rel_err: for LTI_PATH_REFINED the predicted error after the last
+ * correction, min(||dX|| / ||X||, (||dX|| / ||X||) * contraction); for
+ * LTI_PATH_FP64 the product of half the float64 unit roundoff and the ratio
+ * of the largest to the smallest diagonal entry of the triangular factor (a
+ * lower bound on kappa); for LTI_PATH_FALLBACK / _FP64_DD the last
+ * correction norm ||dx|| / ||x|| of the double-double refinement.
+ * iters: float32 solves (refined), plus float64 solves for _FALLBACK and
+ * _FP64_DD.  With the columns of one point split over several kernel tiles,
+ * the record is merged: the largest estimate and the worst path. */
 
 /* Create-time configuration. */
 typedef struct lti_config {
@@ -120,9 +143,12 @@ typedef struct lti_request {
   const double* omega;    /* n_omega frequencies in rad/s, any finite value      */
   int64_t  n_omega;       /* >= 1                                                */
   int32_t  precision;     /* LTI_PREC_*                                          */
-  int32_t  reserved0;     /* must be 0                                           */
-  double   rtol;          /* refined path: stop when ||dX||/||X|| <= rtol / 10;
-                             <= 0 selects 1e-10                                   */
+  int32_t  points;        /* LTI_POINTS_*: how omega is read (n_omega points;
+                             LTI_POINTS_S: 2 * n_omega doubles)                  */
+  double   rtol;          /* error target, <= 0 selects 1e-10.  Refined path:
+                             stop when the predicted ||dX||/||X|| <= rtol / 10.
+                             Float64 path: points whose estimated error exceeds
+                             rtol are refined against A in double-double      */
   uint64_t model_key;     /* 0: no reuse.  Otherwise the reduced model stays
                              resident and later requests with the same key,
                              dimensions and (host memory) content reuse it     */
@@ -141,7 +167,7 @@ typedef struct lti_result {
   int32_t status;           /* LTI_OK, or the error that ended the request   */
   int32_t reduction_reused; /* 1 when a resident reduced model was reused    */
   int64_t n_points;
-  int64_t n_refined, n_fallback, n_singular;
+  int64_t n_refined, n_fallback, n_singular, n_fp64_dd;  /* points per path  */
   double  max_est_rel_err;
   double  t_submit_us;      /* microseconds since the context was created    */
   double  t_admit_us;
@@ -175,8 +201,6 @@ int lti_freqresp_create(const lti_config* config, lti_ctx** out);
  * LTI_EINVAL: NULL pointers, dims <= 0, n_omega <= 0, unknown precision or
  *             mem, non-finite host input.
  * LTI_EUNSUPPORTED: nx > 1024, or nu or ny > 16, or n_omega * nu > 2^32 - 1.
- *             (Refined-precision requests with nx > 256 run the float64
- *             path; their points report LTI_PATH_FP64.)
  * LTI_ENOSPC: the request alone needs more than the whole arena.
  * LTI_EAGAIN: max_pending requests are outstanding.
  * LTI_EDEVICE: the context saw a HIP error.

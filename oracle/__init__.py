@@ -11,6 +11,10 @@ What it computes (all plain, slow and in float64 unless stated):
 * ``freqresp``           the definition G(jw) = C (jw I - A)^{-1} B + D, one
                          dense LU with partial pivoting per frequency
                          (LAPACK zgesv through numpy.linalg.solve);
+* ``freqresp_at``        the same definition at arbitrary complex points s
+                         (off the imaginary axis, or z = exp(j theta) for a
+                         discrete-time model); ``freqresp_at_extended`` with
+                         the extended-precision refinement;
 * ``freqresp_extended``  the same solve followed by iterative refinement whose
                          residual and iterate are held in extended precision
                          (x87 80-bit ``clongdouble``); the oracle of record for
@@ -28,12 +32,15 @@ Kailath, *Linear Systems*, 1980, ch. 2).  The paper this project follows is
 silent on this problem; every function here cites the textbook or published
 method it restates instead.
 """
-from .freqresp import freqresp, freqresp_extended, cond2, rel_err, rel_err_max
+from .freqresp import (freqresp, freqresp_extended, freqresp_at, freqresp_at_extended, cond2, rel_err,
+                       rel_err_max)
 from . import exact, hessenberg
 
 __all__ = [
     "freqresp",
     "freqresp_extended",
+    "freqresp_at",
+    "freqresp_at_extended",
     "cond2",
     "rel_err",
     "rel_err_max",

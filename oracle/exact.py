@@ -94,18 +94,21 @@ def _solve(M, Bcols):
     return [[aug[i][n + j] for j in range(m)] for i in range(n)]
 
 
-def freqresp_exact(A, B, C, D, w):
-    """Exact G(jw) = C (jw I - A)^{-1} B + D for rational inputs.
+def freqresp_exact(A, B, C, D, w, sigma=0):
+    """Exact G(s) = C (s I - A)^{-1} B + D for rational inputs at the point
+    s = sigma + j w (sigma = 0: the frequency response at w).
 
     A: n x n, B: n x m, C: p x n, D: p x m (nested sequences of ints,
     Fractions or floats -- floats are taken at their exact binary value),
-    w: rational.  Returns a p x m nested list of QJ.
+    w, sigma: rational.  Returns a p x m nested list of QJ.
     """
     n = len(A)
     m = len(B[0])
     p = len(C)
     w = Fraction(w)
-    M = [[QJ(-Fraction(A[i][k]), w if i == k else 0) for k in range(n)] for i in range(n)]
+    sigma = Fraction(sigma)
+    M = [[QJ(sigma - Fraction(A[i][k]) if i == k else -Fraction(A[i][k]), w if i == k else 0) for k in range(n)]
+         for i in range(n)]
     Bq = [[QJ(Fraction(B[i][j])) for j in range(m)] for i in range(n)]
     X = _solve(M, Bq)
     G = []

@@ -18,7 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["freqresp", "freqresp_extended", "cond2", "rel_err", "rel_err_max"]
+__all__ = ["freqresp", "freqresp_extended", "freqresp_at", "freqresp_at_extended", "cond2", "rel_err",
+           "rel_err_max"]
 
 
 def _check(A, B, C, D, omega):
@@ -89,6 +90,53 @@ def freqresp_extended(A, B, C, D, omega, iters: int = 3, return_longdouble: bool
             X = X + d.astype(ld)
         G = C_ld @ X + D_ld
         out[k] = G if return_longdouble else G.astype(np.complex128)
+    return out
+
+
+def freqresp_at(A, B, C, D, s, chunk: int = 256) -> np.ndarray:
+    """G(s_k) = C (s_k I - A)^{-1} B + D at arbitrary complex points s_k,
+    shape (K, p, m): the transfer matrix of the model off the imaginary axis
+    (continuous time, s = sigma + j w), or of a discrete-time model
+    x[t+1] = A x[t] + B u[t], y = C x + D u at z = s (z = exp(j theta) on the
+    unit circle gives its frequency response; any linear-systems text, e.g.
+    Kailath 1980, ch. 2).  One dense LU with partial pivoting per point."""
+    A, B, C, D, _ = _check(A, B, C, D, [0.0])
+    s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+    n = A.shape[0]
+    K = s.shape[0]
+    G = np.empty((K, C.shape[0], B.shape[1]), dtype=np.complex128)
+    eye = np.eye(n)
+    Bc = B.astype(np.complex128)
+    for k0 in range(0, K, chunk):
+        sk = s[k0:k0 + chunk]
+        M = sk[:, None, None] * eye[None, :, :] - A[None, :, :]
+        X = np.linalg.solve(M, np.broadcast_to(Bc, (len(sk),) + Bc.shape))
+        G[k0:k0 + chunk] = C[None, :, :] @ X + D[None, :, :]
+    return G
+
+
+def freqresp_at_extended(A, B, C, D, s, iters: int = 3) -> np.ndarray:
+    """``freqresp_at`` followed by the extended-precision refinement of
+    ``freqresp_extended`` (residual and iterate in x87 extended precision);
+    s_k is rounded to float64 real and imaginary parts first, and those are
+    the points evaluated exactly."""
+    A, B, C, D, _ = _check(A, B, C, D, [0.0])
+    s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+    n = A.shape[0]
+    ld = np.clongdouble
+    A_ld, B_ld, C_ld, D_ld = A.astype(ld), B.astype(ld), C.astype(ld), D.astype(ld)
+    eye = np.eye(n)
+    out = np.empty((len(s), C.shape[0], B.shape[1]), dtype=np.complex128)
+    for k, sk in enumerate(s):
+        M64 = sk * eye - A
+        s_ld = np.longdouble(sk.real) + 1j * np.longdouble(sk.imag)
+        M_ld = s_ld * np.eye(n, dtype=ld) - A_ld
+        X = np.linalg.solve(M64, B.astype(np.complex128)).astype(ld)
+        for _ in range(iters):
+            r = B_ld - M_ld @ X
+            d = np.linalg.solve(M64, r.astype(np.complex128))
+            X = X + d.astype(ld)
+        out[k] = (C_ld @ X + D_ld).astype(np.complex128)
     return out
 
 

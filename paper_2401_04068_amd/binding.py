@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblti_freqresp.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 LTI_OK = 0
 LTI_PENDING = 1
@@ -41,8 +41,15 @@ PATH_FP64 = 0
 PATH_REFINED = 1
 PATH_FALLBACK = 2
 PATH_SINGULAR = 3
+PATH_FP64_DD = 4
+
+POINTS_JW = 0
+POINTS_S = 1
+POINTS_Z = 2
 
 CFG_KERNEL_TIMING = 1
+CFG_FORCE_DD = 2
+CFG_NO_TRANSPOSE = 4
 
 POINT_INFO_DTYPE = np.dtype(
     [("est_rel_err", "<f4"), ("iters", "u1"), ("path", "u1"), ("reserved", "<u2")]
@@ -89,7 +96,7 @@ class LtiRequest(ctypes.Structure):
         ("omega", ctypes.c_void_p),
         ("n_omega", ctypes.c_int64),
         ("precision", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("points", ctypes.c_int32),
         ("rtol", ctypes.c_double),
         ("model_key", ctypes.c_uint64),
         ("G_out", ctypes.c_void_p),
@@ -105,6 +112,7 @@ class LtiResult(ctypes.Structure):
         ("n_refined", ctypes.c_int64),
         ("n_fallback", ctypes.c_int64),
         ("n_singular", ctypes.c_int64),
+        ("n_fp64_dd", ctypes.c_int64),
         ("max_est_rel_err", ctypes.c_double),
         ("t_submit_us", ctypes.c_double),
         ("t_admit_us", ctypes.c_double),
@@ -212,6 +220,7 @@ class Engine:
         max_batch_tiles: int = 0,
         max_pending: int = 0,
         host_staging_bytes: int = 0,
+        flags: int = 0,
     ):
         import torch
 
@@ -227,7 +236,7 @@ class Engine:
         cfg.arena_bytes = int(arena_bytes)
         cfg.stream = stream.cuda_stream if stream is not None else None
         cfg.max_pending = max_pending
-        cfg.flags = CFG_KERNEL_TIMING if kernel_timing else 0
+        cfg.flags = (CFG_KERNEL_TIMING if kernel_timing else 0) | int(flags)
         cfg.tile_points = tile_points
         cfg.max_batch_tiles = max_batch_tiles
         cfg.host_staging_bytes = host_staging_bytes
@@ -240,13 +249,20 @@ class Engine:
 
     # ------------------------------------------------------------ requests
     def submit(self, A, B, C, D, omega, precision: int = PREC_FP64, model_key: int = 0,
-               rtol: float = 0.0, want_info: bool = True) -> Handle:
-        """Host-memory request; inputs are copied before this returns."""
+               rtol: float = 0.0, want_info: bool = True, points: int = POINTS_JW) -> Handle:
+        """Host-memory request; inputs are copied before this returns.
+
+        points: POINTS_JW (omega real, s = j omega), POINTS_S (omega complex
+        points s), POINTS_Z (omega = theta in rad/sample, z = exp(j theta))."""
         A, B, C = _f64(A), _f64(B), _f64(C)
         n, m, p = A.shape[0], B.shape[1], C.shape[0]
         Dm = None if D is None else _f64(D)
-        w = _f64(omega).reshape(-1)
-        K = w.shape[0]
+        if points == POINTS_S:
+            w = np.ascontiguousarray(np.asarray(omega, dtype=np.complex128).reshape(-1)).view(np.float64)
+            K = w.shape[0] // 2
+        else:
+            w = _f64(omega).reshape(-1)
+            K = w.shape[0]
         G = np.empty((K, p, m), dtype=np.complex128)
         info = np.zeros(K, dtype=POINT_INFO_DTYPE) if want_info else None
         req = LtiRequest()
@@ -257,7 +273,7 @@ class Engine:
         req.omega = w.ctypes.data
         req.n_omega = K
         req.precision = int(precision)
-        req.reserved0 = 0
+        req.points = int(points)
         req.rtol = float(rtol)
         req.model_key = int(model_key)
         req.G_out = G.ctypes.data
@@ -269,7 +285,7 @@ class Engine:
         return Handle(rid.value, G, info, keep=[G, info])
 
     def submit_device(self, A, B, C, D, omega, G, info=None, precision: int = PREC_FP64,
-                      model_key: int = 0, rtol: float = 0.0) -> Handle:
+                      model_key: int = 0, rtol: float = 0.0, points: int = POINTS_JW) -> Handle:
         """Device-memory request: torch float64 tensors on this engine's device;
         G is a float64 tensor of 2*K*p*m entries (or complex128 (K, p, m)).
         Nothing is copied; the tensors must stay alive and unmodified until
@@ -285,9 +301,9 @@ class Engine:
         req.A, req.B, req.C = A.data_ptr(), B.data_ptr(), C.data_ptr()
         req.D = None if D is None else D.data_ptr()
         req.omega = omega.data_ptr()
-        req.n_omega = omega.numel()
+        req.n_omega = omega.numel() // (2 if points == POINTS_S else 1)
         req.precision = int(precision)
-        req.reserved0 = 0
+        req.points = int(points)
         req.rtol = float(rtol)
         req.model_key = int(model_key)
         req.G_out = G.data_ptr()

@@ -17,10 +17,22 @@ namespace lti {
 __host__ __device__ inline int64_t hoff(int j) { return (int64_t)j * (j + 3) / 2; }
 __host__ __device__ inline int64_t hlen(int n) { return (int64_t)(n - 1) * (n + 2) / 2 + n; }
 
+// Reflector storage of a reduction: reflector k (k = 0 .. n-3) is
+// P_k = I - tau_k v v^T with v = e_{k+1} + (entries k+2 .. n-1), and those
+// entries are kept at V[voff(n, k) + (i - k - 2)], so that Q = P_0 P_1 ...
+// P_{n-3} can be applied to vectors afterwards.
+__host__ __device__ inline int64_t voff(int n, int k) { return (int64_t)k * (n - 2) - (int64_t)k * (k - 1) / 2; }
+__host__ __device__ inline int64_t vlen(int n) { return n >= 3 ? (int64_t)(n - 2) * (n - 1) / 2 : 0; }
+
 // The resident reduced model of one state-space system, all in one arena
 // block.  H = Q^T A Q (packed), Bt = Q^T B (n x m row-major), Ct = (C Q)^T
 // (n x p row-major, so row i holds column i of C Q), D (p x m row-major),
-// plus float32 copies of H, Bt and Ct for the refined path.
+// plus float32 copies of H, Bt and Ct for the refined path.  The solved
+// system is (A, B, C, D) itself, or (A^T, C^T, B^T, D^T) when `trans` is set
+// (fewer outputs than inputs: G^T of the transposed system needs only
+// min(nu, ny) right-hand sides); n, m, p are the solved system's sizes.  A0,
+// B0, C0 hold that system as given (row-major, float64) and V, tau the
+// reflectors, for the extended-precision refinement of ill-conditioned points.
 struct ReducedModel {
   double* H;
   double* Bt;
@@ -29,15 +41,21 @@ struct ReducedModel {
   float* H32;
   float* Bt32;
   float* Ct32;
-  int n, m, p, pad;
+  double* A0;
+  double* B0;
+  double* C0;
+  double* V;
+  double* tau;
+  int n, m, p, trans;
 };
 
 size_t reduced_bytes(int n, int m, int p);
-void reduced_layout(void* base, int n, int m, int p, ReducedModel* out);
+void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* out);
 
-// One reduction job: read A, B, C, D (device pointers, row-major; D may be
-// null), write the reduced model.  `work` is a scratch area of
-// reduce_work_bytes(n, m, p) bytes (null for the register kernel).
+// One reduction job: read A, B, C, D (device pointers, row-major, the
+// request's own sizes; D may be null), write the reduced model (out.trans
+// says whether the transposed system is reduced).  `work` is a scratch area
+// of reduce_work_bytes(n, m, p) bytes (null for the register kernel).
 struct ReduceJob {
   const double* A;
   const double* B;
@@ -45,6 +63,27 @@ struct ReduceJob {
   const double* D;
   ReducedModel out;
   double* work;
+};
+
+// Entry (i, j) of the solved system's matrices, read from the request's
+// arrays (n, m, p: the solved system's sizes).
+struct ModelIn {
+  const double *A, *B, *C, *D;
+  int n, m, p, trans;
+  __host__ __device__ ModelIn(const ReduceJob& j)
+      : A(j.A), B(j.B), C(j.C), D(j.D), n(j.out.n), m(j.out.m), p(j.out.p), trans(j.out.trans) {}
+  __host__ __device__ double a(int i, int k) const {
+    return trans ? A[(size_t)k * n + i] : A[(size_t)i * n + k];
+  }
+  __host__ __device__ double b(int i, int c) const {
+    return trans ? C[(size_t)c * n + i] : B[(size_t)i * m + c];
+  }
+  __host__ __device__ double c(int r, int k) const {
+    return trans ? B[(size_t)k * p + r] : C[(size_t)r * n + k];
+  }
+  __host__ __device__ double d(int r, int c) const {
+    return !D ? 0.0 : trans ? D[(size_t)c * p + r] : D[(size_t)r * m + c];
+  }
 };
 
 constexpr int kMaxReduceN = 1024;
@@ -64,18 +103,49 @@ int reduce_class(int n, int m, int p);
 size_t reduce_work_bytes(int n, int m, int p);
 size_t reduce_blocked_work_bytes(int n, int m, int p);
 hipError_t launch_reduce_blocked(const ReduceJob& job, hipStream_t s);
-// Up to kMaxInlineJobs reduction jobs of one class, passed to the kernel by
-// value; one workgroup per job.
-constexpr int kMaxInlineJobs = 24;
+// The reduction jobs of one class in one launch, one workgroup per job (the
+// blocked class runs its jobs one after another): `jobs` is a table in device
+// memory, uploaded with the pass that queued them.  `host_jobs` is the same
+// table in host memory (the blocked class reads its jobs from there).
 struct ReduceLaunch {
+  const ReduceJob* jobs;
+  const ReduceJob* host_jobs;
   int njobs;
-  ReduceJob job[kMaxInlineJobs];
 };
-static_assert(sizeof(ReduceLaunch) <= 3072, "reduction launch arguments must stay small");
 hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s);
+
+// Clear up to kMaxZero device ranges (32-bit words), one workgroup each: the
+// refinement queue counters and merged point records of newly admitted
+// requests.  A kernel, not hipMemsetAsync, so that a captured stream replays
+// it faithfully.
+constexpr int kMaxZero = 64;
+struct ZeroLaunch {
+  int n;
+  struct {
+    uint32_t* p;
+    uint32_t words;
+  } e[kMaxZero];
+};
+hipError_t launch_zero(const ZeroLaunch& Z, hipStream_t s);
 
 // Per-request descriptor, handed to the sweep kernels in their launch
 // arguments.
+//
+// Evaluation points (flags bits 8-9): kPointsJW, s_k = j omega[k];
+// kPointsS, s_k = omega[2k] + j omega[2k+1]; kPointsZ, the discrete-time
+// point z_k = exp(j omega[k] Ts).  Every kernel solves (s_k I - H) X = Q^T B.
+//
+// Points whose solve cannot be trusted in the kernel's own precision (a
+// refined point whose iteration stalled, a float64 point whose estimated
+// error exceeds rtol) are not written by the sweep: they are appended to the
+// request's queue `fbq` (fbq[0] = count, entry e at fbq[2 + 2e]: the point
+// index, then first column | columns << 8 | float32 solves << 16 | reason
+// << 24) and finished by the extended-precision refinement kernel.
+constexpr uint32_t kFlagTrans = 1u;      // G^T of the transposed system
+constexpr uint32_t kFlagMergeInfo = 2u;  // columns split over tiles: info merged with atomic max
+constexpr uint32_t kFlagForceDD = 4u;    // every point takes the extended refinement (testing)
+constexpr int kPointsJW = 0, kPointsS = 1, kPointsZ = 2;
+constexpr int kReasonFP64 = 0, kReasonStall = 1;
 struct ReqDesc {
   const double* H;
   const double* Bt;
@@ -87,9 +157,19 @@ struct ReqDesc {
   const double* omega;
   double* G;
   lti_point_info* info;
+  uint32_t* fbq;
   int n, m, p, precision;
   double rtol;
+  double Ts;
+  uint32_t flags;
+  uint32_t pad;
 };
+
+// Output index of G(a, j) (rows a < p, columns j < m of the solved system)
+// within one point's p x m block of the caller's [k][row][column] layout.
+__host__ __device__ inline int g_index(const ReqDesc& rd, int a, int j) {
+  return (rd.flags & kFlagTrans) ? j * rd.p + a : a * rd.m + j;
+}
 
 // A sweep launch covers tiles of up to kMaxSegs requests and is passed to the
 // kernel by value (kernel arguments: no copy, no descriptor in memory).
@@ -112,7 +192,7 @@ struct SweepLaunch {
   int ntiles;
   SweepSeg seg[kMaxSegs];
 };
-static_assert(sizeof(SweepLaunch) <= 2048, "sweep launch arguments must stay small");
+static_assert(sizeof(SweepLaunch) <= 3072, "sweep launch arguments must stay small");
 
 // Sweep kernel classes: precision x rows-per-lane (1, 2, 4 -> n <= 64, 128,
 // 256) x right-hand-side capacity (1, 2, 4, 8, 16).
@@ -130,12 +210,29 @@ constexpr int kNumSweep16Classes = 18;
 int sweep16_class(int precision, int n, int mc);
 hipError_t launch_sweep16(int cls, const SweepLaunch& L, hipStream_t s);
 
-// Workgroup-per-frequency kernels (sweepwg.hip): float64 path, 256 < n <= 1024,
-// at most 4 right-hand-side columns per tile; -1 when not covered.
+// Workgroup-per-frequency kernels (sweepwg.hip): both precisions,
+// 256 < n <= 1024, at most 4 right-hand-side columns per tile; -1 when not
+// covered.
 constexpr int kMaxNWG = 1024;
-constexpr int kNumSweepWGClasses = 3;
+constexpr int kNumSweepWGClasses = 6;
 int sweep_wg_class(int precision, int n, int mc);
 hipError_t launch_sweep_wg(int cls, const SweepLaunch& L, hipStream_t s);
+
+// Extended-precision refinement (sweepwg.hip) of the points the sweeps of a
+// request queued (ReqDesc.fbq), after all of the request's sweep tiles: one
+// workgroup per queued entry at a time, `grid` workgroups in all.
+constexpr int kMaxDDSegs = 12;
+struct DDSeg {
+  ReqDesc rd;
+  ReducedModel rm;
+  uint64_t K;  // points of the request (bounds the queue)
+};
+struct DDLaunch {
+  int nseg;
+  DDSeg seg[kMaxDDSegs];
+};
+static_assert(sizeof(DDLaunch) <= 3072, "refinement launch arguments must stay small");
+hipError_t launch_refine_dd(const DDLaunch& L, int grid, hipStream_t s);
 
 // LDS staging of one request's reduced model by a sweep workgroup: H, Bt and
 // Ct in float64, plus H and Bt in float32 for the refined path, each block

@@ -73,7 +73,9 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
   // a reduction is a chain of dependent steps that often shares its CU with
   // sweep wavefronts: let the SIMDs issue its instructions first
   __builtin_amdgcn_s_setprio(LTI_REDUCE_PRIO);
-  const ReduceJob job = L.job[blockIdx.x];
+  const ReduceJob job = L.jobs[blockIdx.x];
+  const ModelIn in(job);
+  const ReducedModel& o = job.out;
   const int n = job.out.n, m = job.out.m, p = job.out.p;
   const int nrow = n + p, ncol = n + m;
   const int lane = threadIdx.x & 63;
@@ -95,14 +97,19 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
 #pragma unroll
     for (int b = 0; b < S; ++b) {
       const int c = tc + 16 * b;
+      // the solved system, also kept as given for the extended refinement
       double x = 0.0;
       if (i < n) {
-        if (c < n)
-          x = job.A[(size_t)i * n + c];
-        else if (c < ncol)
-          x = job.B[(size_t)i * m + (c - n)];
+        if (c < n) {
+          x = in.a(i, c);
+          o.A0[(size_t)c * n + i] = x;
+        } else if (c < ncol) {
+          x = in.b(i, c - n);
+          o.B0[(size_t)(c - n) * n + i] = x;
+        }
       } else if (i < nrow && c < n) {
-        x = job.C[(size_t)(i - n) * n + c];
+        x = in.c(i - n, c);
+        o.C0[(size_t)(i - n) * n + c] = x;
       }
       W[a][b] = x;
     }
@@ -173,6 +180,16 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
       for (int b = kb; b < S; ++b) {
         vc[b] = xc[b] * scale;
         if (b <= kb + 1) vc[b] = (tc + 16 * b == k + 1) ? 1.0 : vc[b];
+      }
+      // keep the reflector (entries below row k+1, and tau)
+      if (tc == 0) {
+        const int64_t vo = voff(n, k) - (k + 2);
+#pragma unroll
+        for (int a = kb; a < S; ++a) {
+          const int i = tr + 16 * a;
+          if (i >= k + 2 && i < n) o.V[vo + i] = vr[a];
+        }
+        if (tr == 0) o.tau[k] = tau;
       }
       // partial W^T v over this thread's rows, partial W v over its columns
       double pp[S], qq[S];
@@ -253,7 +270,6 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
   });
 
   // write the reduced model
-  const ReducedModel& o = job.out;
 #pragma unroll
   for (int a = 0; a < S; ++a) {
     const int i = tr + 16 * a;
@@ -280,7 +296,7 @@ __global__ __launch_bounds__(kRegThreads) void hess_reg_kernel(const ReduceLaunc
       }
     }
   }
-  for (int idx = threadIdx.x; idx < p * m; idx += kRegThreads) o.D[idx] = job.D ? job.D[idx] : 0.0;
+  for (int idx = threadIdx.x; idx < p * m; idx += kRegThreads) o.D[idx] = in.d(idx / m, idx % m);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,7 +313,9 @@ template <int NT, int G>
 __global__ __launch_bounds__(NT) void hess_global_kernel(const ReduceLaunch L) {
   __shared__ double v[kMaxReduceN];
   __shared__ double sc[1];
-  const ReduceJob job = L.job[blockIdx.x];
+  const ReduceJob job = L.jobs[blockIdx.x];
+  const ModelIn in(job);
+  const ReducedModel& o = job.out;
   const int n = job.out.n, m = job.out.m, p = job.out.p;
   const int ldw = ld_of(n, p);
   const int ncol = n + m;
@@ -308,11 +326,19 @@ __global__ __launch_bounds__(NT) void hess_global_kernel(const ReduceLaunch L) {
   for (int idx = tid; idx < nrow * ncol; idx += NT) {
     const int i = idx % nrow;
     const int c = idx / nrow;
+    // the solved system, also kept as given for the extended refinement
     double x = 0.0;
     if (i < n) {
-      x = (c < n) ? job.A[(size_t)i * n + c] : job.B[(size_t)i * m + (c - n)];
+      if (c < n) {
+        x = in.a(i, c);
+        o.A0[(size_t)c * n + i] = x;
+      } else {
+        x = in.b(i, c - n);
+        o.B0[(size_t)(c - n) * n + i] = x;
+      }
     } else if (c < n) {
-      x = job.C[(size_t)(i - n) * n + c];
+      x = in.c(i - n, c);
+      o.C0[(size_t)(i - n) * n + c] = x;
     }
     W[(size_t)i + (size_t)ldw * c] = x;
   }
@@ -339,14 +365,18 @@ __global__ __launch_bounds__(NT) void hess_global_kernel(const ReduceLaunch L) {
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
+      const int64_t vo = voff(n, k) - (k + 2);
       for (int i = k + 2 + tid; i < n; i += 64) {
-        v[i] = colk[i] * scale;
+        const double vi = colk[i] * scale;
+        v[i] = vi;
+        o.V[vo + i] = vi;
         colk[i] = 0.0;
       }
       if (tid == 0) {
         v[k + 1] = 1.0;
         colk[k + 1] = beta;
         sc[0] = tau;
+        o.tau[k] = tau;
       }
     }
     __syncthreads();
@@ -396,7 +426,6 @@ __global__ __launch_bounds__(NT) void hess_global_kernel(const ReduceLaunch L) {
     __syncthreads();
   }
 
-  const ReducedModel& o = job.out;
   for (int j = 0; j < n; ++j) {
     const int len = (j + 2 < n) ? j + 2 : n;
     const int64_t off = hoff(j);
@@ -418,7 +447,13 @@ __global__ __launch_bounds__(NT) void hess_global_kernel(const ReduceLaunch L) {
     o.Ct[idx] = x;
     o.Ct32[idx] = (float)x;
   }
-  for (int idx = tid; idx < p * m; idx += NT) o.D[idx] = job.D ? job.D[idx] : 0.0;
+  for (int idx = tid; idx < p * m; idx += NT) o.D[idx] = in.d(idx / m, idx % m);
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(const ZeroLaunch Z) {
+  uint32_t* p = Z.e[blockIdx.x].p;
+  const uint32_t w = Z.e[blockIdx.x].words;
+  for (uint32_t i = threadIdx.x; i < w; i += 256) p[i] = 0u;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -448,34 +483,45 @@ size_t reduced_bytes(int n, int m, int p) {
   const size_t hl = (size_t)hlen(n);
   return align256(hl * 8) + align256((size_t)n * m * 8) + align256((size_t)n * p * 8) +
          align256((size_t)p * m * 8) + align256(hl * 4) + align256((size_t)n * m * 4) +
-         align256((size_t)n * p * 4);
+         align256((size_t)n * p * 4) + align256((size_t)n * n * 8) + align256((size_t)n * m * 8) +
+         align256((size_t)p * n * 8) + align256((size_t)vlen(n) * 8) + align256((size_t)n * 8);
 }
 
-void reduced_layout(void* base, int n, int m, int p, ReducedModel* o) {
+void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* o) {
   char* b = static_cast<char*>(base);
   const size_t hl = (size_t)hlen(n);
-  o->H = reinterpret_cast<double*>(b);
-  b += align256(hl * 8);
-  o->Bt = reinterpret_cast<double*>(b);
-  b += align256((size_t)n * m * 8);
-  o->Ct = reinterpret_cast<double*>(b);
-  b += align256((size_t)n * p * 8);
-  o->D = reinterpret_cast<double*>(b);
-  b += align256((size_t)p * m * 8);
-  o->H32 = reinterpret_cast<float*>(b);
-  b += align256(hl * 4);
-  o->Bt32 = reinterpret_cast<float*>(b);
-  b += align256((size_t)n * m * 4);
-  o->Ct32 = reinterpret_cast<float*>(b);
+  auto take = [&b](size_t bytes) {
+    char* x = b;
+    b += align256(bytes);
+    return x;
+  };
+  o->H = reinterpret_cast<double*>(take(hl * 8));
+  o->Bt = reinterpret_cast<double*>(take((size_t)n * m * 8));
+  o->Ct = reinterpret_cast<double*>(take((size_t)n * p * 8));
+  o->D = reinterpret_cast<double*>(take((size_t)p * m * 8));
+  o->H32 = reinterpret_cast<float*>(take(hl * 4));
+  o->Bt32 = reinterpret_cast<float*>(take((size_t)n * m * 4));
+  o->Ct32 = reinterpret_cast<float*>(take((size_t)n * p * 4));
+  o->A0 = reinterpret_cast<double*>(take((size_t)n * n * 8));
+  o->B0 = reinterpret_cast<double*>(take((size_t)n * m * 8));
+  o->C0 = reinterpret_cast<double*>(take((size_t)p * n * 8));
+  o->V = reinterpret_cast<double*>(take((size_t)vlen(n) * 8));
+  o->tau = reinterpret_cast<double*>(take((size_t)n * 8));
   o->n = n;
   o->m = m;
   o->p = p;
-  o->pad = 0;
+  o->trans = trans;
+}
+
+hipError_t launch_zero(const ZeroLaunch& Z, hipStream_t s) {
+  if (Z.n <= 0) return hipSuccess;
+  if (Z.n > kMaxZero) return hipErrorInvalidValue;
+  zero_kernel<<<Z.n, 256, 0, s>>>(Z);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s) {
   if (L.njobs <= 0) return hipSuccess;
-  if (L.njobs > kMaxInlineJobs) return hipErrorInvalidValue;
   switch (rclass) {
     case 0: return launch_reg<1>(L, s);
     case 1: return launch_reg<2>(L, s);
@@ -491,7 +537,7 @@ hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s) {
       return hipGetLastError();
     case kReduceBlocked:
       for (int i = 0; i < L.njobs; ++i) {
-        const hipError_t e = launch_reduce_blocked(L.job[i], s);
+        const hipError_t e = launch_reduce_blocked(L.host_jobs[i], s);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;

@@ -107,17 +107,28 @@ struct Blk {
 };
 
 // M = [[A, B], [C, 0]], padding rows zero.
+// The solved system is also kept as given (A0, B0, C0) for the extended
+// refinement.
 __global__ __launch_bounds__(256) void blk_load(const BlkArgs a) {
   const Blk b(a.job);
+  const ModelIn in(a.job);
+  const ReducedModel& o = a.job.out;
   const size_t total = (size_t)b.L.ldm * b.C;
   for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
     const int i = (int)(idx % b.L.ldm);
     const int c = (int)(idx / b.L.ldm);
     double x = 0.0;
     if (i < b.n) {
-      x = (c < b.n) ? a.job.A[(size_t)i * b.n + c] : a.job.B[(size_t)i * b.m + (c - b.n)];
+      if (c < b.n) {
+        x = in.a(i, c);
+        o.A0[(size_t)c * b.n + i] = x;
+      } else {
+        x = in.b(i, c - b.n);
+        o.B0[(size_t)(c - b.n) * b.n + i] = x;
+      }
     } else if (i < b.N && c < b.n) {
-      x = a.job.C[(size_t)(i - b.n) * b.n + c];
+      x = in.c(i - b.n, c);
+      o.C0[(size_t)(i - b.n) * b.n + c] = x;
     }
     b.M[idx] = x;
   }
@@ -202,9 +213,17 @@ __global__ __launch_bounds__(kPThreads) void blk_panel(const BlkArgs a) {
       x = bv[i];
     B.M[(size_t)c * ldm + i] = x;
   }
-  for (int i = k + 1 + tid; i < n; i += kPThreads)
-    B.V[(size_t)j * ldv + i] = (i <= c) ? 0.0 : (i == c + 1) ? 1.0 : bv[i] * scale;
-  if (tid == 0) B.tau[j] = tau;
+  // the panel's V, and every reflector kept in the reduced model
+  const int64_t vo = voff(n, c) - (c + 2);
+  for (int i = k + 1 + tid; i < n; i += kPThreads) {
+    const double vi = (i <= c) ? 0.0 : (i == c + 1) ? 1.0 : bv[i] * scale;
+    B.V[(size_t)j * ldv + i] = vi;
+    if (i >= c + 2) a.job.out.V[vo + i] = vi;
+  }
+  if (tid == 0) {
+    B.tau[j] = tau;
+    a.job.out.tau[c] = tau;
+  }
   __syncthreads();
   if (j > 0) {
     // w = V^T v_j over rows c+1 .. n-1
@@ -465,7 +484,8 @@ __global__ __launch_bounds__(256) void blk_store(const BlkArgs a) {
     o.Ct[idx] = x;
     o.Ct32[idx] = (float)x;
   }
-  for (size_t idx = t0; idx < (size_t)p * m; idx += gsz) o.D[idx] = a.job.D ? a.job.D[idx] : 0.0;
+  const ModelIn in(a.job);
+  for (size_t idx = t0; idx < (size_t)p * m; idx += gsz) o.D[idx] = in.d((int)(idx / m), (int)(idx % m));
 }
 
 }  // namespace

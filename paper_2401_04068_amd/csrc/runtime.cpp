@@ -2,14 +2,15 @@
 // models, admission by memory budget, and continuous batching of the
 // per-frequency solves of every live request into shared kernel launches.
 //
-// Device work is issued on two streams by a scheduling pass
-// (pump) that runs under the context lock: on the context's scheduler thread,
-// and inline on the caller's thread in submit() and in a waiting poll(), so a
-// lone request starts and completes without a thread hand-off.  A pass:
+// Device work is issued by a scheduling pass (pump) that runs under the
+// context lock: on the context's scheduler thread, and inline on the caller's
+// thread in submit() and in a waiting poll(), so a lone request starts and
+// completes without a thread hand-off.  A pass:
 //
 //   admit    pending requests in arrival order while their memory fits:
-//            upload inputs, reuse a resident reduced model or queue a
-//            reduction job (the jobs of one pass share a launch per kernel
+//            upload inputs, clear their refinement queues, reuse a resident
+//            reduced model or queue a reduction job (the jobs of one pass go
+//            to the device as one table and share a launch per kernel
 //            class).  Uploads and reductions go to an idle one of
 //            kAdmitStreams admission streams and end with an event that the
 //            requests of the pass (and the models it reduced) keep; a sweep
@@ -19,18 +20,19 @@
 //            reductions share launches and run side by side (one reduction
 //            occupies a single CU);
 //   launch   gather up to max_batch_tiles tiles from the live requests
-//            (oldest first), group them by kernel class and launch on the
-//            sweep stream; at most kInflight batches are outstanding, so
-//            requests that arrive meanwhile join the next batch;
+//            (oldest first), group them by kernel class and launch them on
+//            the sweep stream; a request whose last tiles are in the batch is
+//            finished in it: the extended refinement of its queued points,
+//            then the copy of its results to pinned host memory.  One batch
+//            is outstanding, so requests that arrive meanwhile join the next;
 //   retire   when a batch's event has fired, credit its tiles; a request
-//            whose tiles are all done gets its D2H copy and then becomes
-//            visible to poll().
+//            whose tiles are all done becomes visible to poll().
 //
 // Host inputs are copied at submit() into pinned staging owned by the
 // library, so every H2D and D2H copy is a true asynchronous DMA that never
-// stalls the scheduler behind queued kernels.  The descriptors the kernels
-// need (reduction jobs, per-request descriptors and tile ranges) travel in
-// the kernel arguments: nothing but the inputs and results is ever copied.
+// stalls the scheduler behind queued kernels.  The descriptors the sweep
+// kernels need (per-request descriptors and tile ranges) travel in the kernel
+// arguments; reduction jobs travel as one small table per pass.
 #include <hip/hip_runtime.h>
 #include <sys/prctl.h>
 
@@ -65,9 +67,10 @@ constexpr int kInflight = 1;
 // gets few hardware queues, four by default, and streams that share one run
 // in order).  With one admission stream, requests that arrive during a
 // reduction are admitted together afterwards, so their reductions and their
-// sweeps share launches; more streams (a tuning knob) measured slower.
+// sweeps share launches; a second admission stream (a tuning knob) measured
+// slower.  Every sweep goes to the one sweep stream, which orders a
+// request's refinement and result copy after all of its tiles.
 constexpr int kAdmitStreams = 2;
-constexpr int kSweepStreams = 2;
 // Reduction jobs queued by one admission pass (bounds one pass's work).
 constexpr int kMaxJobs = 1024;
 constexpr int kDefaultMaxPending = 8192;
@@ -144,8 +147,9 @@ class Arena {
   size_t used_ = 0, peak_ = 0;
 };
 
-// The end of one admission pass on its stream (uploads and reductions),
-// shared by the requests admitted in it and by the models it reduced.
+// The end of one admission pass on its stream (uploads, queue clearing and
+// reductions), shared by the requests admitted in it and by the models it
+// reduced.
 struct PassEvent {
   hipEvent_t ev = nullptr;
   hipStream_t stream = nullptr;  // where the pass was issued
@@ -156,7 +160,8 @@ struct Resident {
   PassEvent* ready = nullptr;  // pass that reduced it, until a user completed
   uint64_t key = 0;
   uint64_t hash = 0;
-  int n = 0, m = 0, p = 0;
+  int n = 0, m = 0, p = 0;     // the request's sizes
+  int trans = 0;
   void* block = nullptr;
   size_t bytes = 0;
   ReducedModel rm{};
@@ -164,16 +169,23 @@ struct Resident {
   uint64_t last_use = 0;
 };
 
-enum class RState { kPending, kLive, kFinishing, kDone, kFailed };
+enum class RState { kPending, kLive, kDone, kFailed };
 
-// Host-side staging of a host-memory request: A, B, C, D, omega and (at
-// completion) G and info, in one pinned block when the pool has room.
-struct HostStage {
+// Host memory of a request, from the pinned pool when it has room.
+struct HostBuf {
   char* base = nullptr;  // pinned block, or fallback.data()
   size_t bytes = 0;
   bool pinned = false;
   std::vector<char> fallback;
-  size_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0, offG = 0, offInfo = 0;
+};
+// Host-side staging of a request: `in` holds A, B, C, D and omega of a
+// host-memory request (copied at submit); `out` receives the results as the
+// device returns them, G and the point records (the records only, for
+// device-memory requests), and is taken at admission.
+struct HostStage {
+  HostBuf in, out;
+  size_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0;  // in `in`
+  size_t offG = 0, offInfo = 0;                              // in `out`
 };
 
 struct Request {
@@ -183,13 +195,16 @@ struct Request {
   int status = LTI_OK;
   uint64_t hash = 0;
   HostStage hs;
+  int trans = 0;          // the transposed system is solved (ny < nu)
+  int sm = 0, sp = 0;     // the solved system's inputs and outputs
   Resident* model = nullptr;
   bool reused = false;
   PassEvent* ready = nullptr;        // its own admission pass
   PassEvent* model_ready = nullptr;  // the pass that reduced a reused model
-  void* block = nullptr;  // device: A..D, omega, G, info, reduction scratch
+  void* block = nullptr;  // device: A..D, omega, G, info, queue, reduction scratch
   size_t block_bytes = 0;
-  size_t dOffG = 0;
+  size_t dOffG = 0;       // G (host requests; info follows at the staging offset)
+  lti_point_info* dinfo = nullptr;  // the point records on the device
   ReqDesc desc{};         // handed to the sweep kernels in their arguments
   int kclass = -1;
   int64_t K = 0;
@@ -199,12 +214,10 @@ struct Request {
   size_t stage = 0; // LDS bytes a sweep workgroup needs to stage the model
   int64_t ntiles = 0, next_tile = 0, tiles_done = 0;
   int waves_per_tile = 1;
-  hipEvent_t d2h_ev = nullptr;
   lti_result res{};
 };
 
 struct Batch {
-  hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   bool timed = false;
@@ -239,6 +252,11 @@ bool all_finite(const double* x, size_t n) {
   return true;
 }
 
+// Doubles a request's omega array holds.
+size_t omega_doubles(const lti_request& q) {
+  return (q.points == LTI_POINTS_S ? 2 : 1) * (size_t)q.n_omega;
+}
+
 }  // namespace
 }  // namespace lti
 
@@ -246,16 +264,18 @@ using namespace lti;
 
 struct lti_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;               // first sweep stream; result copies
-  hipStream_t sstreams[kSweepStreams] = {};  // sweeps ([0] = stream)
-  int next_sstream = 0;
-  int n_sstreams = 1;
+  hipStream_t stream = nullptr;              // sweeps, refinement, result copies
   hipStream_t rstreams[kAdmitStreams] = {};  // uploads and reductions
   int next_rstream = 0;
   int n_rstreams = 1;
   int max_inflight = kInflight;  // sweep batches outstanding
   hipStream_t rstream = nullptr;             // the current pass's stream
   PassEvent* last_pass[kAdmitStreams] = {};  // the last pass on each
+  // reduction job tables, one per admission stream (a pass claims the
+  // stream's table only when the stream's previous pass has completed)
+  ReduceJob* jobtab_host[kAdmitStreams] = {};
+  ReduceJob* jobtab_dev[kAdmitStreams] = {};
+  int pass_slot = 0;
   std::atomic<double> client_pump_us{-1e30};  // when a caller's thread last ran a pass
   PassEvent* pass = nullptr;                 // the current pass's event
   std::vector<PassEvent*> pass_events;       // all live ones
@@ -291,6 +311,7 @@ struct lti_ctx {
   std::deque<TimedPair> reduce_timing;
 
   char* staging_block = nullptr;  // the pinned allocation behind `staging`
+  char* jobtab_block = nullptr;   // the pinned allocation behind jobtab_host
   std::vector<hipEvent_t> event_pool, timing_pool;
 
   lti_stats stats{};
@@ -349,35 +370,62 @@ void fail_all(lti_ctx* c, int code) {
   c->cv_done.notify_all();
 }
 
+void release_buf(lti_ctx* c, HostBuf& hb) {
+  if (hb.pinned && hb.base) c->staging.release(hb.base, hb.bytes);
+  hb.base = nullptr;
+  hb.pinned = false;
+  hb.fallback.clear();
+  hb.fallback.shrink_to_fit();
+}
+
 void release_stage(lti_ctx* c, HostStage& hs) {
-  if (hs.pinned && hs.base) c->staging.release(hs.base, hs.bytes);
-  hs.base = nullptr;
-  hs.pinned = false;
-  hs.fallback.clear();
-  hs.fallback.shrink_to_fit();
+  release_buf(c, hs.in);
+  release_buf(c, hs.out);
+}
+
+// Take `bytes` of host memory: pinned when the pool has room; pageable only
+// when `may_page` (otherwise nullptr: wait for the pool).
+bool take_buf(lti_ctx* c, HostBuf& hb, size_t bytes, bool may_page) {
+  hb.bytes = bytes;
+  hb.base = static_cast<char*>(c->staging.alloc(bytes));
+  hb.pinned = hb.base != nullptr;
+  if (hb.pinned) return true;
+  if (!may_page) return false;
+  try {
+    hb.fallback.resize(bytes);
+  } catch (...) {
+    return false;
+  }
+  hb.base = hb.fallback.data();
+  return true;
 }
 
 // Device bytes of a request (besides a shared resident model); the block holds
-// [A..D | omega | G | info] (host-memory requests), then the reduction scratch.
+// [A..D | omega | G | info] (host-memory requests), its own point records
+// (device requests without info_out), the refinement queue, then the
+// reduction scratch.
 struct Need {
-  size_t omega = 0, G = 0, info = 0, inputs = 0, work = 0, model = 0;
-  size_t block() const { return omega + G + info + inputs + work; }
+  size_t omega = 0, G = 0, info = 0, queue = 0, inputs = 0, work = 0, model = 0;
+  size_t block() const { return omega + G + info + queue + inputs + work; }
 };
 
-Need request_need(const lti_request& q, bool needs_model) {
+// n, sm, sp: the solved system's sizes.
+Need request_need(const lti_request& q, bool needs_model, int sm, int sp) {
   const int n = q.nx, m = q.nu, p = q.ny;
   Need nd;
   if (q.mem == LTI_MEM_HOST) {
-    nd.omega = align_up(sizeof(double) * q.n_omega);
+    nd.omega = align_up(sizeof(double) * omega_doubles(q));
     nd.G = align_up(sizeof(double) * 2 * (size_t)q.n_omega * p * m);
-    nd.info = q.info_out ? align_up(sizeof(lti_point_info) * q.n_omega) : 0;
   }
+  if (q.mem == LTI_MEM_HOST || !q.info_out) nd.info = align_up(sizeof(lti_point_info) * q.n_omega);
+  // one queue entry per (point, column group) at most; sm groups at most
+  nd.queue = align_up(8 + 8 * (size_t)q.n_omega * sm);
   if (needs_model) {
     if (q.mem == LTI_MEM_HOST)  // same per-matrix alignment as the host staging
       nd.inputs = align_up(sizeof(double) * n * n) + align_up(sizeof(double) * n * m) +
                   align_up(sizeof(double) * p * n) + align_up(sizeof(double) * p * m);
-    nd.work = reduce_work_bytes(n, m, p);
-    nd.model = align_up(reduced_bytes(n, m, p));
+    nd.work = reduce_work_bytes(n, sm, sp);
+    nd.model = align_up(reduced_bytes(n, sm, sp));
   }
   return nd;
 }
@@ -387,7 +435,7 @@ Resident* find_resident(lti_ctx* c, const Request& r) {
   for (auto& up : c->residents) {
     Resident* res = up.get();
     if (res->key == r.req.model_key && res->n == r.req.nx && res->m == r.req.nu && res->p == r.req.ny &&
-        res->hash == r.hash)
+        res->hash == r.hash && res->trans == r.trans)
       return res;
   }
   return nullptr;
@@ -434,9 +482,10 @@ void release_request_memory(lti_ctx* c, Request* r) {
   }
 }
 
-// Try to admit one request.  Returns false when it has to wait for memory.
-struct JobLists {
+// Work collected by one admission pass.
+struct PassWork {
   std::vector<ReduceJob> jobs[kNumReduceClasses];
+  std::vector<std::pair<uint32_t*, uint32_t>> zero;  // device ranges to clear (words)
   bool copies = false;  // uploads were issued on the admission stream
   size_t total() const {
     size_t t = 0;
@@ -445,21 +494,34 @@ struct JobLists {
   }
 };
 
-bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
+bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   const lti_request& q = r->req;
-  const int n = q.nx, m = q.nu, p = q.ny;
+  const int n = q.nx, sm = r->sm, sp = r->sp;
   Resident* res = find_resident(c, *r);
   const bool needs_model = (res == nullptr);
-  if (needs_model && (int)jl.total() >= kMaxJobs) return false;
-  const Need nd = request_need(q, needs_model);
+  if (needs_model && (int)pw.total() >= kMaxJobs) return false;
+  const Need nd = request_need(q, needs_model, sm, sp);
+  // pinned host memory for the results (pageable only for results larger
+  // than the whole pool), then device memory; a request that does not fit
+  // waits
+  HostStage& hs = r->hs;
+  const size_t ibytes = sizeof(lti_point_info) * q.n_omega;
+  const size_t gbytes = q.mem == LTI_MEM_HOST ? sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu : 0;
+  hs.offG = 0;
+  hs.offInfo = align_up(gbytes);
+  if (!take_buf(c, hs.out, hs.offInfo + ibytes, align_up(hs.offInfo + ibytes) > c->staging.size())) return false;
   void* mblock = nullptr;
   if (needs_model) {
     mblock = alloc_evicting(c, nd.model);
-    if (!mblock) return false;
+    if (!mblock) {
+      release_buf(c, hs.out);
+      return false;
+    }
   }
   void* block = alloc_evicting(c, nd.block());
   if (!block) {
     if (mblock) c->arena.release(mblock, nd.model);
+    release_buf(c, hs.out);
     return false;
   }
   if (needs_model) {
@@ -468,11 +530,12 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
     res->key = q.model_key;
     res->hash = r->hash;
     res->n = n;
-    res->m = m;
-    res->p = p;
+    res->m = q.nu;
+    res->p = q.ny;
+    res->trans = r->trans;
     res->block = mblock;
     res->bytes = nd.model;
-    reduced_layout(mblock, n, m, p, &res->rm);
+    reduced_layout(mblock, n, sm, sp, r->trans, &res->rm);
     c->residents.push_back(std::move(up));
     c->stats.reductions++;
   } else {
@@ -482,15 +545,15 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   res->last_use = ++c->use_clock;
   r->model = res;
   r->reused = !needs_model;
-  // what the request's sweeps have to wait for
+  // what the request's sweeps have to wait for: its own pass (uploads, the
+  // cleared queue) and the pass that reduces its model
   if (needs_model) res->ready = pass_ref(c->pass);
-  if (needs_model || q.mem == LTI_MEM_HOST) r->ready = pass_ref(c->pass);
+  r->ready = pass_ref(c->pass);
   if (!needs_model) r->model_ready = pass_ref(res->ready);
   r->block = block;
   r->block_bytes = nd.block();
 
   char* b = static_cast<char*>(block);
-  HostStage& hs = r->hs;
   const bool host = q.mem == LTI_MEM_HOST;
   const double* d_omega = q.omega;
   double* d_G = q.G_out;
@@ -507,9 +570,9 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
     // A..D (when this request reduces its model) and omega sit back to back
     // in staging; the block mirrors that layout, so one H2D copy moves them
     const size_t src0 = needs_model ? hs.offA : hs.offW;
-    const size_t bytes = hs.offW - src0 + sizeof(double) * q.n_omega;
-    e = hipMemcpyAsync(b, hs.base + src0, bytes, hipMemcpyHostToDevice, c->rstream);
-    jl.copies = true;
+    const size_t bytes = hs.offW - src0 + sizeof(double) * omega_doubles(q);
+    e = hipMemcpyAsync(b, hs.in.base + src0, bytes, hipMemcpyHostToDevice, c->rstream);
+    pw.copies = true;
     if (needs_model) {
       job.A = reinterpret_cast<const double*>(b);
       job.B = reinterpret_cast<const double*>(b + (hs.offB - hs.offA));
@@ -522,14 +585,20 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
     r->dOffG = (size_t)(b - static_cast<char*>(block));
     d_G = reinterpret_cast<double*>(b);
     b += nd.G;
-    d_info = nd.info ? reinterpret_cast<lti_point_info*>(b) : nullptr;
+  }
+  if (nd.info) {
+    d_info = reinterpret_cast<lti_point_info*>(b);
     b += nd.info;
   }
+  r->dinfo = d_info;
+  uint32_t* fbq = reinterpret_cast<uint32_t*>(b);
+  b += nd.queue;
+  pw.zero.emplace_back(fbq, 1u);
   if (needs_model) {
     job.out = res->rm;
     job.work = nd.work ? reinterpret_cast<double*>(b) : nullptr;
     b += nd.work;
-    jl.jobs[reduce_class(n, m, p)].push_back(job);
+    pw.jobs[reduce_class(n, sm, sp)].push_back(job);
   }
   ReqDesc& desc = r->desc;
   desc = ReqDesc{};
@@ -543,11 +612,15 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   desc.omega = d_omega;
   desc.G = d_G;
   desc.info = d_info;
+  desc.fbq = fbq;
   desc.n = n;
-  desc.m = m;
-  desc.p = p;
+  desc.m = sm;
+  desc.p = sp;
   desc.precision = q.precision;
   desc.rtol = q.rtol;
+  desc.Ts = 0.0;
+  desc.flags = (r->trans ? kFlagTrans : 0u) | ((c->flags & LTI_CFG_FORCE_DD) ? kFlagForceDD : 0u) |
+               ((uint32_t)q.points << 8);
   if (e != hipSuccess) {
     fail_all(c, LTI_EDEVICE);
     return true;
@@ -555,10 +628,9 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   r->K = q.n_omega;
   // Kernel family: four frequencies per wavefront (n <= 64, at most four
   // right-hand-side columns per tile), one frequency per wavefront
-  // (n <= 256), or one frequency per workgroup (n <= 1024, float64; refined
-  // requests of that size run the float64 path and report it per point).
+  // (n <= 256), or one frequency per workgroup (n <= 1024).
   const bool wg = n > kMaxN;
-  const bool four = !wg && c->use_sweep16 && sweep16_class(q.precision, n, std::min(m, 4)) >= 0;
+  const bool four = !wg && c->use_sweep16 && sweep16_class(q.precision, n, std::min(sm, 4)) >= 0;
   int F = c->tile_points;
   if (F <= 0) F = four ? 4 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, r->K / 2048));
   if (four) F = (F + 3) & ~3;
@@ -571,12 +643,12 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
   const int64_t avail = std::max<int64_t>(0, target - c->outstanding_waves);
   int S = c->rhs_split;
   if (S <= 0) S = (fblocks >= avail) ? 1 : (int)((avail + fblocks - 1) / fblocks);
-  S = std::max(1, std::min(S, m));
-  if (four || wg) S = std::max(S, (m + 3) / 4);
-  r->mc = (m + S - 1) / S;
-  r->S = (m + r->mc - 1) / r->mc;
+  S = std::max(1, std::min(S, sm));
+  if (four || wg) S = std::max(S, (sm + 3) / 4);
+  r->mc = (sm + S - 1) / S;
+  r->S = (sm + r->mc - 1) / r->mc;
   if (wg)
-    r->kclass = kNumSweepClasses + kNumSweep16Classes + sweep_wg_class(LTI_PREC_FP64, n, r->mc);
+    r->kclass = kNumSweepClasses + kNumSweep16Classes + sweep_wg_class(q.precision, n, r->mc);
   else if (four)
     r->kclass = kNumSweepClasses + sweep16_class(q.precision, n, r->mc);
   else {
@@ -584,12 +656,17 @@ bool admit_one(lti_ctx* c, Request* r, JobLists& jl) {
     // split further until the column count fits
     while (sweep_class(q.precision, n, r->mc) < 0 && r->mc > 1) {
       ++S;
-      r->mc = (m + S - 1) / S;
-      r->S = (m + r->mc - 1) / r->mc;
+      r->mc = (sm + S - 1) / S;
+      r->S = (sm + r->mc - 1) / r->mc;
     }
     r->kclass = sweep_class(q.precision, n, r->mc);
   }
-  r->stage = (four || wg) ? 0 : stage_bytes(q.precision, n, m, p);
+  // several column groups per point: their records are merged (cleared first)
+  if (r->S > 1) {
+    desc.flags |= kFlagMergeInfo;
+    pw.zero.emplace_back(reinterpret_cast<uint32_t*>(d_info), (uint32_t)(2 * r->K));
+  }
+  r->stage = (four || wg) ? 0 : stage_bytes(q.precision, n, sm, sp);
   r->ntiles = fblocks * r->S;
   r->waves_per_tile = wg ? 4 : 1;
   c->outstanding_waves += r->ntiles * r->waves_per_tile;
@@ -616,10 +693,10 @@ void admit(lti_ctx* c) {
     }
   }
   if (rs < 0) return;
-  JobLists jl;
-  // with no sweeps outstanding the pass goes on the stream the next sweep
-  // batch will use, which orders the two without a cross-stream wait
-  c->rstream = c->inflight.empty() ? c->sstreams[c->next_sstream] : c->rstreams[rs];
+  PassWork pw;
+  // with no sweeps outstanding the pass goes on the sweep stream, which
+  // orders the two without a cross-stream wait
+  c->rstream = c->inflight.empty() ? c->stream : c->rstreams[rs];
   PassEvent* pe = new PassEvent{};
   pe->stream = c->rstream;
   pe->ev = get_event(c, false);
@@ -636,27 +713,46 @@ void admit(lti_ctx* c) {
   } drop{c, pe};
   while (!c->pending.empty() && !c->device_error) {
     Request* r = c->pending.front();
-    if (!admit_one(c, r, jl)) break;
+    if (!admit_one(c, r, pw)) break;
     c->pending.pop_front();
     if (r->state == RState::kLive) c->live.push_back(r);
   }
-  if (c->device_error || (jl.total() == 0 && !jl.copies)) return;
+  if (c->device_error || (pw.total() == 0 && !pw.copies && pw.zero.empty())) return;
   c->next_rstream = (rs + 1) % c->n_rstreams;
-  const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0 && jl.total() > 0;
-  TimedPair tp{nullptr, nullptr};
   hipError_t e = hipSuccess;
-  if (timed) {
+  // the cleared queues and records (before any kernel of these requests)
+  ZeroLaunch Z;
+  for (size_t i0 = 0; i0 < pw.zero.size() && e == hipSuccess; i0 += kMaxZero) {
+    Z.n = (int)std::min<size_t>(kMaxZero, pw.zero.size() - i0);
+    for (int i = 0; i < Z.n; ++i) {
+      Z.e[i].p = pw.zero[i0 + i].first;
+      Z.e[i].words = pw.zero[i0 + i].second;
+    }
+    e = launch_zero(Z, c->rstream);
+  }
+  const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0 && pw.total() > 0;
+  TimedPair tp{nullptr, nullptr};
+  if (timed && e == hipSuccess) {
     tp.a = get_event(c, true);
     tp.b = get_event(c, true);
     e = hipEventRecord(tp.a, c->rstream);
   }
-  // the jobs travel in the kernel arguments, kMaxInlineJobs per launch
-  ReduceLaunch L;
-  for (int rc = 0; rc < kNumReduceClasses && e == hipSuccess; ++rc) {
-    const std::vector<ReduceJob>& v = jl.jobs[rc];
-    for (size_t i0 = 0; i0 < v.size() && e == hipSuccess; i0 += kMaxInlineJobs) {
-      L.njobs = (int)std::min<size_t>(kMaxInlineJobs, v.size() - i0);
-      std::copy(v.begin() + i0, v.begin() + i0 + L.njobs, L.job);
+  // the pass's jobs go to the device as one table (this admission stream's:
+  // its previous pass has completed), one launch per kernel class
+  if (pw.total() > 0 && e == hipSuccess) {
+    ReduceJob* th = c->jobtab_host[rs];
+    ReduceJob* td = c->jobtab_dev[rs];
+    size_t o = 0;
+    size_t first[kNumReduceClasses];
+    for (int rc = 0; rc < kNumReduceClasses; ++rc) {
+      first[rc] = o;
+      std::copy(pw.jobs[rc].begin(), pw.jobs[rc].end(), th + o);
+      o += pw.jobs[rc].size();
+    }
+    e = hipMemcpyAsync(td, th, o * sizeof(ReduceJob), hipMemcpyHostToDevice, c->rstream);
+    for (int rc = 0; rc < kNumReduceClasses && e == hipSuccess; ++rc) {
+      if (pw.jobs[rc].empty()) continue;
+      ReduceLaunch L{td + first[rc], th + first[rc], (int)pw.jobs[rc].size()};
       e = launch_reduce(L, rc, c->rstream);
     }
   }
@@ -673,9 +769,25 @@ void admit(lti_ctx* c) {
   c->last_pass[rs] = pass_ref(pe);
 }
 
+// Copy a finished request's results to its pinned staging (host requests:
+// G and its records in one copy; device requests: the records, for the
+// counts of poll()'s result).
+hipError_t copy_results(lti_ctx* c, Request* r, hipStream_t s) {
+  const lti_request& q = r->req;
+  HostStage& hs = r->hs;
+  const size_t ibytes = sizeof(lti_point_info) * q.n_omega;
+  if (q.mem == LTI_MEM_HOST) {
+    // G and info are back to back in the block and in staging (same offsets)
+    const char* src = static_cast<const char*>(r->block) + r->dOffG;
+    return hipMemcpyAsync(hs.out.base + hs.offG, src, hs.offInfo + ibytes, hipMemcpyDeviceToHost, s);
+  }
+  return hipMemcpyAsync(hs.out.base + hs.offInfo, r->dinfo, ibytes, hipMemcpyDeviceToHost, s);
+}
+
 // Gather up to batch_tiles tiles from the live requests (oldest first) into
 // one batch: one launch per kernel class and kMaxSegs requests, each request
-// a contiguous range of its tiles.
+// a contiguous range of its tiles.  Requests whose last tiles are in the
+// batch are finished in it: refinement of their queued points, result copy.
 void launch(lti_ctx* c) {
   if (c->live.empty() || (int)c->inflight.size() >= c->max_inflight) return;
   constexpr int kAllClasses = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
@@ -718,6 +830,7 @@ void launch(lti_ctx* c) {
     if (any_ready) return rd && md;
     return (rd || r->ready == oldest) && (md || r->model_ready == oldest);
   };
+  std::vector<Request*> fin;  // requests whose last tiles are in this batch
   for (Request* r : c->live) {
     if (total >= c->batch_tiles) break;
     if (r->state != RState::kLive || r->next_tile >= r->ntiles) continue;
@@ -728,13 +841,12 @@ void launch(lti_ctx* c) {
     r->next_tile += take;
     total += take;
     b.credit.emplace_back(r, take);
+    if (r->next_tile == r->ntiles) fin.push_back(r);
     if (r->res.t_first_launch_us == 0.0) r->res.t_first_launch_us = c->now_us();
   }
   if (total == 0) return;
   hipError_t e = hipSuccess;
-  hipStream_t ss = c->sstreams[c->next_sstream];
-  c->next_sstream = (c->next_sstream + 1) % c->n_sstreams;
-  b.stream = ss;
+  hipStream_t ss = c->stream;
   // wait for the uploads and reductions the batch's requests depend on
   std::vector<PassEvent*> waited;
   for (auto& cr : b.credit)
@@ -778,8 +890,29 @@ void launch(lti_ctx* c) {
     }
   }
   if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, ss);
+  // finish the requests whose last tiles are in the batch: the extended
+  // refinement of their queued points (the grid is sized by their points; a
+  // workgroup that finds the queues empty exits at once), then the results
+  // to host memory
+  if (!fin.empty() && e == hipSuccess) {
+    DDLaunch D;
+    for (size_t i0 = 0; i0 < fin.size() && e == hipSuccess; i0 += kMaxDDSegs) {
+      D.nseg = (int)std::min<size_t>(kMaxDDSegs, fin.size() - i0);
+      int64_t pts = 0;
+      for (int i = 0; i < D.nseg; ++i) {
+        Request* r = fin[i0 + i];
+        D.seg[i].rd = r->desc;
+        D.seg[i].rm = r->model->rm;
+        D.seg[i].K = (uint64_t)r->K;
+        pts += r->K * r->S;
+      }
+      const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(1024, pts / 32));
+      e = launch_refine_dd(D, grid, ss);
+    }
+    for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i) e = copy_results(c, fin[i], ss);
+  }
   b.done = get_event(c, false);
-  if (e == hipSuccess) e = hipEventRecord(b.done, ss);
+  if (e == hipSuccess) e = b.done ? hipEventRecord(b.done, ss) : hipErrorOutOfMemory;
   c->stats.tiles_launched += total;
   if (e != hipSuccess) {
     fail_all(c, LTI_EDEVICE);
@@ -788,23 +921,25 @@ void launch(lti_ctx* c) {
   c->inflight.push_back(std::move(b));
 }
 
+// Results are in pinned staging (the batch that finished the request copied
+// them there): hand them to the caller and count the point records.
 void complete_request(lti_ctx* c, Request* r) {
   const lti_request& q = r->req;
   r->res.status = LTI_OK;
   r->res.n_points = q.n_omega;
+  HostStage& hs = r->hs;
+  const lti_point_info* info = reinterpret_cast<const lti_point_info*>(hs.out.base + hs.offInfo);
   if (q.mem == LTI_MEM_HOST) {
-    HostStage& hs = r->hs;
-    std::memcpy(q.G_out, hs.base + hs.offG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
-    if (q.info_out) {
-      std::memcpy(q.info_out, hs.base + hs.offInfo, sizeof(lti_point_info) * q.n_omega);
-      for (int64_t k = 0; k < q.n_omega; ++k) {
-        const lti_point_info& pi = q.info_out[k];
-        if (pi.path == LTI_PATH_REFINED) r->res.n_refined++;
-        if (pi.path == LTI_PATH_FALLBACK) r->res.n_fallback++;
-        if (pi.path == LTI_PATH_SINGULAR) r->res.n_singular++;
-        r->res.max_est_rel_err = std::max(r->res.max_est_rel_err, (double)pi.est_rel_err);
-      }
-    }
+    std::memcpy(q.G_out, hs.out.base + hs.offG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
+    if (q.info_out) std::memcpy(q.info_out, info, sizeof(lti_point_info) * q.n_omega);
+  }
+  for (int64_t k = 0; k < q.n_omega; ++k) {
+    const lti_point_info& pi = info[k];
+    if (pi.path == LTI_PATH_REFINED) r->res.n_refined++;
+    if (pi.path == LTI_PATH_FALLBACK) r->res.n_fallback++;
+    if (pi.path == LTI_PATH_SINGULAR) r->res.n_singular++;
+    if (pi.path == LTI_PATH_FP64_DD) r->res.n_fp64_dd++;
+    r->res.max_est_rel_err = std::max(r->res.max_est_rel_err, (double)pi.est_rel_err);
   }
   release_stage(c, r->hs);
   r->res.t_done_us = c->now_us();
@@ -812,30 +947,6 @@ void complete_request(lti_ctx* c, Request* r) {
   c->stats.requests_done++;
   c->stats.points_done += q.n_omega;
   release_request_memory(c, r);
-}
-
-void finish_tiles(lti_ctx* c, Request* r) {
-  const lti_request& q = r->req;
-  if (q.mem == LTI_MEM_DEVICE) {
-    // results are already in the caller's device buffers; the batch event
-    // that credited the last tile orders them
-    complete_request(c, r);
-    return;
-  }
-  HostStage& hs = r->hs;
-  char* b = static_cast<char*>(r->block);
-  // G and info are back to back in the block and in staging (same aligned
-  // offsets): one D2H copy
-  const size_t gbytes = sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu;
-  const size_t bytes = q.info_out ? (hs.offInfo - hs.offG) + sizeof(lti_point_info) * q.n_omega : gbytes;
-  hipError_t e = hipMemcpyAsync(hs.base + hs.offG, b + r->dOffG, bytes, hipMemcpyDeviceToHost, c->stream);
-  r->d2h_ev = get_event(c, false);
-  if (e == hipSuccess) e = hipEventRecord(r->d2h_ev, c->stream);
-  if (e != hipSuccess) {
-    fail_all(c, LTI_EDEVICE);
-    return;
-  }
-  r->state = RState::kFinishing;
 }
 
 bool retire(lti_ctx* c) {
@@ -853,14 +964,10 @@ bool retire(lti_ctx* c) {
     put_event(c, tp.b, true);
     c->reduce_timing.pop_front();
   }
-  // batches on different sweep streams may finish in any order
-  for (auto bit = c->inflight.begin(); bit != c->inflight.end();) {
-    Batch& b = *bit;
+  while (!c->inflight.empty()) {
+    Batch& b = c->inflight.front();
     const hipError_t q = hipEventQuery(b.done);
-    if (q == hipErrorNotReady) {
-      ++bit;
-      continue;
-    }
+    if (q == hipErrorNotReady) break;
     if (q != hipSuccess) {
       fail_all(c, LTI_EDEVICE);
       return true;
@@ -878,29 +985,14 @@ bool retire(lti_ctx* c) {
       Request* r = cr.first;
       r->tiles_done += cr.second;
       c->outstanding_waves -= cr.second * r->waves_per_tile;
-      if (r->tiles_done == r->ntiles && r->state == RState::kLive) finish_tiles(c, r);
-      if (c->device_error) return true;
+      if (r->tiles_done == r->ntiles && r->state == RState::kLive) complete_request(c, r);
     }
     put_event(c, b.done, false);
-    bit = c->inflight.erase(bit);
+    c->inflight.pop_front();
     progressed = true;
   }
   for (auto it = c->live.begin(); it != c->live.end();) {
     Request* r = *it;
-    if (r->state == RState::kFinishing) {
-      const hipError_t q = hipEventQuery(r->d2h_ev);
-      if (q == hipErrorNotReady) {
-        ++it;
-        continue;
-      }
-      put_event(c, r->d2h_ev, false);
-      r->d2h_ev = nullptr;
-      if (q != hipSuccess) {
-        fail_all(c, LTI_EDEVICE);
-        return true;
-      }
-      complete_request(c, r);
-    }
     if (r->state == RState::kDone || r->state == RState::kFailed) {
       it = c->live.erase(it);
       progressed = true;
@@ -940,10 +1032,6 @@ void destroy_admit_streams(lti_ctx* c) {
   for (int i = 0; i < kAdmitStreams; ++i) {
     if (c->rstreams[i]) (void)hipStreamDestroy(c->rstreams[i]);
     c->rstreams[i] = nullptr;
-  }
-  for (int i = 1; i < kSweepStreams; ++i) {  // [0] is c->stream
-    if (c->sstreams[i]) (void)hipStreamDestroy(c->sstreams[i]);
-    c->sstreams[i] = nullptr;
   }
 }
 
@@ -1008,7 +1096,7 @@ int validate(const lti_request* q) {
   if (!q->A || !q->B || !q->C || !q->omega || !q->G_out) return LTI_EINVAL;
   if (q->mem != LTI_MEM_HOST && q->mem != LTI_MEM_DEVICE) return LTI_EINVAL;
   if (q->precision != LTI_PREC_FP64 && q->precision != LTI_PREC_REFINED) return LTI_EINVAL;
-  if (q->reserved0 != 0) return LTI_EINVAL;
+  if (q->points != LTI_POINTS_JW && q->points != LTI_POINTS_S && q->points != LTI_POINTS_Z) return LTI_EINVAL;
   if (q->n_omega > (int64_t)UINT32_MAX) return LTI_EINVAL;
   if (std::isnan(q->rtol) || q->rtol >= 1.0) return LTI_EINVAL;
   if (q->nx > kMaxNWG || q->nu > kMaxRhs || q->ny > kMaxRhs) return LTI_EUNSUPPORTED;
@@ -1017,7 +1105,8 @@ int validate(const lti_request* q) {
   return LTI_OK;
 }
 
-// Stage a host-memory request's inputs (and room for its outputs).
+// Stage a host-memory request's inputs in `hs.in` (pinned when the pool has
+// room, else pageable: the H2D copy is then a synchronous one).
 int stage_inputs(lti_ctx* c, Request* r) {
   const lti_request& q = r->req;
   const int n = q.nx, m = q.nu, p = q.ny;
@@ -1032,32 +1121,23 @@ int stage_inputs(lti_ctx* c, Request* r) {
   hs.offB = take(sizeof(double) * n * m);
   hs.offC = take(sizeof(double) * p * n);
   hs.offD = take(sizeof(double) * p * m);
-  hs.offW = take(sizeof(double) * q.n_omega);
-  hs.offG = take(sizeof(double) * 2 * (size_t)q.n_omega * p * m);
-  hs.offInfo = take(q.info_out ? sizeof(lti_point_info) * q.n_omega : 0);
-  hs.bytes = off;
+  hs.offW = take(sizeof(double) * omega_doubles(q));
+  bool ok;
   {
     std::lock_guard<std::mutex> lk(c->mu);
-    hs.base = static_cast<char*>(c->staging.alloc(hs.bytes));
+    ok = take_buf(c, hs.in, off, true);
   }
-  hs.pinned = hs.base != nullptr;
-  if (!hs.pinned) {
-    try {
-      hs.fallback.resize(hs.bytes);
-    } catch (...) {
-      return LTI_ENOMEM;
-    }
-    hs.base = hs.fallback.data();
-  }
+  if (!ok) return LTI_ENOMEM;
+  char* base = hs.in.base;
   // A..D must be contiguous in this order (one H2D copy)
-  std::memcpy(hs.base + hs.offA, q.A, sizeof(double) * n * n);
-  std::memcpy(hs.base + hs.offB, q.B, sizeof(double) * n * m);
-  std::memcpy(hs.base + hs.offC, q.C, sizeof(double) * p * n);
+  std::memcpy(base + hs.offA, q.A, sizeof(double) * n * n);
+  std::memcpy(base + hs.offB, q.B, sizeof(double) * n * m);
+  std::memcpy(base + hs.offC, q.C, sizeof(double) * p * n);
   if (q.D)
-    std::memcpy(hs.base + hs.offD, q.D, sizeof(double) * p * m);
+    std::memcpy(base + hs.offD, q.D, sizeof(double) * p * m);
   else
-    std::memset(hs.base + hs.offD, 0, sizeof(double) * p * m);
-  std::memcpy(hs.base + hs.offW, q.omega, sizeof(double) * q.n_omega);
+    std::memset(base + hs.offD, 0, sizeof(double) * p * m);
+  std::memcpy(base + hs.offW, q.omega, sizeof(double) * omega_doubles(q));
   // the model's identity: its dimensions and the bytes of A, B, C, D (not
   // the alignment gaps between them in staging, which hold whatever the
   // pool held before); only keyed requests are ever matched
@@ -1066,10 +1146,10 @@ int stage_inputs(lti_ctx* c, Request* r) {
   uint64_t h = 1469598103934665603ull;
   const int dims[3] = {n, m, p};
   h = fnv1a(dims, sizeof(dims), h);
-  h = fnv1a(hs.base + hs.offA, sizeof(double) * n * n, h);
-  h = fnv1a(hs.base + hs.offB, sizeof(double) * n * m, h);
-  h = fnv1a(hs.base + hs.offC, sizeof(double) * p * n, h);
-  h = fnv1a(hs.base + hs.offD, sizeof(double) * p * m, h);
+  h = fnv1a(base + hs.offA, sizeof(double) * n * n, h);
+  h = fnv1a(base + hs.offB, sizeof(double) * n * m, h);
+  h = fnv1a(base + hs.offC, sizeof(double) * p * n, h);
+  h = fnv1a(base + hs.offD, sizeof(double) * p * m, h);
   r->hash = h;
   return LTI_OK;
 }
@@ -1118,16 +1198,31 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
     c->max_inflight = std::max(1, std::min(64, std::atoi(e)));
   if (const char* e = std::getenv("LTI_FREQRESP_ADMIT_STREAMS"))
     c->n_rstreams = std::max(1, std::min(kAdmitStreams, std::atoi(e)));
-  if (const char* e = std::getenv("LTI_FREQRESP_SWEEP_STREAMS"))
-    c->n_sstreams = std::max(1, std::min(kSweepStreams, std::atoi(e)));
   c->t0 = Clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
-  c->arena.init(static_cast<char*>(cfg->arena), cfg->arena_bytes);
+  // the arena, minus the reduction job tables (one per admission stream)
+  const size_t tab_bytes = align_up(sizeof(ReduceJob) * kMaxJobs);
+  if (cfg->arena_bytes < kAdmitStreams * tab_bytes + (size_t(1) << 20)) return LTI_EINVAL;
+  char* abase = static_cast<char*>(cfg->arena);
+  for (int i = 0; i < kAdmitStreams; ++i) c->jobtab_dev[i] = reinterpret_cast<ReduceJob*>(abase + i * tab_bytes);
+  c->arena.init(abase + kAdmitStreams * tab_bytes, cfg->arena_bytes - kAdmitStreams * tab_bytes);
   const size_t staging = cfg->host_staging_bytes ? cfg->host_staging_bytes : kDefaultStaging;
   void* hp = nullptr;
   if (hipHostMalloc(&hp, staging, hipHostMallocDefault) != hipSuccess) return LTI_EDEVICE;
   c->staging_block = static_cast<char*>(hp);
   c->staging.init(c->staging_block, staging);
+  void* jp = nullptr;
+  if (hipHostMalloc(&jp, kAdmitStreams * tab_bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipHostFree(hp);
+    return LTI_EDEVICE;
+  }
+  c->jobtab_block = static_cast<char*>(jp);
+  for (int i = 0; i < kAdmitStreams; ++i)
+    c->jobtab_host[i] = reinterpret_cast<ReduceJob*>(c->jobtab_block + i * tab_bytes);
+  auto free_host = [&] {
+    (void)hipHostFree(hp);
+    (void)hipHostFree(jp);
+  };
   // tuning knob (not part of the ABI): keep the sweeps off the first N CUs,
   // so that reductions always find room beside them
   int reserved_cus = 0;
@@ -1147,7 +1242,7 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
       e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     }
     if (e != hipSuccess) {
-      (void)hipHostFree(hp);
+      free_host();
       return LTI_EDEVICE;
     }
     c->own_stream = true;
@@ -1155,19 +1250,16 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   bool ok = true;
   for (int i = 0; i < c->n_rstreams && ok; ++i)
     ok = hipStreamCreateWithFlags(&c->rstreams[i], hipStreamNonBlocking) == hipSuccess;
-  c->sstreams[0] = c->stream;
-  for (int i = 1; i < c->n_sstreams && ok; ++i)
-    ok = hipStreamCreateWithFlags(&c->sstreams[i], hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     destroy_admit_streams(c.get());
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
-    (void)hipHostFree(hp);
+    free_host();
     return LTI_EDEVICE;
   }
   try {
     c->thread = std::thread(scheduler, c.get());
   } catch (...) {
-    (void)hipHostFree(hp);
+    free_host();
     destroy_admit_streams(c.get());
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     return LTI_ENOMEM;
@@ -1183,19 +1275,24 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
   const int n = q->nx, m = q->nu, p = q->ny;
   if (q->mem == LTI_MEM_HOST) {
     if (!all_finite(q->A, (size_t)n * n) || !all_finite(q->B, (size_t)n * m) || !all_finite(q->C, (size_t)p * n) ||
-        (q->D && !all_finite(q->D, (size_t)p * m)) || !all_finite(q->omega, (size_t)q->n_omega))
+        (q->D && !all_finite(q->D, (size_t)p * m)) || !all_finite(q->omega, omega_doubles(*q)))
       return LTI_EINVAL;
   }
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return LTI_ENOMEM;
   r->req = *q;
   if (q->rtol <= 0.0) r->req.rtol = 1e-10;
-  if (q->mem == LTI_MEM_HOST) {
+  // fewer outputs than inputs: solve the transposed system, whose
+  // right-hand sides are the min(nu, ny) outputs
+  r->trans = (p < m && !(c->flags & LTI_CFG_NO_TRANSPOSE)) ? 1 : 0;
+  r->sm = r->trans ? p : m;
+  r->sp = r->trans ? m : p;
+  {
     // checked before staging (the pinned pool is not taken for a request
-    // that can never run); device requests check under the lock below
+    // that can never run)
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->device_error) return LTI_EDEVICE;
-    const Need nd = request_need(r->req, true);
+    const Need nd = request_need(r->req, true, r->sm, r->sp);
     if (!c->arena.can_ever_fit(nd.block() + nd.model)) return LTI_ENOSPC;
     if ((int)c->all.size() >= c->max_pending) return LTI_EAGAIN;
   }
@@ -1209,10 +1306,6 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
   if (c->device_error) {
     release_stage(c, r->hs);
     return LTI_EDEVICE;
-  }
-  if (q->mem == LTI_MEM_DEVICE) {
-    const Need nd = request_need(r->req, true);
-    if (!c->arena.can_ever_fit(nd.block() + nd.model)) return LTI_ENOSPC;
   }
   if ((int)c->all.size() >= c->max_pending) {
     release_stage(c, r->hs);
@@ -1290,8 +1383,7 @@ int lti_freqresp_destroy(lti_ctx* c) {
   (void)hipSetDevice(c->device);
   for (hipStream_t rs : c->rstreams)
     if (rs) (void)hipStreamSynchronize(rs);
-  for (hipStream_t ss : c->sstreams)
-    if (ss) (void)hipStreamSynchronize(ss);
+  (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->inflight) {
     put_event(c, b.done, false);
     put_event(c, b.t0, true);
@@ -1301,8 +1393,6 @@ int lti_freqresp_destroy(lti_ctx* c) {
     put_event(c, tp.a, true);
     put_event(c, tp.b, true);
   }
-  for (auto& kv : c->all)
-    if (kv.second->d2h_ev) put_event(c, kv.second->d2h_ev, false);
   for (PassEvent*& lp : c->last_pass) lp = nullptr;
   for (PassEvent* pe : c->pass_events) {
     put_event(c, pe->ev, false);
@@ -1312,6 +1402,7 @@ int lti_freqresp_destroy(lti_ctx* c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->timing_pool) (void)hipEventDestroy(e);
   if (c->staging_block) (void)hipHostFree(c->staging_block);
+  if (c->jobtab_block) (void)hipHostFree(c->jobtab_block);
   destroy_admit_streams(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -1332,13 +1423,12 @@ int lti_freqresp_get_reduced(lti_ctx* c, uint64_t key, int32_t nx, int32_t nu, i
     rm = held->rm;
     held->refs++;
   }
-  const int n = nx, m = nu, p = ny;
-  std::vector<double> hp((size_t)hlen(n)), bt((size_t)n * m), ct((size_t)n * p);
+  const int n = nx, sm = rm.m, sp = rm.p;  // the solved system's sizes
+  std::vector<double> hp((size_t)hlen(n)), bt((size_t)n * sm), ct((size_t)n * sp);
   hipError_t e = hipSetDevice(c->device);
   for (hipStream_t rs : c->rstreams)
-    if (e == hipSuccess) e = hipStreamSynchronize(rs);
-  for (hipStream_t ss : c->sstreams)
-    if (e == hipSuccess) e = hipStreamSynchronize(ss);
+    if (e == hipSuccess && rs) e = hipStreamSynchronize(rs);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = hipMemcpy(hp.data(), rm.H, hp.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(bt.data(), rm.Bt, bt.size() * 8, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(ct.data(), rm.Ct, ct.size() * 8, hipMemcpyDeviceToHost);
@@ -1347,14 +1437,29 @@ int lti_freqresp_get_reduced(lti_ctx* c, uint64_t key, int32_t nx, int32_t nu, i
     held->refs--;
   }
   if (e != hipSuccess) return LTI_EDEVICE;
+  // Stored: Hs = Qs^T As Qs (packed), Bts = Qs^T Bs (n x sm), Cts = (Cs Qs)^T
+  // (n x sp).  Without transposition (As, Bs, Cs) = (A, B, C).  With it,
+  // (As, Bs, Cs) = (A^T, C^T, B^T), and the reduction of the model itself is
+  // H = Hs^T (lower Hessenberg), Q^T B = (Cs Qs)^T, C Q = (Qs^T Bs)^T.
+  auto hs = [&](int i, int j) { return (i <= j + 1) ? hp[hoff(j) + i] : 0.0; };
   if (H) {
     for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) H[(size_t)i * n + j] = (i <= j + 1) ? hp[hoff(j) + i] : 0.0;
+      for (int j = 0; j < n; ++j) H[(size_t)i * n + j] = rm.trans ? hs(j, i) : hs(i, j);
   }
-  if (Bt) std::memcpy(Bt, bt.data(), bt.size() * 8);
+  if (Bt) {
+    if (rm.trans)
+      std::memcpy(Bt, ct.data(), ct.size() * 8);  // n x sp = n x nu
+    else
+      std::memcpy(Bt, bt.data(), bt.size() * 8);
+  }
   if (Ct) {
-    for (int a = 0; a < p; ++a)
-      for (int i = 0; i < n; ++i) Ct[(size_t)a * n + i] = ct[(size_t)i * p + a];
+    if (rm.trans) {
+      for (int a = 0; a < ny; ++a)
+        for (int i = 0; i < n; ++i) Ct[(size_t)a * n + i] = bt[(size_t)i * sm + a];
+    } else {
+      for (int a = 0; a < ny; ++a)
+        for (int i = 0; i < n; ++i) Ct[(size_t)a * n + i] = ct[(size_t)i * sp + a];
+    }
   }
   return LTI_OK;
 }

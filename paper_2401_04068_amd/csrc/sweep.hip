@@ -58,7 +58,7 @@ struct Sweep {
 // right-hand-side rows; on exit they hold y.  `bcast` is this wavefront's
 // 2 * MM values of LDS.
 template <typename T, int R, int MM, bool kLds>
-__device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T w, Sweep<T, R, MM>& st, T* bcast) {
+__device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, Sweep<T, R, MM>& st, T* bcast) {
   const int lane = threadIdx.x & 63;
   st.singular = false;
   {
@@ -67,7 +67,7 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T w, Sweep<T
     for (int r = 0; r < R; ++r) {
       const int i = lane + 64 * r;
       const T h = (i < n) ? H[off + i] : (T)0;
-      st.cr[r] = -h;
+      st.cr[r] = (i == n - 1) ? sg - h : -h;
       st.ci[r] = (i == n - 1) ? w : (T)0;
       st.rc[r] = (T)0;
       st.rsr[r] = (T)1;
@@ -152,12 +152,13 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T w, Sweep<T
         const int i = lane + 64 * t;
         if (t < s || lane < kl) {
           const T cr_ = st.cr[t], ci_ = st.ci[t];
-          const T o = -hc[t];  // M(i, k-1), real off the diagonal
+          // M(i, k-1): real off the diagonal; the diagonal entry also holds s
+          const T o = (i == k - 1) ? sg - hc[t] : -hc[t];
           T nkr = c * o + sr * cr_ + si * ci_;
           T nki = sr * ci_ - si * cr_;
           T n1r = sr * o - c * cr_;
           T n1i = si * o - c * ci_;
-          if (i == k - 1) {  // diagonal entry: M(k-1, k-1) also holds j w
+          if (i == k - 1) {  // imaginary part of the diagonal entry
             nki += c * w;
             n1r -= si * w;
             n1i += sr * w;
@@ -402,7 +403,7 @@ __device__ __forceinline__ void write_output(const ReqDesc& rd, Src<double, kLds
           double2 g;
           g.x = vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
           g.y = vi[0];
-          store_c(G, a * m + j0 + j, g);
+          store_c(G, g_index(rd, a, j0 + j), g);
         }
       }
     }
@@ -414,7 +415,7 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
                            double* bcast) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m;
-  const double w = ((gptr<double>)rd.omega)[k];
+  const SPoint sp = point_of(rd, k);
   const Src<double, kLds> Bt = md.Bt;
   Sweep<double, R, MM> st;
 #pragma unroll
@@ -426,26 +427,32 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
       st.bi[r][j] = 0.0;
     }
   }
-  givens_sweep<double, R, MM, kLds>(md.H, n, w, st, bcast);
-  const double ratio = rd.info ? diag_ratio<double, R, MM>(n, st) : 0.0;
+  givens_sweep<double, R, MM, kLds>(md.H, n, sp.re, sp.im, st, bcast);
+  // estimated error: u times the spread of R's diagonal; points above the
+  // request's tolerance are finished by the extended refinement
+  const double est = 0.5 * DBL_EPSILON * diag_ratio<double, R, MM>(n, st);
+  if (!(est <= rd.rtol) || (rd.flags & kFlagForceDD)) {
+    if (lane == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
+    return;
+  }
   apply_rotations<double, R, MM>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
   write_output<R, MM, kLds>(rd, md.Ct, j0, mc, st.br, st.bi, G);
-  if (rd.info && lane == 0 && j0 == 0) {
+  if (lane == 0) {
     lti_point_info inf;
-    inf.est_rel_err = (float)(0.5 * DBL_EPSILON * ratio);
+    inf.est_rel_err = (float)est;
     inf.iters = 1;
-    inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
+    inf.path = LTI_PATH_FP64;
     inf.reserved = 0;
-    store_info(rd.info, k, inf);
+    put_info(rd, k, inf);
   }
 }
 
 // ---------------------------------------------------------------- refined
 
-// r = Bt - (j w X - H X), float64, rows lane + 64 t, columns j0 .. j0+MM-1.
+// r = Bt - (s X - H X), float64, rows lane + 64 t, columns j0 .. j0+MM-1.
 template <int R, int MM, bool kLds>
-__device__ __forceinline__ void residual64(const ReqDesc& rd, const ModelSrc<kLds>& md, double w, int j0,
+__device__ __forceinline__ void residual64(const ReqDesc& rd, const ModelSrc<kLds>& md, double sg, double w, int j0,
                                            int mc, const double (&xr)[R][MM], const double (&xi)[R][MM],
                                            double (&rr)[R][MM], double (&ri)[R][MM]) {
   const int lane = threadIdx.x & 63;
@@ -458,8 +465,8 @@ __device__ __forceinline__ void residual64(const ReqDesc& rd, const ModelSrc<kLd
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       const double b = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
-      rr[t][j] = b + w * xi[t][j];
-      ri[t][j] = -w * xr[t][j];
+      rr[t][j] = fma(w, xi[t][j], fma(-sg, xr[t][j], b));
+      ri[t][j] = fma(-w, xr[t][j], -sg * xi[t][j]);
     }
   }
 #pragma unroll
@@ -496,10 +503,11 @@ template <int R, int MM, bool kLds>
 __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t k, int j0, int mc,
                               double* bcast64) {
   const int lane = threadIdx.x & 63;
-  const int n = rd.n, m = rd.m;
-  const double w = ((gptr<double>)rd.omega)[k];
-  const float wf = (float)w;
-  const double tol = 0.1 * ((rd.rtol > 0.0) ? rd.rtol : 1e-10);
+  const int n = rd.n;
+  const int m = rd.m;
+  const SPoint sp = point_of(rd, k);
+  const float sgf = (float)sp.re, wf = (float)sp.im;
+  const double tol = 0.1 * rd.rtol;
   constexpr int kMaxIters = 6;
   float* bcast = reinterpret_cast<float*>(bcast64);
   const Src<float, kLds> Bt32 = md.Bt32;
@@ -515,7 +523,7 @@ __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64
       st.bi[r][j] = 0.0f;
     }
   }
-  givens_sweep<float, R, MM, kLds>(md.H32, n, wf, st, bcast);
+  givens_sweep<float, R, MM, kLds>(md.H32, n, sgf, wf, st, bcast);
   apply_rotations<float, R, MM>(n, st);
   double dprev = 0.0;
   {
@@ -531,15 +539,12 @@ __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64
     dprev = sqrt(wave_sum(s2));
   }
   int iters = 1;
-  int path = LTI_PATH_REFINED;
   double est = 1.0;
   bool ok = false;
-  if (st.singular || !(dprev < INFINITY)) {
-    path = LTI_PATH_FALLBACK;
-  } else {
+  if (!st.singular && dprev < INFINITY && !(rd.flags & kFlagForceDD)) {
     for (int it = 0; it < kMaxIters; ++it) {
       double rr[R][MM], ri[R][MM];
-      residual64<R, MM, kLds>(rd, md, w, j0, mc, xr, xi, rr, ri);
+      residual64<R, MM, kLds>(rd, md, sp.re, sp.im, j0, mc, xr, xi, rr, ri);
       double amax = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -559,7 +564,7 @@ __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64
           st.br[r][j] = (float)(rr[r][j] * scale);
           st.bi[r][j] = (float)(ri[r][j] * scale);
         }
-      givens_sweep<float, R, MM, kLds>(md.H32, n, wf, st, bcast);
+      givens_sweep<float, R, MM, kLds>(md.H32, n, sgf, wf, st, bcast);
       apply_rotations<float, R, MM>(n, st);
       ++iters;
       double d2 = 0.0, x2 = 0.0;
@@ -576,7 +581,7 @@ __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64
         }
       const double dn = sqrt(wave_sum(d2));
       const double xn = sqrt(wave_sum(x2));
-      if (!(dn < INFINITY) || !(xn > 0.0)) break;  // non-finite: fall back
+      if (!(dn < INFINITY) || !(xn > 0.0)) break;  // non-finite: stalled
       // predicted error after this correction: contraction (dn / dprev) times dn
       const double rel = dn / xn;
       const double pred = rel * (dn / dprev);
@@ -588,43 +593,20 @@ __device__ void solve_refined(const ReqDesc& rd, const ModelSrc<kLds>& md, int64
       if (dn > 0.5 * dprev) break;  // stalled
       dprev = dn;
     }
-    if (!ok) path = LTI_PATH_FALLBACK;
   }
-  if (path == LTI_PATH_FALLBACK) {
-    const Src<double, kLds> Bt = md.Bt;
-    Sweep<double, R, MM> sd;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = lane + 64 * r;
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        sd.br[r][j] = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
-        sd.bi[r][j] = 0.0;
-      }
-    }
-    givens_sweep<double, R, MM, kLds>(md.H, n, w, sd, bcast64);
-    est = 0.5 * DBL_EPSILON * diag_ratio<double, R, MM>(n, sd);
-    apply_rotations<double, R, MM>(n, sd);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        xr[r][j] = sd.br[r][j];
-        xi[r][j] = sd.bi[r][j];
-      }
-    if (sd.singular) path = LTI_PATH_SINGULAR;
+  if (!ok) {  // stalled (or singular): the extended refinement finishes it
+    if (lane == 0) enqueue_dd(rd, k, j0, mc, iters, kReasonStall);
+    return;
   }
   double* G = rd.G + (size_t)k * rd.p * m * 2;
   write_output<R, MM, kLds>(rd, md.Ct, j0, mc, xr, xi, G);
-  // with the columns split over several tiles, the tile holding column 0
-  // reports the point
-  if (rd.info && lane == 0 && j0 == 0) {
+  if (lane == 0) {
     lti_point_info inf;
     inf.est_rel_err = (float)est;
     inf.iters = (uint8_t)iters;
-    inf.path = (uint8_t)path;
+    inf.path = LTI_PATH_REFINED;
     inf.reserved = 0;
-    store_info(rd.info, k, inf);
+    put_info(rd, k, inf);
   }
 }
 

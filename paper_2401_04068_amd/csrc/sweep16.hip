@@ -74,7 +74,7 @@ __device__ __forceinline__ T group_max16(T x) {
 // carry entry and right-hand side.  Slices are unrolled at compile time; the
 // 16 steps inside a slice are a loop, so the code stays small.
 template <typename T, int R, int MM, bool kLds>
-__device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM>& st, T* bcast) {
+__device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T, R, MM>& st, T* bcast) {
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, gl = lane & 15;
   T* mine = bcast + g * (2 + 2 * MM);
@@ -85,7 +85,7 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
     for (int r = 0; r < R; ++r) {
       const int i = gl + 16 * r;
       const T h = (i < n) ? H[off + i] : (T)0;
-      st.cr[r] = -h;
+      st.cr[r] = (i == n - 1) ? sg - h : -h;
       st.ci[r] = (i == n - 1) ? w : (T)0;
       st.rc[r] = (T)0;
       st.rsr[r] = (T)1;
@@ -188,15 +188,16 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T w, S16<T, R, MM
       constexpr int t = decltype(TT)::value;
       if (t < s || gl < jl) {
         const T cr_ = st.cr[t], ci_ = st.ci[t];
-        const T o = -hc[t];
+        // the diagonal entry of column k-1 (row k-1, in slice sp) also
+        // holds s = sg + j w
+        T d = (T)0;
+        if constexpr (t == sp) d = (gl + 16 * t == k - 1) ? (T)1 : (T)0;
+        const T o = (t == sp) ? fma(d, sg, -hc[t]) : -hc[t];
         T nkr = c * o + sr * cr_ + si * ci_;
         T nki = sr * ci_ - si * cr_;
         T n1r = sr * o - c * cr_;
         T n1i = si * o - c * ci_;
-        // the diagonal entry of column k-1 (row k-1, in slice sp) also
-        // holds j w
         if constexpr (t == sp) {
-          const T d = (gl + 16 * t == k - 1) ? (T)1 : (T)0;
           nki = fma(d, cw, nki);
           n1r = fma(-d, sw_i, n1r);
           n1i = fma(d, sw_r, n1i);
@@ -435,7 +436,7 @@ __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc
           double2 gv;
           gv.x = vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
           gv.y = vi[0];
-          store_c(G, a * m + j0 + j, gv);
+          store_c(G, g_index(rd, a, j0 + j), gv);
         }
       }
     }
@@ -447,7 +448,7 @@ __device__ void solve16_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, 
                              double* bcast) {
   const int gl = threadIdx.x & 15;
   const int n = rd.n, m = rd.m;
-  const double w = ((gptr<double>)rd.omega)[k];
+  const SPoint sp = point_of(rd, k);
   const gptr<double> Bt = (gptr<double>)rd.Bt;
   S16<double, R, MM> st;
 #pragma unroll
@@ -459,18 +460,22 @@ __device__ void solve16_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, 
       st.bi[r][j] = 0.0;
     }
   }
-  sweep16<double, R, MM, kLds>(H, n, w, st, bcast);
-  const double ratio = rd.info ? diag_ratio16<double, R, MM>(n, st) : 0.0;
+  sweep16<double, R, MM, kLds>(H, n, sp.re, sp.im, st, bcast);
+  // estimated error: u times the spread of R's diagonal; points above the
+  // request's tolerance are finished by the extended refinement
+  const double est = 0.5 * DBL_EPSILON * diag_ratio16<double, R, MM>(n, st);
+  const bool dd = !(est <= rd.rtol) || (rd.flags & kFlagForceDD);
+  if (dd && valid && gl == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
   apply_rotations16<double, R, MM>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
-  write_output16<R, MM>(rd, j0, mc, valid, st.br, st.bi, G);
-  if (rd.info && valid && gl == 0 && j0 == 0) {
+  write_output16<R, MM>(rd, j0, mc, valid && !dd, st.br, st.bi, G);
+  if (valid && !dd && gl == 0) {
     lti_point_info inf;
-    inf.est_rel_err = (float)(0.5 * DBL_EPSILON * ratio);
+    inf.est_rel_err = (float)est;
     inf.iters = 1;
-    inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
+    inf.path = LTI_PATH_FP64;
     inf.reserved = 0;
-    store_info(rd.info, k, inf);
+    put_info(rd, k, inf);
   }
 }
 
@@ -485,10 +490,10 @@ __device__ __forceinline__ double bperm_d(int addr, double v) {
   return __hiloint2double(hi, lo);
 }
 
-// r = Q^T B - (j w X - H X) in float64 for this lane's frequency; the row
+// r = Q^T B - (s X - H X) in float64 for this lane's frequency; the row
 // X(j, :) reaches the other lanes of its 16-lane row through ds_bpermute.
 template <int R, int MM, bool kLds>
-__device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> H, double w, int j0, int mc,
+__device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> H, double sg, double w, int j0, int mc,
                                            const double (&xr)[R][MM], const double (&xi)[R][MM],
                                            double (&rr)[R][MM], double (&ri)[R][MM]) {
   const int lane = threadIdx.x & 63, gl = lane & 15;
@@ -500,8 +505,8 @@ __device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> 
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       const double b = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
-      rr[t][j] = b + w * xi[t][j];
-      ri[t][j] = -w * xr[t][j];
+      rr[t][j] = fma(w, xi[t][j], fma(-sg, xr[t][j], b));
+      ri[t][j] = fma(-w, xr[t][j], -sg * xi[t][j]);
     }
   }
   static_for<0, R>([&](auto sc) {
@@ -535,17 +540,18 @@ __device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> 
   });
 }
 
-// Refined path: complex-float32 solves, float64 residuals and accumulation,
-// float64 fallback (see solve_refined in sweep.hip).  The four frequencies of
-// the wavefront iterate in lockstep until all have stopped.
+// Refined path: complex-float32 solves, float64 residuals and accumulation;
+// stalled points go to the extended refinement (see solve_refined in
+// sweep.hip).  The four frequencies of the wavefront iterate in lockstep
+// until all have stopped.
 template <int R, int MM, bool kLds>
 __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<float, kLds> H32, int64_t k, bool valid,
                                 int j0, int mc, double* bcast64) {
   const int gl = threadIdx.x & 15;
   const int n = rd.n, m = rd.m;
-  const double w = ((gptr<double>)rd.omega)[k];
-  const float wf = (float)w;
-  const double tol = 0.1 * ((rd.rtol > 0.0) ? rd.rtol : 1e-10);
+  const SPoint sp = point_of(rd, k);
+  const float sgf = (float)sp.re, wf = (float)sp.im;
+  const double tol = 0.1 * rd.rtol;
   constexpr int kMaxIters = 6;
   float* bcast = reinterpret_cast<float*>(bcast64);
   const gptr<float> Bt32 = (gptr<float>)rd.Bt32;
@@ -561,7 +567,7 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
       st.bi[r][j] = 0.0f;
     }
   }
-  sweep16<float, R, MM, kLds>(H32, n, wf, st, bcast);
+  sweep16<float, R, MM, kLds>(H32, n, sgf, wf, st, bcast);
   apply_rotations16<float, R, MM>(n, st);
   double s2 = 0.0;
 #pragma unroll
@@ -576,11 +582,12 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
   int iters = 1;
   double est = 1.0;
   bool done = false, ok = false;
-  if (st.singular || !(dprev < INFINITY)) done = true;  // -> float64 fallback
+  // singular or non-finite: the extended refinement takes it
+  if (st.singular || !(dprev < INFINITY) || (rd.flags & kFlagForceDD)) done = true;
   for (int it = 0; it < kMaxIters; ++it) {
     if (__all(done)) break;
     double rr[R][MM], ri[R][MM];
-    residual16<R, MM, kLds>(rd, H, w, j0, mc, xr, xi, rr, ri);
+    residual16<R, MM, kLds>(rd, H, sp.re, sp.im, j0, mc, xr, xi, rr, ri);
     double amax = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -600,7 +607,7 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
         st.br[r][j] = (float)(rr[r][j] * scale);
         st.bi[r][j] = (float)(ri[r][j] * scale);
       }
-    sweep16<float, R, MM, kLds>(H32, n, wf, st, bcast);
+    sweep16<float, R, MM, kLds>(H32, n, sgf, wf, st, bcast);
     apply_rotations16<float, R, MM>(n, st);
     double d2 = 0.0, x2 = 0.0;
 #pragma unroll
@@ -619,7 +626,7 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
     if (!done) {
       ++iters;
       if (!(dn < INFINITY) || !(xn > 0.0)) {
-        done = true;  // non-finite: fall back
+        done = true;  // non-finite: stalled
       } else {
         const double rel = dn / xn;
         const double pred = rel * (dn / dprev);
@@ -634,43 +641,17 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
       }
     }
   }
-  int path = ok ? LTI_PATH_REFINED : LTI_PATH_FALLBACK;
-  if (__any(!ok)) {
-    const gptr<double> Bt = (gptr<double>)rd.Bt;
-    S16<double, R, MM> sd;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = gl + 16 * r;
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        sd.br[r][j] = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
-        sd.bi[r][j] = 0.0;
-      }
-    }
-    sweep16<double, R, MM, kLds>(H, n, w, sd, bcast64);
-    const double ratio = diag_ratio16<double, R, MM>(n, sd);
-    apply_rotations16<double, R, MM>(n, sd);
-    if (!ok) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int j = 0; j < MM; ++j) {
-          xr[r][j] = sd.br[r][j];
-          xi[r][j] = sd.bi[r][j];
-        }
-      est = 0.5 * DBL_EPSILON * ratio;
-      if (sd.singular) path = LTI_PATH_SINGULAR;
-    }
-  }
+  // stalled (or singular) points: the extended refinement finishes them
+  if (!ok && valid && gl == 0) enqueue_dd(rd, k, j0, mc, iters, kReasonStall);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
-  write_output16<R, MM>(rd, j0, mc, valid, xr, xi, G);
-  if (rd.info && valid && gl == 0 && j0 == 0) {
+  write_output16<R, MM>(rd, j0, mc, valid && ok, xr, xi, G);
+  if (valid && ok && gl == 0) {
     lti_point_info inf;
     inf.est_rel_err = (float)est;
     inf.iters = (uint8_t)iters;
-    inf.path = (uint8_t)path;
+    inf.path = LTI_PATH_REFINED;
     inf.reserved = 0;
-    store_info(rd.info, k, inf);
+    put_info(rd, k, inf);
   }
 }
 

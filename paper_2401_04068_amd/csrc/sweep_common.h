@@ -33,6 +33,53 @@ __device__ __forceinline__ void store_info(lti_point_info* info, int64_t k, cons
   ((gmut<uint64_t>)info)[k] = bits;
 }
 
+// A point's record: plain store, or (columns split over tiles) merged with
+// the other column groups' records by atomic maxima on its two 32-bit words:
+// the larger error estimate, and the worse path (FP64 < REFINED < FALLBACK <
+// SINGULAR < FP64_DD order of the codes), then the larger solve count.
+// Merged records start from zero (the runtime clears them).
+__device__ __forceinline__ void put_info(const ReqDesc& rd, int64_t k, const lti_point_info& v) {
+  if (rd.flags & kFlagMergeInfo) {
+    gmut<uint32_t> w = (gmut<uint32_t>)rd.info + 2 * k;
+    const uint32_t w0 = __float_as_uint(v.est_rel_err);
+    const uint32_t w1 = (uint32_t)v.iters | ((uint32_t)v.path << 8);
+    atomicMax((uint32_t*)&w[0], w0);
+    atomicMax((uint32_t*)&w[1], w1);
+  } else {
+    store_info(rd.info, k, v);
+  }
+}
+
+// Hand point k, columns j0 .. j0+mc-1, to the extended-precision refinement
+// (one lane calls this).
+__device__ __forceinline__ void enqueue_dd(const ReqDesc& rd, int64_t k, int j0, int mc, int fp32_solves,
+                                           int reason) {
+  const uint32_t e = atomicAdd(rd.fbq, 1u);
+  gmut<uint32_t> q = (gmut<uint32_t>)rd.fbq + 2 + 2 * (size_t)e;
+  q[0] = (uint32_t)k;
+  q[1] = (uint32_t)j0 | ((uint32_t)mc << 8) | ((uint32_t)min(fp32_solves, 255) << 16) | ((uint32_t)reason << 24);
+}
+
+// Evaluation point s_k = sr + j si of a request (see ReqDesc).
+struct SPoint {
+  double re, im;
+};
+__device__ __forceinline__ SPoint point_of(const ReqDesc& rd, int64_t k) {
+  const gptr<double> w = (gptr<double>)rd.omega;
+  const int kind = (int)((rd.flags >> 8) & 3u);
+  SPoint s;
+  if (kind == kPointsS) {
+    s.re = w[2 * k];
+    s.im = w[2 * k + 1];
+  } else if (kind == kPointsZ) {
+    sincos(w[k] * rd.Ts, &s.im, &s.re);
+  } else {
+    s.re = 0.0;
+    s.im = w[k];
+  }
+  return s;
+}
+
 // Launch tile t (wave-uniform) of a sweep launch: its segment, and the
 // frequencies and columns it covers.
 struct Tile {

@@ -49,10 +49,50 @@ struct ShWG {
   double first[4 * kRWG][3 + 2 * 4];  // rotation and y of each segment's first row
   double red[4][8][2];            // per-wavefront partial sums of G
   double misc[4];
+  double ring[2][8];              // block reductions (alternating buffers)
+};
+
+// Reductions over the workgroup's four wavefronts; every thread gets the same
+// total (same operands, same order).  Consecutive calls alternate between two
+// LDS buffers, so one barrier per call suffices: a buffer is written again
+// only after the barrier of the call in between.
+struct BlockRed {
+  ShWG& sh;
+  int parity = 0;
+  __device__ explicit BlockRed(ShWG& s) : sh(s) {}
+  __device__ double sum(double x) {
+    double* b = sh.ring[parity];
+    parity ^= 1;
+    x = wave_sum(x);
+    if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return (b[0] + b[1]) + (b[2] + b[3]);
+  }
+  // two sums at once
+  __device__ double2 sum2(double x, double y) {
+    double* b = sh.ring[parity];
+    parity ^= 1;
+    x = wave_sum(x);
+    y = wave_sum(y);
+    if ((threadIdx.x & 63) == 0) {
+      b[threadIdx.x >> 6] = x;
+      b[4 + (threadIdx.x >> 6)] = y;
+    }
+    __syncthreads();
+    return double2{(b[0] + b[1]) + (b[2] + b[3]), (b[4] + b[5]) + (b[6] + b[7])};
+  }
+  __device__ double max(double x) {
+    double* b = sh.ring[parity];
+    parity ^= 1;
+    x = wave_max(x);
+    if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return fmax(fmax(b[0], b[1]), fmax(b[2], b[3]));
+  }
 };
 
 template <typename T, int MM>
-__device__ __forceinline__ void sweep_wg(const T* Hg, int n, T w, SWG<T, MM>& st, ShWG& sh) {
+__device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, MM>& st, ShWG& sh) {
   const int tid = threadIdx.x;
   const gptr<T> H = (gptr<T>)Hg;
   const cptr<T> Hs = (cptr<T>)Hg;
@@ -63,7 +103,7 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T w, SWG<T, MM>& st
     for (int r = 0; r < kRWG; ++r) {
       const int i = tid + kThreadsWG * r;
       const T h = (i < n) ? H[off + i] : (T)0;
-      st.cr[r] = -h;
+      st.cr[r] = (i == n - 1) ? sg - h : -h;
       st.ci[r] = (i == n - 1) ? w : (T)0;
       st.rc[r] = (T)0;
       st.rsr[r] = (T)1;
@@ -146,7 +186,7 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T w, SWG<T, MM>& st
       const int i = tid + kThreadsWG * r;
       if (r <= rk && i < k) {
         const T cr_ = st.cr[r], ci_ = st.ci[r];
-        const T o = -hc[r];
+        const T o = (i == k - 1) ? sg - hc[r] : -hc[r];  // M(i, k-1)
         T nkr = c * o + sr * cr_ + si * ci_;
         T nki = sr * ci_ - si * cr_;
         T n1r = sr * o - c * cr_;
@@ -391,17 +431,43 @@ __device__ __forceinline__ void write_output_wg(const ReqDesc& rd, int j0, int m
       double2 g;
       g.x = gr + ((gptr<double>)rd.D)[a * m + j0 + j];
       g.y = gi;
-      store_c(G, a * m + j0 + j, g);
+      store_c(G, g_index(rd, a, j0 + j), g);
     }
     __syncthreads();
   }
+}
+
+// Largest over smallest |R(k,k)| after sweep_wg (1 / R(k,k) sits on the row
+// k of its step; R(0,0) is thread 0's final carry entry).
+template <typename T, int MM>
+__device__ __forceinline__ double diag_ratio_wg(int n, const SWG<T, MM>& st, BlockRed& br) {
+  const int tid = threadIdx.x;
+  double lo = INFINITY, hi = 0.0;
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    const int i = tid + kThreadsWG * r;
+    double ri = INFINITY;
+    if (i == 0) {
+      const double ar = (double)st.cr[0], ai = (double)st.ci[0];
+      ri = 1.0 / sqrt(ar * ar + ai * ai);
+    } else if (i < n) {
+      ri = (double)st.rinv[r];
+    }
+    if (i < n) {
+      lo = fmin(lo, ri);
+      hi = fmax(hi, ri);
+    }
+  }
+  lo = -br.max(-lo);
+  hi = br.max(hi);
+  return hi / lo;
 }
 
 template <int MM>
 __device__ void solve_wg_fp64(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG& sh) {
   const int tid = threadIdx.x;
   const int n = rd.n, m = rd.m;
-  const double w = ((gptr<double>)rd.omega)[k];
+  const SPoint sp = point_of(rd, k);
   const gptr<double> Bt = (gptr<double>)rd.Bt;
   SWG<double, MM> st;
 #pragma unroll
@@ -413,50 +479,493 @@ __device__ void solve_wg_fp64(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG
       st.bi[r][j] = 0.0;
     }
   }
-  sweep_wg<double, MM>(rd.H, n, w, st, sh);
+  sweep_wg<double, MM>(rd.H, n, sp.re, sp.im, st, sh);
+  BlockRed br(sh);
+  // estimated error: u times the spread of R's diagonal; points above the
+  // request's tolerance are finished by the extended refinement
+  const double est = 0.5 * DBL_EPSILON * diag_ratio_wg<double, MM>(n, st, br);
+  if (!(est <= rd.rtol) || (rd.flags & kFlagForceDD)) {  // uniform
+    if (tid == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
+    __syncthreads();  // LDS reuse by the next point
+    return;
+  }
   apply_rotations_wg<double, MM>(n, st, sh);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
   write_output_wg<MM>(rd, j0, mc, st.br, st.bi, G, sh);
-  if (rd.info && tid == 0 && j0 == 0) {
+  if (tid == 0) {
     lti_point_info inf;
-    inf.est_rel_err = 0.0f;  // no diagonal-ratio estimate on this path
+    inf.est_rel_err = (float)est;
     inf.iters = 1;
-    inf.path = st.singular ? LTI_PATH_SINGULAR : LTI_PATH_FP64;
+    inf.path = LTI_PATH_FP64;
     inf.reserved = 0;
-    store_info(rd.info, k, inf);
+    put_info(rd, k, inf);
   }
 }
 
+// r = Q^T B - (s X - H X) in float64.  X reaches every thread through LDS,
+// one 256-row slice at a time (xs: 256 x MM complex values); thread i sums
+// row i of H X over the slice's columns j >= i - 1.
 template <int MM>
+__device__ __forceinline__ void residual_wg(const ReqDesc& rd, double sg, double w, int j0, int mc,
+                                            const double (&xr)[kRWG][MM], const double (&xi)[kRWG][MM],
+                                            double (&rr)[kRWG][MM], double (&ri)[kRWG][MM], double2* xs) {
+  const int tid = threadIdx.x;
+  const int n = rd.n, m = rd.m;
+  const gptr<double> Bt = (gptr<double>)rd.Bt;
+  const gptr<double> H = (gptr<double>)rd.H;
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    const int i = tid + kThreadsWG * r;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      const double b = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
+      rr[r][j] = fma(w, xi[r][j], fma(-sg, xr[r][j], b));
+      ri[r][j] = fma(-w, xr[r][j], -sg * xi[r][j]);
+    }
+  }
+  sfor<0, kRWG>([&](auto sc_) {
+    constexpr int sj = decltype(sc_)::value;
+    if (kThreadsWG * sj >= n) return;  // uniform
+#pragma unroll
+    for (int j = 0; j < MM; ++j) xs[tid * MM + j] = double2{xr[sj][j], xi[sj][j]};
+    __syncthreads();
+    const int jend = min(kThreadsWG, n - kThreadsWG * sj);
+    for (int jl = 0; jl < jend; ++jl) {
+      const int jc = kThreadsWG * sj + jl;
+      const int64_t off = hoff(jc);
+      double2 xj[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) xj[j] = xs[jl * MM + j];
+#pragma unroll
+      for (int r = 0; r < kRWG; ++r) {
+        const int i = tid + kThreadsWG * r;
+        if (r <= sj + 1 && i <= jc + 1 && i < n) {  // H(i, jc) = 0 below the subdiagonal
+          const double h = H[off + i];
+#pragma unroll
+          for (int j = 0; j < MM; ++j) {
+            rr[r][j] = fma(h, xj[j].x, rr[r][j]);
+            ri[r][j] = fma(h, xj[j].y, ri[r][j]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  });
+}
+
+// Refined path for 257 .. 1024 states: complex-float32 solves of the scaled
+// residual, float64 residuals and accumulation (Higham, Accuracy and
+// Stability of Numerical Algorithms, ch. 12); stalled points go to the
+// extended refinement.  Every decision below is uniform over the workgroup.
+template <int MM>
+__device__ void solve_wg_refined(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG& sh, double2* xs) {
+  const int tid = threadIdx.x;
+  const int n = rd.n, m = rd.m;
+  const SPoint sp = point_of(rd, k);
+  const float sgf = (float)sp.re, wf = (float)sp.im;
+  const double tol = 0.1 * rd.rtol;
+  constexpr int kMaxIters = 6;
+  const gptr<float> Bt32 = (gptr<float>)rd.Bt32;
+  BlockRed br(sh);
+  SWG<float, MM> st;
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    const int i = tid + kThreadsWG * r;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      st.br[r][j] = (i < n && j < mc) ? Bt32[i * m + j0 + j] : 0.0f;
+      st.bi[r][j] = 0.0f;
+    }
+  }
+  sweep_wg<float, MM>(rd.H32, n, sgf, wf, st, sh);
+  apply_rotations_wg<float, MM>(n, st, sh);
+  double xr[kRWG][MM], xi[kRWG][MM];
+  double s2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r)
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      xr[r][j] = (double)st.br[r][j];
+      xi[r][j] = (double)st.bi[r][j];
+      s2 += xr[r][j] * xr[r][j] + xi[r][j] * xi[r][j];
+    }
+  double dprev = sqrt(br.sum(s2));
+  const bool singular = br.max(st.singular ? 1.0 : 0.0) > 0.0;
+  int iters = 1;
+  double est = 1.0;
+  bool ok = false;
+  if (!singular && dprev < INFINITY && !(rd.flags & kFlagForceDD)) {
+    for (int it = 0; it < kMaxIters; ++it) {
+      double rr[kRWG][MM], ri[kRWG][MM];
+      residual_wg<MM>(rd, sp.re, sp.im, j0, mc, xr, xi, rr, ri, xs);
+      double amax = 0.0;
+#pragma unroll
+      for (int r = 0; r < kRWG; ++r)
+#pragma unroll
+        for (int j = 0; j < MM; ++j) amax = fmax(amax, fmax(fabs(rr[r][j]), fabs(ri[r][j])));
+      amax = br.max(amax);
+      if (amax == 0.0) {  // X solves the float64 system exactly
+        est = 0.0;
+        ok = true;
+        break;
+      }
+      const double scale = 1.0 / amax;
+#pragma unroll
+      for (int r = 0; r < kRWG; ++r)
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          st.br[r][j] = (float)(rr[r][j] * scale);
+          st.bi[r][j] = (float)(ri[r][j] * scale);
+        }
+      sweep_wg<float, MM>(rd.H32, n, sgf, wf, st, sh);
+      apply_rotations_wg<float, MM>(n, st, sh);
+      ++iters;
+      double d2 = 0.0, x2 = 0.0;
+#pragma unroll
+      for (int r = 0; r < kRWG; ++r)
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          const double dr = (double)st.br[r][j] * amax;
+          const double di = (double)st.bi[r][j] * amax;
+          xr[r][j] += dr;
+          xi[r][j] += di;
+          d2 += dr * dr + di * di;
+          x2 += xr[r][j] * xr[r][j] + xi[r][j] * xi[r][j];
+        }
+      const double2 dx = br.sum2(d2, x2);
+      const double dn = sqrt(dx.x), xn = sqrt(dx.y);
+      if (!(dn < INFINITY) || !(xn > 0.0)) break;  // non-finite: stalled
+      const double rel = dn / xn;
+      const double pred = rel * (dn / dprev);
+      est = (pred < rel) ? pred : rel;
+      if (rel <= tol || pred <= tol) {
+        ok = true;
+        break;
+      }
+      if (dn > 0.5 * dprev) break;  // stalled
+      dprev = dn;
+    }
+  }
+  if (!ok) {
+    if (tid == 0) enqueue_dd(rd, k, j0, mc, iters, kReasonStall);
+    __syncthreads();
+    return;
+  }
+  double* G = rd.G + (size_t)k * rd.p * m * 2;
+  write_output_wg<MM>(rd, j0, mc, xr, xi, G, sh);
+  if (tid == 0) {
+    lti_point_info inf;
+    inf.est_rel_err = (float)est;
+    inf.iters = (uint8_t)iters;
+    inf.path = LTI_PATH_REFINED;
+    inf.reserved = 0;
+    put_info(rd, k, inf);
+  }
+}
+
 // At most 256 registers per lane, so that two workgroups share a CU (the
 // step loop is latency-bound: one barrier and one LDS round trip per step);
 // the four-column kernel then keeps a few values of its set-up and output
 // phases in scratch memory, none in the step loop.
+template <int PREC, int MM>
 __global__ __launch_bounds__(kThreadsWG) __attribute__((amdgpu_waves_per_eu(2))) void sweep_wg_kernel(
     const SweepLaunch L) {
   __shared__ ShWG sh;
+  __shared__ double2 xs[PREC == LTI_PREC_FP64 ? 1 : kThreadsWG * MM];
   const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
   if (tile >= L.ntiles) return;
   const int s = seg_of(L, tile);
   const ReqDesc rd = L.seg[s].rd;
   const Tile td = tile_of(L.seg[s], tile);
-  for (uint32_t f = 0; f < td.count; ++f) solve_wg_fp64<MM>(rd, (int64_t)td.start + f, td.j0, td.mc, sh);
+  for (uint32_t f = 0; f < td.count; ++f) {
+    if (PREC == LTI_PREC_FP64)
+      solve_wg_fp64<MM>(rd, (int64_t)td.start + f, td.j0, td.mc, sh);
+    else
+      solve_wg_refined<MM>(rd, (int64_t)td.start + f, td.j0, td.mc, sh, xs);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Extended-precision refinement of queued points.
+//
+// Near an eigenvalue of A the error of a float64 result is dominated by the
+// rounding of the reduction H = Q^T A Q itself (a relative perturbation of A
+// of order u is amplified by kappa(s I - A)), which no refinement against H
+// can remove.  So the residual is taken against the original model: with x
+// in double-double (Dekker's pair arithmetic), r = B - (s I - A) x is formed
+// exactly enough (each product split by FMA, sums by two-sum) and rounded,
+// and the correction solves (s I - A) d = r through the reduced model,
+// d = Q (s I - H)^{-1} Q^T r, by the float64 Givens sweep.  The iteration
+// converges while kappa(s I - A) u64 is well below one, to a forward error of
+// order u64 (Higham, Accuracy and Stability of Numerical Algorithms, 2nd ed.,
+// sec. 12.1, residual in higher precision).  Q is applied as its reflectors.
+
+struct dd {
+  double hi, lo;
+};
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return dd{s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {
+  const double s = a + b;
+  return dd{s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+  const dd s = two_sum(x.hi, y.hi);
+  return fast_two_sum(s.hi, s.lo + (x.lo + y.lo));
+}
+// x * a, a a double
+__device__ __forceinline__ dd dd_mul_d(dd x, double a) {
+  const double p = x.hi * a;
+  const double e = fma(x.hi, a, -p);
+  return fast_two_sum(p, fma(x.lo, a, e));
+}
+
+struct DDShared {
+  ShWG sh;
+  double4 x[kMaxNWG];  // x (re hi, re lo, im hi, im lo) for the row products
+};
+
+// v <- Q^T v (forward = true) or Q v, Q = P_0 ... P_{n-3}.
+__device__ __forceinline__ void apply_q(const ReducedModel& rm, bool forward, double (&vr)[kRWG],
+                                        double (&vi)[kRWG], BlockRed& br) {
+  const int n = rm.n, tid = threadIdx.x;
+  const gptr<double> V = (gptr<double>)rm.V;
+  const gptr<double> tau = (gptr<double>)rm.tau;
+  for (int q = 0; q + 2 < n; ++q) {
+    const int kk = forward ? q : n - 3 - q;
+    const int64_t vo = voff(n, kk) - (kk + 2);
+    double v[kRWG];
+    double pr = 0.0, pi = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      const int i = tid + kThreadsWG * r;
+      v[r] = (i == kk + 1) ? 1.0 : (i >= kk + 2 && i < n) ? V[vo + i] : 0.0;
+      pr = fma(v[r], vr[r], pr);
+      pi = fma(v[r], vi[r], pi);
+    }
+    const double2 d = br.sum2(pr, pi);
+    const double t = tau[kk];
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      vr[r] = fma(-t * d.x, v[r], vr[r]);
+      vi[r] = fma(-t * d.y, v[r], vi[r]);
+    }
+  }
+}
+
+// (s I - H) y = c for one right-hand side through the float64 sweep; on
+// return y = (yr, yi); returns whether R had a zero diagonal entry.
+__device__ __forceinline__ bool hess_solve(const ReducedModel& rm, SPoint sp, double (&yr)[kRWG],
+                                           double (&yi)[kRWG], ShWG& sh, BlockRed& br) {
+  SWG<double, 1> st;
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    st.br[r][0] = yr[r];
+    st.bi[r][0] = yi[r];
+  }
+  sweep_wg<double, 1>(rm.H, rm.n, sp.re, sp.im, st, sh);
+  const bool singular = br.max(st.singular ? 1.0 : 0.0) > 0.0;
+  apply_rotations_wg<double, 1>(rm.n, st, sh);
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    yr[r] = st.br[r][0];
+    yi[r] = st.bi[r][0];
+  }
+  return singular;
+}
+
+struct DDResult {
+  double est;
+  int solves;
+  bool singular;
+};
+
+// Column j of point k: G(:, j) = C0 x + D(:, j) with x refined as above.
+__device__ DDResult refine_column(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j, DDShared& S,
+                                  BlockRed& br) {
+  const int tid = threadIdx.x;
+  const int n = rm.n, m = rm.m, p = rm.p;
+  const SPoint sp = point_of(rd, k);
+  const double tol = 0.1 * rd.rtol;
+  constexpr int kMaxDD = 4;
+  const gptr<double> Bt = (gptr<double>)rm.Bt;
+  const gptr<double> A0 = (gptr<double>)rm.A0;  // column-major
+  const gptr<double> B0 = (gptr<double>)rm.B0;  // column-major
+  const gptr<double> C0 = (gptr<double>)rm.C0;  // row-major
+  DDResult res{0.0, 1, false};
+  double yr[kRWG], yi[kRWG];
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    const int i = tid + kThreadsWG * r;
+    yr[r] = (i < n) ? Bt[i * m + j] : 0.0;
+    yi[r] = 0.0;
+  }
+  res.singular = hess_solve(rm, sp, yr, yi, S.sh, br);
+  double* G = rd.G + (size_t)k * rd.p * rd.m * 2;
+  if (res.singular) {  // the float64 solution as it is (IEEE values)
+    double xr1[kRWG][1], xi1[kRWG][1];
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      xr1[r][0] = yr[r];
+      xi1[r][0] = yi[r];
+    }
+    write_output_wg<1>(rd, j, 1, xr1, xi1, G, S.sh);
+    res.est = INFINITY;
+    return res;
+  }
+  apply_q(rm, false, yr, yi, br);  // x = Q y
+  dd xr[kRWG], xi[kRWG];
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    xr[r] = dd{yr[r], 0.0};
+    xi[r] = dd{yi[r], 0.0};
+  }
+  double dprev = INFINITY;
+  for (int it = 0; it < kMaxDD; ++it) {
+    // r = B0(:, j) - s x + A0 x, in double-double, then rounded
+    __syncthreads();  // S.x of the previous pass has been read
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      const int i = tid + kThreadsWG * r;
+      if (i < n) S.x[i] = double4{xr[r].hi, xr[r].lo, xi[r].hi, xi[r].lo};
+    }
+    __syncthreads();
+    dd ar[kRWG], ai[kRWG];
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      const int i = tid + kThreadsWG * r;
+      const double b = (i < n) ? B0[(size_t)j * n + i] : 0.0;
+      // b - sg x + w i x:  re = b - sg xr + w xi,  im = -sg xi - w xr
+      ar[r] = dd_add(dd_add(dd{b, 0.0}, dd_mul_d(xr[r], -sp.re)), dd_mul_d(xi[r], sp.im));
+      ai[r] = dd_add(dd_mul_d(xi[r], -sp.re), dd_mul_d(xr[r], -sp.im));
+    }
+    for (int c = 0; c < n; ++c) {
+      const double4 xc = S.x[c];
+#pragma unroll
+      for (int r = 0; r < kRWG; ++r) {
+        const int i = tid + kThreadsWG * r;
+        if (i < n) {
+          const double a = A0[(size_t)c * n + i];
+          ar[r] = dd_add(ar[r], dd_mul_d(dd{xc.x, xc.y}, a));
+          ai[r] = dd_add(ai[r], dd_mul_d(dd{xc.z, xc.w}, a));
+        }
+      }
+    }
+    double rr[kRWG], ri[kRWG];
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      rr[r] = ar[r].hi + ar[r].lo;
+      ri[r] = ai[r].hi + ai[r].lo;
+    }
+    // d = Q (s I - H)^{-1} Q^T r
+    apply_q(rm, true, rr, ri, br);
+    hess_solve(rm, sp, rr, ri, S.sh, br);
+    apply_q(rm, false, rr, ri, br);
+    ++res.solves;
+    double d2 = 0.0, x2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      xr[r] = dd_add(xr[r], dd{rr[r], 0.0});
+      xi[r] = dd_add(xi[r], dd{ri[r], 0.0});
+      d2 += rr[r] * rr[r] + ri[r] * ri[r];
+      x2 += xr[r].hi * xr[r].hi + xi[r].hi * xi[r].hi;
+    }
+    const double2 dx = br.sum2(d2, x2);
+    const double dn = sqrt(dx.x), xn = sqrt(dx.y);
+    res.est = (xn > 0.0) ? dn / xn : (dn > 0.0 ? INFINITY : 0.0);
+    if (!(res.est > tol)) break;        // converged (or x = 0 exactly)
+    if (!(dn < 0.5 * dprev)) break;     // no longer contracting
+    dprev = dn;
+  }
+  // G(:, j) = C0 x + D(:, j): per-thread double-double sums, then the
+  // workgroup sum of the high and low parts
+  for (int a = 0; a < p; ++a) {
+    dd gr{0.0, 0.0}, gi{0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      const int i = tid + kThreadsWG * r;
+      if (i < n) {
+        const double c = C0[(size_t)a * n + i];
+        gr = dd_add(gr, dd_mul_d(xr[r], c));
+        gi = dd_add(gi, dd_mul_d(xi[r], c));
+      }
+    }
+    const double2 hi = br.sum2(gr.hi, gi.hi);
+    const double2 lo = br.sum2(gr.lo, gi.lo);
+    if (tid == 0) {
+      double2 g;
+      g.x = (hi.x + lo.x) + ((gptr<double>)rm.D)[a * m + j];
+      g.y = hi.y + lo.y;
+      store_c(G, g_index(rd, a, j), g);
+    }
+  }
+  return res;
+}
+
+// One workgroup per queued entry at a time; entries of every segment are
+// spread over the grid.
+__global__ __launch_bounds__(kThreadsWG) void refine_dd_kernel(const DDLaunch L) {
+  __shared__ DDShared S;
+  for (int sgi = 0; sgi < L.nseg; ++sgi) {
+    const DDSeg& g = L.seg[sgi];
+    // entries: one per (point, column group) at most, K x m
+    const uint32_t cap = g.rd.n > 0 ? (uint32_t)min((uint64_t)UINT32_MAX, (uint64_t)L.seg[sgi].K * g.rd.m) : 0u;
+    const uint32_t cnt = min(*((const volatile uint32_t*)g.rd.fbq), cap);
+    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
+      const uint32_t k = ((gptr<uint32_t>)g.rd.fbq)[2 + 2 * (size_t)e];
+      const uint32_t w1 = ((gptr<uint32_t>)g.rd.fbq)[3 + 2 * (size_t)e];
+      const int j0 = (int)(w1 & 0xffu), mc = (int)((w1 >> 8) & 0xffu);
+      const int solves32 = (int)((w1 >> 16) & 0xffu), reason = (int)(w1 >> 24);
+      BlockRed br(S.sh);
+      double est = 0.0;
+      int solves = 0;
+      bool singular = false;
+      for (int j = j0; j < j0 + mc; ++j) {
+        const DDResult rr = refine_column(g.rd, g.rm, (int64_t)k, j, S, br);
+        est = fmax(est, rr.est);
+        solves = max(solves, rr.solves);
+        singular = singular || rr.singular;
+      }
+      if (threadIdx.x == 0) {
+        lti_point_info inf;
+        inf.est_rel_err = (float)est;
+        inf.iters = (uint8_t)min(255, solves32 + solves);
+        inf.path = singular ? LTI_PATH_SINGULAR : (reason == kReasonStall ? LTI_PATH_FALLBACK : LTI_PATH_FP64_DD);
+        inf.reserved = 0;
+        put_info(g.rd, (int64_t)k, inf);
+      }
+      __syncthreads();  // LDS reuse by the next entry
+    }
+  }
 }
 
 }  // namespace
 
 int sweep_wg_class(int precision, int n, int mc) {
-  if (precision != LTI_PREC_FP64) return -1;
+  if (precision != LTI_PREC_FP64 && precision != LTI_PREC_REFINED) return -1;
   if (n <= kMaxN || n > kThreadsWG * kRWG || mc < 1 || mc > 4) return -1;
-  return (mc <= 1) ? 0 : (mc <= 2) ? 1 : 2;
+  return precision * 3 + ((mc <= 1) ? 0 : (mc <= 2) ? 1 : 2);
 }
 
 hipError_t launch_sweep_wg(int cls, const SweepLaunch& L, hipStream_t s) {
   if (L.ntiles <= 0) return hipSuccess;
-  if (cls < 0 || cls > 2) return hipErrorInvalidValue;
+  if (cls < 0 || cls >= kNumSweepWGClasses) return hipErrorInvalidValue;
   using Fn = void (*)(const SweepLaunch);
-  const Fn fn = cls == 0 ? sweep_wg_kernel<1> : cls == 1 ? sweep_wg_kernel<2> : sweep_wg_kernel<4>;
-  hipLaunchKernelGGL(fn, dim3(L.ntiles), dim3(kThreadsWG), 0, s, L);
+  static const Fn fns[kNumSweepWGClasses] = {
+      sweep_wg_kernel<LTI_PREC_FP64, 1>,    sweep_wg_kernel<LTI_PREC_FP64, 2>,
+      sweep_wg_kernel<LTI_PREC_FP64, 4>,    sweep_wg_kernel<LTI_PREC_REFINED, 1>,
+      sweep_wg_kernel<LTI_PREC_REFINED, 2>, sweep_wg_kernel<LTI_PREC_REFINED, 4>};
+  hipLaunchKernelGGL(fns[cls], dim3(L.ntiles), dim3(kThreadsWG), 0, s, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_dd(const DDLaunch& L, int grid, hipStream_t s) {
+  if (L.nseg <= 0) return hipSuccess;
+  if (L.nseg > kMaxDDSegs || grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(refine_dd_kernel, dim3(grid), dim3(kThreadsWG), 0, s, L);
   return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ __all__ = [
     "pole_matrix",
     "mixed_pole_model",
     "damped_pole_model",
+    "resonant_model",
     "logspace_grid",
     "siso8",
     "mimo64",
@@ -171,6 +172,24 @@ def damped_pole_model(rng, n: int, m: int, p: int, seed: int = -1):
     Lam, poles = pole_matrix(np.zeros(0), sigma, omega_d)
     mdl = _finish_model(rng, Lam, poles, m, p, np.zeros(0), seed)
     return mdl, omega_d
+
+
+def resonant_model(n: int, m: int, p: int, zeta: float, wn: float, seed: int,
+                   offsets=(0.0, 1e-8, -1e-8, 1e-7, -1e-7, 1e-6, 1e-5)) -> Model:
+    """Mixed poles (as ``mixed_pole_model``, n - 2 states) plus one pair with
+    damping ratio ``zeta`` and natural frequency ``wn``; the grid holds 24
+    log-spaced points in [1e-2, 1e2] and the points omega_d (1 + offset) next
+    to that pair's damped frequency (kappa(jw I - A) ~ max|pole| / (zeta wn)
+    there)."""
+    rng = np.random.default_rng(seed)
+    n_pairs = (n - 2) // 4
+    n_real = (n - 2) - 2 * n_pairs
+    real_poles = -rng.uniform(0.1, 2.0, n_real)
+    sigma = np.concatenate([[-zeta * wn], -rng.uniform(0.05, 1.0, n_pairs)])
+    omega_d = np.concatenate([[wn * np.sqrt(1.0 - zeta * zeta)], rng.uniform(0.5, 10.0, n_pairs)])
+    Lam, poles = pole_matrix(real_poles, sigma, omega_d)
+    w = np.concatenate([logspace_grid(1e-2, 1e2, 24), omega_d[0] * (1.0 + np.asarray(offsets))])
+    return _finish_model(rng, Lam, poles, m, p, w, seed)
 
 
 def logspace_grid(lo: float, hi: float, K: int) -> np.ndarray:

@@ -1,11 +1,11 @@
 """GPU parity on the lightly damped workload at full size: 256 states, 4x4,
 4096 frequencies of which 1024 sit within 1 % of a resonance.
 
-Near a resonance kappa(jw I - A) reaches ~1e7, where no float64 method (the
-float64 oracle included) is better than ~kappa * u64; sampled points are
-therefore judged against the extended-precision oracle, with the bound
-max(1e-9, 64 kappa u64), kappa in closed form (A is normal by construction).
-Points that refined in float32 must meet 1e-9 outright.
+Near a resonance kappa(jw I - A) reaches ~1e6 here; the float64 oracle is
+then off by up to ~kappa * u64, so sampled points are judged against the
+extended-precision oracle.  The contract holds outright: refined points
+<= 1e-9, float64 points <= 1e-10 (points whose estimated error exceeds the
+request's tolerance take the double-double refinement against A).
 """
 import numpy as np
 import pytest
@@ -14,8 +14,6 @@ import oracle
 from paper_2401_04068_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
-
-U64 = 2.0 ** -53
 
 
 def _kappa_normal(poles, omega):
@@ -32,7 +30,7 @@ def eng():
     e.close()
 
 
-@pytest.mark.parametrize("j", [0, 1])
+@pytest.mark.parametrize("j", [0, 1, 24])
 def test_damped256_refined_full_grid(eng, j):
     from paper_2401_04068_amd import binding
 
@@ -44,8 +42,10 @@ def test_damped256_refined_full_grid(eng, j):
     assert np.all(np.isfinite(G.view(np.float64)))
     paths = info["path"]
     assert set(np.unique(paths)) <= {binding.PATH_REFINED, binding.PATH_FALLBACK}
+    assert h.result["n_fallback"] == int(np.sum(paths == binding.PATH_FALLBACK))
     kappa = _kappa_normal(mdl.poles, mdl.omega)
-    # sample: spread over the log grid, the clustered points, and every fallback point
+    # sample: spread over the log grid, the clustered points, every fallback
+    # point and the most ill-conditioned points
     idx = np.unique(np.concatenate([
         np.arange(0, 3072, 97),
         3072 + np.arange(0, 1024, 41),
@@ -54,23 +54,23 @@ def test_damped256_refined_full_grid(eng, j):
     ]))
     ref = oracle.freqresp_extended(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[idx])
     err = oracle.rel_err(G[idx], ref)
-    bound = np.maximum(1e-9, 64 * kappa[idx] * U64)
-    bad = np.flatnonzero(err > bound)
-    assert bad.size == 0, [(int(idx[b]), err[b], kappa[idx[b]], int(paths[idx[b]])) for b in bad[:5]]
-    refined = paths[idx] == binding.PATH_REFINED
-    assert np.all(err[refined] <= 1e-9)
-    print(f"damped256 model {j}: fallback points {int(np.sum(paths == binding.PATH_FALLBACK))}, "
-          f"sample max err {err.max():.2e}, max kappa {kappa.max():.2e}", flush=True)
+    assert err.max() <= 1e-9, (int(idx[err.argmax()]), err.max(), kappa[idx[err.argmax()]])
+    # the refinement's own stopping target is 1e-10
+    assert np.all(err[paths[idx] == binding.PATH_FALLBACK] <= 1e-10)
 
 
-def test_damped256_fp64_sampled(eng):
+@pytest.mark.parametrize("j", [2, 24])
+def test_damped256_fp64_sampled(eng, j):
     from paper_2401_04068_amd import binding
 
-    mdl = wl.damped256_model(2)
+    mdl = wl.damped256_model(j)
     h = eng.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=binding.PREC_FP64)
     assert eng.poll(h, -1)
     kappa = _kappa_normal(mdl.poles, mdl.omega)
-    idx = np.unique(np.concatenate([np.arange(0, 4096, 128), np.argsort(kappa)[-8:]]))
+    paths = h.info["path"]
+    assert set(np.unique(paths)) <= {binding.PATH_FP64, binding.PATH_FP64_DD}
+    idx = np.unique(np.concatenate([np.arange(0, 4096, 128), np.argsort(kappa)[-8:],
+                                    np.flatnonzero(paths == binding.PATH_FP64_DD)[:20]]))
     ref = oracle.freqresp_extended(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[idx])
     err = oracle.rel_err(h.G[idx], ref)
-    assert np.all(err <= np.maximum(1e-10, 64 * kappa[idx] * U64))
+    assert err.max() <= 1e-10, (int(idx[err.argmax()]), err.max(), kappa[idx[err.argmax()]])

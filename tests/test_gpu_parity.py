@@ -92,10 +92,21 @@ def test_reduced_model_matches_oracle(eng, n, m, p):
     print(f"case reduced n={n} m={m} p={p}", flush=True)
     _run(eng, mdl, _prec("fp64"), key=key)
     H, Bt, Ct = eng.get_reduced(key, n, m, p)
-    assert np.all(np.tril(H, -2) == 0.0)
-    Ho, Bo, Co = hessenberg.hessenberg(mdl.A, mdl.B, mdl.C)
-    Hn, Bn, Cn = hessenberg.normalize_signs(H, Bt, Ct)
-    Hon, Bon, Con = hessenberg.normalize_signs(Ho, Bo, Co)
+    if p < m:
+        # reduced through the transposed system (A^T, C^T, B^T): H is the
+        # transpose of that system's Hessenberg form
+        assert np.all(np.triu(H, 2) == 0.0)
+        Ho, Bo, Co = hessenberg.hessenberg(mdl.A.T, mdl.C.T, mdl.B.T)
+        Hn, Cn_t, Bn_t = hessenberg.normalize_signs(H.T, Ct.T, Bt.T)
+        Bn, Cn = Bn_t.T, Cn_t.T
+        Hn = Hn.T
+        Hon, Con_t, Bon_t = hessenberg.normalize_signs(Ho, Bo, Co)
+        Hon, Bon, Con = Hon.T, Bon_t.T, Con_t.T
+    else:
+        assert np.all(np.tril(H, -2) == 0.0)
+        Ho, Bo, Co = hessenberg.hessenberg(mdl.A, mdl.B, mdl.C)
+        Hn, Bn, Cn = hessenberg.normalize_signs(H, Bt, Ct)
+        Hon, Bon, Con = hessenberg.normalize_signs(Ho, Bo, Co)
     tol = 1e-12 * max(n, 64)
     assert np.abs(Hn - Hon).max() <= tol * np.abs(mdl.A).max()
     assert np.abs(Bn - Bon).max() <= tol * np.abs(mdl.B).max()

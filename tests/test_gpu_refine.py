@@ -1,0 +1,158 @@
+"""GPU: the double-double refinement against the original model (stalled
+refined points and ill-conditioned float64 points), merged point records
+when a point's columns are split over tiles, and the transposed solve.
+
+Every error is measured against the extended-precision oracle; at the
+constructed resonances kappa(jw I - A) ~ 1e8, where float64 Hessenberg
+solves are off by ~1e-9 and the oracle of record by ~kappa * 2^-64 ~ 5e-12.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_04068_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10  # both paths, against the extended oracle
+
+
+@pytest.fixture(scope="module")
+def eng():
+    from paper_2401_04068_amd import binding
+
+    e = binding.Engine(arena_bytes=2 << 30)
+    yield e
+    e.close()
+
+
+def _kappa(mdl):
+    d = np.abs(1j * mdl.omega[:, None] - mdl.poles[None, :])
+    return d.max(axis=1) / d.min(axis=1)
+
+
+@pytest.mark.parametrize("n", [16, 64, 100, 300])
+def test_stall_goes_to_double_double_refinement(eng, n):
+    """A pair with zeta = 1e-7 probed at its damped frequency: kappa * u32 is
+    far above 1, so float32 refinement stalls; the float64 solve alone misses
+    1e-9 there.  Both paths must meet 1e-10 after the extended refinement."""
+    from paper_2401_04068_amd import binding
+
+    mdl = wl.resonant_model(n, 2, 3, 1e-7, 1.0, seed=4100 + n)
+    kap = _kappa(mdl)
+    hard = kap > 1e7
+    assert hard.sum() >= 4
+    ref = oracle.freqresp_extended(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    for prec, dd_path in ((binding.PREC_REFINED, binding.PATH_FALLBACK), (binding.PREC_FP64, binding.PATH_FP64_DD)):
+        print(f"case resonant n={n} precision={prec}", flush=True)
+        h = eng.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=prec)
+        assert eng.poll(h, -1)
+        err = oracle.rel_err(h.G, ref)
+        paths = h.info["path"]
+        assert np.all(paths[hard] == dd_path), (paths[hard], kap[hard])
+        assert err.max() <= TOL, (err.max(), int(err.argmax()), kap[err.argmax()], int(paths[err.argmax()]))
+        n_dd = int(np.sum(paths == dd_path))
+        key = "n_fallback" if prec == binding.PREC_REFINED else "n_fp64_dd"
+        assert h.result[key] == n_dd >= hard.sum()
+        assert np.all(h.info["est_rel_err"][hard] <= TOL)
+
+
+def test_fallback_in_second_column_group_is_reported(eng):
+    """Eight inputs on a 40-state model: the columns are split over tiles of
+    at most four.  Columns 0-3 of B are zero (that group converges at once),
+    columns 4-7 are not (that group stalls at the resonance): the merged
+    record must say FALLBACK, with the second group's estimate."""
+    from paper_2401_04068_amd import binding
+
+    mdl = wl.resonant_model(40, 8, 8, 1e-7, 1.0, seed=4242)
+    mdl.B[:, :4] = 0.0
+    kap = _kappa(mdl)
+    hard = kap > 1e7
+    h = eng.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=binding.PREC_REFINED)
+    assert eng.poll(h, -1)
+    ref = oracle.freqresp_extended(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    assert oracle.rel_err(h.G, ref).max() <= TOL
+    assert np.all(h.info["path"][hard] == binding.PATH_FALLBACK)
+    assert np.all(h.info["iters"][hard] >= 2)
+    assert h.result["n_fallback"] == int(np.sum(h.info["path"] == binding.PATH_FALLBACK))
+
+
+@pytest.mark.parametrize("n,m,p", [(1, 1, 1), (2, 3, 3), (5, 2, 4), (64, 4, 4), (100, 3, 5), (256, 2, 2),
+                                   (300, 4, 4), (520, 1, 2)])
+def test_forced_refinement_matches_oracle(n, m, p):
+    """Every point through the double-double refinement (a testing flag),
+    both precisions, at sizes that span the kernel families."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(4300 + n)
+    w = np.concatenate([[0.0, -0.9], wl.logspace_grid(1e-2, 1e2, 9)])
+    mdl = wl.mixed_pole_model(rng, n, m, p, w)
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    with binding.Engine(arena_bytes=1 << 30, flags=binding.CFG_FORCE_DD) as e:
+        for prec, path in ((binding.PREC_FP64, binding.PATH_FP64_DD), (binding.PREC_REFINED, binding.PATH_FALLBACK)):
+            print(f"case forced n={n} m={m} p={p} precision={prec}", flush=True)
+            h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=prec)
+            assert e.poll(h, -1)
+            assert np.all(h.info["path"] == path)
+            err = oracle.rel_err(h.G, ref)
+            assert err.max() <= TOL, (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("n,m,p", [(8, 5, 2), (40, 8, 1), (100, 16, 3), (200, 6, 5), (300, 9, 4)])
+def test_transposed_solve_matches_untransposed(eng, n, m, p):
+    """Fewer outputs than inputs: the transposed system is solved (p
+    right-hand sides instead of m).  Same G as solving the system itself, and
+    as the oracle."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(4400 + n)
+    mdl = wl.mixed_pole_model(rng, n, m, p, np.concatenate([[0.0, -2.0], wl.logspace_grid(1e-2, 1e2, 30)]))
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    outs = {}
+    with binding.Engine(arena_bytes=512 << 20, flags=binding.CFG_NO_TRANSPOSE) as e2:
+        for prec in (binding.PREC_FP64, binding.PREC_REFINED):
+            h = e2.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=prec)
+            assert e2.poll(h, -1)
+            outs[("plain", prec)] = h.G
+    for prec in (binding.PREC_FP64, binding.PREC_REFINED):
+        print(f"case transposed n={n} m={m} p={p} precision={prec}", flush=True)
+        h = eng.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=prec)
+        assert eng.poll(h, -1)
+        tol = 1e-10 if prec == binding.PREC_FP64 else 1e-9
+        assert oracle.rel_err(h.G, ref).max() <= tol
+        assert oracle.rel_err(h.G, outs[("plain", prec)]).max() <= tol
+
+
+def test_damped_batch_side_by_side(eng):
+    """Thirty-two lightly damped 256-state models (full 4096-point grids)
+    submitted at once, refined: their reductions share one launch; sampled
+    points (the most ill-conditioned of each model among them, and its
+    fallback points) meet 1e-10 against the extended oracle, and the per-path
+    counts agree with the point records."""
+    from paper_2401_04068_amd import binding
+
+    models = [wl.damped256_model(j) for j in range(32)]
+    s0 = eng.stats()
+    hs = [eng.submit(m.A, m.B, m.C, m.D, m.omega, precision=binding.PREC_REFINED) for m in models]
+    for h in hs:
+        assert eng.poll(h, -1)
+    s1 = eng.stats()
+    assert s1["reductions"] - s0["reductions"] == 32
+    n_fb = sum(h.result["n_fallback"] for h in hs)
+    print(f"damped batch: fallback points {n_fb}", flush=True)
+    for h in hs:
+        paths = h.info["path"]
+        assert set(np.unique(paths)) <= {binding.PATH_REFINED, binding.PATH_FALLBACK}
+        assert h.result["n_fallback"] == int(np.sum(paths == binding.PATH_FALLBACK))
+        assert h.result["n_refined"] + h.result["n_fallback"] == 4096
+    worst = 0.0
+    for j in range(0, 32, 4):
+        mdl, h = models[j], hs[j]
+        kap = _kappa(mdl)
+        fb = np.flatnonzero(h.info["path"] == binding.PATH_FALLBACK)
+        idx = np.unique(np.concatenate([np.argsort(kap)[-3:], fb[:3], np.arange(0, 4096, 512)]))
+        ref = oracle.freqresp_extended(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[idx])
+        err = oracle.rel_err(h.G[idx], ref)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= TOL, (j, err.max(), int(idx[err.argmax()]), kap[idx[err.argmax()]])
+    print(f"damped batch: sampled max err {worst:.2e}", flush=True)

@@ -291,3 +291,94 @@ def test_hessenberg_preserves_transfer_function():
     assert np.max(oracle.rel_err(G2, G1)) < 1e-12
     ev = np.sort_complex(np.linalg.eigvals(H))
     assert np.max(np.abs(ev - np.sort_complex(mdl.poles))) < 1e-11
+
+
+# ---------------------------------------------------------------- complex points
+
+GOLDEN_S = os.path.join(os.path.dirname(__file__), "golden", "closed_forms_s.txt")
+
+
+def _golden_s_rows():
+    rows = []
+    with open(GOLDEN_S) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            kind, *vals = line.split()
+            rows.append((kind, [float(v) for v in vals]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_s_rows(), ids=lambda r: f"{r[0]}-{r[1]}")
+def test_golden_closed_forms_complex_points(row):
+    """Hand-derived first-order values at s off the imaginary axis
+    (continuous time) and at z = exp(j theta) (discrete time)."""
+    kind, (a, b, c, d, x, y, re, im) = row
+    if kind == "cs":
+        sys_ = (np.array([[-a]]), np.array([[b]]), np.array([[c]]), np.array([[d]]))
+        s = complex(x, y)
+    else:
+        sys_ = (np.array([[a]]), np.array([[b]]), np.array([[c]]), np.array([[d]]))
+        s = np.exp(1j * x)
+    ref = complex(re, im)
+    for fn in (oracle.freqresp_at, oracle.freqresp_at_extended):
+        G = fn(*sys_, [s])[0, 0, 0]
+        assert abs(G - ref) <= 1e-14 * abs(ref), (fn.__name__, G, ref)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_complex_points_exact_rational(seed):
+    """Brute force over Q(j) at rational s = sigma + j w: a dropped or
+    sign-flipped real part of s, or a transposed A, fails this."""
+    rng = np.random.default_rng(300 + seed)
+    n = 1 + seed % 4
+    m, p = 1 + seed % 2, 1 + (seed + 1) % 3
+    A, B, C, D = _rand_small_int_system(rng, n, m, p)
+    for sig, w in [(Fraction(1, 2), Fraction(3, 8)), (Fraction(-7, 4), Fraction(-5, 4)), (Fraction(9, 2), Fraction(0)),
+                   (Fraction(-1, 8), Fraction(33, 16))]:
+        try:
+            Gx = exact.freqresp_exact(A.tolist(), B.tolist(), C.tolist(), D.tolist(), w, sigma=sig)
+        except ZeroDivisionError:
+            continue
+        Gref = np.array([[exact.to_complex(z) for z in row] for row in Gx])
+        s = complex(float(sig), float(w))
+        M = s * np.eye(n) - A
+        kappa = np.linalg.cond(M)
+        for fn, u in ((oracle.freqresp_at, 1e-15), (oracle.freqresp_at_extended, 1e-18)):
+            G = fn(A, B, C, D, [s])[0]
+            err = np.linalg.norm(G - Gref) / max(np.linalg.norm(Gref), 1e-300)
+            assert err <= max(u * kappa * 10, 1e-15), (fn.__name__, seed, s, err, kappa)
+
+
+def test_discrete_time_impulse_response_series():
+    """For |z| > rho(A): G(z) = D + sum_k C A^k B z^-(k+1) (the z-transform of
+    the impulse response).  A stable discrete model (rho(A) = 0.8), on the
+    unit circle, summed to 400 terms (0.8^400 ~ 1e-39)."""
+    rng = np.random.default_rng(17)
+    n, m, p = 6, 2, 3
+    A = rng.standard_normal((n, n))
+    A *= 0.8 / np.max(np.abs(np.linalg.eigvals(A)))
+    B = rng.standard_normal((n, m))
+    C = rng.standard_normal((p, n))
+    D = rng.standard_normal((p, m))
+    theta = np.linspace(-np.pi, np.pi, 17)
+    z = np.exp(1j * theta)
+    G = oracle.freqresp_at(A, B, C, D, z)
+    Ak_B = B.astype(np.complex128)
+    series = np.broadcast_to(D.astype(np.complex128), (len(z), p, m)).copy()
+    zinv = 1.0 / z
+    zpow = zinv.copy()
+    for _ in range(400):
+        series += (C @ Ak_B)[None, :, :] * zpow[:, None, None]
+        Ak_B = A @ Ak_B
+        zpow = zpow * zinv
+    assert np.max(oracle.rel_err(G, series)) < 1e-12
+
+
+def test_complex_points_on_the_axis_agree_with_frequency_grid():
+    """s = j w gives the frequency response (two separate code paths)."""
+    mdl = wl.mimo64(K=40)
+    G1 = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    G2 = oracle.freqresp_at(mdl.A, mdl.B, mdl.C, mdl.D, 1j * mdl.omega)
+    assert np.max(oracle.rel_err(G2, G1)) < 1e-14
