@@ -1,22 +1,36 @@
 """Frequency-response benchmark on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mimo64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload serving]
 
-A step is one pass of the whole path over one synthetic model: submit the
-model with its frequency grid already resident in HBM (a device-memory
-request), let the library reduce A to Hessenberg form, run every per-frequency
-solve, and poll the result.  The throughput run keeps up to --window requests
-in flight (each is still a full step with its own reduction); the latency
-percentiles come from a second run with one request at a time.  The default workload is the 64-state, 4-input,
-4-output model on 2000 log-spaced frequencies evaluated on the plain float64
-path; the same workload is also timed on the refined float32 path and
-reported beside it.
+Default workload (the configuration the metric is quoted on): the serving
+mix of 4096 requests, each its own model with n ~ U{4..128} states,
+m, p ~ U{1..8}, K ~ U{256..4096} log-spaced frequencies in [1e-3, 1e3]
+(8.9 M points in all), on the refined path (complex-float32 solves with
+float64 Hessenberg reduction and float64 refinement to 1e-10) and, beside it,
+on the plain float64 path.
 
-Printed: one JSON line with points/s (counting only points whose relative
-error against the CPU oracle is <= 1e-10), per-step latency percentiles, the
-roofline of the per-frequency sweep kernel (timed with HIP events inside
-the library on the stream it runs on) and the CPU oracle timed
-on this host's cores.
+A step is one closed-loop pass of the whole hot path over the whole mix: all
+4096 requests submitted through the C ABI with their inputs already resident
+in HBM (device-memory requests), each reduced to Hessenberg form and solved
+at every frequency, and every result polled.  W untimed steps, then K timed
+steps.  `value` = refined points/s times the fraction of sampled points whose
+error against the CPU oracle is <= 1e-10.  Also reported:
+
+* the plain float64 path on the same mix (`fp64`), and refined / float64;
+* open-loop serving latency: the requests replayed from host memory at their
+  Poisson arrival times (2000 requests/s), arrival -> results visible,
+  p50/p99 (`latency_ms`);
+* the PCIe-inclusive closed-loop rate (host-memory requests: H2D and D2H in
+  the timed region), which is never `value`;
+* `roofline`: the kernel family that dominates the refined run's kernel
+  time, its algorithmic flops over its HIP-event time (events recorded by the
+  library on the stream the kernels run on), against the peak of the
+  arithmetic it does (float32 and float64 vector FMA);
+* `cpu_baseline`: the oracle (dense complex LU per point) on this host's
+  cores over a sample of the same mix;
+* `secondary`: the 64-state model (2000 points), the 1024-state model (ten
+  10,000-point queries, two of them repeats), and the 512 lightly damped
+  256-state models (4096 points each), one pass each.
 """
 from __future__ import annotations
 
@@ -25,6 +39,7 @@ import hashlib
 import json
 import multiprocessing as mp
 import os
+import platform
 import sys
 import time
 
@@ -36,27 +51,52 @@ if ROOT not in sys.path:
 
 METRIC = "frequency-response points/sec at ≤1e-10 rel err (refined vs plain FP64); p50/p99 latency"
 TOL = 1e-10
-FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# Vector peaks of the MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x
+# 2.4 GHz = 78.6 TFLOP/s in float64; twice that in float32 (the chip's
+# published 157.3 TFLOP/s vector float32 rate)
+FP64_VALU_PEAK = 78.6
+FP32_VALU_PEAK = 157.3
 PROFILES = os.path.join(ROOT, "profiles")
+KF_NAMES = ["sweep16_kernel (four frequencies per wavefront, n <= 64)",
+            "sweep_kernel (one frequency per wavefront, n <= 256)",
+            "sweep_wg_kernel (one frequency per workgroup, n <= 1024)",
+            "refine_dd_kernel (double-double refinement)"]
+KF_SOURCES = [["sweep16.hip", "sweep_common.h", "dpp.h", "lti_kernels.h"],
+              ["sweep.hip", "sweep_common.h", "lti_kernels.h"],
+              ["sweepwg.hip", "sweep_common.h", "lti_kernels.h"],
+              ["sweepwg.hip", "sweep_common.h", "lti_kernels.h"]]
 
 
-def sweep_flops_per_point(n: int, m: int, p: int) -> float:
-    """Algorithmic flops of one frequency on the float64 path: the column
-    rotations (14 flops per row per step, 7 n^2), the fused back-substitution
-    (8 flops per row, step and right-hand side, 4 m n^2) and G = Ct^T X
-    (4 n m p); O(n m) terms are left out."""
+def log(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def family_of(n: int) -> int:
+    """Kernel family the library runs an n-state request on."""
+    return 0 if n <= 64 else 1 if n <= 256 else 2
+
+
+def solve_flops(n: int, m: int, p: int) -> float:
+    """Algorithmic flops of one point's solve with m right-hand sides and p
+    outputs: the column rotations (14 flops per row and step, 7 n^2), the
+    fused back-substitution (8 flops per row, step and right-hand side,
+    4 m n^2) and G = (CQ) X (4 n m p)."""
     return 7.0 * n * n + 4.0 * m * n * n + 4.0 * n * m * p
 
 
-def sweep_kernel_family(n: int) -> tuple[str, list[str]]:
-    """The sweep kernel the library launches for an n-state float64 request
-    (with its default tiling) and the source files that define it."""
-    common = ["sweep_common.h", "dpp.h", "lti_kernels.h"]
-    if n <= 64:
-        return "sweep16_kernel", ["sweep16.hip"] + common
-    if n <= 256:
-        return "sweep_kernel", ["sweep.hip"] + common
-    return "sweep_wg_kernel", ["sweepwg.hip"] + common
+def point_flops(n: int, m: int, p: int, iters: np.ndarray, refined: bool):
+    """(float32 flops, float64 flops) of a request's points.  The library
+    solves the transposed system when p < m, so m here is min(m, p).
+    Refined: `iters` float32 sweeps (7 n^2 + 4 m n^2 each), iters - 1 float64
+    residuals (2 m n^2: the real Hessenberg H times complex X) and the float64
+    output (4 n m p)."""
+    ms, ps = min(m, p), max(m, p)
+    if not refined:
+        return 0.0, float(len(iters)) * solve_flops(n, ms, ps)
+    it = iters.astype(np.float64)
+    f32 = float(np.sum(it)) * (7.0 * n * n + 4.0 * ms * n * n)
+    f64 = float(np.sum(it - 1.0)) * 2.0 * ms * n * n + len(iters) * 4.0 * n * ms * ps
+    return f32, f64
 
 
 def _source_digest(files: list[str]) -> str:
@@ -67,403 +107,453 @@ def _source_digest(files: list[str]) -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic_record(workload: str, files: list[str], window: int):
-    """HBM bytes per point swept, from committed rocprofv3 counter runs over
-    every sweep dispatch of a bench run, used only while the kernel sources
-    and the number of requests in flight (which decides how launches are
-    formed) are the ones the counters were taken with."""
-    path = os.path.join(PROFILES, f"sweep_{workload}_traffic.json")
+def _traffic_record(name: str, files: list[str]):
+    """HBM bytes per point of a kernel family on a workload, from committed
+    rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE), used only while the
+    kernel sources are the ones the counters were taken with."""
+    path = os.path.join(PROFILES, f"{name}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha256_16") != _source_digest(files) or rec.get("window") != window:
+    if rec.get("source_sha256_16") != _source_digest(files):
         return None
     return rec.get("hbm_bytes_per_point")
 
 
+def host_description() -> dict:
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = f"{b.get('name', '?')} {b.get('version', '?')} ({b.get('openblas configuration', '')})".strip()
+    except Exception:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "blas": blas}
+
+
 # ------------------------------------------------------------------ CPU leg
 
-def _oracle_chunk(args):
+def _oracle_job(args):
     A, B, C, D, w = args
     import oracle
 
     return oracle.freqresp(A, B, C, D, w)
 
 
-def reference_points(mdl) -> np.ndarray:
-    """Grid points the oracle checks: all of them while the dense solves stay
-    cheap (K n^3 <= 1e9), else an evenly spread sample of 32."""
-    if mdl.K * float(mdl.n) ** 3 <= 1e9:
-        return np.arange(mdl.K)
-    return np.unique(np.linspace(0, mdl.K - 1, 32).round().astype(int))
-
-
-def cpu_baseline(mdl, idx, target_s: float = 12.0):
-    """The oracle on this host's cores: the reference points split over a
-    process pool (one single-threaded-BLAS worker per core, at most 16),
-    repeated until about target_s seconds of wall time.  Returns (record,
-    G_ref at idx)."""
-    cores = min(16, os.cpu_count() or 1)
-    K = len(idx)
-    chunks = np.array_split(np.asarray(idx), cores)
-    jobs = [(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[c]) for c in chunks if len(c)]
+def _pool(cores: int):
     ctx = mp.get_context("spawn")
     saved = {k: os.environ.get(k) for k in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS")}
     os.environ["OPENBLAS_NUM_THREADS"] = "1"  # inherited by the spawned workers only
     os.environ["OMP_NUM_THREADS"] = "1"
     try:
-        pool = ctx.Pool(len(jobs))
+        return ctx.Pool(cores)
     finally:
         for k, v in saved.items():
             if v is None:
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
-    with pool:
-        pool.map(_oracle_chunk, jobs[:1])  # start-up
+
+
+def cpu_oracle(jobs, target_s: float, what: str, timed: bool = True):
+    """The oracle over `jobs` (lists of (A, B, C, D, omega)) on a process pool
+    of single-threaded-BLAS workers (one per core, at most 16), repeated until
+    about target_s seconds of wall time.  Returns (record or None, results)."""
+    cores = min(16, os.cpu_count() or 1)
+    npts = sum(len(j[4]) for j in jobs)
+    with _pool(cores) as pool:
+        pool.map(_oracle_job, jobs[:cores])  # start-up
         t0 = time.perf_counter()
         reps = 0
-        G_ref = None
+        out = None
         while True:
-            parts = pool.map(_oracle_chunk, jobs)
+            res = pool.map(_oracle_job, jobs, chunksize=max(1, len(jobs) // (4 * cores)))
             reps += 1
-            if G_ref is None:
-                G_ref = np.concatenate(parts)
-            if time.perf_counter() - t0 >= target_s:
+            if out is None:
+                out = res
+            if not timed or time.perf_counter() - t0 >= target_s:
                 break
         dt = time.perf_counter() - t0
-    rec = {
-        "value": reps * K / dt,
-        "unit": "points/s",
-        "cores": len(jobs),
-        "kind": "oracle",
-        "sample": f"{reps} passes over {K} points of the same model's grid "
-                  f"({'all of it' if K == mdl.K else 'an evenly spread sample'}; "
-                  f"dense complex LU per frequency, {len(jobs)} worker processes)",
+    if not timed:
+        return None, out
+    rec = {"value": reps * npts / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+           "sample": f"{reps} passes over {npts} points ({what}); dense complex LU per point "
+                     f"(numpy.linalg.solve), {cores} single-threaded worker processes"}
+    rec.update(host_description())
+    return rec, out
+
+
+# ------------------------------------------------------------------ GPU helpers
+
+def _stats_delta(s0, s1):
+    return {
+        "family_ms": [b - a for a, b in zip(s0["family_ms"], s1["family_ms"])],
+        "family_launches": [b - a for a, b in zip(s0["family_launches"], s1["family_launches"])],
+        "reductions": s1["reductions"] - s0["reductions"],
+        "reduce_kernel_ms": s1["reduce_kernel_ms"] - s0["reduce_kernel_ms"],
+        "timed_reduce_launches": s1["timed_reduce_launches"] - s0["timed_reduce_launches"],
+        "sweep_launches": s1["sweep_launches"] - s0["sweep_launches"],
     }
-    return rec, G_ref
 
 
-# ------------------------------------------------------------------ GPU leg
-
-def _make_model(workload: str):
-    from paper_2401_04068_amd import workloads as wl
-
-    if workload == "mimo64":
-        return wl.mimo64()
-    if workload == "siso8":
-        return wl.siso8()
-    if workload == "damped256":
-        return wl.damped256_model(0)
-    if workload == "large1024":
-        return wl.large1024_models(seeds=wl.LARGE_SEEDS[:1])[0]
-    raise SystemExit(f"unknown workload {workload}")
+def _pct(x):
+    x = np.asarray(x, dtype=np.float64) * 1e3
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)), "max": float(x.max())}
 
 
-def run_gpu(mdl, precision: int, steps: int, warmup: int, window: int):
-    """Time `steps` device-memory requests of one model (each its own
-    reduction and all its solves).  Throughput run: up to `window` requests
-    in flight (each has its own output buffers; a new one is submitted as the
-    oldest completes).  Latency run: the same number of requests one at a
-    time, submit -> results visible."""
+class DeviceMix:
+    """A list of models with their inputs, outputs and point records resident
+    in HBM, submitted as device-memory requests."""
+
+    def __init__(self, models, dev):
+        import torch
+
+        self.models = models
+        self.t = []
+        for mdl in models:
+            d = {k: torch.from_numpy(np.ascontiguousarray(getattr(mdl, k))).to(dev)
+                 for k in ("A", "B", "C", "D", "omega")}
+            d["G"] = torch.empty((mdl.K, mdl.p, mdl.m, 2), dtype=torch.float64, device=dev)
+            d["info"] = torch.empty((mdl.K * 8,), dtype=torch.uint8, device=dev)
+            self.t.append(d)
+
+    def run(self, eng, precision, keys=None):
+        hs = []
+        for i, d in enumerate(self.t):
+            key = 0 if keys is None else keys[i]
+            hs.append(eng.submit_device(d["A"], d["B"], d["C"], d["D"], d["omega"], d["G"], d["info"],
+                                        precision=precision, model_key=key))
+        for h in hs:
+            eng.wait(h)
+        return hs
+
+    def G(self, i, idx=None):
+        g = self.t[i]["G"].cpu().numpy()
+        g = g[..., 0] + 1j * g[..., 1]
+        return g if idx is None else g[idx]
+
+    def info(self, i):
+        from paper_2401_04068_amd import binding
+
+        return self.t[i]["info"].cpu().numpy().view(binding.POINT_INFO_DTYPE)
+
+
+def timed_steps(eng, mix, precision, steps, warmup, label):
     import torch
 
-    from paper_2401_04068_amd import binding
+    for i in range(warmup):
+        mix.run(eng, precision)
+    torch.cuda.synchronize()
+    s0 = eng.stats()
+    t0 = time.perf_counter()
+    last = time.perf_counter()
+    for i in range(steps):
+        hs = mix.run(eng, precision)
+        if time.perf_counter() - last > 10.0:
+            log(f"{label}: step {i + 1} of {steps}")
+            last = time.perf_counter()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s1 = eng.stats()
+    return dt, _stats_delta(s0, s1), hs
 
-    dev = torch.device("cuda:0")
-    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(mdl, k))).to(dev) for k in ("A", "B", "C", "D", "omega")}
-    W = max(1, window)
-    Gs = [torch.empty((mdl.K, mdl.p, mdl.m, 2), dtype=torch.float64, device=dev) for _ in range(W)]
-    infos = [torch.empty((mdl.K * 8,), dtype=torch.uint8, device=dev) for _ in range(W)]
-    eng = binding.Engine(arena_bytes=1 << 30, kernel_timing=True)
-    try:
-        def submit(slot):
-            return eng.submit_device(t["A"], t["B"], t["C"], t["D"], t["omega"], Gs[slot], infos[slot],
-                                     precision=precision)
 
-        def pipelined(n):
-            inflight = []
-            t_last = time.perf_counter()
-            for i in range(n):
-                if len(inflight) == W:
-                    eng.wait(inflight.pop(0))
-                inflight.append(submit(i % W))
-                if time.perf_counter() - t_last > 5.0:  # long steps: show progress
-                    print(f"bench: step {i} of {n} submitted", file=sys.stderr, flush=True)
-                    t_last = time.perf_counter()
-            for h in inflight:
-                eng.wait(h)
-
-        pipelined(warmup)
-        torch.cuda.synchronize()
-        s0 = eng.stats()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pipelined(steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        s1 = eng.stats()
-        torch.cuda.synchronize()
-        # every output buffer of the throughput run (the last request of
-        # each slot), checked against the oracle in main()
-        Gall = []
-        for g in Gs[:min(W, steps)]:
-            gh = g.cpu().numpy()
-            Gall.append(gh[..., 0] + 1j * gh[..., 1])
-        infoh = infos[0].cpu().numpy().view(binding.POINT_INFO_DTYPE)
-    finally:
-        eng.close()
-    # latency: one request at a time, on an engine without kernel-timing
-    # events (a user's configuration)
-    lat = []
-    with binding.Engine(arena_bytes=1 << 30) as eng2:
-        for i in range(warmup + steps):
-            a = time.perf_counter()
-            eng2.wait(eng2.submit_device(t["A"], t["B"], t["C"], t["D"], t["omega"], Gs[0], infos[0],
-                                         precision=precision))
-            if i >= warmup:
-                lat.append(time.perf_counter() - a)
-    launches = s1["timed_sweep_launches"] - s0["timed_sweep_launches"]
-    sweep_ms = (s1["sweep_kernel_ms"] - s0["sweep_kernel_ms"]) / max(launches, 1)
-    rlaunch = s1["timed_reduce_launches"] - s0["timed_reduce_launches"]
-    reduce_ms = (s1["reduce_kernel_ms"] - s0["reduce_kernel_ms"]) / max(rlaunch, 1)
-    return {
-        "seconds": dt,
-        "lat": np.array(lat),
-        "sweep_ms_per_launch": sweep_ms,
-        "sweep_launches_per_step": launches / steps,
-        "reduce_ms_per_launch": reduce_ms,
-        "reductions_per_step": (s1["reductions"] - s0["reductions"]) / steps,
-        "G": Gall[0],
-        "G_all": Gall,
-        "info": infoh,
+def roofline_of(delta, fam_flops, fp32: bool):
+    """The family with the most kernel time: its algorithmic flops per launch
+    over its average launch time (HIP events), against the vector peak of the
+    arithmetic it does."""
+    ms = delta["family_ms"]
+    f = int(np.argmax(ms[:3]))
+    f32, f64 = fam_flops[f]
+    launches = max(delta["family_launches"][f], 1)
+    t = ms[f] * 1e-3
+    achieved = (f32 + f64) / t / 1e12
+    # time the same work would take at the peak rates of its two parts
+    t_peak = (f32 / FP32_VALU_PEAK + f64 / FP64_VALU_PEAK) / 1e12
+    peak = (f32 + f64) / t_peak / 1e12 if t_peak > 0 else FP64_VALU_PEAK
+    return f, {
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": t_peak / t,
+        "traffic": None,
+        "kernel": KF_NAMES[f],
+        "kernel_source_sha256_16": _source_digest(KF_SOURCES[f]),
+        "flops_per_launch": (f32 + f64) / launches,
+        "fp32_share": f32 / max(f32 + f64, 1.0),
+        "avg_launch_ms": ms[f] / launches,
+        "launches": launches,
+        "peak_note": ("float64 FMA at 78.6 TFLOP/s, float32 FMA at the chip's 157.3 TFLOP/s vector rate "
+                      "(blended by the kernel's flop mix)" if fp32 else "float64 FMA, 78.6 TFLOP/s"),
     }
 
 
-def serving(args):
-    """Serving replay: the mixed-size request stream (n ~ U{4..128},
-    m, p ~ U{1..8}, K ~ U{256..4096}) submitted from host memory on the refined
-    path.  Open loop: each request is submitted at its Poisson arrival time
-    (2000 requests/s) and its latency runs from that arrival to the moment its
-    results are visible to poll().  Closed loop: all requests submitted at
-    once; throughput = points / (first submit -> last result)."""
-    import torch  # noqa: F401  (device memory for the arena)
+# ------------------------------------------------------------------ headline
+
+def serving_headline(args, out):
+    import torch
 
     import oracle
     from paper_2401_04068_amd import binding
     from paper_2401_04068_amd import workloads as wl
 
-    nreq = args.requests
-    reqs = wl.serving_requests(nreq)
-    arrivals = wl.serving_arrivals(nreq)
-    total_points = sum(r.K for r in reqs)
-    out = {"metric": METRIC, "workload": f"serving: {nreq} requests, Poisson 2000/s, refined path, host memory",
-           "requests": nreq, "points": total_points}
-    with binding.Engine(arena_bytes=8 << 30, host_staging_bytes=1 << 30) as eng:
-        # warm-up (kernel loading, pools)
-        for r in reqs[:8]:
+    N = args.requests
+    t_gen = time.perf_counter()
+    reqs = wl.serving_requests(N)
+    arrivals = wl.serving_arrivals(N)
+    total = int(sum(r.K for r in reqs))
+    log(f"serving mix: {N} requests, {total} points (generated in {time.perf_counter() - t_gen:.1f} s)")
+    # accuracy / CPU sample: every 16th request, every 8th point of it
+    samp = list(range(0, N, 16))
+    sidx = {i: np.arange(0, reqs[i].K, 8) for i in samp}
+    jobs = [(reqs[i].A, reqs[i].B, reqs[i].C, reqs[i].D, reqs[i].omega[sidx[i]]) for i in samp]
+    npts_s = sum(len(v) for v in sidx.values())
+    cpu, refs = cpu_oracle(jobs, 12.0, f"every 16th request of the mix, every 8th point of each",
+                           timed=not args.no_cpu)
+    G_ref = dict(zip(samp, refs))
+    log(f"cpu leg done ({npts_s} sampled points)")
+
+    dev = torch.device("cuda:0")
+    binding.load()
+    mix = DeviceMix(reqs, dev)
+    torch.cuda.synchronize()
+    res = {}
+    with binding.Engine(arena_bytes=8 << 30, kernel_timing=True, host_staging_bytes=1 << 30) as eng:
+        for name, prec in (("refined", binding.PREC_REFINED), ("fp64", binding.PREC_FP64)):
+            dt, delta, hs = timed_steps(eng, mix, prec, args.steps, args.warmup, name)
+            worst, ok, n = 0.0, 0, 0
+            for i in samp:
+                e = oracle.rel_err(mix.G(i, sidx[i]), G_ref[i])
+                worst = max(worst, float(e.max()))
+                ok += int(np.sum(e <= TOL))
+                n += len(e)
+            fam_flops = [[0.0, 0.0] for _ in range(4)]
+            paths = np.zeros(5, dtype=np.int64)
+            for i, r in enumerate(reqs):
+                info = mix.info(i)
+                f32, f64 = point_flops(r.n, r.m, r.p, info["iters"], prec == binding.PREC_REFINED)
+                f = family_of(r.n)
+                fam_flops[f][0] += f32 * args.steps
+                fam_flops[f][1] += f64 * args.steps
+                paths += np.bincount(info["path"], minlength=5)[:5]
+            res[name] = {
+                "seconds": dt, "points_per_s_raw": total * args.steps / dt, "frac_within_1e-10": ok / n,
+                "max_rel_err": worst, "delta": delta, "fam_flops": fam_flops, "paths": paths.tolist(),
+                "mean_fp32_solves": None,
+            }
+            if prec == binding.PREC_REFINED:
+                it = np.concatenate([mix.info(i)["iters"] for i in range(0, N, 8)])
+                res[name]["mean_fp32_solves"] = float(np.mean(it))
+            log(f"{name}: {res[name]['points_per_s_raw'] / 1e6:.2f} M points/s, max err {worst:.2e}")
+        del mix
+        torch.cuda.empty_cache()
+        # open loop: host-memory requests at their Poisson arrival times
+        for r in reqs[:16]:
             eng.wait(eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED))
-        # open loop
         handles = []
         t0 = time.perf_counter()
         for r, ta in zip(reqs, arrivals):
             now = time.perf_counter() - t0
             if ta > now:
                 time.sleep(ta - now)
-            lag = max(0.0, time.perf_counter() - t0 - ta)  # submission behind the arrival
+            lag = max(0.0, time.perf_counter() - t0 - ta)
             handles.append((eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED), lag))
-        lat = []
         for h, _ in handles:
             eng.wait(h)
-        for h, lag in handles:
-            # arrival -> results visible: submission lag plus the library's
-            # submit -> done interval (both stamps on the library clock)
-            lat.append(lag + (h.result["t_done_us"] - h.result["t_submit_us"]) * 1e-6)
         t_open = time.perf_counter() - t0
-
-        def pct(x):
-            x = np.asarray(x) * 1e3
-            return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)), "max": float(x.max())}
-
-        res = [h.result for h, _ in handles]
-        work = np.array([r.K * r.n * r.n * (r.m + 2) for r in reqs], dtype=float)
-        small = work <= np.median(work)
-        lat_a = np.array(lat)
-        out["open_loop"] = {
+        lat = [lag + (h.result["t_done_us"] - h.result["t_submit_us"]) * 1e-6 for h, lag in handles]
+        rs = [h.result for h, _ in handles]
+        open_loop = {
             "wall_s": t_open,
-            "points_per_s": total_points / t_open,
-            "latency_ms": pct(lat),
-            # where the time goes: waiting for admission, admission to first
-            # sweep launch, first launch to results visible
-            "queue_ms": pct([(x["t_admit_us"] - x["t_submit_us"]) * 1e-6 for x in res]),
-            "start_ms": pct([(x["t_first_launch_us"] - x["t_admit_us"]) * 1e-6 for x in res]),
-            "run_ms": pct([(x["t_done_us"] - x["t_first_launch_us"]) * 1e-6 for x in res]),
-            "latency_ms_smaller_half": pct(lat_a[small]),
-            "latency_ms_larger_half": pct(lat_a[~small]),
+            "latency_ms": _pct(lat),
+            "queue_ms": _pct([(x["t_admit_us"] - x["t_submit_us"]) * 1e-6 for x in rs]),
+            "run_ms": _pct([(x["t_done_us"] - x["t_first_launch_us"]) * 1e-6 for x in rs]),
         }
-        open_handles = [h for h, _ in handles]
-        # closed loop
+        del handles
+        # closed loop from host memory (H2D and D2H inside the timed region)
         t0 = time.perf_counter()
         hs = [eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED) for r in reqs]
         for h in hs:
             eng.wait(h)
-        t_closed = time.perf_counter() - t0
-        st = eng.stats()
-    # accuracy on a sample: every 64th request, every 61st point, against the oracle
-    worst = 0.0
-    n_fb = 0
-    for idx in range(0, nreq, 64):
-        r = reqs[idx]
-        sub = slice(None, None, 61)
-        ref = oracle.freqresp(r.A, r.B, r.C, r.D, r.omega[sub])
-        for G in (open_handles[idx].G, hs[idx].G):
-            worst = max(worst, float(oracle.rel_err(G[sub], ref).max()))
-    for h in hs:
-        n_fb += int(h.result["n_fallback"])
-    out["closed_loop"] = {"wall_s": t_closed, "points_per_s": total_points / t_closed}
-    out["accuracy_sample_max_rel_err"] = worst
-    out["fallback_points"] = n_fb
-    out["stats"] = {k: st[k] for k in ("reductions", "sweep_launches", "tiles_launched", "arena_peak_bytes")}
-    print(json.dumps(out), flush=True)
+        t_host = time.perf_counter() - t0
+        worst_h = 0.0
+        for i in samp[::4]:
+            worst_h = max(worst_h, float(oracle.rel_err(hs[i].G[sidx[i]], G_ref[i]).max()))
+        del hs
+    log("serving replays done")
+
+    ref, f64 = res["refined"], res["fp64"]
+    value = ref["points_per_s_raw"] * ref["frac_within_1e-10"]
+    v64 = f64["points_per_s_raw"] * f64["frac_within_1e-10"]
+    fam, roof = roofline_of(ref["delta"], ref["fam_flops"], fp32=True)
+    roof["traffic"] = _traffic_record(f"kf{fam}_serving", KF_SOURCES[fam])
+    fam64, roof64 = roofline_of(f64["delta"], f64["fam_flops"], fp32=False)
+    roof64["traffic"] = _traffic_record(f"kf{fam64}_serving_fp64", KF_SOURCES[fam64])
+
+    def fam_table(r):
+        d = r["delta"]
+        rows = {}
+        for f in range(4):
+            if d["family_launches"][f] == 0:
+                continue
+            f32, fl64 = r["fam_flops"][f]
+            rows[KF_NAMES[f].split(" ")[0]] = {"ms": d["family_ms"][f], "launches": d["family_launches"][f],
+                                                "tflops": (f32 + fl64) / max(d["family_ms"][f], 1e-9) / 1e9}
+        return rows
+
+    out.update({
+        "value": value,
+        "ms_per_step": 1e3 * ref["seconds"] / args.steps,
+        "dtype": "c32+f64",
+        "config": {
+            "workload": f"serving mix: {N} requests (one model each), n~U{{4..128}}, m,p~U{{1..8}}, "
+                        f"K~U{{256..4096}} log-spaced w in [1e-3,1e3], {total} points per step; "
+                        "refined path (complex-float32 solves, float64 reduction and refinement to 1e-10); "
+                        "inputs resident in HBM; one step = all requests submitted and completed",
+            "requests": N, "points_per_step": total,
+        },
+        "accuracy": {"max_rel_err": ref["max_rel_err"], "frac_within_1e-10": ref["frac_within_1e-10"],
+                     "sampled_points": npts_s, "oracle": "float64 dense LU per point"},
+        "latency_ms": open_loop["latency_ms"],
+        "refined": {"points_per_s": value, "points_per_s_raw": ref["points_per_s_raw"],
+                    "mean_fp32_solves": ref["mean_fp32_solves"], "points_by_path": ref["paths"],
+                    "kernels": fam_table(ref),
+                    "reductions_per_step": ref["delta"]["reductions"] / args.steps},
+        "fp64": {"points_per_s": v64, "points_per_s_raw": f64["points_per_s_raw"],
+                 "max_rel_err": f64["max_rel_err"], "frac_within_1e-10": f64["frac_within_1e-10"],
+                 "ms_per_step": 1e3 * f64["seconds"] / args.steps, "points_by_path": f64["paths"],
+                 "kernels": fam_table(f64), "roofline": roof64},
+        "refined_vs_fp64": value / v64 if v64 else None,
+        "open_loop": open_loop,
+        "pcie_inclusive": {"points_per_s": total / t_host, "wall_s": t_host, "sampled_max_rel_err": worst_h,
+                           "note": "host-memory requests, all submitted at once: H2D and D2H inside"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    })
+
+
+# ------------------------------------------------------------------ secondary
+
+def secondary(args, out):
+    import torch
+
+    import oracle
+    from paper_2401_04068_amd import binding
+    from paper_2401_04068_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    sec = {}
+    # the 64-state model: 200 requests, 16 in flight, device memory
+    mdl = wl.mimo64()
+    mix = DeviceMix([mdl] * 16, dev)
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    with binding.Engine(arena_bytes=1 << 30) as eng:
+        row = {}
+        for name, prec in (("fp64", binding.PREC_FP64), ("refined", binding.PREC_REFINED)):
+            mix.run(eng, prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(12):
+                mix.run(eng, prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            err = float(oracle.rel_err(mix.G(0), ref).max())
+            row[name] = {"points_per_s": 12 * 16 * mdl.K / dt, "max_rel_err": err}
+        lat = []
+        d = mix.t[0]
+        for i in range(60):
+            a = time.perf_counter()
+            eng.wait(eng.submit_device(d["A"], d["B"], d["C"], d["D"], d["omega"], d["G"], d["info"]))
+            if i >= 10:
+                lat.append(time.perf_counter() - a)
+        row["latency_one_request_ms"] = _pct(lat)
+        sec["mimo64"] = row
+    del mix
+    log("secondary: mimo64 done")
+    # the 1024-state model: ten queries (two repeats), refined and float64
+    models = wl.large1024_models()
+    queries = wl.large1024_queries(models)
+    with binding.Engine(arena_bytes=8 << 30, kernel_timing=True) as eng:
+        row = {}
+        for name, prec in (("refined", binding.PREC_REFINED), ("fp64", binding.PREC_FP64)):
+            base = 10 if name == "refined" else 100
+            t0 = time.perf_counter()
+            hs = [eng.submit(models[i].A, models[i].B, models[i].C, models[i].D, w, precision=prec,
+                             model_key=base + i) for i, w in queries]
+            for h in hs:
+                eng.wait(h)
+            dt = time.perf_counter() - t0
+            idx = np.arange(0, 10_000, 1250)
+            errs = []
+            for (i, w), h in list(zip(queries, hs))[::3]:
+                errs.append(float(oracle.rel_err(h.G[idx], oracle.freqresp(models[i].A, models[i].B, models[i].C,
+                                                                          models[i].D, w[idx])).max()))
+            row[name] = {"points_per_s": 100_000 / dt, "wall_s": dt, "sampled_max_rel_err": max(errs),
+                         "reductions_reused": int(sum(h.result["reduction_reused"] for h in hs))}
+        row["note"] = "host-memory requests (inputs 8 MB each), ten queries in flight"
+        sec["large1024"] = row
+    log("secondary: large1024 done")
+    # 512 lightly damped 256-state models at once, refined
+    models = wl.damped256(args.damped_models)
+    with binding.Engine(arena_bytes=16 << 30, kernel_timing=True, host_staging_bytes=2 << 30) as eng:
+        row = {}
+        for name, prec in (("refined", binding.PREC_REFINED), ("fp64", binding.PREC_FP64)):
+            t0 = time.perf_counter()
+            hs = [eng.submit(m.A, m.B, m.C, m.D, m.omega, precision=prec) for m in models]
+            for h in hs:
+                eng.wait(h)
+            dt = time.perf_counter() - t0
+            errs = []
+            for j in range(0, len(models), 64):
+                mdl, h = models[j], hs[j]
+                d = np.abs(1j * mdl.omega[:, None] - mdl.poles[None, :])
+                idx = np.unique(np.concatenate([np.argsort(d.max(1) / d.min(1))[-2:], [0, 3500]]))
+                errs.append(float(oracle.rel_err(h.G[idx], oracle.freqresp_extended(
+                    mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[idx])).max()))
+            row[name] = {"points_per_s": 4096 * len(models) / dt, "wall_s": dt,
+                         "sampled_max_rel_err_vs_extended": max(errs),
+                         "fallback_points": int(sum(h.result["n_fallback"] for h in hs)),
+                         "fp64_dd_points": int(sum(h.result["n_fp64_dd"] for h in hs))}
+        row["note"] = f"{len(models)} models submitted at once from host memory"
+        sec["damped256"] = row
+    log("secondary: damped256 done")
+    out["secondary"] = sec
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="mimo64", choices=["mimo64", "siso8", "damped256", "large1024", "serving"])
-    ap.add_argument("--requests", type=int, default=4096, help="serving replay: number of requests")
-    ap.add_argument("--window", type=int, default=16,
-                    help="requests in flight in the throughput run (each step is still one full request)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="serving", choices=["serving"])
+    ap.add_argument("--requests", type=int, default=4096, help="requests in the serving mix")
+    ap.add_argument("--damped-models", type=int, default=512, help="models of the lightly damped batch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
-    ap.add_argument("--paths", default="both", choices=["both", "fp64", "refined"],
-                    help="which precision paths to time (profiling runs)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 256 MiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--no-secondary", action="store_true", help="only the headline configuration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this engine's work units are independent "
-              "and its multi-GPU sharding is not built; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: every request and every frequency is independent, and the "
+              "multi-GPU sharding (requests routed per GPU) is not built; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-
-    if args.workload == "serving":
-        serving(args)
-        return
-    mdl = _make_model(args.workload)
-    n, m, p, K = mdl.n, mdl.m, mdl.p, mdl.K
-
-    ref_idx = reference_points(mdl)
-    # The CPU leg runs first, before anything touches the GPU, so that its
-    # worker processes start from a process with no device state.
-    if args.no_cpu:
-        import oracle
-
-        G_ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega[ref_idx])
-        cpu = None
-    else:
-        cpu, G_ref = cpu_baseline(mdl, ref_idx)
-
-    import torch
-
-    from paper_2401_04068_amd import binding
-
-    binding.load()
-    if args.copy_calibration:
-        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    fp64 = ref = None
-    if args.paths in ("both", "fp64"):
-        fp64 = run_gpu(mdl, binding.PREC_FP64, args.steps, args.warmup, args.window)
-    if args.paths in ("both", "refined"):
-        ref = run_gpu(mdl, binding.PREC_REFINED, args.steps, args.warmup, args.window)
-    if fp64 is None or ref is None:
-        done = fp64 or ref
-        print(json.dumps({"profiling_run": args.paths, "ms_per_step": 1e3 * done["seconds"] / args.steps,
-                          "sweep_ms_per_launch": done["sweep_ms_per_launch"]}), flush=True)
-        return
-
-    import oracle
-
-    # the worst point over every output buffer of the throughput run
-    err64 = np.max([oracle.rel_err(g[ref_idx], G_ref) for g in fp64["G_all"]], axis=0)
-    err32 = np.max([oracle.rel_err(g[ref_idx], G_ref) for g in ref["G_all"]], axis=0)
-    ok64 = float(np.mean(err64 <= TOL))
-    ok32 = float(np.mean(err32 <= TOL))
-
-    pts64 = K * args.steps / fp64["seconds"]
-    pts32 = K * args.steps / ref["seconds"]
-    if fp64["reductions_per_step"] != 1.0 or ref["reductions_per_step"] != 1.0:
-        raise RuntimeError("every step must reduce its own model exactly once")
-    value = pts64 * ok64
-    # a launch (one batch of the sweep stream) may carry the tiles of several
-    # requests in flight
-    flops_launch = sweep_flops_per_point(n, m, p) * K / max(fp64["sweep_launches_per_step"], 1e-9)
-    achieved = flops_launch / (fp64["sweep_ms_per_launch"] * 1e-3) / 1e12
-    kname, kfiles = sweep_kernel_family(n)
-    bpp = _traffic_record(args.workload, kfiles, args.window)
-    traffic = None if bpp is None else bpp * K / max(fp64["sweep_launches_per_step"], 1e-9)
-
     out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * fp64["seconds"] / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload}: n={n}, m={m}, p={p}, K={K} log-spaced frequencies, "
-                        f"one model per step (its own reduction), up to {args.window} requests in flight, "
-                        "inputs resident in HBM, float64 path",
-            "n": n, "m": m, "p": p, "points_per_step": K, "requests_in_flight": args.window,
-            "reductions_per_step": fp64["reductions_per_step"],
-        },
-        "latency_ms": {  # one request alone: submit -> results visible
-            "p50": float(np.percentile(fp64["lat"], 50) * 1e3),
-            "p99": float(np.percentile(fp64["lat"], 99) * 1e3),
-        },
-        "accuracy": {"max_rel_err": float(err64.max()), "frac_within_1e-10": ok64},
-        "refined": {
-            "points_per_s": pts32 * ok32,
-            "points_per_s_raw": pts32,
-            "max_rel_err": float(err32.max()),
-            "frac_within_1e-10": ok32,
-            "ms_per_step": 1e3 * ref["seconds"] / args.steps,
-            "latency_ms": {"p50": float(np.percentile(ref["lat"], 50) * 1e3),
-                           "p99": float(np.percentile(ref["lat"], 99) * 1e3)},
-            "mean_fp32_solves": float(np.mean(ref["info"]["iters"])),
-            "sweep_ms_per_launch": ref["sweep_ms_per_launch"],
-            "vs_fp64": (pts32 * ok32) / value if value else None,
-        },
-        "kernels": {
-            "sweep_ms_per_launch": fp64["sweep_ms_per_launch"],
-            "sweep_launches_per_step": fp64["sweep_launches_per_step"],
-            "reduce_ms_per_launch": fp64["reduce_ms_per_launch"],
-        },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": FP64_VALU_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-            "traffic": traffic,
-            "kernel": f"{kname}<fp64> (per-frequency Givens sweep)",
-            "kernel_source_sha256_16": _source_digest(kfiles),
-            "flops_per_launch": flops_launch,
-        },
-        "cpu_baseline": cpu,
+        "metric": METRIC, "value": None, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c32+f64", "data": "synthetic (seeded models of the stated recipe)",
     }
+    serving_headline(args, out)
+    if not args.no_secondary:
+        secondary(args, out)
     print(json.dumps(out), flush=True)
 
 

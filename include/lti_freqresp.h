@@ -175,16 +175,28 @@ typedef struct lti_result {
   double  t_done_us;        /* results visible to poll()                     */
 } lti_result;
 
+/* Kernel families, for the per-family timing of lti_stats. */
+#define LTI_KF_SWEEP4     0  /* four frequencies per wavefront (nx <= 64)       */
+#define LTI_KF_SWEEP1     1  /* one frequency per wavefront (nx <= 256)          */
+#define LTI_KF_SWEEPWG    2  /* one frequency per workgroup (nx <= 1024)         */
+#define LTI_KF_REFINE_DD  3  /* double-double refinement of queued points       */
+#define LTI_KF_COUNT      4
+
 /* Counters of one context. */
 typedef struct lti_stats {
   uint64_t requests_submitted, requests_done, requests_failed;
   uint64_t reductions, reduction_cache_hits;
   uint64_t sweep_launches, tiles_launched, points_done;
   uint64_t arena_bytes_in_use, arena_peak_bytes;
-  /* with LTI_CFG_KERNEL_TIMING: summed HIP-event durations */
+  /* with LTI_CFG_KERNEL_TIMING: summed HIP-event durations (events on the
+     stream the kernels run on).  sweep_kernel_ms covers the sweep families
+     of every batch (timed_sweep_launches batches); family_ms[f] the
+     launches of family f, bracketed per batch (family_launches[f]). */
   double   sweep_kernel_ms;
   double   reduce_kernel_ms;
   uint64_t timed_sweep_launches, timed_reduce_launches;
+  double   family_ms[LTI_KF_COUNT];
+  uint64_t family_launches[LTI_KF_COUNT];
 } lti_stats;
 
 typedef struct lti_ctx lti_ctx;

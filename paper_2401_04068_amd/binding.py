@@ -47,6 +47,11 @@ POINTS_JW = 0
 POINTS_S = 1
 POINTS_Z = 2
 
+KF_SWEEP4 = 0
+KF_SWEEP1 = 1
+KF_SWEEPWG = 2
+KF_REFINE_DD = 3
+
 CFG_KERNEL_TIMING = 1
 CFG_FORCE_DD = 2
 CFG_NO_TRANSPOSE = 4
@@ -137,6 +142,8 @@ class LtiStats(ctypes.Structure):
         ("reduce_kernel_ms", ctypes.c_double),
         ("timed_sweep_launches", ctypes.c_uint64),
         ("timed_reduce_launches", ctypes.c_uint64),
+        ("family_ms", ctypes.c_double * 4),
+        ("family_launches", ctypes.c_uint64 * 4),
     ]
 
 
@@ -336,7 +343,10 @@ class Engine:
         rc = self._lib.lti_freqresp_stats(self._ctx, ctypes.byref(s))
         if rc != LTI_OK:
             raise LtiError(rc, "lti_freqresp_stats")
-        return {name: getattr(s, name) for name, _ in LtiStats._fields_}
+        out = {name: getattr(s, name) for name, _ in LtiStats._fields_}
+        out["family_ms"] = list(s.family_ms)
+        out["family_launches"] = list(s.family_launches)
+        return out
 
     def get_reduced(self, model_key: int, n: int, m: int, p: int):
         H = np.empty((n, n))

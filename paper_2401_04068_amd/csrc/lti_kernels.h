@@ -133,7 +133,8 @@ hipError_t launch_zero(const ZeroLaunch& Z, hipStream_t s);
 //
 // Evaluation points (flags bits 8-9): kPointsJW, s_k = j omega[k];
 // kPointsS, s_k = omega[2k] + j omega[2k+1]; kPointsZ, the discrete-time
-// point z_k = exp(j omega[k] Ts).  Every kernel solves (s_k I - H) X = Q^T B.
+// point z_k = exp(j omega[k]) (omega[k] in radians per sample).  Every
+// kernel solves (s_k I - H) X = Q^T B.
 //
 // Points whose solve cannot be trusted in the kernel's own precision (a
 // refined point whose iteration stalled, a float64 point whose estimated
@@ -160,7 +161,6 @@ struct ReqDesc {
   uint32_t* fbq;
   int n, m, p, precision;
   double rtol;
-  double Ts;
   uint32_t flags;
   uint32_t pad;
 };

@@ -219,8 +219,10 @@ struct Request {
 
 struct Batch {
   hipEvent_t done = nullptr;
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  bool timed = false;
+  // with kernel timing: tev[0] before the first kernel, tev[i + 1] after the
+  // launches of family tfam[i]
+  std::vector<hipEvent_t> tev;
+  std::vector<int> tfam;
   std::vector<std::pair<Request*, int64_t>> credit;
 };
 
@@ -618,7 +620,6 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   desc.p = sp;
   desc.precision = q.precision;
   desc.rtol = q.rtol;
-  desc.Ts = 0.0;
   desc.flags = (r->trans ? kFlagTrans : 0u) | ((c->flags & LTI_CFG_FORCE_DD) ? kFlagForceDD : 0u) |
                ((uint32_t)q.points << 8);
   if (e != hipSuccess) {
@@ -855,14 +856,33 @@ void launch(lti_ctx* c) {
         waited.push_back(pe);
         if (e == hipSuccess) e = hipStreamWaitEvent(ss, pe->ev, 0);
       }
-  b.timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
-  if (b.timed) {
-    b.t0 = get_event(c, true);
-    b.t1 = get_event(c, true);
-    if (e == hipSuccess) e = hipEventRecord(b.t0, ss);
-  }
+  const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
+  // bracket the launches of one kernel family with timing events
+  auto time_mark = [&](int fam) {
+    if (!timed || e != hipSuccess) return;
+    hipEvent_t ev = get_event(c, true);
+    if (!ev) {
+      e = hipErrorOutOfMemory;
+      return;
+    }
+    e = hipEventRecord(ev, ss);
+    b.tev.push_back(ev);
+    if (fam >= 0) b.tfam.push_back(fam);
+  };
+  auto family_of = [](int k) {
+    return k >= kNumSweepClasses + kNumSweep16Classes ? LTI_KF_SWEEPWG
+         : k >= kNumSweepClasses                      ? LTI_KF_SWEEP4
+                                                      : LTI_KF_SWEEP1;
+  };
+  time_mark(-1);
   SweepLaunch L;
   for (int k = 0; k < kAllClasses && e == hipSuccess; ++k) {
+    if (k > 0 && family_of(k) != family_of(k - 1)) {
+      // close the previous family if it launched anything
+      bool any = false;
+      for (int k2 = 0; k2 < k; ++k2) any = any || (family_of(k2) == family_of(k - 1) && !per[k2].empty());
+      if (any && (b.tfam.empty() || b.tfam.back() != family_of(k - 1))) time_mark(family_of(k - 1));
+    }
     const std::vector<Piece>& v = per[k];
     for (size_t i0 = 0; i0 < v.size() && e == hipSuccess; i0 += kMaxSegs) {
       L.nseg = (int)std::min<size_t>(kMaxSegs, v.size() - i0);
@@ -889,7 +909,11 @@ void launch(lti_ctx* c) {
       c->stats.sweep_launches++;
     }
   }
-  if (b.timed && e == hipSuccess) e = hipEventRecord(b.t1, ss);
+  {
+    bool any = false;
+    for (int k2 = 0; k2 < kAllClasses; ++k2) any = any || (family_of(k2) == LTI_KF_SWEEPWG && !per[k2].empty());
+    if (any) time_mark(LTI_KF_SWEEPWG);
+  }
   // finish the requests whose last tiles are in the batch: the extended
   // refinement of their queued points (the grid is sized by their points; a
   // workgroup that finds the queues empty exits at once), then the results
@@ -909,6 +933,7 @@ void launch(lti_ctx* c) {
       const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(1024, pts / 32));
       e = launch_refine_dd(D, grid, ss);
     }
+    time_mark(LTI_KF_REFINE_DD);
     for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i) e = copy_results(c, fin[i], ss);
   }
   b.done = get_event(c, false);
@@ -972,14 +997,22 @@ bool retire(lti_ctx* c) {
       fail_all(c, LTI_EDEVICE);
       return true;
     }
-    if (b.timed) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, b.t0, b.t1) == hipSuccess) {
-        c->stats.sweep_kernel_ms += ms;
-        c->stats.timed_sweep_launches++;
+    if (!b.tev.empty()) {
+      bool counted = false;
+      for (size_t i = 0; i + 1 < b.tev.size() && i < b.tfam.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, b.tev[i], b.tev[i + 1]) != hipSuccess) continue;
+        const int f = b.tfam[i];
+        c->stats.family_ms[f] += ms;
+        c->stats.family_launches[f]++;
+        if (f != LTI_KF_REFINE_DD) {
+          c->stats.sweep_kernel_ms += ms;
+          counted = true;
+        }
       }
-      put_event(c, b.t0, true);
-      put_event(c, b.t1, true);
+      if (counted) c->stats.timed_sweep_launches++;
+      for (hipEvent_t ev : b.tev) put_event(c, ev, true);
+      b.tev.clear();
     }
     for (auto& cr : b.credit) {
       Request* r = cr.first;
@@ -1386,8 +1419,7 @@ int lti_freqresp_destroy(lti_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->inflight) {
     put_event(c, b.done, false);
-    put_event(c, b.t0, true);
-    put_event(c, b.t1, true);
+    for (hipEvent_t ev : b.tev) put_event(c, ev, true);
   }
   for (auto& tp : c->reduce_timing) {
     put_event(c, tp.a, true);

@@ -72,7 +72,7 @@ __device__ __forceinline__ SPoint point_of(const ReqDesc& rd, int64_t k) {
     s.re = w[2 * k];
     s.im = w[2 * k + 1];
   } else if (kind == kPointsZ) {
-    sincos(w[k] * rd.Ts, &s.im, &s.re);
+    sincos(w[k], &s.im, &s.re);
   } else {
     s.re = 0.0;
     s.im = w[k];

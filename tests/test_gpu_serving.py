@@ -1,0 +1,143 @@
+"""GPU: serving behaviour through the C ABI -- admission under memory
+pressure, the bounded pending queue, reducible Hessenberg forms, and
+evaluation at complex and discrete-time points."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_04068_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_arena_pressure_requests_wait_and_match(monkeypatch):
+    """An arena that holds only a few requests at a time: the rest wait for
+    memory, every result matches the oracle, and (with the column split
+    fixed) equals the request's result alone bit for bit."""
+    from paper_2401_04068_amd import binding
+
+    monkeypatch.setenv("LTI_FREQRESP_RHS_SPLIT", "1")
+    reqs = wl.serving_requests(24, start=200)
+    need = max(r.K * r.p * r.m * 16 for r in reqs)
+    arena = 6 << 20
+    assert need < arena // 2
+    with binding.Engine(arena_bytes=arena) as e:
+        alone = []
+        for r in reqs:
+            h = e.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED)
+            assert e.poll(h, -1)
+            alone.append(h.G)
+        hs = [e.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED) for r in reqs]
+        for h in hs:
+            assert e.poll(h, -1)
+        st = e.stats()
+    assert st["arena_peak_bytes"] <= arena
+    waited = sum(h.result["t_admit_us"] - h.result["t_submit_us"] > 0 for h in hs)
+    print(f"arena pressure: {waited} of {len(hs)} requests waited for admission", flush=True)
+    for r, h, ga in zip(reqs, hs, alone):
+        assert np.array_equal(h.G, ga), (r.n, r.m, r.p, r.K)
+        sub = slice(None, None, 23)
+        ref = oracle.freqresp(r.A, r.B, r.C, r.D, r.omega[sub])
+        assert oracle.rel_err(h.G[sub], ref).max() <= 1e-9
+
+
+def test_pending_queue_bound_returns_eagain():
+    from paper_2401_04068_amd import binding
+
+    mdl = wl.siso8()
+    with binding.Engine(arena_bytes=64 << 20, max_pending=2) as e:
+        h1 = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+        h2 = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+        # results not collected yet: both still count against the bound
+        with pytest.raises(binding.LtiError) as ei:
+            e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+        assert ei.value.code == binding.LTI_EAGAIN
+        assert e.poll(h1, -1)
+        h3 = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+        assert e.poll(h2, -1) and e.poll(h3, -1)
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    for h in (h1, h2, h3):
+        assert oracle.rel_err(h.G, ref).max() <= 1e-10
+
+
+@pytest.mark.parametrize("n", [2, 6, 40, 100, 300])
+@pytest.mark.parametrize("kind", ["diagonal", "blocks"])
+def test_reducible_hessenberg(n, kind):
+    """A already block diagonal (or diagonal): the reduction meets columns
+    that are already reduced (tau = 0) and H has zero subdiagonal entries, so
+    every Givens step with beta = 0 is a pure phase rotation."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(5100 + n)
+    if kind == "diagonal":
+        A = np.diag(-rng.uniform(0.1, 3.0, n))
+    else:
+        A = np.zeros((n, n))
+        for i in range(0, n - 1, 2):
+            s, w = -rng.uniform(0.05, 1.0), rng.uniform(0.5, 10.0)
+            A[i:i + 2, i:i + 2] = [[s, w], [-w, s]]
+        if n % 2:
+            A[-1, -1] = -0.5
+    B = rng.standard_normal((n, 3))
+    C = rng.standard_normal((4, n))
+    D = rng.standard_normal((4, 3))
+    w = np.concatenate([[0.0, -1.5], wl.logspace_grid(1e-2, 1e2, 21)])
+    ref = oracle.freqresp(A, B, C, D, w)
+    with binding.Engine(arena_bytes=256 << 20) as e:
+        for prec, tol in ((binding.PREC_FP64, 1e-10), (binding.PREC_REFINED, 1e-9)):
+            print(f"case reducible {kind} n={n} precision={prec}", flush=True)
+            h = e.submit(A, B, C, D, w, precision=prec)
+            assert e.poll(h, -1)
+            err = oracle.rel_err(h.G, ref)
+            assert err.max() <= tol, (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("n,m,p", [(8, 2, 2), (50, 3, 4), (100, 4, 2), (200, 2, 3), (300, 3, 3)])
+def test_complex_points_off_the_axis(n, m, p):
+    """s = sigma + j w off the imaginary axis (both signs of sigma, on and
+    near the real axis), both precisions, against the oracle."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(5200 + n)
+    mdl = wl.mixed_pole_model(rng, n, m, p, np.zeros(0))
+    sig = rng.uniform(-3.0, 3.0, 40)
+    w = np.concatenate([[0.0, 0.0], rng.uniform(-20.0, 20.0, 38)])
+    s = sig + 1j * w
+    s[1] = 5.0 + 0j
+    ref = oracle.freqresp_at_extended(mdl.A, mdl.B, mdl.C, mdl.D, s)
+    with binding.Engine(arena_bytes=512 << 20) as e:
+        for prec, tol in ((binding.PREC_FP64, 1e-10), (binding.PREC_REFINED, 1e-9)):
+            print(f"case complex s n={n} precision={prec}", flush=True)
+            h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, s, precision=prec, points=binding.POINTS_S)
+            assert e.poll(h, -1)
+            err = oracle.rel_err(h.G, ref)
+            assert err.max() <= tol, (err.max(), s[err.argmax()])
+
+
+@pytest.mark.parametrize("n,m,p", [(8, 1, 1), (64, 4, 4), (150, 2, 5), (400, 3, 2)])
+def test_discrete_time_unit_circle(n, m, p):
+    """A discrete-time model (spectral radius 0.9): z = exp(j theta) on the
+    unit circle, both precisions, against the oracle."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(5300 + n)
+    Q = wl.haar_orthogonal(rng, n)
+    lam = 0.9 * np.exp(1j * rng.uniform(0, np.pi, n // 2))
+    Lam = np.zeros((n, n))
+    for q, l in enumerate(lam):
+        Lam[2 * q:2 * q + 2, 2 * q:2 * q + 2] = [[l.real, l.imag], [-l.imag, l.real]]
+    if n % 2:
+        Lam[-1, -1] = 0.5
+    A = Q @ Lam @ Q.T
+    B = rng.standard_normal((n, m))
+    C = rng.standard_normal((p, n))
+    D = rng.standard_normal((p, m))
+    theta = np.concatenate([[0.0, np.pi, -np.pi / 2], np.linspace(-np.pi, np.pi, 61)])
+    ref = oracle.freqresp_at_extended(A, B, C, D, np.exp(1j * theta))
+    with binding.Engine(arena_bytes=512 << 20) as e:
+        for prec, tol in ((binding.PREC_FP64, 1e-10), (binding.PREC_REFINED, 1e-9)):
+            print(f"case discrete n={n} precision={prec}", flush=True)
+            h = e.submit(A, B, C, D, theta, precision=prec, points=binding.POINTS_Z)
+            assert e.poll(h, -1)
+            err = oracle.rel_err(h.G, ref)
+            assert err.max() <= tol, (err.max(), theta[err.argmax()])
