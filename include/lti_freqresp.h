@@ -155,6 +155,11 @@ typedef struct lti_request {
   double*  G_out;         /* n_omega*ny*nu complex = 2*n_omega*ny*nu doubles,
                              layout [k][i][j] (re, im)                           */
   lti_point_info* info_out; /* optional, n_omega entries                          */
+  double*  dG_out;        /* optional: the derivative dG/ds = -C (s I - A)^{-2} B
+                             at each point, same layout as G_out (on the
+                             imaginary axis dG/dw = j dG/ds).  A request with
+                             dG_out runs the float64 path whatever its
+                             precision says                                     */
 } lti_request;
 /* Ownership: with LTI_MEM_HOST, submit() copies A, B, C, D and omega before
  * it returns; G_out and info_out must stay valid until poll() reports the
@@ -241,6 +246,35 @@ int lti_freqresp_destroy(lti_ctx* ctx);
  * Returns LTI_ENOENT if no such model is resident. */
 int lti_freqresp_get_reduced(lti_ctx* ctx, uint64_t model_key, int32_t nx, int32_t nu,
                              int32_t ny, double* H, double* Bt, double* Ct);
+
+/* A resonance peak: frequency (rad/s) and gain sigma_max(G(j w)). */
+typedef struct lti_peak {
+  double w;
+  double gain;
+} lti_peak;
+
+typedef struct lti_hinf_result {
+  double  hinf;         /* estimate of ||G||_inf = sup_w sigma_max(G(j w))     */
+  double  w_hinf;       /* where it is attained (INFINITY: the D term)         */
+  int32_t n_peaks;      /* refined local maxima written to peaks_out            */
+  int32_t evaluations;  /* frequency points evaluated in all                    */
+} lti_hinf_result;
+
+/* Resonance peaks and the H-infinity norm estimate of the model in `req`
+ * (LTI_MEM_HOST, LTI_POINTS_JW; omega is the starting grid, any order).
+ * sigma(w) = sigma_max(G(j w)) and d sigma / d w = Re(u1^H (dG/dw) v1) (a
+ * simple largest singular value's first-order perturbation) come from G and
+ * dG/ds evaluated through `ctx` on the float64 path; every interior local
+ * maximum of sigma on the grid (the max_peaks largest) is bracketed by its
+ * grid neighbours and refined by a safeguarded secant iteration on
+ * d sigma / d w = 0 until the bracket is below wtol (relative; <= 0 selects
+ * 1e-12).  hinf is the largest of the refined peaks, the grid values and
+ * sigma_max(D) (w -> infinity).  Blocks until done (it submits and polls
+ * requests itself; the reduced model stays resident between them).  peaks_out
+ * receives n_peaks entries, largest gain first.
+ * Returns LTI_OK, LTI_EINVAL, or the error of an underlying submit/poll. */
+int lti_freqresp_peaks(lti_ctx* ctx, const lti_request* req, int32_t max_peaks, double wtol,
+                       lti_peak* peaks_out, lti_hinf_result* out);
 
 /* Snapshot of the context's counters. */
 int lti_freqresp_stats(lti_ctx* ctx, lti_stats* out);

@@ -15,6 +15,8 @@ What it computes (all plain, slow and in float64 unless stated):
                          (off the imaginary axis, or z = exp(j theta) for a
                          discrete-time model); ``freqresp_at_extended`` with
                          the extended-precision refinement;
+* ``derivative_at``      dG/ds = -C (s I - A)^{-2} B by two dense solves;
+                         ``derivative_at_extended`` with both refined;
 * ``freqresp_extended``  the same solve followed by iterative refinement whose
                          residual and iterate are held in extended precision
                          (x87 80-bit ``clongdouble``); the oracle of record for
@@ -22,6 +24,8 @@ What it computes (all plain, slow and in float64 unless stated):
 * ``cond2``              2-norm condition number of jw I - A per frequency;
 * ``rel_err``            the per-frequency relative Frobenius error metric;
 * ``exact.freqresp_exact``  exact rational evaluation for tiny systems;
+* ``peaks.peaks_bruteforce``  resonance peaks and the H-infinity norm by a
+                         dense grid and derivative-free golden-section search;
 * ``hessenberg.hessenberg`` unblocked Householder reduction to upper
                          Hessenberg form with Q^T B and C Q.
 
@@ -32,18 +36,21 @@ Kailath, *Linear Systems*, 1980, ch. 2).  The paper this project follows is
 silent on this problem; every function here cites the textbook or published
 method it restates instead.
 """
-from .freqresp import (freqresp, freqresp_extended, freqresp_at, freqresp_at_extended, cond2, rel_err,
-                       rel_err_max)
-from . import exact, hessenberg
+from .freqresp import (freqresp, freqresp_extended, freqresp_at, freqresp_at_extended, derivative_at,
+                       derivative_at_extended, cond2, rel_err, rel_err_max)
+from . import exact, hessenberg, peaks
 
 __all__ = [
     "freqresp",
     "freqresp_extended",
     "freqresp_at",
     "freqresp_at_extended",
+    "derivative_at",
+    "derivative_at_extended",
     "cond2",
     "rel_err",
     "rel_err_max",
     "exact",
     "hessenberg",
+    "peaks",
 ]

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 from fractions import Fraction
 
-__all__ = ["QJ", "freqresp_exact", "to_complex"]
+__all__ = ["QJ", "freqresp_exact", "derivative_exact", "to_complex"]
 
 
 class QJ:
@@ -121,3 +121,27 @@ def freqresp_exact(A, B, C, D, w, sigma=0):
             row.append(acc)
         G.append(row)
     return G
+
+
+def derivative_exact(A, B, C, D, w, sigma=0):
+    """Exact dG/ds = -C (s I - A)^{-2} B at s = sigma + j w (rational inputs):
+    two exact solves over Q(j).  Returns a p x m nested list of QJ."""
+    n = len(A)
+    m = len(B[0])
+    p = len(C)
+    w = Fraction(w)
+    sigma = Fraction(sigma)
+    M = [[QJ(sigma - Fraction(A[i][k]) if i == k else -Fraction(A[i][k]), w if i == k else 0) for k in range(n)]
+         for i in range(n)]
+    Bq = [[QJ(Fraction(B[i][j])) for j in range(m)] for i in range(n)]
+    Y = _solve(M, _solve(M, Bq))
+    out = []
+    for i in range(p):
+        row = []
+        for j in range(m):
+            acc = QJ(0)
+            for k in range(n):
+                acc = acc - Y[k][j] * Fraction(C[i][k])
+            row.append(acc)
+        out.append(row)
+    return out

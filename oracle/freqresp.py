@@ -18,8 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["freqresp", "freqresp_extended", "freqresp_at", "freqresp_at_extended", "cond2", "rel_err",
-           "rel_err_max"]
+__all__ = ["freqresp", "freqresp_extended", "freqresp_at", "freqresp_at_extended", "derivative_at", "derivative_at_extended", "cond2",
+           "rel_err", "rel_err_max"]
 
 
 def _check(A, B, C, D, omega):
@@ -137,6 +137,52 @@ def freqresp_at_extended(A, B, C, D, s, iters: int = 3) -> np.ndarray:
             d = np.linalg.solve(M64, r.astype(np.complex128))
             X = X + d.astype(ld)
         out[k] = (C_ld @ X + D_ld).astype(np.complex128)
+    return out
+
+
+def derivative_at(A, B, C, D, s) -> np.ndarray:
+    """dG/ds = -C (s I - A)^{-2} B at complex points s_k, shape (K, p, m): the
+    derivative of G(s) = C (s I - A)^{-1} B + D (from d/ds M^{-1} =
+    -M^{-1} (dM/ds) M^{-1} with dM/ds = I).  Two dense LU solves per point:
+    X = M^{-1} B, then Y = M^{-1} X, dG/ds = -C Y.  On the imaginary axis
+    dG/dw = j dG/ds."""
+    A, B, C, D, _ = _check(A, B, C, D, [0.0])
+    s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+    n = A.shape[0]
+    out = np.empty((len(s), C.shape[0], B.shape[1]), dtype=np.complex128)
+    Bc = B.astype(np.complex128)
+    for k, sk in enumerate(s):
+        M = sk * np.eye(n) - A
+        X = np.linalg.solve(M, Bc)
+        Y = np.linalg.solve(M, X)
+        out[k] = -(C @ Y)
+    return out
+
+
+def _refined_solve_ld(M64, M_ld, rhs_ld, iters):
+    X = np.linalg.solve(M64, rhs_ld.astype(np.complex128)).astype(np.clongdouble)
+    for _ in range(iters):
+        r = rhs_ld - M_ld @ X
+        X = X + np.linalg.solve(M64, r.astype(np.complex128)).astype(np.clongdouble)
+    return X
+
+
+def derivative_at_extended(A, B, C, D, s, iters: int = 3) -> np.ndarray:
+    """``derivative_at`` with both solves refined in extended precision (the
+    residual and iterate in x87 clongdouble, as in ``freqresp_extended``)."""
+    A, B, C, D, _ = _check(A, B, C, D, [0.0])
+    s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+    n = A.shape[0]
+    ld = np.clongdouble
+    A_ld, B_ld, C_ld = A.astype(ld), B.astype(ld), C.astype(ld)
+    out = np.empty((len(s), C.shape[0], B.shape[1]), dtype=np.complex128)
+    for k, sk in enumerate(s):
+        M64 = sk * np.eye(n) - A
+        s_ld = np.longdouble(sk.real) + 1j * np.longdouble(sk.imag)
+        M_ld = s_ld * np.eye(n, dtype=ld) - A_ld
+        X = _refined_solve_ld(M64, M_ld, B_ld, iters)
+        Y = _refined_solve_ld(M64, M_ld, X, iters)
+        out[k] = (-(C_ld @ Y)).astype(np.complex128)
     return out
 
 

@@ -70,6 +70,7 @@ EXPORTS = (
     "lti_freqresp_stats",
     "lti_freqresp_strerror",
     "lti_freqresp_abi_version",
+    "lti_freqresp_peaks",
 )
 
 
@@ -106,6 +107,7 @@ class LtiRequest(ctypes.Structure):
         ("model_key", ctypes.c_uint64),
         ("G_out", ctypes.c_void_p),
         ("info_out", ctypes.c_void_p),
+        ("dG_out", ctypes.c_void_p),
     ]
 
 
@@ -124,6 +126,15 @@ class LtiResult(ctypes.Structure):
         ("t_first_launch_us", ctypes.c_double),
         ("t_done_us", ctypes.c_double),
     ]
+
+
+class LtiPeak(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_double), ("gain", ctypes.c_double)]
+
+
+class LtiHinfResult(ctypes.Structure):
+    _fields_ = [("hinf", ctypes.c_double), ("w_hinf", ctypes.c_double), ("n_peaks", ctypes.c_int32),
+                ("evaluations", ctypes.c_int32)]
 
 
 class LtiStats(ctypes.Structure):
@@ -179,6 +190,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lti_freqresp_stats.restype = ctypes.c_int
     lib.lti_freqresp_strerror.argtypes = [ctypes.c_int]
     lib.lti_freqresp_strerror.restype = ctypes.c_char_p
+    lib.lti_freqresp_peaks.argtypes = [ctypes.c_void_p, P(LtiRequest), ctypes.c_int32, ctypes.c_double,
+                                       P(LtiPeak), P(LtiHinfResult)]
+    lib.lti_freqresp_peaks.restype = ctypes.c_int
     lib.lti_freqresp_abi_version.argtypes = []
     lib.lti_freqresp_abi_version.restype = ctypes.c_uint32
     if lib.lti_freqresp_abi_version() != ABI_VERSION:
@@ -208,6 +222,7 @@ class Handle:
     info: Any
     keep: list = field(default_factory=list)
     result: Optional[dict] = None
+    dG: Any = None  # dG/ds, when requested
 
 
 def _result_dict(r: LtiResult) -> dict:
@@ -256,7 +271,8 @@ class Engine:
 
     # ------------------------------------------------------------ requests
     def submit(self, A, B, C, D, omega, precision: int = PREC_FP64, model_key: int = 0,
-               rtol: float = 0.0, want_info: bool = True, points: int = POINTS_JW) -> Handle:
+               rtol: float = 0.0, want_info: bool = True, points: int = POINTS_JW,
+               want_derivative: bool = False) -> Handle:
         """Host-memory request; inputs are copied before this returns.
 
         points: POINTS_JW (omega real, s = j omega), POINTS_S (omega complex
@@ -285,14 +301,16 @@ class Engine:
         req.model_key = int(model_key)
         req.G_out = G.ctypes.data
         req.info_out = None if info is None else info.ctypes.data
+        dG = np.empty((K, p, m), dtype=np.complex128) if want_derivative else None
+        req.dG_out = None if dG is None else dG.ctypes.data
         rid = ctypes.c_uint64()
         rc = self._lib.lti_freqresp_submit(self._ctx, ctypes.byref(req), ctypes.byref(rid))
         if rc != LTI_OK:
             raise LtiError(rc, "lti_freqresp_submit")
-        return Handle(rid.value, G, info, keep=[G, info])
+        return Handle(rid.value, G, info, keep=[G, info, dG], dG=dG)
 
     def submit_device(self, A, B, C, D, omega, G, info=None, precision: int = PREC_FP64,
-                      model_key: int = 0, rtol: float = 0.0, points: int = POINTS_JW) -> Handle:
+                      model_key: int = 0, rtol: float = 0.0, points: int = POINTS_JW, dG=None) -> Handle:
         """Device-memory request: torch float64 tensors on this engine's device;
         G is a float64 tensor of 2*K*p*m entries (or complex128 (K, p, m)).
         Nothing is copied; the tensors must stay alive and unmodified until
@@ -315,11 +333,12 @@ class Engine:
         req.model_key = int(model_key)
         req.G_out = G.data_ptr()
         req.info_out = None if info is None else info.data_ptr()
+        req.dG_out = None if dG is None else dG.data_ptr()
         rid = ctypes.c_uint64()
         rc = self._lib.lti_freqresp_submit(self._ctx, ctypes.byref(req), ctypes.byref(rid))
         if rc != LTI_OK:
             raise LtiError(rc, "lti_freqresp_submit")
-        return Handle(rid.value, G, info, keep=[A, B, C, D, omega, G, info])
+        return Handle(rid.value, G, info, keep=[A, B, C, D, omega, G, info, dG], dG=dG)
 
     def poll(self, h: Handle, timeout_us: int = -1) -> bool:
         """True when done (result in h.result); False while pending."""
@@ -336,6 +355,31 @@ class Engine:
     def wait(self, h: Handle) -> Handle:
         self.poll(h, -1)
         return h
+
+    def peaks(self, A, B, C, D, omega, max_peaks: int = 8, wtol: float = 1e-12):
+        """lti_freqresp_peaks: resonance peaks [(w, gain), ...] (largest
+        first) and {'hinf', 'w_hinf', 'n_peaks', 'evaluations'}."""
+        A, B, C = _f64(A), _f64(B), _f64(C)
+        Dm = None if D is None else _f64(D)
+        w = _f64(omega).reshape(-1)
+        req = LtiRequest()
+        req.nx, req.nu, req.ny = A.shape[0], B.shape[1], C.shape[0]
+        req.mem = MEM_HOST
+        req.A, req.B, req.C = A.ctypes.data, B.ctypes.data, C.ctypes.data
+        req.D = None if Dm is None else Dm.ctypes.data
+        req.omega = w.ctypes.data
+        req.n_omega = w.shape[0]
+        req.precision = PREC_FP64
+        req.points = POINTS_JW
+        req.G_out = w.ctypes.data  # not written: the call evaluates into its own buffers
+        out = LtiHinfResult()
+        pk = (LtiPeak * max(1, max_peaks))()
+        rc = self._lib.lti_freqresp_peaks(self._ctx, ctypes.byref(req), int(max_peaks), float(wtol), pk,
+                                          ctypes.byref(out))
+        if rc != LTI_OK:
+            raise LtiError(rc, "lti_freqresp_peaks")
+        peaks = [(pk[i].w, pk[i].gain) for i in range(out.n_peaks)]
+        return peaks, {name: getattr(out, name) for name, _ in LtiHinfResult._fields_}
 
     # ------------------------------------------------------------ helpers
     def stats(self) -> dict:

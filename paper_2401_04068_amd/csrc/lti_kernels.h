@@ -157,6 +157,7 @@ struct ReqDesc {
   const float* Ct32;
   const double* omega;
   double* G;
+  double* dG;  // dG/ds (float64 path only), or null
   lti_point_info* info;
   uint32_t* fbq;
   int n, m, p, precision;
@@ -272,5 +273,29 @@ __host__ __device__ inline size_t stage_bytes(int precision, int n, int m, int p
 // lds_bytes: dynamic LDS for staging (the largest stage_bytes() of the
 // launch's requests; 0 disables staging).
 hipError_t launch_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s);
+
+// All sweep kernel classes in one index space: [0, kNumSweepClasses) one
+// frequency per wavefront, then the four-frequency classes, then the
+// workgroup classes.
+constexpr int kAllSweepClasses = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
+hipError_t launch_any_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s);
+
+// How a request's solves are cut into tiles (runtime.cpp): F frequencies
+// per tile, its m right-hand-side columns in S groups of mc, the kernel
+// class, and the waves each tile occupies.  `avail_waves`: wavefronts the
+// device can still take before splitting columns stops paying (columns are
+// split only while the request alone would leave the device short).
+struct TilePlan {
+  int kclass, F, S, mc, waves_per_tile;
+  int64_t ntiles;
+  size_t stage;
+};
+struct TileKnobs {
+  int tile_points = 0;   // 0: automatic
+  int rhs_split = 0;     // 0: automatic
+  bool use_sweep16 = true;
+};
+TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t avail_waves4, int64_t avail_waves1,
+                    const TileKnobs& kn);
 
 }  // namespace lti

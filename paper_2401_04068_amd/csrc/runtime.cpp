@@ -185,7 +185,7 @@ struct HostBuf {
 struct HostStage {
   HostBuf in, out;
   size_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0;  // in `in`
-  size_t offG = 0, offInfo = 0;                              // in `out`
+  size_t offG = 0, offInfo = 0, offDG = 0, outBytes = 0;     // in `out`
 };
 
 struct Request {
@@ -253,6 +253,59 @@ bool all_finite(const double* x, size_t n) {
     if (!std::isfinite(x[i])) return false;
   return true;
 }
+
+}  // namespace
+
+TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t avail_waves4, int64_t avail_waves1,
+                    const TileKnobs& kn) {
+  TilePlan t{};
+  // Kernel family: four frequencies per wavefront (n <= 64, at most four
+  // right-hand-side columns per tile), one frequency per wavefront
+  // (n <= 256), or one frequency per workgroup (n <= 1024).
+  const bool wg = n > kMaxN;
+  const bool four = !wg && kn.use_sweep16 && sweep16_class(precision, n, std::min(sm, 4)) >= 0;
+  int F = kn.tile_points;
+  if (F <= 0) F = four ? 4 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, K / 2048));
+  if (four) F = (F + 3) & ~3;
+  t.F = F;
+  // Split the right-hand-side columns over several tiles (each split
+  // repeats the rotations) only while the device would otherwise be short of
+  // wavefronts: `avail` counts the waves it can still take.
+  const int64_t fblocks = (K + F - 1) / F;
+  const int64_t avail = four ? avail_waves4 : avail_waves1;
+  int S = kn.rhs_split;
+  if (S <= 0) S = (fblocks >= avail) ? 1 : (int)((avail + fblocks - 1) / fblocks);
+  S = std::max(1, std::min(S, sm));
+  if (four || wg) S = std::max(S, (sm + 3) / 4);
+  t.mc = (sm + S - 1) / S;
+  t.S = (sm + t.mc - 1) / t.mc;
+  if (wg) {
+    t.kclass = kNumSweepClasses + kNumSweep16Classes + sweep_wg_class(precision, n, t.mc);
+  } else if (four) {
+    t.kclass = kNumSweepClasses + sweep16_class(precision, n, t.mc);
+  } else {
+    // one-frequency kernels keep R * MM <= 32 (R = 1, 2, 4 row slices):
+    // split further until the column count fits
+    while (sweep_class(precision, n, t.mc) < 0 && t.mc > 1) {
+      ++S;
+      t.mc = (sm + S - 1) / S;
+      t.S = (sm + t.mc - 1) / t.mc;
+    }
+    t.kclass = sweep_class(precision, n, t.mc);
+  }
+  t.stage = (four || wg) ? 0 : stage_bytes(precision, n, sm, sp);
+  t.ntiles = fblocks * t.S;
+  t.waves_per_tile = wg ? 4 : 1;
+  return t;
+}
+
+hipError_t launch_any_sweep(int k, const SweepLaunch& L, size_t lds_bytes, hipStream_t s) {
+  if (k >= kNumSweepClasses + kNumSweep16Classes) return launch_sweep_wg(k - kNumSweepClasses - kNumSweep16Classes, L, s);
+  if (k >= kNumSweepClasses) return launch_sweep16(k - kNumSweepClasses, L, s);
+  return launch_sweep(k, L, lds_bytes, s);
+}
+
+namespace {
 
 // Doubles a request's omega array holds.
 size_t omega_doubles(const lti_request& q) {
@@ -407,8 +460,8 @@ bool take_buf(lti_ctx* c, HostBuf& hb, size_t bytes, bool may_page) {
 // (device requests without info_out), the refinement queue, then the
 // reduction scratch.
 struct Need {
-  size_t omega = 0, G = 0, info = 0, queue = 0, inputs = 0, work = 0, model = 0;
-  size_t block() const { return omega + G + info + queue + inputs + work; }
+  size_t omega = 0, G = 0, info = 0, dG = 0, queue = 0, inputs = 0, work = 0, model = 0;
+  size_t block() const { return omega + G + info + dG + queue + inputs + work; }
 };
 
 // n, sm, sp: the solved system's sizes.
@@ -420,6 +473,7 @@ Need request_need(const lti_request& q, bool needs_model, int sm, int sp) {
     nd.G = align_up(sizeof(double) * 2 * (size_t)q.n_omega * p * m);
   }
   if (q.mem == LTI_MEM_HOST || !q.info_out) nd.info = align_up(sizeof(lti_point_info) * q.n_omega);
+  if (q.mem == LTI_MEM_HOST && q.dG_out) nd.dG = nd.G;
   // one queue entry per (point, column group) at most; sm groups at most
   nd.queue = align_up(8 + 8 * (size_t)q.n_omega * sm);
   if (needs_model) {
@@ -511,7 +565,9 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   const size_t gbytes = q.mem == LTI_MEM_HOST ? sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu : 0;
   hs.offG = 0;
   hs.offInfo = align_up(gbytes);
-  if (!take_buf(c, hs.out, hs.offInfo + ibytes, align_up(hs.offInfo + ibytes) > c->staging.size())) return false;
+  hs.offDG = hs.offInfo + align_up(ibytes);
+  hs.outBytes = (q.mem == LTI_MEM_HOST && q.dG_out) ? hs.offDG + gbytes : hs.offInfo + ibytes;
+  if (!take_buf(c, hs.out, hs.outBytes, align_up(hs.outBytes) > c->staging.size())) return false;
   void* mblock = nullptr;
   if (needs_model) {
     mblock = alloc_evicting(c, nd.model);
@@ -592,6 +648,11 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
     d_info = reinterpret_cast<lti_point_info*>(b);
     b += nd.info;
   }
+  double* d_dG = q.dG_out;
+  if (nd.dG) {  // host requests: right after the records, as in staging
+    d_dG = reinterpret_cast<double*>(b);
+    b += nd.dG;
+  }
   r->dinfo = d_info;
   uint32_t* fbq = reinterpret_cast<uint32_t*>(b);
   b += nd.queue;
@@ -613,6 +674,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   desc.Ct32 = res->rm.Ct32;
   desc.omega = d_omega;
   desc.G = d_G;
+  desc.dG = d_dG;
   desc.info = d_info;
   desc.fbq = fbq;
   desc.n = n;
@@ -627,49 +689,24 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
     return true;
   }
   r->K = q.n_omega;
-  // Kernel family: four frequencies per wavefront (n <= 64, at most four
-  // right-hand-side columns per tile), one frequency per wavefront
-  // (n <= 256), or one frequency per workgroup (n <= 1024).
-  const bool wg = n > kMaxN;
-  const bool four = !wg && c->use_sweep16 && sweep16_class(q.precision, n, std::min(sm, 4)) >= 0;
-  int F = c->tile_points;
-  if (F <= 0) F = four ? 4 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, r->K / 2048));
-  if (four) F = (F + 3) & ~3;
-  r->F = F;
-  // Split the right-hand-side columns over several tiles (each split
-  // repeats the rotations) only while the device would otherwise be short of
-  // wavefronts: the target counts the waves of tiles already outstanding.
-  const int64_t fblocks = (r->K + F - 1) / F;
-  const int64_t target = four ? c->target_tiles16 : c->target_tiles;
-  const int64_t avail = std::max<int64_t>(0, target - c->outstanding_waves);
-  int S = c->rhs_split;
-  if (S <= 0) S = (fblocks >= avail) ? 1 : (int)((avail + fblocks - 1) / fblocks);
-  S = std::max(1, std::min(S, sm));
-  if (four || wg) S = std::max(S, (sm + 3) / 4);
-  r->mc = (sm + S - 1) / S;
-  r->S = (sm + r->mc - 1) / r->mc;
-  if (wg)
-    r->kclass = kNumSweepClasses + kNumSweep16Classes + sweep_wg_class(q.precision, n, r->mc);
-  else if (four)
-    r->kclass = kNumSweepClasses + sweep16_class(q.precision, n, r->mc);
-  else {
-    // one-frequency kernels keep R * MM <= 32 (R = 1, 2, 4 row slices):
-    // split further until the column count fits
-    while (sweep_class(q.precision, n, r->mc) < 0 && r->mc > 1) {
-      ++S;
-      r->mc = (sm + S - 1) / S;
-      r->S = (sm + r->mc - 1) / r->mc;
-    }
-    r->kclass = sweep_class(q.precision, n, r->mc);
-  }
+  TileKnobs kn;
+  kn.tile_points = c->tile_points;
+  kn.rhs_split = c->rhs_split;
+  kn.use_sweep16 = c->use_sweep16;
+  const TilePlan tp = plan_tiles(q.precision, n, sm, sp, r->K, std::max<int64_t>(0, c->target_tiles16 - c->outstanding_waves),
+                                 std::max<int64_t>(0, c->target_tiles - c->outstanding_waves), kn);
+  r->F = tp.F;
+  r->S = tp.S;
+  r->mc = tp.mc;
+  r->kclass = tp.kclass;
   // several column groups per point: their records are merged (cleared first)
   if (r->S > 1) {
     desc.flags |= kFlagMergeInfo;
     pw.zero.emplace_back(reinterpret_cast<uint32_t*>(d_info), (uint32_t)(2 * r->K));
   }
-  r->stage = (four || wg) ? 0 : stage_bytes(q.precision, n, sm, sp);
-  r->ntiles = fblocks * r->S;
-  r->waves_per_tile = wg ? 4 : 1;
+  r->stage = tp.stage;
+  r->ntiles = tp.ntiles;
+  r->waves_per_tile = tp.waves_per_tile;
   c->outstanding_waves += r->ntiles * r->waves_per_tile;
   r->next_tile = 0;
   r->tiles_done = 0;
@@ -778,9 +815,10 @@ hipError_t copy_results(lti_ctx* c, Request* r, hipStream_t s) {
   HostStage& hs = r->hs;
   const size_t ibytes = sizeof(lti_point_info) * q.n_omega;
   if (q.mem == LTI_MEM_HOST) {
-    // G and info are back to back in the block and in staging (same offsets)
+    // G, info (and dG) are back to back in the block and in staging (same
+    // offsets)
     const char* src = static_cast<const char*>(r->block) + r->dOffG;
-    return hipMemcpyAsync(hs.out.base + hs.offG, src, hs.offInfo + ibytes, hipMemcpyDeviceToHost, s);
+    return hipMemcpyAsync(hs.out.base + hs.offG, src, hs.outBytes, hipMemcpyDeviceToHost, s);
   }
   return hipMemcpyAsync(hs.out.base + hs.offInfo, r->dinfo, ibytes, hipMemcpyDeviceToHost, s);
 }
@@ -791,7 +829,7 @@ hipError_t copy_results(lti_ctx* c, Request* r, hipStream_t s) {
 // batch are finished in it: refinement of their queued points, result copy.
 void launch(lti_ctx* c) {
   if (c->live.empty() || (int)c->inflight.size() >= c->max_inflight) return;
-  constexpr int kAllClasses = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
+  constexpr int kAllClasses = kAllSweepClasses;
   struct Piece {
     Request* r;
     int64_t first, count;
@@ -900,12 +938,7 @@ void launch(lti_ctx* c) {
         t += (uint32_t)pc.count;
       }
       L.ntiles = (int)t;
-      if (k >= kNumSweepClasses + kNumSweep16Classes)
-        e = launch_sweep_wg(k - kNumSweepClasses - kNumSweep16Classes, L, ss);
-      else if (k >= kNumSweepClasses)
-        e = launch_sweep16(k - kNumSweepClasses, L, ss);
-      else
-        e = launch_sweep(k, L, c->stage_lds ? lds[k] : 0, ss);
+      e = launch_any_sweep(k, L, c->stage_lds ? lds[k] : 0, ss);
       c->stats.sweep_launches++;
     }
   }
@@ -957,6 +990,8 @@ void complete_request(lti_ctx* c, Request* r) {
   if (q.mem == LTI_MEM_HOST) {
     std::memcpy(q.G_out, hs.out.base + hs.offG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
     if (q.info_out) std::memcpy(q.info_out, info, sizeof(lti_point_info) * q.n_omega);
+    if (q.dG_out)
+      std::memcpy(q.dG_out, hs.out.base + hs.offDG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
   }
   for (int64_t k = 0; k < q.n_omega; ++k) {
     const lti_point_info& pi = info[k];
@@ -1315,6 +1350,7 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
   if (!r) return LTI_ENOMEM;
   r->req = *q;
   if (q->rtol <= 0.0) r->req.rtol = 1e-10;
+  if (q->dG_out) r->req.precision = LTI_PREC_FP64;  // derivatives: float64 path
   // fewer outputs than inputs: solve the transposed system, whose
   // right-hand sides are the min(nu, ny) outputs
   r->trans = (p < m && !(c->flags & LTI_CFG_NO_TRANSPOSE)) ? 1 : 0;

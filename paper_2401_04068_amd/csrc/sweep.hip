@@ -362,11 +362,12 @@ __device__ __forceinline__ void reduce_scatter8(double (&vr)[kV], double (&vi)[k
   }
 }
 
-// G(:, j0 .. j0+mc-1) = Ct^T X + D for one frequency, X in xr/xi.
+// G(:, j0 .. j0+mc-1) = Ct^T X + D for one frequency, X in xr/xi; with
+// `deriv`, -Ct^T X (the derivative -C (sI - A)^{-2} B from X = (sI - H)^{-2} Q^T B).
 template <int R, int MM, bool kLds>
 __device__ __forceinline__ void write_output(const ReqDesc& rd, Src<double, kLds> Ct, int j0, int mc,
                                              const double (&xr)[R][MM], const double (&xi)[R][MM],
-                                             double* __restrict__ G) {
+                                             double* __restrict__ G, bool deriv = false) {
   const int lane = threadIdx.x & 63;
   const int n = rd.n, m = rd.m, p = rd.p;
   constexpr int PC = (kV / MM > 0) ? kV / MM : 1;  // rows of G per pass
@@ -401,8 +402,8 @@ __device__ __forceinline__ void write_output(const ReqDesc& rd, Src<double, kLds
         const int j = jb + idx % MC;
         if (a < p && j < mc) {
           double2 g;
-          g.x = vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
-          g.y = vi[0];
+          g.x = deriv ? -vr[0] : vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
+          g.y = deriv ? -vi[0] : vi[0];
           store_c(G, g_index(rd, a, j0 + j), g);
         }
       }
@@ -438,10 +439,16 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
   apply_rotations<double, R, MM>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
   write_output<R, MM, kLds>(rd, md.Ct, j0, mc, st.br, st.bi, G);
+  if (rd.dG) {
+    // dG/ds = -C (sI - A)^{-2} B: the same sweep with X as right-hand side
+    givens_sweep<double, R, MM, kLds>(md.H, n, sp.re, sp.im, st, bcast);
+    apply_rotations<double, R, MM>(n, st);
+    write_output<R, MM, kLds>(rd, md.Ct, j0, mc, st.br, st.bi, rd.dG + (size_t)k * rd.p * m * 2, true);
+  }
   if (lane == 0) {
     lti_point_info inf;
     inf.est_rel_err = (float)est;
-    inf.iters = 1;
+    inf.iters = rd.dG ? 2 : 1;
     inf.path = LTI_PATH_FP64;
     inf.reserved = 0;
     put_info(rd, k, inf);

@@ -393,7 +393,7 @@ __device__ __forceinline__ void rs16_stage(double (&vr)[8], double (&vi)[8], boo
 template <int R, int MM>
 __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc, bool valid,
                                                const double (&xr)[R][MM], const double (&xi)[R][MM],
-                                               double* __restrict__ G) {
+                                               double* __restrict__ G, bool deriv = false) {
   const int gl = threadIdx.x & 15;
   const int n = rd.n, m = rd.m, p = rd.p;
   const gptr<double> Ct = (gptr<double>)rd.Ct;
@@ -434,8 +434,8 @@ __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc
         const int j = jb + idx % MC;
         if (a < p && j < mc) {
           double2 gv;
-          gv.x = vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
-          gv.y = vi[0];
+          gv.x = deriv ? -vr[0] : vr[0] + ((gptr<double>)rd.D)[a * m + j0 + j];
+          gv.y = deriv ? -vi[0] : vi[0];
           store_c(G, g_index(rd, a, j0 + j), gv);
         }
       }
@@ -469,10 +469,16 @@ __device__ void solve16_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, 
   apply_rotations16<double, R, MM>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
   write_output16<R, MM>(rd, j0, mc, valid && !dd, st.br, st.bi, G);
+  if (rd.dG) {
+    // dG/ds = -C (sI - A)^{-2} B: the same sweep with X as right-hand side
+    sweep16<double, R, MM, kLds>(H, n, sp.re, sp.im, st, bcast);
+    apply_rotations16<double, R, MM>(n, st);
+    write_output16<R, MM>(rd, j0, mc, valid && !dd, st.br, st.bi, rd.dG + (size_t)k * rd.p * m * 2, true);
+  }
   if (valid && !dd && gl == 0) {
     lti_point_info inf;
     inf.est_rel_err = (float)est;
-    inf.iters = 1;
+    inf.iters = rd.dG ? 2 : 1;
     inf.path = LTI_PATH_FP64;
     inf.reserved = 0;
     put_info(rd, k, inf);

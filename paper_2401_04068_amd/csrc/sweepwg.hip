@@ -387,7 +387,7 @@ __device__ __forceinline__ void apply_rotations_wg(int n, SWG<T, MM>& st, ShWG& 
 template <int MM>
 __device__ __forceinline__ void write_output_wg(const ReqDesc& rd, int j0, int mc, const double (&xr)[kRWG][MM],
                                                 const double (&xi)[kRWG][MM], double* __restrict__ G,
-                                                ShWG& sh) {
+                                                ShWG& sh, bool deriv = false) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = rd.n, m = rd.m, p = rd.p;
   const gptr<double> Ct = (gptr<double>)rd.Ct;
@@ -429,8 +429,8 @@ __device__ __forceinline__ void write_output_wg(const ReqDesc& rd, int j0, int m
         gi += sh.red[q][j][1];
       }
       double2 g;
-      g.x = gr + ((gptr<double>)rd.D)[a * m + j0 + j];
-      g.y = gi;
+      g.x = deriv ? -gr : gr + ((gptr<double>)rd.D)[a * m + j0 + j];
+      g.y = deriv ? -gi : gi;
       store_c(G, g_index(rd, a, j0 + j), g);
     }
     __syncthreads();
@@ -492,10 +492,16 @@ __device__ void solve_wg_fp64(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG
   apply_rotations_wg<double, MM>(n, st, sh);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
   write_output_wg<MM>(rd, j0, mc, st.br, st.bi, G, sh);
+  if (rd.dG) {
+    // dG/ds = -C (sI - A)^{-2} B: the same sweep with X as right-hand side
+    sweep_wg<double, MM>(rd.H, n, sp.re, sp.im, st, sh);
+    apply_rotations_wg<double, MM>(n, st, sh);
+    write_output_wg<MM>(rd, j0, mc, st.br, st.bi, rd.dG + (size_t)k * rd.p * m * 2, sh, true);
+  }
   if (tid == 0) {
     lti_point_info inf;
     inf.est_rel_err = (float)est;
-    inf.iters = 1;
+    inf.iters = rd.dG ? 2 : 1;
     inf.path = LTI_PATH_FP64;
     inf.reserved = 0;
     put_info(rd, k, inf);
@@ -783,49 +789,46 @@ struct DDResult {
   bool singular;
 };
 
-// Column j of point k: G(:, j) = C0 x + D(:, j) with x refined as above.
-__device__ DDResult refine_column(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j, DDShared& S,
-                                  BlockRed& br) {
+// x = (s I - A)^{-1} c for one right-hand side c (in the model's own
+// coordinates, float64), refined with the residual in double-double.  On
+// return x = (xr, xi) in double-double; res.est is the last correction norm
+// ||dx|| / ||x||.  If the float64 solve meets an exactly zero diagonal entry
+// of R, returns at once with res.singular and y = (s I - H)^{-1} Q^T c in
+// (yr, yi), reduced coordinates.
+__device__ DDResult refine_solve(const ReducedModel& rm, SPoint sp, double tol, const double (&cr)[kRWG],
+                                 const double (&ci)[kRWG], dd (&xr)[kRWG], dd (&xi)[kRWG], double (&yr)[kRWG],
+                                 double (&yi)[kRWG], DDShared& S, BlockRed& br) {
   const int tid = threadIdx.x;
-  const int n = rm.n, m = rm.m, p = rm.p;
-  const SPoint sp = point_of(rd, k);
-  const double tol = 0.1 * rd.rtol;
+  const int n = rm.n;
   constexpr int kMaxDD = 4;
-  const gptr<double> Bt = (gptr<double>)rm.Bt;
   const gptr<double> A0 = (gptr<double>)rm.A0;  // column-major
-  const gptr<double> B0 = (gptr<double>)rm.B0;  // column-major
-  const gptr<double> C0 = (gptr<double>)rm.C0;  // row-major
   DDResult res{0.0, 1, false};
-  double yr[kRWG], yi[kRWG];
 #pragma unroll
   for (int r = 0; r < kRWG; ++r) {
-    const int i = tid + kThreadsWG * r;
-    yr[r] = (i < n) ? Bt[i * m + j] : 0.0;
-    yi[r] = 0.0;
+    yr[r] = cr[r];
+    yi[r] = ci[r];
   }
+  apply_q(rm, true, yr, yi, br);  // Q^T c
   res.singular = hess_solve(rm, sp, yr, yi, S.sh, br);
-  double* G = rd.G + (size_t)k * rd.p * rd.m * 2;
-  if (res.singular) {  // the float64 solution as it is (IEEE values)
-    double xr1[kRWG][1], xi1[kRWG][1];
-#pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
-      xr1[r][0] = yr[r];
-      xi1[r][0] = yi[r];
-    }
-    write_output_wg<1>(rd, j, 1, xr1, xi1, G, S.sh);
+  if (res.singular) {
     res.est = INFINITY;
     return res;
   }
-  apply_q(rm, false, yr, yi, br);  // x = Q y
-  dd xr[kRWG], xi[kRWG];
+  double tr[kRWG], ti[kRWG];
 #pragma unroll
   for (int r = 0; r < kRWG; ++r) {
-    xr[r] = dd{yr[r], 0.0};
-    xi[r] = dd{yi[r], 0.0};
+    tr[r] = yr[r];
+    ti[r] = yi[r];
+  }
+  apply_q(rm, false, tr, ti, br);  // x = Q y
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    xr[r] = dd{tr[r], 0.0};
+    xi[r] = dd{ti[r], 0.0};
   }
   double dprev = INFINITY;
   for (int it = 0; it < kMaxDD; ++it) {
-    // r = B0(:, j) - s x + A0 x, in double-double, then rounded
+    // r = c - s x + A0 x, in double-double, then rounded
     __syncthreads();  // S.x of the previous pass has been read
 #pragma unroll
     for (int r = 0; r < kRWG; ++r) {
@@ -836,11 +839,9 @@ __device__ DDResult refine_column(const ReqDesc& rd, const ReducedModel& rm, int
     dd ar[kRWG], ai[kRWG];
 #pragma unroll
     for (int r = 0; r < kRWG; ++r) {
-      const int i = tid + kThreadsWG * r;
-      const double b = (i < n) ? B0[(size_t)j * n + i] : 0.0;
-      // b - sg x + w i x:  re = b - sg xr + w xi,  im = -sg xi - w xr
-      ar[r] = dd_add(dd_add(dd{b, 0.0}, dd_mul_d(xr[r], -sp.re)), dd_mul_d(xi[r], sp.im));
-      ai[r] = dd_add(dd_mul_d(xi[r], -sp.re), dd_mul_d(xr[r], -sp.im));
+      // c - sg x + w i x:  re = c - sg xr + w xi,  im = ci - sg xi - w xr
+      ar[r] = dd_add(dd_add(dd{cr[r], 0.0}, dd_mul_d(xr[r], -sp.re)), dd_mul_d(xi[r], sp.im));
+      ai[r] = dd_add(dd_add(dd{ci[r], 0.0}, dd_mul_d(xi[r], -sp.re)), dd_mul_d(xr[r], -sp.im));
     }
     for (int c = 0; c < n; ++c) {
       const double4 xc = S.x[c];
@@ -854,34 +855,41 @@ __device__ DDResult refine_column(const ReqDesc& rd, const ReducedModel& rm, int
         }
       }
     }
-    double rr[kRWG], ri[kRWG];
 #pragma unroll
     for (int r = 0; r < kRWG; ++r) {
-      rr[r] = ar[r].hi + ar[r].lo;
-      ri[r] = ai[r].hi + ai[r].lo;
+      tr[r] = ar[r].hi + ar[r].lo;
+      ti[r] = ai[r].hi + ai[r].lo;
     }
     // d = Q (s I - H)^{-1} Q^T r
-    apply_q(rm, true, rr, ri, br);
-    hess_solve(rm, sp, rr, ri, S.sh, br);
-    apply_q(rm, false, rr, ri, br);
+    apply_q(rm, true, tr, ti, br);
+    hess_solve(rm, sp, tr, ti, S.sh, br);
+    apply_q(rm, false, tr, ti, br);
     ++res.solves;
     double d2 = 0.0, x2 = 0.0;
 #pragma unroll
     for (int r = 0; r < kRWG; ++r) {
-      xr[r] = dd_add(xr[r], dd{rr[r], 0.0});
-      xi[r] = dd_add(xi[r], dd{ri[r], 0.0});
-      d2 += rr[r] * rr[r] + ri[r] * ri[r];
+      xr[r] = dd_add(xr[r], dd{tr[r], 0.0});
+      xi[r] = dd_add(xi[r], dd{ti[r], 0.0});
+      d2 += tr[r] * tr[r] + ti[r] * ti[r];
       x2 += xr[r].hi * xr[r].hi + xi[r].hi * xi[r].hi;
     }
     const double2 dx = br.sum2(d2, x2);
     const double dn = sqrt(dx.x), xn = sqrt(dx.y);
     res.est = (xn > 0.0) ? dn / xn : (dn > 0.0 ? INFINITY : 0.0);
-    if (!(res.est > tol)) break;        // converged (or x = 0 exactly)
-    if (!(dn < 0.5 * dprev)) break;     // no longer contracting
+    if (!(res.est > tol)) break;     // converged (or x = 0 exactly)
+    if (!(dn < 0.5 * dprev)) break;  // no longer contracting
     dprev = dn;
   }
-  // G(:, j) = C0 x + D(:, j): per-thread double-double sums, then the
-  // workgroup sum of the high and low parts
+  return res;
+}
+
+// out(:, j) = sign * C0 x (+ D(:, j) for G): per-thread double-double sums,
+// then the workgroup sum of the high and low parts.
+__device__ void write_cx(const ReqDesc& rd, const ReducedModel& rm, int j, const dd (&xr)[kRWG],
+                         const dd (&xi)[kRWG], double* out, bool deriv, BlockRed& br) {
+  const int tid = threadIdx.x;
+  const int n = rm.n, m = rm.m, p = rm.p;
+  const gptr<double> C0 = (gptr<double>)rm.C0;  // row-major
   for (int a = 0; a < p; ++a) {
     dd gr{0.0, 0.0}, gi{0.0, 0.0};
 #pragma unroll
@@ -897,10 +905,60 @@ __device__ DDResult refine_column(const ReqDesc& rd, const ReducedModel& rm, int
     const double2 lo = br.sum2(gr.lo, gi.lo);
     if (tid == 0) {
       double2 g;
-      g.x = (hi.x + lo.x) + ((gptr<double>)rm.D)[a * m + j];
-      g.y = hi.y + lo.y;
-      store_c(G, g_index(rd, a, j), g);
+      if (deriv) {
+        g.x = -(hi.x + lo.x);
+        g.y = -(hi.y + lo.y);
+      } else {
+        g.x = (hi.x + lo.x) + ((gptr<double>)rm.D)[a * m + j];
+        g.y = hi.y + lo.y;
+      }
+      store_c(out, g_index(rd, a, j), g);
     }
+  }
+}
+
+// Column j of point k: G(:, j) = C0 x + D(:, j) with x = (s I - A)^{-1}
+// B0(:, j) refined as above; with a derivative requested, also
+// dG/ds(:, j) = -C0 (s I - A)^{-1} x, the second solve refined the same way.
+__device__ DDResult refine_column(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j, DDShared& S,
+                                  BlockRed& br) {
+  const int tid = threadIdx.x;
+  const int n = rm.n;
+  const SPoint sp = point_of(rd, k);
+  const double tol = 0.1 * rd.rtol;
+  const gptr<double> B0 = (gptr<double>)rm.B0;  // column-major
+  double cr[kRWG], ci[kRWG], yr[kRWG], yi[kRWG];
+#pragma unroll
+  for (int r = 0; r < kRWG; ++r) {
+    const int i = tid + kThreadsWG * r;
+    cr[r] = (i < n) ? B0[(size_t)j * n + i] : 0.0;
+    ci[r] = 0.0;
+  }
+  dd xr[kRWG], xi[kRWG];
+  DDResult res = refine_solve(rm, sp, tol, cr, ci, xr, xi, yr, yi, S, br);
+  double* G = rd.G + (size_t)k * rd.p * rd.m * 2;
+  if (res.singular) {  // the float64 solution as it is (IEEE values)
+    double xr1[kRWG][1], xi1[kRWG][1];
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      xr1[r][0] = yr[r];
+      xi1[r][0] = yi[r];
+    }
+    write_output_wg<1>(rd, j, 1, xr1, xi1, G, S.sh);
+    return res;
+  }
+  write_cx(rd, rm, j, xr, xi, G, false, br);
+  if (rd.dG) {
+#pragma unroll
+    for (int r = 0; r < kRWG; ++r) {
+      cr[r] = xr[r].hi + xr[r].lo;
+      ci[r] = xi[r].hi + xi[r].lo;
+    }
+    dd x2r[kRWG], x2i[kRWG];
+    const DDResult r2 = refine_solve(rm, sp, tol, cr, ci, x2r, x2i, yr, yi, S, br);
+    write_cx(rd, rm, j, x2r, x2i, rd.dG + (size_t)k * rd.p * rd.m * 2, true, br);
+    res.est = fmax(res.est, r2.est);
+    res.solves += r2.solves;
   }
   return res;
 }

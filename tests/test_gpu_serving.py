@@ -141,3 +141,83 @@ def test_discrete_time_unit_circle(n, m, p):
             assert e.poll(h, -1)
             err = oracle.rel_err(h.G, ref)
             assert err.max() <= tol, (err.max(), theta[err.argmax()])
+
+
+@pytest.mark.parametrize("n,m,p", [(8, 1, 1), (40, 3, 2), (100, 2, 4), (300, 3, 3)])
+def test_derivative(n, m, p):
+    """dG/ds = -C (sI - A)^{-2} B from the second sweep, on the frequency grid
+    and at complex points, against the oracle (requests with a derivative run
+    the float64 path)."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(5400 + n)
+    mdl = wl.mixed_pole_model(rng, n, m, p, np.concatenate([[0.0, -1.7], wl.logspace_grid(1e-2, 1e2, 30)]))
+    with binding.Engine(arena_bytes=512 << 20) as e:
+        print(f"case derivative n={n}", flush=True)
+        h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=binding.PREC_REFINED, want_derivative=True)
+        assert e.poll(h, -1)
+        s = 1j * mdl.omega
+        assert oracle.rel_err(h.G, oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)).max() <= 1e-10
+        assert oracle.rel_err(h.dG, oracle.derivative_at(mdl.A, mdl.B, mdl.C, mdl.D, s)).max() <= 1e-10
+        assert np.all(h.info["path"] == binding.PATH_FP64)
+        sc = s + rng.uniform(-1, 1, len(s))
+        h2 = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, sc, points=binding.POINTS_S, want_derivative=True)
+        assert e.poll(h2, -1)
+        assert oracle.rel_err(h2.dG, oracle.derivative_at(mdl.A, mdl.B, mdl.C, mdl.D, sc)).max() <= 1e-10
+
+
+def test_derivative_near_resonance():
+    """At kappa ~ 1e8 the derivative (error ~ kappa^2 u in plain float64)
+    comes from the double-double refinement; against the extended oracle."""
+    from paper_2401_04068_amd import binding
+
+    mdl = wl.resonant_model(24, 2, 2, 1e-7, 1.0, seed=5500)
+    with binding.Engine(arena_bytes=256 << 20) as e:
+        h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, want_derivative=True)
+        assert e.poll(h, -1)
+    s = 1j * mdl.omega
+    ref = oracle.derivative_at_extended(mdl.A, mdl.B, mdl.C, mdl.D, s)
+    err = oracle.rel_err(h.dG, ref)
+    hard = h.info["path"] == binding.PATH_FP64_DD
+    assert hard.sum() >= 4
+    assert err.max() <= 1e-9, (err.max(), int(err.argmax()))
+
+
+@pytest.mark.parametrize("wn,zeta", [(1.0, 0.05), (7.0, 1e-3), (30.0, 0.3)])
+def test_peaks_second_order_closed_form(wn, zeta):
+    """lti_freqresp_peaks on wn^2 / (s^2 + 2 zeta wn s + wn^2): the peak at
+    w_r = wn sqrt(1 - 2 zeta^2) with gain 1 / (2 zeta sqrt(1 - zeta^2))."""
+    from paper_2401_04068_amd import binding
+
+    A = np.array([[0.0, 1.0], [-wn * wn, -2.0 * zeta * wn]])
+    B = np.array([[0.0], [1.0]])
+    C = np.array([[wn * wn, 0.0]])
+    D = np.zeros((1, 1))
+    with binding.Engine(arena_bytes=64 << 20) as e:
+        pk, res = e.peaks(A, B, C, D, wl.logspace_grid(wn / 100, wn * 100, 200))
+    wr = wn * np.sqrt(1 - 2 * zeta * zeta)
+    gr = 1.0 / (2 * zeta * np.sqrt(1 - zeta * zeta))
+    assert len(pk) == 1
+    assert abs(pk[0][0] - wr) <= 1e-9 * wr, (pk, wr)
+    assert abs(pk[0][1] - gr) <= 1e-12 * gr
+    assert abs(res["hinf"] - gr) <= 1e-12 * gr
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_peaks_mimo_against_bruteforce(seed):
+    """A 40-state 3x2 model: the library's derivative-based peaks and
+    H-infinity estimate against the oracle's dense grid + golden-section
+    search."""
+    from oracle import peaks as opk
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(5600 + seed)
+    mdl = wl.mixed_pole_model(rng, 40, 3, 2, np.zeros(0))
+    hinf_o, wh_o, pk_o = opk.peaks_bruteforce(mdl.A, mdl.B, mdl.C, mdl.D, 1e-2, 1e2, n=4000)
+    with binding.Engine(arena_bytes=256 << 20) as e:
+        pk, res = e.peaks(mdl.A, mdl.B, mdl.C, mdl.D, wl.logspace_grid(1e-2, 1e2, 1000))
+    print(f"peaks: library {res}, oracle hinf {hinf_o} at {wh_o}", flush=True)
+    assert abs(res["hinf"] - hinf_o) <= 1e-9 * hinf_o
+    # the largest peak agrees in frequency and gain
+    (w, g), (wo, go) = pk[0], pk_o[0]
+    assert abs(g - go) <= 1e-9 * go and abs(w - wo) <= 1e-5 * wo, (pk, pk_o)

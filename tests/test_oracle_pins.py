@@ -382,3 +382,91 @@ def test_complex_points_on_the_axis_agree_with_frequency_grid():
     G1 = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
     G2 = oracle.freqresp_at(mdl.A, mdl.B, mdl.C, mdl.D, 1j * mdl.omega)
     assert np.max(oracle.rel_err(G2, G1)) < 1e-14
+
+
+# ---------------------------------------------------------------- derivative
+
+def test_derivative_closed_forms():
+    """First order: d/ds [c b / (s + a) + d] = -c b / (s + a)^2.  Second order
+    (companion form): d/ds [wn^2 / (s^2 + 2 zeta wn s + wn^2)] =
+    -wn^2 (2 s + 2 zeta wn) / (s^2 + 2 zeta wn s + wn^2)^2."""
+    a, b, c, d = 0.7, -1.3, 2.1, 0.4
+    s = np.array([0.3j, -0.2 + 1.5j, 2.0 + 0j, -1.0 - 4.0j])
+    dG = oracle.derivative_at(*_first_order(a, b, c, d), s)[:, 0, 0]
+    ref = -c * b / (s + a) ** 2
+    assert np.max(np.abs(dG - ref) / np.abs(ref)) < 1e-14
+    for wn, zeta in [(1.0, 0.1), (7.0, 1e-3)]:
+        s = 1j * wn * np.array([0.3, 0.999, 1.0, 2.0]) + 0.01
+        dG = oracle.derivative_at(*_second_order(wn, zeta), s)[:, 0, 0]
+        den = s * s + 2 * zeta * wn * s + wn * wn
+        ref = -wn * wn * (2 * s + 2 * zeta * wn) / den ** 2
+        assert np.max(np.abs(dG - ref) / np.abs(ref)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_derivative_exact_rational(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = 1 + seed % 4
+    A, B, C, D = _rand_small_int_system(rng, n, 2, 2)
+    for sig, w in [(Fraction(1, 2), Fraction(3, 8)), (Fraction(-7, 4), Fraction(5, 4)), (Fraction(0), Fraction(9, 4))]:
+        try:
+            Gx = exact.derivative_exact(A.tolist(), B.tolist(), C.tolist(), D.tolist(), w, sigma=sig)
+        except ZeroDivisionError:
+            continue
+        ref = np.array([[exact.to_complex(z) for z in row] for row in Gx])
+        s = complex(float(sig), float(w))
+        kappa = np.linalg.cond(s * np.eye(n) - A)
+        dG = oracle.derivative_at(A, B, C, D, [s])[0]
+        assert np.linalg.norm(dG - ref) <= 1e-14 * kappa ** 2 * max(np.linalg.norm(ref), 1e-300), (seed, s)
+
+
+def test_derivative_matches_central_difference():
+    """(G(s + h) - G(s - h)) / 2h = dG/ds + O(h^2) along the imaginary axis."""
+    mdl = wl.mimo64(K=16)
+    s = 1j * mdl.omega
+    h = 1e-5
+    fd = (oracle.freqresp_at(mdl.A, mdl.B, mdl.C, mdl.D, s + 1j * h)
+          - oracle.freqresp_at(mdl.A, mdl.B, mdl.C, mdl.D, s - 1j * h)) / (2j * h)
+    dG = oracle.derivative_at(mdl.A, mdl.B, mdl.C, mdl.D, s)
+    assert np.max(oracle.rel_err(fd, dG)) < 1e-6
+
+
+def test_derivative_extended_exact_ill_conditioned():
+    """Near an eigenvalue (kappa ~ 1e7) the extended derivative stays within
+    kappa^2 u_ext of the exact rational value, where the float64 one cannot."""
+    A = [[0, 1], [-1, Fraction(-2e-7)]]  # zeta = 1e-7, wn = 1 (the float's exact value)
+    B = [[0], [1]]
+    C = [[1, 0]]
+    D = [[0]]
+    w = Fraction(1)
+    Gx = exact.derivative_exact(A, B, C, D, w)
+    ref = exact.to_complex(Gx[0][0])
+    Af = np.array([[0.0, 1.0], [-1.0, -2e-7]])
+    dG = oracle.derivative_at_extended(Af, np.array(B, float), np.array(C, float), np.zeros((1, 1)), [1j])[0, 0, 0]
+    assert abs(dG - ref) <= 1e-8 * abs(ref), (dG, ref)
+
+
+# ---------------------------------------------------------------- peaks
+
+@pytest.mark.parametrize("wn,zeta", [(1.0, 0.05), (7.0, 1e-3), (30.0, 0.3)])
+def test_peak_bruteforce_second_order_closed_form(wn, zeta):
+    """|wn^2 / (wn^2 - w^2 + 2 j zeta wn w)| peaks at w_r = wn sqrt(1 - 2 zeta^2)
+    with value 1 / (2 zeta sqrt(1 - zeta^2)) (zeta < 1/sqrt 2)."""
+    from oracle import peaks
+
+    hinf, wh, pk = peaks.peaks_bruteforce(*_second_order(wn, zeta), wn / 100, wn * 100, n=2000)
+    wr = wn * np.sqrt(1 - 2 * zeta * zeta)
+    gr = 1.0 / (2 * zeta * np.sqrt(1 - zeta * zeta))
+    assert abs(pk[0][0] - wr) <= 1e-6 * wr
+    assert abs(pk[0][1] - gr) <= 1e-12 * gr
+    assert abs(hinf - gr) <= 1e-12 * gr
+
+
+def test_peak_bruteforce_monotone_first_order():
+    """c b / (jw + a) + d decreases in |.| when d = 0: sup at w -> 0, no
+    interior peak."""
+    from oracle import peaks
+
+    hinf, wh, pk = peaks.peaks_bruteforce(*_first_order(2.0, 1.0, 3.0, 0.0), 1e-4, 1e4, n=500)
+    assert pk == []
+    assert abs(hinf - 1.5) <= 1e-8 * 1.5
