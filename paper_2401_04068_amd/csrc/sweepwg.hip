@@ -706,24 +706,35 @@ __global__ __launch_bounds__(kThreadsWG) __attribute__((amdgpu_waves_per_eu(2)))
 // order u64 (Higham, Accuracy and Stability of Numerical Algorithms, 2nd ed.,
 // sec. 12.1, residual in higher precision).  Q is applied as its reflectors.
 
+// The pair operations are error-free transformations only if every sum and
+// product in them is rounded on its own: floating-point contraction (which
+// HIP enables by default) must not fuse, say, the product x.hi * a with the
+// sums that follow it once the functions are inlined -- that counts the
+// product's rounding error twice and leaves the residual with float64
+// accuracy.  Each function therefore turns contraction off; the fused steps
+// they need are written as explicit fma().
 struct dd {
   double hi, lo;
 };
 __device__ __forceinline__ dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
   const double s = a + b;
   const double bb = s - a;
   return dd{s, (a - (s - bb)) + (b - bb)};
 }
 __device__ __forceinline__ dd fast_two_sum(double a, double b) {
+#pragma clang fp contract(off)
   const double s = a + b;
   return dd{s, b - (s - a)};
 }
 __device__ __forceinline__ dd dd_add(dd x, dd y) {
+#pragma clang fp contract(off)
   const dd s = two_sum(x.hi, y.hi);
   return fast_two_sum(s.hi, s.lo + (x.lo + y.lo));
 }
 // x * a, a a double
 __device__ __forceinline__ dd dd_mul_d(dd x, double a) {
+#pragma clang fp contract(off)
   const double p = x.hi * a;
   const double e = fma(x.hi, a, -p);
   return fast_two_sum(p, fma(x.lo, a, e));

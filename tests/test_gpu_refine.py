@@ -43,18 +43,26 @@ def test_stall_goes_to_double_double_refinement(eng, n):
     hard = kap > 1e7
     assert hard.sum() >= 4
     ref = oracle.freqresp_extended(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
-    for prec, dd_path in ((binding.PREC_REFINED, binding.PATH_FALLBACK), (binding.PREC_FP64, binding.PATH_FP64_DD)):
+    # Refined: kappa * u32 > 0.5 at every hard point, so the float32
+    # iteration cannot contract there and must fall back.  Float64: the
+    # library's estimate (u/2 times the spread of R's diagonal, a lower bound
+    # on kappa * u/2) decides; at the exact resonance (kappa > 5e7, where a
+    # float64 solve is off by ~1e-9) it must exceed rtol.  Every point, on
+    # whatever path, meets the contract against the extended oracle.
+    for prec, dd_path, must in ((binding.PREC_REFINED, binding.PATH_FALLBACK, hard),
+                                (binding.PREC_FP64, binding.PATH_FP64_DD, kap > 5e7)):
         print(f"case resonant n={n} precision={prec}", flush=True)
         h = eng.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=prec)
         assert eng.poll(h, -1)
         err = oracle.rel_err(h.G, ref)
         paths = h.info["path"]
-        assert np.all(paths[hard] == dd_path), (paths[hard], kap[hard])
+        assert must.sum() >= 2
+        assert np.all(paths[must] == dd_path), (paths[must], kap[must])
         assert err.max() <= TOL, (err.max(), int(err.argmax()), kap[err.argmax()], int(paths[err.argmax()]))
         n_dd = int(np.sum(paths == dd_path))
         key = "n_fallback" if prec == binding.PREC_REFINED else "n_fp64_dd"
-        assert h.result[key] == n_dd >= hard.sum()
-        assert np.all(h.info["est_rel_err"][hard] <= TOL)
+        assert h.result[key] == n_dd >= must.sum()
+        assert np.all(h.info["est_rel_err"][paths == dd_path] <= TOL)
 
 
 def test_fallback_in_second_column_group_is_reported(eng):
