@@ -397,9 +397,13 @@ def serving_headline(args, out):
     value = ref["points_per_s_raw"] * ref["frac_within_1e-10"]
     v64 = f64["points_per_s_raw"] * f64["frac_within_1e-10"]
     fam, roof = roofline_of(ref["delta"], ref["fam_flops"], fp32=True)
-    roof["traffic"] = _traffic_record(f"kf{fam}_serving", KF_SOURCES[fam])
+    bpp = _traffic_record(f"kf{fam}_serving", KF_SOURCES[fam])
+    pts_fam = sum(r.K for r in reqs if family_of(r.n) == fam) * args.steps
+    per_launch = pts_fam / max(ref["delta"]["family_launches"][fam], 1)
+    roof["traffic"] = None if bpp is None else bpp * per_launch
+    roof["traffic_bytes_per_point"] = bpp
+    roof["points_per_launch"] = per_launch
     fam64, roof64 = roofline_of(f64["delta"], f64["fam_flops"], fp32=False)
-    roof64["traffic"] = _traffic_record(f"kf{fam64}_serving_fp64", KF_SOURCES[fam64])
 
     def fam_table(r):
         d = r["delta"]
@@ -531,6 +535,87 @@ def secondary(args, out):
     out["secondary"] = sec
 
 
+# ------------------------------------------------------------------ counters
+
+def profile_pass(args):
+    """The run that HBM counters are taken on: one 256 MiB device copy (the
+    calibration: FETCH_SIZE / WRITE_SIZE of a copy of known size), then
+    `args.profile_pass` refined passes over the serving mix (device-memory
+    requests).  Prints the points each kernel family swept."""
+    import torch
+
+    from paper_2401_04068_amd import binding
+    from paper_2401_04068_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    reqs = wl.serving_requests(args.requests)
+    mix = DeviceMix(reqs, dev)
+    with binding.Engine(arena_bytes=8 << 30) as eng:
+        for _ in range(args.profile_pass):
+            mix.run(eng, binding.PREC_REFINED)
+    torch.cuda.synchronize()
+    pts = [0, 0, 0]
+    for r in reqs:
+        pts[family_of(r.n)] += r.K * args.profile_pass
+    print(json.dumps({"copy_bytes": 256 << 20, "passes": args.profile_pass, "requests": args.requests,
+                      "points_by_family": pts}), flush=True)
+
+
+def _pmc_totals(csv_path, counter):
+    """Sum of `counter` per kernel name over every dispatch in a rocprofv3
+    counter-collection CSV."""
+    import csv
+
+    tot = {}
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            k = row["Kernel_Name"]
+            tot[k] = tot.get(k, 0.0) + float(row["Counter_Value"])
+    return tot
+
+
+def traffic_record(args):
+    """profiles/kf<f>_serving_traffic.json from two counter runs of
+    `--profile-pass` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch): HBM
+    bytes per point of the refined kernels of family f, each counter scaled by
+    true bytes / counter for the calibration copy."""
+    fetch_csv, write_csv, pass_json = args.traffic_record
+    with open(pass_json) as f:
+        ps = json.loads(f.read().strip().splitlines()[-1])
+    fetch = _pmc_totals(fetch_csv, "FETCH_SIZE")
+    write = _pmc_totals(write_csv, "WRITE_SIZE")
+    copy_kib = ps["copy_bytes"] / 1024.0
+    cal = [k for k in fetch if "copyBuffer" in k or "elementwise_kernel" in k]
+    # the calibration copy is the largest copy dispatch of the run
+    fk = max((fetch[k] for k in cal), default=0.0)
+    wk = max((write.get(k, 0.0) for k in cal), default=0.0)
+    if not fk or not wk:
+        raise SystemExit("calibration copy not found in the counter CSVs")
+    ff, wf = copy_kib / fk, copy_kib / wk
+    fam = args.traffic_family
+    tag = ["sweep16_kernel<1,", "sweep_kernel<1,", "sweep_wg_kernel<1,"][fam]
+    names = [k for k in fetch if tag in k.replace(" ", "")]
+    fb = sum(fetch[k] for k in names) * ff * 1024.0
+    wb = sum(write.get(k, 0.0) for k in names) * wf * 1024.0
+    pts = ps["points_by_family"][fam]
+    rec = {"kernel_family": KF_NAMES[fam], "precision": "refined", "workload": "serving mix",
+           "source_files": KF_SOURCES[fam], "source_sha256_16": _source_digest(KF_SOURCES[fam]),
+           "kernels": sorted(names), "fetch_factor": ff, "write_factor": wf,
+           "fetch_bytes": fb, "write_bytes": wb, "points_swept": pts,
+           "hbm_bytes_per_point": (fb + wb) / max(pts, 1),
+           "commands": args.traffic_commands or []}
+    path = os.path.join(PROFILES, f"kf{fam}_serving_traffic.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -541,7 +626,16 @@ def main():
     ap.add_argument("--damped-models", type=int, default=512, help="models of the lightly damped batch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-secondary", action="store_true", help="only the headline configuration")
+    ap.add_argument("--profile-pass", type=int, default=0,
+                    help="counter run: a calibration copy, then this many refined passes of the mix")
+    ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PASS_JSON"),
+                    help="write the HBM-traffic record of a kernel family from two counter runs")
+    ap.add_argument("--traffic-family", type=int, default=1)
+    ap.add_argument("--traffic-commands", nargs="*")
     args = ap.parse_args()
+    if args.traffic_record:
+        traffic_record(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: every request and every frequency is independent, and the "
               "multi-GPU sharding (requests routed per GPU) is not built; run with --gpus 1", file=sys.stderr)
@@ -551,6 +645,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c32+f64", "data": "synthetic (seeded models of the stated recipe)",
     }
+    if args.profile_pass:
+        profile_pass(args)
+        return
     serving_headline(args, out)
     if not args.no_secondary:
         secondary(args, out)

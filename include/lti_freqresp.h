@@ -82,7 +82,8 @@ extern "C" {
 #define LTI_PATH_FALLBACK  2  /* refinement stalled; float64 solve used        */
 #define LTI_PATH_SINGULAR  3  /* j w I - A singular to working precision       */
 #define LTI_PATH_FP64_DD   4  /* float64 solve, then double-double residual
-                                 refinement against A (estimated error > rtol) */
+                                 refinement against A (estimated error
+                                 > rtol / 4)                                  */
 
 /* request.points: what omega holds */
 #define LTI_POINTS_JW     0   /* real frequencies w_k in rad/s: s_k = j w_k            */
@@ -105,9 +106,10 @@ typedef struct lti_point_info {
 } lti_point_info;
 /* est_rel_err: for LTI_PATH_REFINED the predicted error after the last
  * correction, min(||dX|| / ||X||, (||dX|| / ||X||) * contraction); for
- * LTI_PATH_FP64 the product of half the float64 unit roundoff and the ratio
- * of the largest to the smallest diagonal entry of the triangular factor (a
- * lower bound on kappa); for LTI_PATH_FALLBACK / _FP64_DD the last
+ * LTI_PATH_FP64 (u/2) sqrt(nx) max|R(k,k)| / min|R(k,k)|, u the float64
+ * unit roundoff and R the triangular factor of the shifted solve (the
+ * diagonal spread alone underestimates kappa by about sqrt(nx) on isolated
+ * resonances); for LTI_PATH_FALLBACK / _FP64_DD the last
  * correction norm ||dx|| / ||x|| of the double-double refinement.
  * iters: float32 solves (refined), plus float64 solves for _FALLBACK and
  * _FP64_DD.  With the columns of one point split over several kernel tiles,
@@ -148,7 +150,7 @@ typedef struct lti_request {
   double   rtol;          /* error target, <= 0 selects 1e-10.  Refined path:
                              stop when the predicted ||dX||/||X|| <= rtol / 10.
                              Float64 path: points whose estimated error exceeds
-                             rtol are refined against A in double-double      */
+                             rtol / 4 are refined against A in double-double  */
   uint64_t model_key;     /* 0: no reuse.  Otherwise the reduced model stays
                              resident and later requests with the same key,
                              dimensions and (host memory) content reuse it     */

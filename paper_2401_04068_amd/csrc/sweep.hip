@@ -429,10 +429,10 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
     }
   }
   givens_sweep<double, R, MM, kLds>(md.H, n, sp.re, sp.im, st, bcast);
-  // estimated error: u times the spread of R's diagonal; points above the
+  // estimated error from the spread of R's diagonal; points above the
   // request's tolerance are finished by the extended refinement
-  const double est = 0.5 * DBL_EPSILON * diag_ratio<double, R, MM>(n, st);
-  if (!(est <= rd.rtol) || (rd.flags & kFlagForceDD)) {
+  const double est = fp64_estimate(n, diag_ratio<double, R, MM>(n, st));
+  if (fp64_needs_dd(rd, est)) {
     if (lane == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
     return;
   }

@@ -461,10 +461,10 @@ __device__ void solve16_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, 
     }
   }
   sweep16<double, R, MM, kLds>(H, n, sp.re, sp.im, st, bcast);
-  // estimated error: u times the spread of R's diagonal; points above the
+  // estimated error from the spread of R's diagonal; points above the
   // request's tolerance are finished by the extended refinement
-  const double est = 0.5 * DBL_EPSILON * diag_ratio16<double, R, MM>(n, st);
-  const bool dd = !(est <= rd.rtol) || (rd.flags & kFlagForceDD);
+  const double est = fp64_estimate(n, diag_ratio16<double, R, MM>(n, st));
+  const bool dd = fp64_needs_dd(rd, est);
   if (dd && valid && gl == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
   apply_rotations16<double, R, MM>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;

@@ -2,6 +2,8 @@
 // wavefront; sweep16.hip: four frequencies per wavefront).
 #pragma once
 
+#include <cfloat>
+
 #include <hip/hip_runtime.h>
 
 #include "lti_kernels.h"
@@ -48,6 +50,21 @@ __device__ __forceinline__ void put_info(const ReqDesc& rd, int64_t k, const lti
   } else {
     store_info(rd.info, k, v);
   }
+}
+
+// Estimated relative error of a float64 point from its triangular factor:
+// (u / 2) sqrt(n) max|R(k,k)| / min|R(k,k)|.  The diagonal spread alone is a
+// lower bound on kappa(s I - H) that falls short by about 0.6 / sqrt(n) on
+// an isolated near-resonance (measured on reduced models with random
+// orthogonal bases, n = 16 .. 300), hence the sqrt(n).  A point whose
+// estimate exceeds kFP64QueueFraction * rtol is finished by the
+// double-double refinement against A.
+constexpr double kFP64QueueFraction = 0.25;
+__device__ __forceinline__ double fp64_estimate(int n, double diag_spread) {
+  return 0.5 * DBL_EPSILON * sqrt((double)n) * diag_spread;
+}
+__device__ __forceinline__ bool fp64_needs_dd(const ReqDesc& rd, double est) {
+  return !(est <= kFP64QueueFraction * rd.rtol) || (rd.flags & kFlagForceDD);
 }
 
 // Hand point k, columns j0 .. j0+mc-1, to the extended-precision refinement

@@ -481,10 +481,10 @@ __device__ void solve_wg_fp64(const ReqDesc& rd, int64_t k, int j0, int mc, ShWG
   }
   sweep_wg<double, MM>(rd.H, n, sp.re, sp.im, st, sh);
   BlockRed br(sh);
-  // estimated error: u times the spread of R's diagonal; points above the
+  // estimated error from the spread of R's diagonal; points above the
   // request's tolerance are finished by the extended refinement
-  const double est = 0.5 * DBL_EPSILON * diag_ratio_wg<double, MM>(n, st, br);
-  if (!(est <= rd.rtol) || (rd.flags & kFlagForceDD)) {  // uniform
+  const double est = fp64_estimate(n, diag_ratio_wg<double, MM>(n, st, br));
+  if (fp64_needs_dd(rd, est)) {  // uniform
     if (tid == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
     __syncthreads();  // LDS reuse by the next point
     return;
