@@ -278,6 +278,27 @@ typedef struct lti_hinf_result {
 int lti_freqresp_peaks(lti_ctx* ctx, const lti_request* req, int32_t max_peaks, double wtol,
                        lti_peak* peaks_out, lti_hinf_result* out);
 
+/* Evaluation without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid
+ * hipMalloc): the work of submit() + poll() for one LTI_MEM_DEVICE request,
+ * enqueued on `stream` (a hipStream_t of `device`; NULL = the null stream)
+ * with no context.  Nothing is allocated: the reduced model, the reduction's
+ * working matrix, the refinement queue and (when info_out is NULL) the point
+ * records live in one fixed device array of 8 MiB inside the library, one
+ * copy per device, held until the process ends.  The same kernels as the
+ * context path run, tiled as an idle context would tile the request, so G
+ * equals a context's result for the same request alone.
+ * Limits: nx <= 256, nu, ny <= 16, n_omega <= 2^18 and
+ * n_omega * min(nu, ny) <= 2^18; beyond them LTI_EUNSUPPORTED.  Returns
+ * LTI_OK once the work is enqueued: G_out, info_out and dG_out are written
+ * when the stream reaches it (synchronise the stream before reading them);
+ * nothing is reduced or kept for reuse.  LTI_EINVAL for a host-memory
+ * request or bad arguments, LTI_EDEVICE for a HIP error.  Calls that overlap
+ * on one device -- on different streams or threads, or before an earlier
+ * call's work has finished on another stream -- race on the shared array:
+ * serialise them (one stream per device). */
+int lti_freqresp_eval_noalloc(int32_t device, const lti_request* req, void* stream);
+
 /* Snapshot of the context's counters. */
 int lti_freqresp_stats(lti_ctx* ctx, lti_stats* out);
 

@@ -71,6 +71,7 @@ EXPORTS = (
     "lti_freqresp_strerror",
     "lti_freqresp_abi_version",
     "lti_freqresp_peaks",
+    "lti_freqresp_eval_noalloc",
 )
 
 
@@ -193,12 +194,46 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lti_freqresp_peaks.argtypes = [ctypes.c_void_p, P(LtiRequest), ctypes.c_int32, ctypes.c_double,
                                        P(LtiPeak), P(LtiHinfResult)]
     lib.lti_freqresp_peaks.restype = ctypes.c_int
+    lib.lti_freqresp_eval_noalloc.argtypes = [ctypes.c_int32, P(LtiRequest), ctypes.c_void_p]
+    lib.lti_freqresp_eval_noalloc.restype = ctypes.c_int
     lib.lti_freqresp_abi_version.argtypes = []
     lib.lti_freqresp_abi_version.restype = ctypes.c_uint32
     if lib.lti_freqresp_abi_version() != ABI_VERSION:
         raise ImportError("liblti_freqresp.so ABI version mismatch; rebuild it")
     _lib = lib
     return lib
+
+
+def eval_noalloc(A, B, C, D, omega, G, info=None, precision: int = PREC_FP64, rtol: float = 0.0,
+                 points: int = POINTS_JW, dG=None, device: int = 0, stream=None) -> None:
+    """lti_freqresp_eval_noalloc: enqueue one device-memory evaluation on
+    `stream` (default: torch's current stream on `device`) that allocates
+    nothing; the results are ready once that stream reaches this point.
+    Arguments as for Engine.submit_device."""
+    import torch
+
+    lib = load()
+    for t in (A, B, C, omega):
+        if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("device inputs must be contiguous float64 CUDA tensors")
+    req = LtiRequest()
+    req.nx, req.nu, req.ny = A.shape[0], B.shape[1], C.shape[0]
+    req.mem = MEM_DEVICE
+    req.A, req.B, req.C = A.data_ptr(), B.data_ptr(), C.data_ptr()
+    req.D = None if D is None else D.data_ptr()
+    req.omega = omega.data_ptr()
+    req.n_omega = omega.numel() // (2 if points == POINTS_S else 1)
+    req.precision = int(precision)
+    req.points = int(points)
+    req.rtol = float(rtol)
+    req.G_out = G.data_ptr()
+    req.info_out = None if info is None else info.data_ptr()
+    req.dG_out = None if dG is None else dG.data_ptr()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    rc = lib.lti_freqresp_eval_noalloc(int(device), ctypes.byref(req), ctypes.c_void_p(stream.cuda_stream))
+    if rc != LTI_OK:
+        raise LtiError(rc, "lti_freqresp_eval_noalloc")
 
 
 def strerror(code: int) -> str:

@@ -290,6 +290,12 @@ struct TilePlan {
   int64_t ntiles;
   size_t stage;
 };
+// Wavefronts a request alone should offer before its right-hand-side
+// columns stop being split over tiles, on an otherwise idle device: 256 CUs
+// x 4 SIMDs x 4 resident waves for one-frequency tiles, a quarter of that for
+// four-frequency tiles (each already carries four solves).
+constexpr int64_t kTargetTilesOne = 4096;
+constexpr int64_t kTargetTilesFour = 1024;
 struct TileKnobs {
   int tile_points = 0;   // 0: automatic
   int rhs_split = 0;     // 0: automatic

@@ -81,11 +81,6 @@ constexpr int64_t kPollSpinUs = 2000;
 // The scheduler thread backs off while a caller's thread has run a
 // scheduling pass within this window.
 constexpr double kClientActiveUs = 200.0;
-// Tiles (wavefronts) one request should offer before its columns are split:
-// 256 CUs x 4 SIMDs x 4 resident waves.
-constexpr int64_t kTargetTiles = 4096;
-// The same for four-frequency tiles (each already carries four solves).
-constexpr int64_t kTargetTiles16 = 1024;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -342,8 +337,8 @@ struct lti_ctx {
   int rhs_split = 0;        // 0: automatic
   bool stage_lds = true;    // LDS staging of reduced models in the sweep
   bool use_sweep16 = true;  // four-frequencies-per-wavefront kernels where they apply
-  int64_t target_tiles16 = kTargetTiles16;
-  int64_t target_tiles = kTargetTiles;
+  int64_t target_tiles16 = kTargetTilesFour;
+  int64_t target_tiles = kTargetTilesOne;
   int64_t outstanding_waves = 0;  // waves of admitted tiles not yet retired
   Arena arena;
   Arena staging;  // pinned host pool
