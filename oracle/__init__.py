@@ -27,7 +27,11 @@ What it computes (all plain, slow and in float64 unless stated):
 * ``peaks.peaks_bruteforce``  resonance peaks and the H-infinity norm by a
                          dense grid and derivative-free golden-section search;
 * ``hessenberg.hessenberg`` unblocked Householder reduction to upper
-                         Hessenberg form with Q^T B and C Q.
+                         Hessenberg form with Q^T B and C Q;
+* ``imdp``               robust value iteration for interval MDPs (the
+                         paper's own method: its Eq. 2, with the inner
+                         problem of Eq. 3 solved by sequential
+                         O-maximization as its section 4 describes).
 
 The mathematical problem: for a continuous-time LTI system
 x' = A x + B u, y = C x + D u, the transfer matrix evaluated on the imaginary
@@ -38,7 +42,7 @@ method it restates instead.
 """
 from .freqresp import (freqresp, freqresp_extended, freqresp_at, freqresp_at_extended, derivative_at,
                        derivative_at_extended, cond2, rel_err, rel_err_max)
-from . import exact, hessenberg, peaks
+from . import exact, hessenberg, imdp, peaks
 
 __all__ = [
     "freqresp",
@@ -53,4 +57,5 @@ __all__ = [
     "exact",
     "hessenberg",
     "peaks",
+    "imdp",
 ]
