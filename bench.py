@@ -391,6 +391,11 @@ def serving_headline(args, out):
         for i in samp[::4]:
             worst_h = max(worst_h, float(oracle.rel_err(hs[i].G[sidx[i]], G_ref[i]).max()))
         del hs
+        # kernel time of each family over everything this engine ran (both
+        # precisions, warm-up, timed steps and replays): the figure a kernel
+        # trace of the same command sums to
+        s_end = eng.stats()
+        engine_totals = {"family_ms": s_end["family_ms"], "family_launches": s_end["family_launches"]}
     log("serving replays done")
 
     ref, f64 = res["refined"], res["fp64"]
@@ -444,6 +449,7 @@ def serving_headline(args, out):
                            "note": "host-memory requests, all submitted at once: H2D and D2H inside"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "engine_kernel_totals": engine_totals,
     })
 
 
@@ -452,13 +458,26 @@ def serving_headline(args, out):
 def secondary(args, out):
     import torch
 
+    dev = torch.device("cuda:0")
+    sec = {}
+    want = (lambda name: True) if not args.only else (lambda name: name == args.only)
+    if want("mimo64"):
+        _mimo64(args, sec, dev)
+    if want("large1024"):
+        _large1024(args, sec)
+    if want("damped256"):
+        _damped256(args, sec)
+    out["secondary"] = sec
+
+
+def _mimo64(args, sec, dev):
+    import torch
+
     import oracle
     from paper_2401_04068_amd import binding
     from paper_2401_04068_amd import workloads as wl
 
-    dev = torch.device("cuda:0")
-    sec = {}
-    # the 64-state model: 200 requests, 16 in flight, device memory
+    # the 64-state model: 16 requests in flight, device memory
     mdl = wl.mimo64()
     mix = DeviceMix([mdl] * 16, dev)
     ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
@@ -485,6 +504,13 @@ def secondary(args, out):
         sec["mimo64"] = row
     del mix
     log("secondary: mimo64 done")
+
+
+def _large1024(args, sec):
+    import oracle
+    from paper_2401_04068_amd import binding
+    from paper_2401_04068_amd import workloads as wl
+
     # the 1024-state model: ten queries (two repeats), refined and float64
     models = wl.large1024_models()
     queries = wl.large1024_queries(models)
@@ -508,6 +534,13 @@ def secondary(args, out):
         row["note"] = "host-memory requests (inputs 8 MB each), ten queries in flight"
         sec["large1024"] = row
     log("secondary: large1024 done")
+
+
+def _damped256(args, sec):
+    import oracle
+    from paper_2401_04068_amd import binding
+    from paper_2401_04068_amd import workloads as wl
+
     # 512 lightly damped 256-state models at once, refined
     models = wl.damped256(args.damped_models)
     with binding.Engine(arena_bytes=16 << 30, kernel_timing=True, host_staging_bytes=2 << 30) as eng:
@@ -532,7 +565,6 @@ def secondary(args, out):
         row["note"] = f"{len(models)} models submitted at once from host memory"
         sec["damped256"] = row
     log("secondary: damped256 done")
-    out["secondary"] = sec
 
 
 # ------------------------------------------------------------------ counters
@@ -580,6 +612,17 @@ def _pmc_totals(csv_path, counter):
     return tot
 
 
+def _pmc_max_dispatch(csv_path, counter, name_part):
+    import csv
+
+    best = 0.0
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") == counter and name_part in row["Kernel_Name"]:
+                best = max(best, float(row["Counter_Value"]))
+    return best
+
+
 def traffic_record(args):
     """profiles/kf<f>_serving_traffic.json from two counter runs of
     `--profile-pass` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch): HBM
@@ -591,10 +634,9 @@ def traffic_record(args):
     fetch = _pmc_totals(fetch_csv, "FETCH_SIZE")
     write = _pmc_totals(write_csv, "WRITE_SIZE")
     copy_kib = ps["copy_bytes"] / 1024.0
-    cal = [k for k in fetch if "copyBuffer" in k or "elementwise_kernel" in k]
-    # the calibration copy is the largest copy dispatch of the run
-    fk = max((fetch[k] for k in cal), default=0.0)
-    wk = max((write.get(k, 0.0) for k in cal), default=0.0)
+    # the calibration copy is the largest single copy dispatch of the run
+    fk = _pmc_max_dispatch(fetch_csv, "FETCH_SIZE", "copyBuffer")
+    wk = _pmc_max_dispatch(write_csv, "WRITE_SIZE", "copyBuffer")
     if not fk or not wk:
         raise SystemExit("calibration copy not found in the counter CSVs")
     ff, wf = copy_kib / fk, copy_kib / wk
@@ -626,6 +668,8 @@ def main():
     ap.add_argument("--damped-models", type=int, default=512, help="models of the lightly damped batch")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-secondary", action="store_true", help="only the headline configuration")
+    ap.add_argument("--only", choices=["mimo64", "large1024", "damped256"],
+                    help="run one secondary configuration only (no headline)")
     ap.add_argument("--profile-pass", type=int, default=0,
                     help="counter run: a calibration copy, then this many refined passes of the mix")
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PASS_JSON"),
@@ -647,6 +691,10 @@ def main():
     }
     if args.profile_pass:
         profile_pass(args)
+        return
+    if args.only:
+        secondary(args, out)
+        print(json.dumps(out), flush=True)
         return
     serving_headline(args, out)
     if not args.no_secondary:
