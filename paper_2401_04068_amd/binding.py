@@ -159,6 +159,52 @@ class LtiStats(ctypes.Structure):
     ]
 
 
+# imdp_vi.h: robust value iteration for interval MDPs
+IMDP_EXPORTS = ("imdp_vi_create", "imdp_vi_run", "imdp_vi_destroy")
+IMDP_OK = 0
+IMDP_EINVAL = -1
+IMDP_EDEVICE = -5
+IMDP_ENOMEM = -6
+IMDP_EUNSUPPORTED = -7
+IMDP_REACH = 0
+IMDP_REACH_AVOID = 1
+IMDP_REWARD = 2
+
+
+class ImdpModel(ctypes.Structure):
+    _fields_ = [
+        ("n_states", ctypes.c_int32),
+        ("n_columns", ctypes.c_int32),
+        ("nnz", ctypes.c_int64),
+        ("stateptr", ctypes.c_void_p),
+        ("colptr", ctypes.c_void_p),
+        ("rowval", ctypes.c_void_p),
+        ("lower", ctypes.c_void_p),
+        ("upper", ctypes.c_void_p),
+    ]
+
+
+class ImdpSpec(ctypes.Structure):
+    _fields_ = [
+        ("property", ctypes.c_int32),
+        ("horizon", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("max_iterations", ctypes.c_int32),
+        ("pessimistic", ctypes.c_int32),
+        ("maximize", ctypes.c_int32),
+        ("targets", ctypes.c_void_p),
+        ("n_targets", ctypes.c_int32),
+        ("avoid", ctypes.c_void_p),
+        ("n_avoid", ctypes.c_int32),
+        ("reward", ctypes.c_void_p),
+        ("discount", ctypes.c_double),
+    ]
+
+
+class ImdpResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("residual", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -196,6 +242,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lti_freqresp_peaks.restype = ctypes.c_int
     lib.lti_freqresp_eval_noalloc.argtypes = [ctypes.c_int32, P(LtiRequest), ctypes.c_void_p]
     lib.lti_freqresp_eval_noalloc.restype = ctypes.c_int
+    lib.imdp_vi_create.argtypes = [ctypes.c_int32, P(ImdpModel), P(ctypes.c_void_p)]
+    lib.imdp_vi_create.restype = ctypes.c_int
+    lib.imdp_vi_run.argtypes = [ctypes.c_void_p, P(ImdpSpec), ctypes.c_void_p, ctypes.c_void_p, P(ImdpResult)]
+    lib.imdp_vi_run.restype = ctypes.c_int
+    lib.imdp_vi_destroy.argtypes = [ctypes.c_void_p]
+    lib.imdp_vi_destroy.restype = ctypes.c_int
     lib.lti_freqresp_abi_version.argtypes = []
     lib.lti_freqresp_abi_version.restype = ctypes.c_uint32
     if lib.lti_freqresp_abi_version() != ABI_VERSION:
@@ -467,3 +519,87 @@ def freqresp(A, B, C, D, omega, precision: int = PREC_FP64, engine: Optional[Eng
     finally:
         if own:
             eng.close()
+
+
+class ImdpError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: error {code}")
+
+
+def _i32(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+
+
+class IMDPSolver:
+    """imdp_vi_create / _run / _destroy: an interval MDP in compressed sparse
+    columns (one column per state-action pair) copied to the device once,
+    then value iteration runs against it."""
+
+    def __init__(self, n_states, stateptr, colptr, rowval, lower, upper, device: int = 0):
+        lib = load()
+        self._lib = lib
+        self._keep = [_i32(stateptr), _i32(colptr), _i32(rowval), _f64(lower), _f64(upper)]
+        sp, cp, rv, lo, up = self._keep
+        m = ImdpModel()
+        m.n_states = int(n_states)
+        m.n_columns = len(cp) - 1
+        m.nnz = len(rv)
+        m.stateptr, m.colptr, m.rowval = sp.ctypes.data, cp.ctypes.data, rv.ctypes.data
+        m.lower, m.upper = lo.ctypes.data, up.ctypes.data
+        h = ctypes.c_void_p()
+        rc = lib.imdp_vi_create(int(device), ctypes.byref(m), ctypes.byref(h))
+        self._keep = []  # copied by the library
+        if rc != IMDP_OK:
+            raise ImdpError(rc, "imdp_vi_create")
+        self._h = h
+        self.n_states = int(n_states)
+
+    def run(self, prop: int = IMDP_REACH, horizon: int = 100, eps: float = 1e-6, targets=(), avoid=(),
+            reward=None, discount: float = 1.0, pessimistic: bool = True, maximize: bool = True,
+            want_policy: bool = True, max_iterations: int = 0):
+        """Returns (V, iterations, residual, policy, kernel_ms); policy is
+        (n_states, horizon) for a finite horizon, (n_states,) otherwise."""
+        t = _i32(targets)
+        a = _i32(avoid)
+        r = None if reward is None else _f64(reward)
+        spec = ImdpSpec()
+        spec.property = int(prop)
+        spec.horizon = int(horizon)
+        spec.eps = float(eps)
+        spec.max_iterations = int(max_iterations)
+        spec.pessimistic = 1 if pessimistic else 0
+        spec.maximize = 1 if maximize else 0
+        spec.targets = t.ctypes.data if len(t) else None
+        spec.n_targets = len(t)
+        spec.avoid = a.ctypes.data if len(a) else None
+        spec.n_avoid = len(a)
+        spec.reward = None if r is None else r.ctypes.data
+        spec.discount = float(discount)
+        V = np.empty(self.n_states)
+        pol = None
+        if want_policy:
+            pol = np.empty((self.n_states, horizon) if horizon > 0 else (self.n_states,), dtype=np.int32)
+        res = ImdpResult()
+        rc = self._lib.imdp_vi_run(self._h, ctypes.byref(spec), V.ctypes.data,
+                                   None if pol is None else pol.ctypes.data, ctypes.byref(res))
+        if rc != IMDP_OK:
+            raise ImdpError(rc, "imdp_vi_run")
+        return V, res.iterations, res.residual, pol, res.kernel_ms
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.imdp_vi_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

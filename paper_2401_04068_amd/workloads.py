@@ -285,3 +285,92 @@ WORKLOADS = {
     "damped256": "512 models n=256, m=p=4, zeta in [1e-5,1e-2], 4096 points, "
                  "25% clustered at resonances",
 }
+
+
+# ---------------------------------------------------------------- interval MDPs
+#
+# Stand-ins for the abstraction models of the paper's benchmark table (its
+# appendix "Benchmarking models": grid abstractions of linear and non-linear
+# systems, up to 42,634 states x 3 actions and 48.1 M transitions).  Those
+# model files are not available here, so each synthetic model has the
+# table's shape: n_states states (the last one an absorbing sink), n_actions
+# actions per state, and per state-action pair a window of w consecutive
+# destination states around a drifted centre plus the sink (w + 1
+# transitions).  Nominal probabilities follow a discretised Gaussian over the
+# window with a small sink mass; the interval is [p (1 - a), p (1 + b)] with
+# a, b ~ U(0, spread), clipped to [0, 1], so sum lower <= 1 <= sum upper.
+# Targets: a band of states at the top of the grid.
+
+
+@dataclass
+class IMDPModel:
+    n_states: int
+    stateptr: np.ndarray
+    colptr: np.ndarray
+    rowval: np.ndarray
+    lower: np.ndarray
+    upper: np.ndarray
+    targets: np.ndarray
+    seed: int
+
+    @property
+    def n_columns(self) -> int:
+        return len(self.colptr) - 1
+
+    @property
+    def nnz(self) -> int:
+        return len(self.rowval)
+
+
+def imdp_synthetic(n_states: int, n_actions: int, window: int, seed: int, spread: float = 0.2,
+                   target_frac: float = 0.05) -> IMDPModel:
+    rng = np.random.default_rng(seed)
+    S, A = int(n_states), int(n_actions)
+    grid = S - 1  # the last state is the sink
+    w = int(min(window, grid))
+    C = S * A
+    # the sink has one self-loop column per action
+    cols = np.arange(C)
+    state = cols // A
+    shift = rng.integers(-max(1, w // 2), max(2, w // 2 + 1), size=C)
+    centre = (state + shift) % max(grid, 1)
+    off = np.arange(w) - w // 2
+    dest = (centre[:, None] + off[None, :]) % max(grid, 1)  # (C, w)
+    sigma = rng.uniform(0.15, 0.4, size=C)[:, None] * w
+    p = np.exp(-0.5 * (off[None, :] / sigma) ** 2)
+    sink_mass = rng.uniform(0.0, 0.02, size=C)
+    p *= ((1.0 - sink_mass) / p.sum(axis=1))[:, None]
+    a = rng.uniform(0.0, spread, size=p.shape)
+    b = rng.uniform(0.0, spread, size=p.shape)
+    lo = p * (1.0 - a)
+    up = np.minimum(1.0, p * (1.0 + b))
+    slo = sink_mass * (1.0 - rng.uniform(0.0, spread, size=C))
+    sup = np.minimum(1.0, sink_mass * (1.0 + rng.uniform(0.0, spread, size=C)))
+    # destinations sorted within each column (window wrap-around reorders)
+    order = np.argsort(dest, axis=1, kind="stable")
+    dest = np.take_along_axis(dest, order, axis=1)
+    lo = np.take_along_axis(lo, order, axis=1)
+    up = np.take_along_axis(up, order, axis=1)
+    rowval = np.concatenate([dest, np.full((C, 1), S - 1)], axis=1)
+    lower = np.concatenate([lo, slo[:, None]], axis=1)
+    upper = np.concatenate([up, sup[:, None]], axis=1)
+    # sink columns: stay with probability 1
+    sink = state == S - 1
+    rowval[sink] = S - 1
+    lower[sink] = 0.0
+    upper[sink] = 0.0
+    lower[sink, -1] = 1.0
+    upper[sink, -1] = 1.0
+    m = w + 1
+    colptr = np.arange(C + 1, dtype=np.int64) * m
+    stateptr = np.arange(S + 1, dtype=np.int64) * A
+    nt = max(1, int(target_frac * grid))
+    targets = np.arange(grid - nt, grid)
+    return IMDPModel(S, stateptr.astype(np.int32), colptr.astype(np.int64), rowval.reshape(-1).astype(np.int32),
+                     lower.reshape(-1), upper.reshape(-1), targets.astype(np.int32), seed)
+
+
+def imdp_pimdp2_shape(seed: int = 6000) -> IMDPModel:
+    """The largest model of the paper's table: 42,634 states x 3 actions,
+    375 window destinations + sink per column (48.0 M transitions)."""
+    return imdp_synthetic(42634, 3, 375, seed)

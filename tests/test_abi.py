@@ -6,6 +6,7 @@ import re
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2401_04068_amd import binding
@@ -60,6 +61,55 @@ def test_struct_layout_matches_header(tmp_path):
         binding.LtiConfig.host_staging_bytes.offset,
     ]
     assert got == want
+
+
+IMDP_HEADER = os.path.join(ROOT, "include", "imdp_vi.h")
+
+
+def test_imdp_header_symbols_are_exported():
+    src = re.sub(r"/\*.*?\*/", "", open(IMDP_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(imdp_vi_\w+)\s*\(", src)))
+    assert names == sorted(binding.IMDP_EXPORTS)
+    lib = binding.load()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_imdp_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text(
+        '#include "imdp_vi.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(imdp_model), sizeof(imdp_spec), "
+        "sizeof(imdp_result), offsetof(imdp_spec, reward), offsetof(imdp_model, upper));return 0;}\n"
+    )
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", f"-I{os.path.dirname(IMDP_HEADER)}", str(prog), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [ctypes.sizeof(binding.ImdpModel), ctypes.sizeof(binding.ImdpSpec),
+                   ctypes.sizeof(binding.ImdpResult), binding.ImdpSpec.reward.offset, binding.ImdpModel.upper.offset]
+
+
+def test_imdp_create_rejects_bad_models_without_touching_the_gpu():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    assert lib.imdp_vi_create(0, None, ctypes.byref(h)) == binding.IMDP_EINVAL
+    m = binding.ImdpModel()
+    m.n_states = 0
+    assert lib.imdp_vi_create(0, ctypes.byref(m), ctypes.byref(h)) == binding.IMDP_EINVAL
+    # a destination out of range is caught on the host before any device call
+    sp = np.array([0, 1], dtype=np.int32)
+    cp = np.array([0, 2], dtype=np.int32)
+    rv = np.array([0, 5], dtype=np.int32)
+    lo = np.array([0.2, 0.2])
+    up = np.array([0.8, 0.8])
+    m = binding.ImdpModel(1, 1, 2, sp.ctypes.data, cp.ctypes.data, rv.ctypes.data, lo.ctypes.data, up.ctypes.data)
+    assert lib.imdp_vi_create(0, ctypes.byref(m), ctypes.byref(h)) == binding.IMDP_EINVAL
+    rv[1] = 0
+    lo[1] = 0.9  # lower > upper
+    assert lib.imdp_vi_create(0, ctypes.byref(m), ctypes.byref(h)) == binding.IMDP_EINVAL
+    assert lib.imdp_vi_run(None, None, None, None, None) == binding.IMDP_EINVAL
+    assert lib.imdp_vi_destroy(None) == binding.IMDP_EINVAL
 
 
 def test_create_rejects_bad_config_without_touching_the_gpu():
