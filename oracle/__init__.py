@@ -21,6 +21,9 @@ What it computes (all plain, slow and in float64 unless stated):
                          residual and iterate are held in extended precision
                          (x87 80-bit ``clongdouble``); the oracle of record for
                          ill-conditioned points;
+* ``freqresp_descriptor`` G(s) = C (s E - A)^{-1} B + D of a descriptor
+                         system (E possibly singular), dense LU per point;
+                         ``freqresp_descriptor_extended`` with the refinement;
 * ``cond2``              2-norm condition number of jw I - A per frequency;
 * ``rel_err``            the per-frequency relative Frobenius error metric;
 * ``exact.freqresp_exact``  exact rational evaluation for tiny systems;
@@ -41,7 +44,8 @@ silent on this problem; every function here cites the textbook or published
 method it restates instead.
 """
 from .freqresp import (freqresp, freqresp_extended, freqresp_at, freqresp_at_extended, derivative_at,
-                       derivative_at_extended, cond2, rel_err, rel_err_max)
+                       derivative_at_extended, cond2, rel_err, rel_err_max, freqresp_descriptor,
+                       freqresp_descriptor_extended)
 from . import exact, hessenberg, imdp, peaks
 
 __all__ = [
@@ -54,6 +58,8 @@ __all__ = [
     "cond2",
     "rel_err",
     "rel_err_max",
+    "freqresp_descriptor",
+    "freqresp_descriptor_extended",
     "exact",
     "hessenberg",
     "peaks",

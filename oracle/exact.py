@@ -94,11 +94,12 @@ def _solve(M, Bcols):
     return [[aug[i][n + j] for j in range(m)] for i in range(n)]
 
 
-def freqresp_exact(A, B, C, D, w, sigma=0):
-    """Exact G(s) = C (s I - A)^{-1} B + D for rational inputs at the point
-    s = sigma + j w (sigma = 0: the frequency response at w).
+def freqresp_exact(A, B, C, D, w, sigma=0, E=None):
+    """Exact G(s) = C (s E - A)^{-1} B + D for rational inputs at the point
+    s = sigma + j w (sigma = 0: the frequency response at w); E = None means
+    the identity (a standard state-space model).
 
-    A: n x n, B: n x m, C: p x n, D: p x m (nested sequences of ints,
+    A, E: n x n, B: n x m, C: p x n, D: p x m (nested sequences of ints,
     Fractions or floats -- floats are taken at their exact binary value),
     w, sigma: rational.  Returns a p x m nested list of QJ.
     """
@@ -107,7 +108,9 @@ def freqresp_exact(A, B, C, D, w, sigma=0):
     p = len(C)
     w = Fraction(w)
     sigma = Fraction(sigma)
-    M = [[QJ(sigma - Fraction(A[i][k]) if i == k else -Fraction(A[i][k]), w if i == k else 0) for k in range(n)]
+    if E is None:
+        E = [[1 if i == k else 0 for k in range(n)] for i in range(n)]
+    M = [[QJ(sigma * Fraction(E[i][k]) - Fraction(A[i][k]), w * Fraction(E[i][k])) for k in range(n)]
          for i in range(n)]
     Bq = [[QJ(Fraction(B[i][j])) for j in range(m)] for i in range(n)]
     X = _solve(M, Bq)

@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["freqresp", "freqresp_extended", "freqresp_at", "freqresp_at_extended", "derivative_at", "derivative_at_extended", "cond2",
-           "rel_err", "rel_err_max"]
+           "rel_err", "rel_err_max", "freqresp_descriptor", "freqresp_descriptor_extended"]
 
 
 def _check(A, B, C, D, omega):
@@ -211,3 +211,45 @@ def rel_err(G, G_ref, floor: float = 1e-300) -> np.ndarray:
 def rel_err_max(G, G_ref) -> float:
     e = rel_err(G, G_ref)
     return float(e.max()) if e.size else 0.0
+
+
+def freqresp_descriptor(A, B, C, D, E, s) -> np.ndarray:
+    """G(s_k) = C (s_k E - A)^{-1} B + D for a descriptor system
+    E x' = A x + B u, y = C x + D u (E may be singular: a differential-
+    algebraic system; G is then defined wherever s E - A is nonsingular, and
+    may be improper).  Any text on descriptor systems, e.g. Dai, *Singular
+    Control Systems* (1989), ch. 1.  One dense LU with partial pivoting per
+    point, shape (K, p, m)."""
+    A, B, C, D, _ = _check(A, B, C, D, [0.0])
+    E = np.asarray(E, dtype=np.float64)
+    if E.shape != A.shape:
+        raise ValueError("E must be n x n")
+    s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+    G = np.empty((len(s), C.shape[0], B.shape[1]), dtype=np.complex128)
+    Bc = B.astype(np.complex128)
+    for k, sk in enumerate(s):
+        X = np.linalg.solve(sk * E - A, Bc)
+        G[k] = C @ X + D
+    return G
+
+
+def freqresp_descriptor_extended(A, B, C, D, E, s, iters: int = 3) -> np.ndarray:
+    """``freqresp_descriptor`` followed by the extended-precision refinement
+    of ``freqresp_extended``: residual B - (s E - A) X and iterate in x87
+    extended precision, corrections from the float64 LU."""
+    A, B, C, D, _ = _check(A, B, C, D, [0.0])
+    E = np.asarray(E, dtype=np.float64)
+    s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+    ld = np.clongdouble
+    A_ld, B_ld, C_ld, D_ld, E_ld = A.astype(ld), B.astype(ld), C.astype(ld), D.astype(ld), E.astype(ld)
+    out = np.empty((len(s), C.shape[0], B.shape[1]), dtype=np.complex128)
+    for k, sk in enumerate(s):
+        M64 = sk * E - A
+        s_ld = np.longdouble(sk.real) + 1j * np.longdouble(sk.imag)
+        M_ld = s_ld * E_ld - A_ld
+        X = np.linalg.solve(M64, B.astype(np.complex128)).astype(ld)
+        for _ in range(iters):
+            r = B_ld - M_ld @ X
+            X = X + np.linalg.solve(M64, r.astype(np.complex128)).astype(ld)
+        out[k] = (C_ld @ X + D_ld).astype(np.complex128)
+    return out

@@ -470,3 +470,95 @@ def test_peak_bruteforce_monotone_first_order():
     hinf, wh, pk = peaks.peaks_bruteforce(*_first_order(2.0, 1.0, 3.0, 0.0), 1e-4, 1e4, n=500)
     assert pk == []
     assert abs(hinf - 1.5) <= 1e-8 * 1.5
+
+
+# ---------------------------------------------------------------- descriptor systems
+
+GOLDEN_E = os.path.join(os.path.dirname(__file__), "golden", "closed_forms_descriptor.txt")
+
+
+def _golden_e_rows():
+    rows = []
+    with open(GOLDEN_E) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            kind, *vals = line.split()
+            rows.append((kind, [float(v) for v in vals]))
+    return rows
+
+
+def _descriptor_case(kind, a, e, b, c, d):
+    if kind == "e1":
+        return np.array([[-a]]), np.array([[b]]), np.array([[c]]), np.array([[d]]), np.array([[e]])
+    if kind == "alg":
+        return (np.array([[-a, 0.0], [0.0, 1.0]]), np.array([[1.0], [-1.0]]), np.array([[1.0, 1.0]]),
+                np.array([[d]]), np.diag([1.0, 0.0]))
+    return (np.eye(2), np.array([[0.0], [1.0]]), np.array([[1.0, 0.0]]), np.array([[d]]),
+            np.array([[0.0, 1.0], [0.0, 0.0]]))
+
+
+@pytest.mark.parametrize("row", _golden_e_rows(), ids=lambda r: f"{r[0]}-{r[1]}")
+def test_golden_descriptor_closed_forms(row):
+    """Hand-derived values: first order with e != 1, a differential-algebraic
+    system (singular E: the algebraic state adds a constant), and a nilpotent
+    E (G(s) = -s + d, improper)."""
+    kind, (a, e, b, c, d, sr, si, re, im) = row
+    sys_ = _descriptor_case(kind, a, e, b, c, d)
+    ref = complex(re, im)
+    for fn in (oracle.freqresp_descriptor, oracle.freqresp_descriptor_extended):
+        G = fn(*sys_, [complex(sr, si)])[0, 0, 0]
+        assert abs(G - ref) <= 1e-14 * max(abs(ref), 1.0), (fn.__name__, G, ref)
+
+
+def test_descriptor_identity_E_is_the_standard_system():
+    rng = np.random.default_rng(81)
+    n, m, p = 9, 2, 3
+    A = rng.standard_normal((n, n)) - 3 * np.eye(n)
+    B, C, D = rng.standard_normal((n, m)), rng.standard_normal((p, n)), rng.standard_normal((p, m))
+    s = np.array([0.3j, 1 + 2j, -0.5 + 0.1j, 7j])
+    np.testing.assert_allclose(oracle.freqresp_descriptor(A, B, C, D, np.eye(n), s),
+                               oracle.freqresp_at(A, B, C, D, s), rtol=0, atol=1e-13)
+
+
+def test_descriptor_invertible_E_equals_E_inverse_system_and_equivalence():
+    """E invertible: G = C (s I - E^-1 A)^-1 E^-1 B + D.  Restricted system
+    equivalence (P E R, P A R, P B, C R, D) with invertible P, R leaves G
+    unchanged."""
+    rng = np.random.default_rng(82)
+    n, m, p = 7, 2, 2
+    A = rng.standard_normal((n, n)) - 2 * np.eye(n)
+    E = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    B, C, D = rng.standard_normal((n, m)), rng.standard_normal((p, n)), rng.standard_normal((p, m))
+    s = np.array([0.2j, 2 + 1j, 5j])
+    G = oracle.freqresp_descriptor(A, B, C, D, E, s)
+    Ei = np.linalg.inv(E)
+    np.testing.assert_allclose(G, oracle.freqresp_at(Ei @ A, Ei @ B, C, D, s), rtol=1e-11, atol=1e-11)
+    P = rng.standard_normal((n, n)) + 2 * np.eye(n)
+    R = rng.standard_normal((n, n)) + 2 * np.eye(n)
+    G2 = oracle.freqresp_descriptor(P @ A @ R, P @ B, C @ R, D, P @ E @ R, s)
+    np.testing.assert_allclose(G2, G, rtol=1e-10, atol=1e-10)
+
+
+def test_descriptor_exact_rational_agreement():
+    """Random small integer systems with a singular E against exact
+    arithmetic over Q(j)."""
+    rng = np.random.default_rng(83)
+    for trial in range(12):
+        n, m, p = int(rng.integers(2, 5)), int(rng.integers(1, 3)), int(rng.integers(1, 3))
+        A = rng.integers(-4, 5, (n, n)).astype(float)
+        E = rng.integers(-2, 3, (n, n)).astype(float)
+        E[-1] = 0.0  # singular E
+        B = rng.integers(-3, 4, (n, m)).astype(float)
+        C = rng.integers(-3, 4, (p, n)).astype(float)
+        D = rng.integers(-2, 3, (p, m)).astype(float)
+        w = float(rng.integers(1, 9)) / 4
+        sig = float(rng.integers(-3, 4)) / 2
+        try:
+            ex = exact.freqresp_exact(A.tolist(), B.tolist(), C.tolist(), D.tolist(), w, sig, E=E.tolist())
+        except ZeroDivisionError:
+            continue
+        ref = np.array([[exact.to_complex(z) for z in row] for row in ex])
+        G = oracle.freqresp_descriptor(A, B, C, D, E, [complex(sig, w)])[0]
+        assert np.max(np.abs(G - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), (trial, G, ref)
