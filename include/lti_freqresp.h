@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LTI_ABI_VERSION 2u
+#define LTI_ABI_VERSION 3u
 
 /* ---------------------------------------------------------------- codes */
 #define LTI_OK            0
@@ -162,6 +162,15 @@ typedef struct lti_request {
                              imaginary axis dG/dw = j dG/ds).  A request with
                              dG_out runs the float64 path whatever its
                              precision says                                     */
+  const double* E;        /* optional: a descriptor system E x' = A x + B u
+                             (nx*nx, may be singular); then
+                             G(s) = C (s E - A)^{-1} B + D, computed by a
+                             Hessenberg-triangular reduction Q^T A Z = H,
+                             Q^T E Z = T (Golub & Van Loan, 4th ed., Alg.
+                             7.7.1) and one solve with s T - H per point, on
+                             the float64 path (no double-double refinement;
+                             est_rel_err states the estimate).  nx <= 256, no
+                             dG_out.  NULL: E = I                               */
 } lti_request;
 /* Ownership: with LTI_MEM_HOST, submit() copies A, B, C, D and omega before
  * it returns; G_out and info_out must stay valid until poll() reports the
@@ -187,7 +196,8 @@ typedef struct lti_result {
 #define LTI_KF_SWEEP1     1  /* one frequency per wavefront (nx <= 256)          */
 #define LTI_KF_SWEEPWG    2  /* one frequency per workgroup (nx <= 1024)         */
 #define LTI_KF_REFINE_DD  3  /* double-double refinement of queued points       */
-#define LTI_KF_COUNT      4
+#define LTI_KF_SWEEPDESC  4  /* descriptor systems (one frequency per wavefront) */
+#define LTI_KF_COUNT      5
 
 /* Counters of one context. */
 typedef struct lti_stats {
@@ -289,7 +299,8 @@ int lti_freqresp_peaks(lti_ctx* ctx, const lti_request* req, int32_t max_peaks, 
  * context path run, tiled as an idle context would tile the request, so G
  * equals a context's result for the same request alone.
  * Limits: nx <= 256, nu, ny <= 16, n_omega <= 2^18 and
- * n_omega * min(nu, ny) <= 2^18; beyond them LTI_EUNSUPPORTED.  Returns
+ * n_omega * min(nu, ny) <= 2^18, no descriptor E; beyond them
+ * LTI_EUNSUPPORTED.  Returns
  * LTI_OK once the work is enqueued: G_out, info_out and dG_out are written
  * when the stream reaches it (synchronise the stream before reading them);
  * nothing is reduced or kept for reuse.  LTI_EINVAL for a host-memory

@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblti_freqresp.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 LTI_OK = 0
 LTI_PENDING = 1
@@ -51,6 +51,8 @@ KF_SWEEP4 = 0
 KF_SWEEP1 = 1
 KF_SWEEPWG = 2
 KF_REFINE_DD = 3
+KF_SWEEPDESC = 4
+KF_COUNT = 5
 
 CFG_KERNEL_TIMING = 1
 CFG_FORCE_DD = 2
@@ -109,6 +111,7 @@ class LtiRequest(ctypes.Structure):
         ("G_out", ctypes.c_void_p),
         ("info_out", ctypes.c_void_p),
         ("dG_out", ctypes.c_void_p),
+        ("E", ctypes.c_void_p),
     ]
 
 
@@ -154,8 +157,8 @@ class LtiStats(ctypes.Structure):
         ("reduce_kernel_ms", ctypes.c_double),
         ("timed_sweep_launches", ctypes.c_uint64),
         ("timed_reduce_launches", ctypes.c_uint64),
-        ("family_ms", ctypes.c_double * 4),
-        ("family_launches", ctypes.c_uint64 * 4),
+        ("family_ms", ctypes.c_double * 5),
+        ("family_launches", ctypes.c_uint64 * 5),
     ]
 
 
@@ -359,7 +362,7 @@ class Engine:
     # ------------------------------------------------------------ requests
     def submit(self, A, B, C, D, omega, precision: int = PREC_FP64, model_key: int = 0,
                rtol: float = 0.0, want_info: bool = True, points: int = POINTS_JW,
-               want_derivative: bool = False) -> Handle:
+               want_derivative: bool = False, E=None) -> Handle:
         """Host-memory request; inputs are copied before this returns.
 
         points: POINTS_JW (omega real, s = j omega), POINTS_S (omega complex
@@ -390,6 +393,8 @@ class Engine:
         req.info_out = None if info is None else info.ctypes.data
         dG = np.empty((K, p, m), dtype=np.complex128) if want_derivative else None
         req.dG_out = None if dG is None else dG.ctypes.data
+        Em = None if E is None else _f64(E)
+        req.E = None if Em is None else Em.ctypes.data
         rid = ctypes.c_uint64()
         rc = self._lib.lti_freqresp_submit(self._ctx, ctypes.byref(req), ctypes.byref(rid))
         if rc != LTI_OK:
@@ -397,7 +402,7 @@ class Engine:
         return Handle(rid.value, G, info, keep=[G, info, dG], dG=dG)
 
     def submit_device(self, A, B, C, D, omega, G, info=None, precision: int = PREC_FP64,
-                      model_key: int = 0, rtol: float = 0.0, points: int = POINTS_JW, dG=None) -> Handle:
+                      model_key: int = 0, rtol: float = 0.0, points: int = POINTS_JW, dG=None, E=None) -> Handle:
         """Device-memory request: torch float64 tensors on this engine's device;
         G is a float64 tensor of 2*K*p*m entries (or complex128 (K, p, m)).
         Nothing is copied; the tensors must stay alive and unmodified until
@@ -421,11 +426,12 @@ class Engine:
         req.G_out = G.data_ptr()
         req.info_out = None if info is None else info.data_ptr()
         req.dG_out = None if dG is None else dG.data_ptr()
+        req.E = None if E is None else E.data_ptr()
         rid = ctypes.c_uint64()
         rc = self._lib.lti_freqresp_submit(self._ctx, ctypes.byref(req), ctypes.byref(rid))
         if rc != LTI_OK:
             raise LtiError(rc, "lti_freqresp_submit")
-        return Handle(rid.value, G, info, keep=[A, B, C, D, omega, G, info, dG], dG=dG)
+        return Handle(rid.value, G, info, keep=[A, B, C, D, omega, G, info, dG, E], dG=dG)
 
     def poll(self, h: Handle, timeout_us: int = -1) -> bool:
         """True when done (result in h.result); False while pending."""

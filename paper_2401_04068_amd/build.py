@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblti_freqresp.so")
 
 SOURCES = ["reduce.hip", "reduce_blocked.hip", "sweep.hip", "sweep16.hip", "sweepwg.hip",
-           "runtime.cpp", "peaks.cpp", "noalloc.hip", "imdp.hip"]
+           "runtime.cpp", "peaks.cpp", "noalloc.hip", "imdp.hip", "reduce_ht.hip"]
 ARCH = os.environ.get("LTI_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

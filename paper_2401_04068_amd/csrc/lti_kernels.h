@@ -46,11 +46,14 @@ struct ReducedModel {
   double* C0;
   double* V;
   double* tau;
+  double* T;  // descriptor systems: Q^T E Z, packed upper triangular (column
+              // j holds rows 0 .. j, from j (j + 1) / 2); null otherwise
   int n, m, p, trans;
 };
 
-size_t reduced_bytes(int n, int m, int p);
-void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* out);
+// desc: the model is a descriptor system (T is stored).
+size_t reduced_bytes(int n, int m, int p, bool desc = false);
+void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* out, bool desc = false);
 
 // One reduction job: read A, B, C, D (device pointers, row-major, the
 // request's own sizes; D may be null), write the reduced model (out.trans
@@ -61,6 +64,7 @@ struct ReduceJob {
   const double* B;
   const double* C;
   const double* D;
+  const double* E;  // descriptor systems only (row-major n x n), else null
   ReducedModel out;
   double* work;
 };
@@ -68,10 +72,13 @@ struct ReduceJob {
 // Entry (i, j) of the solved system's matrices, read from the request's
 // arrays (n, m, p: the solved system's sizes).
 struct ModelIn {
-  const double *A, *B, *C, *D;
+  const double *A, *B, *C, *D, *E;
   int n, m, p, trans;
   __host__ __device__ ModelIn(const ReduceJob& j)
-      : A(j.A), B(j.B), C(j.C), D(j.D), n(j.out.n), m(j.out.m), p(j.out.p), trans(j.out.trans) {}
+      : A(j.A), B(j.B), C(j.C), D(j.D), E(j.E), n(j.out.n), m(j.out.m), p(j.out.p), trans(j.out.trans) {}
+  __host__ __device__ double e(int i, int k) const {
+    return trans ? E[(size_t)k * n + i] : E[(size_t)i * n + k];
+  }
   __host__ __device__ double a(int i, int k) const {
     return trans ? A[(size_t)k * n + i] : A[(size_t)i * n + k];
   }
@@ -96,7 +103,12 @@ constexpr int kMaxRegReduceN = 128;
 constexpr int kNumRegClasses = 9;
 constexpr int kReduceGlobal = kNumRegClasses;       // 128 < n <= kMaxGlobalReduceN
 constexpr int kReduceBlocked = kNumRegClasses + 1;  // larger n: blocked, whole GPU
-constexpr int kNumReduceClasses = kNumRegClasses + 2;
+// Descriptor systems (n <= kMaxN): Hessenberg-triangular reduction, one
+// workgroup per model (reduce_ht.hip).
+constexpr int kReduceHT = kNumRegClasses + 2;
+constexpr int kNumReduceClasses = kNumRegClasses + 3;
+size_t reduce_ht_work_bytes(int n, int m, int p);
+hipError_t launch_reduce_ht(const struct ReduceLaunch& L, hipStream_t s);
 constexpr int kMaxGlobalReduceN = 256;
 int reduce_class(int n, int m, int p);
 // Global scratch bytes a job of this shape needs (0 for register classes).
@@ -145,6 +157,7 @@ hipError_t launch_zero(const ZeroLaunch& Z, hipStream_t s);
 constexpr uint32_t kFlagTrans = 1u;      // G^T of the transposed system
 constexpr uint32_t kFlagMergeInfo = 2u;  // columns split over tiles: info merged with atomic max
 constexpr uint32_t kFlagForceDD = 4u;    // every point takes the extended refinement (testing)
+constexpr uint32_t kFlagDescriptor = 8u; // descriptor system: M = s T - H, never queued
 constexpr int kPointsJW = 0, kPointsS = 1, kPointsZ = 2;
 constexpr int kReasonFP64 = 0, kReasonStall = 1;
 struct ReqDesc {
@@ -158,6 +171,7 @@ struct ReqDesc {
   const double* omega;
   double* G;
   double* dG;  // dG/ds (float64 path only), or null
+  const double* T;  // descriptor systems: packed upper triangular Q^T E Z, else null
   lti_point_info* info;
   uint32_t* fbq;
   int n, m, p, precision;
@@ -222,7 +236,7 @@ hipError_t launch_sweep_wg(int cls, const SweepLaunch& L, hipStream_t s);
 // Extended-precision refinement (sweepwg.hip) of the points the sweeps of a
 // request queued (ReqDesc.fbq), after all of the request's sweep tiles: one
 // workgroup per queued entry at a time, `grid` workgroups in all.
-constexpr int kMaxDDSegs = 12;
+constexpr int kMaxDDSegs = 11;
 struct DDSeg {
   ReqDesc rd;
   ReducedModel rm;
@@ -274,10 +288,16 @@ __host__ __device__ inline size_t stage_bytes(int precision, int n, int m, int p
 // launch's requests; 0 disables staging).
 hipError_t launch_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s);
 
+// Descriptor systems, float64, n <= kMaxN: one frequency per wavefront with
+// M = s T - H (sweep.hip); classes as sweep_class(LTI_PREC_FP64, n, m).
+constexpr int kNumSweepDescClasses = kNumRowClasses * kNumRhsClasses;
+hipError_t launch_sweep_desc(int kclass, const SweepLaunch& L, hipStream_t s);
+
 // All sweep kernel classes in one index space: [0, kNumSweepClasses) one
 // frequency per wavefront, then the four-frequency classes, then the
-// workgroup classes.
-constexpr int kAllSweepClasses = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
+// workgroup classes, then the descriptor classes.
+constexpr int kSweepDescBase = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
+constexpr int kAllSweepClasses = kSweepDescBase + kNumSweepDescClasses;
 hipError_t launch_any_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s);
 
 // How a request's solves are cut into tiles (runtime.cpp): F frequencies
@@ -300,6 +320,7 @@ struct TileKnobs {
   int tile_points = 0;   // 0: automatic
   int rhs_split = 0;     // 0: automatic
   bool use_sweep16 = true;
+  bool descriptor = false;  // descriptor system: float64 one-frequency kernels only
 };
 TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t avail_waves4, int64_t avail_waves1,
                     const TileKnobs& kn);

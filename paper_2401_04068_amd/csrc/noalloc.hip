@@ -80,6 +80,7 @@ extern "C" int lti_freqresp_eval_noalloc(int32_t device, const lti_request* q, v
   if (q->precision != LTI_PREC_FP64 && q->precision != LTI_PREC_REFINED) return LTI_EINVAL;
   if (q->points != LTI_POINTS_JW && q->points != LTI_POINTS_S && q->points != LTI_POINTS_Z) return LTI_EINVAL;
   if (q->rtol != q->rtol || q->rtol >= 1.0) return LTI_EINVAL;
+  if (q->E) return LTI_EUNSUPPORTED;  // descriptor systems: context path only
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return LTI_EDEVICE;
   if (device < 0 || device >= ndev || device >= kNoAllocMaxDevices) return LTI_EINVAL;

@@ -479,15 +479,16 @@ size_t reduce_work_bytes(int n, int m, int p) {
   return align256((size_t)ld_of(n, p) * (size_t)(n + m) * sizeof(double));
 }
 
-size_t reduced_bytes(int n, int m, int p) {
+size_t reduced_bytes(int n, int m, int p, bool desc) {
   const size_t hl = (size_t)hlen(n);
   return align256(hl * 8) + align256((size_t)n * m * 8) + align256((size_t)n * p * 8) +
          align256((size_t)p * m * 8) + align256(hl * 4) + align256((size_t)n * m * 4) +
          align256((size_t)n * p * 4) + align256((size_t)n * n * 8) + align256((size_t)n * m * 8) +
-         align256((size_t)p * n * 8) + align256((size_t)vlen(n) * 8) + align256((size_t)n * 8);
+         align256((size_t)p * n * 8) + align256((size_t)vlen(n) * 8) + align256((size_t)n * 8) +
+         (desc ? align256((size_t)n * (n + 1) / 2 * 8) : 0);
 }
 
-void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* o) {
+void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* o, bool desc) {
   char* b = static_cast<char*>(base);
   const size_t hl = (size_t)hlen(n);
   auto take = [&b](size_t bytes) {
@@ -507,6 +508,7 @@ void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* o)
   o->C0 = reinterpret_cast<double*>(take((size_t)p * n * 8));
   o->V = reinterpret_cast<double*>(take((size_t)vlen(n) * 8));
   o->tau = reinterpret_cast<double*>(take((size_t)n * 8));
+  o->T = desc ? reinterpret_cast<double*>(take((size_t)n * (n + 1) / 2 * 8)) : nullptr;
   o->n = n;
   o->m = m;
   o->p = p;
@@ -535,6 +537,8 @@ hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s) {
     case kReduceGlobal:
       hess_global_kernel<kGlobalThreads, kGlobalGroup><<<L.njobs, kGlobalThreads, 0, s>>>(L);
       return hipGetLastError();
+    case kReduceHT:
+      return launch_reduce_ht(L, s);
     case kReduceBlocked:
       for (int i = 0; i < L.njobs; ++i) {
         const hipError_t e = launch_reduce_blocked(L.host_jobs[i], s);

@@ -157,6 +157,7 @@ struct Resident {
   uint64_t hash = 0;
   int n = 0, m = 0, p = 0;     // the request's sizes
   int trans = 0;
+  int desc = 0;                // descriptor system (T stored)
   void* block = nullptr;
   size_t bytes = 0;
   ReducedModel rm{};
@@ -179,7 +180,7 @@ struct HostBuf {
 // device-memory requests), and is taken at admission.
 struct HostStage {
   HostBuf in, out;
-  size_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0;  // in `in`
+  size_t offA = 0, offB = 0, offC = 0, offD = 0, offE = 0, offW = 0;  // in `in`
   size_t offG = 0, offInfo = 0, offDG = 0, outBytes = 0;     // in `out`
 };
 
@@ -257,8 +258,8 @@ TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t ava
   // Kernel family: four frequencies per wavefront (n <= 64, at most four
   // right-hand-side columns per tile), one frequency per wavefront
   // (n <= 256), or one frequency per workgroup (n <= 1024).
-  const bool wg = n > kMaxN;
-  const bool four = !wg && kn.use_sweep16 && sweep16_class(precision, n, std::min(sm, 4)) >= 0;
+  const bool wg = n > kMaxN && !kn.descriptor;
+  const bool four = !wg && !kn.descriptor && kn.use_sweep16 && sweep16_class(precision, n, std::min(sm, 4)) >= 0;
   int F = kn.tile_points;
   if (F <= 0) F = four ? 4 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, K / 2048));
   if (four) F = (F + 3) & ~3;
@@ -287,14 +288,16 @@ TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t ava
       t.S = (sm + t.mc - 1) / t.mc;
     }
     t.kclass = sweep_class(precision, n, t.mc);
+    if (kn.descriptor) t.kclass = t.kclass < 0 ? -1 : kSweepDescBase + sweep_class(LTI_PREC_FP64, n, t.mc);
   }
-  t.stage = (four || wg) ? 0 : stage_bytes(precision, n, sm, sp);
+  t.stage = (four || wg || kn.descriptor) ? 0 : stage_bytes(precision, n, sm, sp);
   t.ntiles = fblocks * t.S;
   t.waves_per_tile = wg ? 4 : 1;
   return t;
 }
 
 hipError_t launch_any_sweep(int k, const SweepLaunch& L, size_t lds_bytes, hipStream_t s) {
+  if (k >= kSweepDescBase) return launch_sweep_desc(k - kSweepDescBase, L, s);
   if (k >= kNumSweepClasses + kNumSweep16Classes) return launch_sweep_wg(k - kNumSweepClasses - kNumSweep16Classes, L, s);
   if (k >= kNumSweepClasses) return launch_sweep16(k - kNumSweepClasses, L, s);
   return launch_sweep(k, L, lds_bytes, s);
@@ -474,9 +477,10 @@ Need request_need(const lti_request& q, bool needs_model, int sm, int sp) {
   if (needs_model) {
     if (q.mem == LTI_MEM_HOST)  // same per-matrix alignment as the host staging
       nd.inputs = align_up(sizeof(double) * n * n) + align_up(sizeof(double) * n * m) +
-                  align_up(sizeof(double) * p * n) + align_up(sizeof(double) * p * m);
-    nd.work = reduce_work_bytes(n, sm, sp);
-    nd.model = align_up(reduced_bytes(n, sm, sp));
+                  align_up(sizeof(double) * p * n) + align_up(sizeof(double) * p * m) +
+                  (q.E ? align_up(sizeof(double) * n * n) : 0);
+    nd.work = q.E ? align_up(reduce_ht_work_bytes(n, sm, sp)) : reduce_work_bytes(n, sm, sp);
+    nd.model = align_up(reduced_bytes(n, sm, sp, q.E != nullptr));
   }
   return nd;
 }
@@ -486,7 +490,7 @@ Resident* find_resident(lti_ctx* c, const Request& r) {
   for (auto& up : c->residents) {
     Resident* res = up.get();
     if (res->key == r.req.model_key && res->n == r.req.nx && res->m == r.req.nu && res->p == r.req.ny &&
-        res->hash == r.hash && res->trans == r.trans)
+        res->hash == r.hash && res->trans == r.trans && res->desc == (r.req.E ? 1 : 0))
       return res;
   }
   return nullptr;
@@ -586,9 +590,10 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
     res->m = q.nu;
     res->p = q.ny;
     res->trans = r->trans;
+    res->desc = q.E ? 1 : 0;
     res->block = mblock;
     res->bytes = nd.model;
-    reduced_layout(mblock, n, sm, sp, r->trans, &res->rm);
+    reduced_layout(mblock, n, sm, sp, r->trans, &res->rm, q.E != nullptr);
     c->residents.push_back(std::move(up));
     c->stats.reductions++;
   } else {
@@ -618,6 +623,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
     job.B = q.B;
     job.C = q.C;
     job.D = q.D;
+    job.E = q.E;
   }
   if (host) {
     // A..D (when this request reduces its model) and omega sit back to back
@@ -631,6 +637,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
       job.B = reinterpret_cast<const double*>(b + (hs.offB - hs.offA));
       job.C = reinterpret_cast<const double*>(b + (hs.offC - hs.offA));
       job.D = reinterpret_cast<const double*>(b + (hs.offD - hs.offA));
+      if (q.E) job.E = reinterpret_cast<const double*>(b + (hs.offE - hs.offA));
     }
     b += nd.inputs;
     d_omega = reinterpret_cast<const double*>(b);
@@ -656,7 +663,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
     job.out = res->rm;
     job.work = nd.work ? reinterpret_cast<double*>(b) : nullptr;
     b += nd.work;
-    pw.jobs[reduce_class(n, sm, sp)].push_back(job);
+    pw.jobs[q.E ? kReduceHT : reduce_class(n, sm, sp)].push_back(job);
   }
   ReqDesc& desc = r->desc;
   desc = ReqDesc{};
@@ -670,6 +677,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   desc.omega = d_omega;
   desc.G = d_G;
   desc.dG = d_dG;
+  desc.T = res->rm.T;
   desc.info = d_info;
   desc.fbq = fbq;
   desc.n = n;
@@ -678,7 +686,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   desc.precision = q.precision;
   desc.rtol = q.rtol;
   desc.flags = (r->trans ? kFlagTrans : 0u) | ((c->flags & LTI_CFG_FORCE_DD) ? kFlagForceDD : 0u) |
-               ((uint32_t)q.points << 8);
+               (q.E ? kFlagDescriptor : 0u) | ((uint32_t)q.points << 8);
   if (e != hipSuccess) {
     fail_all(c, LTI_EDEVICE);
     return true;
@@ -688,6 +696,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   kn.tile_points = c->tile_points;
   kn.rhs_split = c->rhs_split;
   kn.use_sweep16 = c->use_sweep16;
+  kn.descriptor = q.E != nullptr;
   const TilePlan tp = plan_tiles(q.precision, n, sm, sp, r->K, std::max<int64_t>(0, c->target_tiles16 - c->outstanding_waves),
                                  std::max<int64_t>(0, c->target_tiles - c->outstanding_waves), kn);
   r->F = tp.F;
@@ -903,20 +912,25 @@ void launch(lti_ctx* c) {
     if (fam >= 0) b.tfam.push_back(fam);
   };
   auto family_of = [](int k) {
-    return k >= kNumSweepClasses + kNumSweep16Classes ? LTI_KF_SWEEPWG
+    return k >= kSweepDescBase                        ? LTI_KF_SWEEPDESC
+         : k >= kNumSweepClasses + kNumSweep16Classes ? LTI_KF_SWEEPWG
          : k >= kNumSweepClasses                      ? LTI_KF_SWEEP4
                                                       : LTI_KF_SWEEP1;
   };
   time_mark(-1);
+  // the classes of one family are contiguous: close a family's bracket when
+  // the next family starts (or at the end) if it launched anything
+  int cur_fam = -1;
+  bool cur_any = false;
   SweepLaunch L;
   for (int k = 0; k < kAllClasses && e == hipSuccess; ++k) {
-    if (k > 0 && family_of(k) != family_of(k - 1)) {
-      // close the previous family if it launched anything
-      bool any = false;
-      for (int k2 = 0; k2 < k; ++k2) any = any || (family_of(k2) == family_of(k - 1) && !per[k2].empty());
-      if (any && (b.tfam.empty() || b.tfam.back() != family_of(k - 1))) time_mark(family_of(k - 1));
+    if (family_of(k) != cur_fam) {
+      if (cur_any) time_mark(cur_fam);
+      cur_fam = family_of(k);
+      cur_any = false;
     }
     const std::vector<Piece>& v = per[k];
+    if (!v.empty()) cur_any = true;
     for (size_t i0 = 0; i0 < v.size() && e == hipSuccess; i0 += kMaxSegs) {
       L.nseg = (int)std::min<size_t>(kMaxSegs, v.size() - i0);
       uint32_t t = 0;
@@ -937,11 +951,7 @@ void launch(lti_ctx* c) {
       c->stats.sweep_launches++;
     }
   }
-  {
-    bool any = false;
-    for (int k2 = 0; k2 < kAllClasses; ++k2) any = any || (family_of(k2) == LTI_KF_SWEEPWG && !per[k2].empty());
-    if (any) time_mark(LTI_KF_SWEEPWG);
-  }
+  if (cur_any) time_mark(cur_fam);
   // finish the requests whose last tiles are in the batch: the extended
   // refinement of their queued points (the grid is sized by their points; a
   // workgroup that finds the queues empty exits at once), then the results
@@ -1163,6 +1173,9 @@ int validate(const lti_request* q) {
   if (q->n_omega > (int64_t)UINT32_MAX) return LTI_EINVAL;
   if (std::isnan(q->rtol) || q->rtol >= 1.0) return LTI_EINVAL;
   if (q->nx > kMaxNWG || q->nu > kMaxRhs || q->ny > kMaxRhs) return LTI_EUNSUPPORTED;
+  // descriptor systems: float64 one-frequency kernels (n <= kMaxN), no
+  // derivative
+  if (q->E && (q->nx > kMaxN || q->dG_out)) return LTI_EUNSUPPORTED;
   // tile indices (at most n_omega x nu per request) are 32-bit
   if (q->n_omega * q->nu > (int64_t)UINT32_MAX) return LTI_EUNSUPPORTED;
   return LTI_OK;
@@ -1184,6 +1197,7 @@ int stage_inputs(lti_ctx* c, Request* r) {
   hs.offB = take(sizeof(double) * n * m);
   hs.offC = take(sizeof(double) * p * n);
   hs.offD = take(sizeof(double) * p * m);
+  hs.offE = take(q.E ? sizeof(double) * n * n : 0);
   hs.offW = take(sizeof(double) * omega_doubles(q));
   bool ok;
   {
@@ -1200,6 +1214,7 @@ int stage_inputs(lti_ctx* c, Request* r) {
     std::memcpy(base + hs.offD, q.D, sizeof(double) * p * m);
   else
     std::memset(base + hs.offD, 0, sizeof(double) * p * m);
+  if (q.E) std::memcpy(base + hs.offE, q.E, sizeof(double) * n * n);
   std::memcpy(base + hs.offW, q.omega, sizeof(double) * omega_doubles(q));
   // the model's identity: its dimensions and the bytes of A, B, C, D (not
   // the alignment gaps between them in staging, which hold whatever the
@@ -1213,6 +1228,7 @@ int stage_inputs(lti_ctx* c, Request* r) {
   h = fnv1a(base + hs.offB, sizeof(double) * n * m, h);
   h = fnv1a(base + hs.offC, sizeof(double) * p * n, h);
   h = fnv1a(base + hs.offD, sizeof(double) * p * m, h);
+  if (q.E) h = fnv1a(base + hs.offE, sizeof(double) * n * n, h);
   r->hash = h;
   return LTI_OK;
 }
@@ -1338,14 +1354,15 @@ int lti_freqresp_submit(lti_ctx* c, const lti_request* q, uint64_t* out_id) {
   const int n = q->nx, m = q->nu, p = q->ny;
   if (q->mem == LTI_MEM_HOST) {
     if (!all_finite(q->A, (size_t)n * n) || !all_finite(q->B, (size_t)n * m) || !all_finite(q->C, (size_t)p * n) ||
-        (q->D && !all_finite(q->D, (size_t)p * m)) || !all_finite(q->omega, omega_doubles(*q)))
+        (q->D && !all_finite(q->D, (size_t)p * m)) || (q->E && !all_finite(q->E, (size_t)n * n)) ||
+        !all_finite(q->omega, omega_doubles(*q)))
       return LTI_EINVAL;
   }
   std::unique_ptr<Request> r(new (std::nothrow) Request());
   if (!r) return LTI_ENOMEM;
   r->req = *q;
   if (q->rtol <= 0.0) r->req.rtol = 1e-10;
-  if (q->dG_out) r->req.precision = LTI_PREC_FP64;  // derivatives: float64 path
+  if (q->dG_out || q->E) r->req.precision = LTI_PREC_FP64;  // derivatives, descriptors: float64 path
   // fewer outputs than inputs: solve the transposed system, whose
   // right-hand sides are the min(nu, ny) outputs
   r->trans = (p < m && !(c->flags & LTI_CFG_NO_TRANSPOSE)) ? 1 : 0;

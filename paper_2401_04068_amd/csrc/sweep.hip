@@ -57,18 +57,32 @@ struct Sweep {
 // Givens RQ sweep fused with back-substitution.  On entry br/bi hold the
 // right-hand-side rows; on exit they hold y.  `bcast` is this wavefront's
 // 2 * MM values of LDS.
-template <typename T, int R, int MM, bool kLds>
-__device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, Sweep<T, R, MM>& st, T* bcast) {
+//
+// kE (descriptor systems, float64): M = s T - H with T upper triangular
+// (packed, column j rows 0 .. j at j (j + 1) / 2), so every entry on and
+// above the diagonal is s T(i, k) - H(i, k), complex; the subdiagonal stays
+// -H(k+1, k).  The rotations and back-substitution are the same.
+template <typename T, int R, int MM, bool kLds, bool kE = false>
+__device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, Sweep<T, R, MM>& st, T* bcast,
+                                             const T* Tm = nullptr) {
   const int lane = threadIdx.x & 63;
   st.singular = false;
+  const gptr<T> TT = (gptr<T>)Tm;
+  auto toff = [](int j) { return j * (j + 1) / 2; };
   {
     const int off = hoff32(n - 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = lane + 64 * r;
       const T h = (i < n) ? H[off + i] : (T)0;
-      st.cr[r] = (i == n - 1) ? sg - h : -h;
-      st.ci[r] = (i == n - 1) ? w : (T)0;
+      if constexpr (kE) {
+        const T t = (i < n) ? TT[toff(n - 1) + i] : (T)0;
+        st.cr[r] = sg * t - h;
+        st.ci[r] = w * t;
+      } else {
+        st.cr[r] = (i == n - 1) ? sg - h : -h;
+        st.ci[r] = (i == n - 1) ? w : (T)0;
+      }
       st.rc[r] = (T)0;
       st.rsr[r] = (T)1;
       st.rsi[r] = (T)0;
@@ -76,15 +90,21 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
     }
   }
   // column n-2 (rows 0..n-1) for the first step
-  T hc[R];
+  T hc[R], tc[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) hc[r] = (T)0;
+  for (int r = 0; r < R; ++r) {
+    hc[r] = (T)0;
+    tc[r] = (T)0;
+  }
   if (n >= 2) {
     const int off = hoff32(n - 2);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = lane + 64 * r;
       if (i <= n - 1) hc[r] = H[off + i];
+      if constexpr (kE) {
+        if (i <= n - 2) tc[r] = TT[toff(n - 2) + i];
+      }
     }
   }
   // subdiagonal H(k, k-1) for the next two steps (scalar loads)
@@ -107,15 +127,21 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
         }
       }
       // prefetch: column k-2 (rows 0..k-1) and subdiagonal H(k-2, k-3)
-      T hn[R];
+      T hn[R], tn[R];
 #pragma unroll
-      for (int t = 0; t < R; ++t) hn[t] = (T)0;
+      for (int t = 0; t < R; ++t) {
+        hn[t] = (T)0;
+        tn[t] = (T)0;
+      }
       if (k >= 2) {
         const int off = hoff32(k - 2);
 #pragma unroll
         for (int t = 0; t <= s; ++t) {
           const int i = lane + 64 * t;
           if (i <= k - 1) hn[t] = H[off + i];
+          if constexpr (kE) {
+            if (i <= k - 2) tn[t] = TT[toff(k - 2) + i];
+          }
         }
       }
       const T sub2 = (k >= 3) ? H.uniform(hoff32(k - 3) + k - 2) : (T)0;
@@ -152,16 +178,27 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
         const int i = lane + 64 * t;
         if (t < s || lane < kl) {
           const T cr_ = st.cr[t], ci_ = st.ci[t];
-          // M(i, k-1): real off the diagonal; the diagonal entry also holds s
-          const T o = (i == k - 1) ? sg - hc[t] : -hc[t];
-          T nkr = c * o + sr * cr_ + si * ci_;
-          T nki = sr * ci_ - si * cr_;
-          T n1r = sr * o - c * cr_;
-          T n1i = si * o - c * ci_;
-          if (i == k - 1) {  // imaginary part of the diagonal entry
-            nki += c * w;
-            n1r -= si * w;
-            n1i += sr * w;
+          T nkr, nki, n1r, n1i;
+          if constexpr (kE) {
+            // M(i, k-1) = s T(i, k-1) - H(i, k-1), complex
+            const T orr = sg * tc[t] - hc[t];
+            const T oi = w * tc[t];
+            nkr = c * orr + sr * cr_ + si * ci_;
+            nki = c * oi + sr * ci_ - si * cr_;
+            n1r = sr * orr - c * cr_ - si * oi;
+            n1i = si * orr + sr * oi - c * ci_;
+          } else {
+            // M(i, k-1): real off the diagonal; the diagonal entry also holds s
+            const T o = (i == k - 1) ? sg - hc[t] : -hc[t];
+            nkr = c * o + sr * cr_ + si * ci_;
+            nki = sr * ci_ - si * cr_;
+            n1r = sr * o - c * cr_;
+            n1i = si * o - c * ci_;
+            if (i == k - 1) {  // imaginary part of the diagonal entry
+              nki += c * w;
+              n1r -= si * w;
+              n1i += sr * w;
+            }
           }
           st.cr[t] = n1r;
           st.ci[t] = n1i;
@@ -187,7 +224,10 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-      for (int t = 0; t < R; ++t) hc[t] = hn[t];
+      for (int t = 0; t < R; ++t) {
+        hc[t] = hn[t];
+        tc[t] = tn[t];
+      }
       sub0 = sub1;
       sub1 = sub2;
     }
@@ -411,7 +451,7 @@ __device__ __forceinline__ void write_output(const ReqDesc& rd, Src<double, kLds
   }
 }
 
-template <int R, int MM, bool kLds>
+template <int R, int MM, bool kLds, bool kE = false>
 __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t k, int j0, int mc,
                            double* bcast) {
   const int lane = threadIdx.x & 63;
@@ -428,11 +468,12 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
       st.bi[r][j] = 0.0;
     }
   }
-  givens_sweep<double, R, MM, kLds>(md.H, n, sp.re, sp.im, st, bcast);
+  givens_sweep<double, R, MM, kLds, kE>(md.H, n, sp.re, sp.im, st, bcast, rd.T);
   // estimated error from the spread of R's diagonal; points above the
-  // request's tolerance are finished by the extended refinement
+  // request's tolerance are finished by the extended refinement (not for
+  // descriptor systems: their result is written with its estimate)
   const double est = fp64_estimate(n, diag_ratio<double, R, MM>(n, st));
-  if (fp64_needs_dd(rd, est)) {
+  if (!kE && fp64_needs_dd(rd, est)) {
     if (lane == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
     return;
   }
@@ -441,7 +482,7 @@ __device__ void solve_fp64(const ReqDesc& rd, const ModelSrc<kLds>& md, int64_t 
   write_output<R, MM, kLds>(rd, md.Ct, j0, mc, st.br, st.bi, G);
   if (rd.dG) {
     // dG/ds = -C (sI - A)^{-2} B: the same sweep with X as right-hand side
-    givens_sweep<double, R, MM, kLds>(md.H, n, sp.re, sp.im, st, bcast);
+    givens_sweep<double, R, MM, kLds, kE>(md.H, n, sp.re, sp.im, st, bcast, rd.T);
     apply_rotations<double, R, MM>(n, st);
     write_output<R, MM, kLds>(rd, md.Ct, j0, mc, st.br, st.bi, rd.dG + (size_t)k * rd.p * m * 2, true);
   }
@@ -691,6 +732,26 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_kernel(const SweepLaunch L,
   }
 }
 
+// Descriptor systems (float64 path, model read from global memory).
+template <int R, int MM>
+__global__ __launch_bounds__(64 * kWaves) void sweep_desc_kernel(const SweepLaunch L, uint32_t) {
+  __shared__ double bcast_all[kWaves][2 * MM];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves + wave;
+  if (tile >= L.ntiles) return;
+  const int s = seg_of(L, tile);
+  const ReqDesc rd = L.seg[s].rd;
+  const Tile td = tile_of(L.seg[s], tile);
+  ModelSrc<false> md;
+  md.H.p = rd.H;
+  md.Bt.p = rd.Bt;
+  md.Ct.p = rd.Ct;
+  md.H32.p = rd.H32;
+  md.Bt32.p = rd.Bt32;
+  for (uint32_t f = 0; f < td.count; ++f)
+    solve_fp64<R, MM, false, true>(rd, md, (int64_t)td.start + f, td.j0, td.mc, bcast_all[wave]);
+}
+
 using KernelFn = void (*)(const SweepLaunch, uint32_t);
 
 template <int PREC, int R>
@@ -725,6 +786,34 @@ int sweep_class(int precision, int n, int m) {
   const int mi = (m <= 1) ? 0 : (m <= 2) ? 1 : (m <= 4) ? 2 : (m <= 8) ? 3 : 4;
   if (ri == 2 && mi == 4) return -1;
   return (precision * kNumRowClasses + ri) * kNumRhsClasses + mi;
+}
+
+hipError_t launch_sweep_desc(int kclass, const SweepLaunch& L, hipStream_t s) {
+  if (L.ntiles <= 0) return hipSuccess;
+  if (kclass < 0 || kclass >= kNumRowClasses * kNumRhsClasses) return hipErrorInvalidValue;
+  const int mi = kclass % kNumRhsClasses;
+  const int ri = kclass / kNumRhsClasses;
+  KernelFn fn;
+  switch (ri * 8 + mi) {
+    case 0: fn = sweep_desc_kernel<1, 1>; break;
+    case 1: fn = sweep_desc_kernel<1, 2>; break;
+    case 2: fn = sweep_desc_kernel<1, 4>; break;
+    case 3: fn = sweep_desc_kernel<1, 8>; break;
+    case 4: fn = sweep_desc_kernel<1, 16>; break;
+    case 8: fn = sweep_desc_kernel<2, 1>; break;
+    case 9: fn = sweep_desc_kernel<2, 2>; break;
+    case 10: fn = sweep_desc_kernel<2, 4>; break;
+    case 11: fn = sweep_desc_kernel<2, 8>; break;
+    case 12: fn = sweep_desc_kernel<2, 16>; break;
+    case 16: fn = sweep_desc_kernel<4, 1>; break;
+    case 17: fn = sweep_desc_kernel<4, 2>; break;
+    case 18: fn = sweep_desc_kernel<4, 4>; break;
+    case 19: fn = sweep_desc_kernel<4, 8>; break;
+    default: return hipErrorInvalidValue;
+  }
+  const int blocks = (L.ntiles + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves), 0, s, L, 0u);
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s) {

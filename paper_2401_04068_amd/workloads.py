@@ -72,6 +72,7 @@ class Model:
     Q: np.ndarray = field(default=None)  # orthogonal factor, A = Q Lambda Q^T
     Lam: np.ndarray = field(default=None)  # block-diagonal pole matrix
     seed: int = -1
+    E: np.ndarray = field(default=None)  # descriptor systems: E x' = A x + B u
 
     @property
     def n(self) -> int:
@@ -374,3 +375,40 @@ def imdp_pimdp2_shape(seed: int = 6000) -> IMDPModel:
     """The largest model of the paper's table: 42,634 states x 3 actions,
     375 window destinations + sink per column (48.0 M transitions)."""
     return imdp_synthetic(42634, 3, 375, seed)
+
+
+# ---------------------------------------------------------------- descriptor systems
+
+
+def descriptor_model(n: int, m: int, p: int, n_alg: int, seed: int, omega=None) -> Model:
+    """A descriptor system E x' = A x + B u, y = C x + D u with n - n_alg
+    finite poles (the mixed pole recipe: real -U(0.1, 2), pairs with
+    sigma = -U(0.05, 1), omega_d = U(0.5, 10)) and n_alg algebraic states
+    (E singular when n_alg > 0): in Weierstrass-like form
+    E0 = diag(I, 0), A0 = diag(Lambda, I), then E = P E0 R, A = P A0 R with
+    P, R Haar orthogonal times diagonals U(0.5, 2) (well conditioned).  The
+    finite poles are Lambda's; the algebraic block adds a constant part to G.
+    omega: default 300 log-spaced points in [1e-2, 1e2]."""
+    rng = np.random.default_rng(seed)
+    nd = n - n_alg
+    n_pairs = nd // 4
+    n_real = nd - 2 * n_pairs
+    real_poles = -rng.uniform(0.1, 2.0, n_real)
+    sigma = -rng.uniform(0.05, 1.0, n_pairs)
+    omega_d = rng.uniform(0.5, 10.0, n_pairs)
+    Lam, poles = pole_matrix(real_poles, sigma, omega_d)
+    E0 = np.zeros((n, n))
+    E0[:nd, :nd] = np.eye(nd)
+    A0 = np.zeros((n, n))
+    A0[:nd, :nd] = Lam
+    A0[nd:, nd:] = np.eye(n_alg)
+    P = haar_orthogonal(rng, n) * rng.uniform(0.5, 2.0, n)[None, :]
+    R = haar_orthogonal(rng, n) * rng.uniform(0.5, 2.0, n)[None, :]
+    E = P @ E0 @ R
+    A = P @ A0 @ R
+    B = rng.standard_normal((n, m))
+    C = rng.standard_normal((p, n))
+    D = rng.standard_normal((p, m))
+    w = logspace_grid(1e-2, 1e2, 300) if omega is None else np.asarray(omega, dtype=np.float64)
+    return Model(A=np.ascontiguousarray(A), B=B, C=C, D=D, omega=np.ascontiguousarray(w), poles=poles,
+                 seed=seed, E=np.ascontiguousarray(E))

@@ -169,10 +169,11 @@ int reduce_class(int n, int m, int p) {
 }
 size_t reduce_work_bytes(int n, int m, int p) { return reduce_class(n, m, p) >= kReduceGlobal ? 4096 : 0; }
 size_t reduce_blocked_work_bytes(int, int, int) { return 4096; }
-size_t reduced_bytes(int n, int m, int p) {
+size_t reduce_ht_work_bytes(int, int, int) { return 4096; }
+size_t reduced_bytes(int n, int m, int p, bool) {
   return 256 * 13 + 8 * ((size_t)hlen(n) * 2 + (size_t)n * n * 3 + (size_t)vlen(n) + n + (size_t)(n + p) * (m + p) * 4);
 }
-void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* o) {
+void reduced_layout(void* base, int n, int m, int p, int trans, ReducedModel* o, bool) {
   std::memset(o, 0, sizeof(*o));
   char* b = static_cast<char*>(base);
   o->D = reinterpret_cast<double*>(b);  // the stand-in kernels use D only
@@ -263,6 +264,10 @@ hipError_t launch_sweep16(int, const SweepLaunch& L, hipStream_t s) {
   return hipSuccess;
 }
 hipError_t launch_sweep_wg(int, const SweepLaunch& L, hipStream_t s) {
+  s->push([L] { sweep_stub(L); });
+  return hipSuccess;
+}
+hipError_t launch_sweep_desc(int, const SweepLaunch& L, hipStream_t s) {
   s->push([L] { sweep_stub(L); });
   return hipSuccess;
 }
