@@ -61,6 +61,7 @@ KF_NAMES = ["sweep16_kernel (four frequencies per wavefront, n <= 64)",
             "sweep_kernel (one frequency per wavefront, n <= 256)",
             "sweep_wg_kernel (one frequency per workgroup, n <= 1024)",
             "refine_dd_kernel (double-double refinement)"]
+SWEEP_SOURCES = ["sweep16.hip", "sweep.hip", "sweepwg.hip", "sweep_common.h", "dpp.h", "lti_kernels.h"]
 KF_SOURCES = [["sweep16.hip", "sweep_common.h", "dpp.h", "lti_kernels.h"],
               ["sweep.hip", "sweep_common.h", "lti_kernels.h"],
               ["sweepwg.hip", "sweep_common.h", "lti_kernels.h"],
@@ -203,6 +204,8 @@ def _stats_delta(s0, s1):
         "reduce_kernel_ms": s1["reduce_kernel_ms"] - s0["reduce_kernel_ms"],
         "timed_reduce_launches": s1["timed_reduce_launches"] - s0["timed_reduce_launches"],
         "sweep_launches": s1["sweep_launches"] - s0["sweep_launches"],
+        "sweep_kernel_ms": s1["sweep_kernel_ms"] - s0["sweep_kernel_ms"],
+        "timed_sweep_launches": s1["timed_sweep_launches"] - s0["timed_sweep_launches"],
     }
 
 
@@ -269,30 +272,30 @@ def timed_steps(eng, mix, precision, steps, warmup, label):
 
 
 def roofline_of(delta, fam_flops, fp32: bool):
-    """The family with the most kernel time: its algorithmic flops per launch
-    over its average launch time (HIP events), against the vector peak of the
-    arithmetic it does."""
-    ms = delta["family_ms"]
-    f = int(np.argmax(ms[:3]))
-    f32, f64 = fam_flops[f]
-    launches = max(delta["family_launches"][f], 1)
-    t = ms[f] * 1e-3
+    """The sweep phase of a batch (the launches of every sweep kernel class of
+    the batch, spread over up to three streams and timed together by HIP
+    events on the stream they join on): algorithmic flops per batch over the
+    average phase time, against the vector peak of the arithmetic done."""
+    f32 = sum(ff[0] for ff in fam_flops[:3])
+    f64 = sum(ff[1] for ff in fam_flops[:3])
+    launches = max(delta["timed_sweep_launches"], 1)
+    t = delta["sweep_kernel_ms"] * 1e-3
     achieved = (f32 + f64) / t / 1e12
     # time the same work would take at the peak rates of its two parts
     t_peak = (f32 / FP32_VALU_PEAK + f64 / FP64_VALU_PEAK) / 1e12
     peak = (f32 + f64) / t_peak / 1e12 if t_peak > 0 else FP64_VALU_PEAK
-    return f, {
+    return {
         "bound": "alu",
         "achieved": achieved,
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": t_peak / t,
         "traffic": None,
-        "kernel": KF_NAMES[f],
-        "kernel_source_sha256_16": _source_digest(KF_SOURCES[f]),
+        "kernel": "sweep phase of a batch: " + "; ".join(KF_NAMES[:3]),
+        "kernel_source_sha256_16": _source_digest(SWEEP_SOURCES),
         "flops_per_launch": (f32 + f64) / launches,
         "fp32_share": f32 / max(f32 + f64, 1.0),
-        "avg_launch_ms": ms[f] / launches,
+        "avg_launch_ms": delta["sweep_kernel_ms"] / launches,
         "launches": launches,
         "peak_note": ("float64 FMA at 78.6 TFLOP/s, float32 FMA at the chip's 157.3 TFLOP/s vector rate "
                       "(blended by the kernel's flop mix)" if fp32 else "float64 FMA, 78.6 TFLOP/s"),
@@ -395,30 +398,32 @@ def serving_headline(args, out):
         # precisions, warm-up, timed steps and replays): the figure a kernel
         # trace of the same command sums to
         s_end = eng.stats()
-        engine_totals = {"family_ms": s_end["family_ms"], "family_launches": s_end["family_launches"]}
+        engine_totals = {"sweep_phase_ms": s_end["sweep_kernel_ms"], "sweep_batches": s_end["timed_sweep_launches"],
+                         "family_ms": s_end["family_ms"], "family_launches": s_end["family_launches"]}
     log("serving replays done")
 
     ref, f64 = res["refined"], res["fp64"]
     value = ref["points_per_s_raw"] * ref["frac_within_1e-10"]
     v64 = f64["points_per_s_raw"] * f64["frac_within_1e-10"]
-    fam, roof = roofline_of(ref["delta"], ref["fam_flops"], fp32=True)
-    bpp = _traffic_record(f"kf{fam}_serving", KF_SOURCES[fam])
-    pts_fam = sum(r.K for r in reqs if family_of(r.n) == fam) * args.steps
-    per_launch = pts_fam / max(ref["delta"]["family_launches"][fam], 1)
+    roof = roofline_of(ref["delta"], ref["fam_flops"], fp32=True)
+    bpp = _traffic_record("sweep_serving", SWEEP_SOURCES)
+    per_launch = total * args.steps / max(ref["delta"]["timed_sweep_launches"], 1)
     roof["traffic"] = None if bpp is None else bpp * per_launch
     roof["traffic_bytes_per_point"] = bpp
     roof["points_per_launch"] = per_launch
-    fam64, roof64 = roofline_of(f64["delta"], f64["fam_flops"], fp32=False)
+    roof64 = roofline_of(f64["delta"], f64["fam_flops"], fp32=False)
 
     def fam_table(r):
+        """Flops of each sweep family (their launches overlap, so only the
+        whole sweep phase is timed) and the refinement kernel's time."""
         d = r["delta"]
         rows = {}
-        for f in range(4):
-            if d["family_launches"][f] == 0:
-                continue
+        for f in range(3):
             f32, fl64 = r["fam_flops"][f]
-            rows[KF_NAMES[f].split(" ")[0]] = {"ms": d["family_ms"][f], "launches": d["family_launches"][f],
-                                                "tflops": (f32 + fl64) / max(d["family_ms"][f], 1e-9) / 1e9}
+            if f32 + fl64 > 0:
+                rows[KF_NAMES[f].split(" ")[0]] = {"gflop_per_step": (f32 + fl64) / args.steps / 1e9}
+        rows["sweep_phase"] = {"ms": d["sweep_kernel_ms"], "batches": d["timed_sweep_launches"]}
+        rows["refine_dd_kernel"] = {"ms": d["family_ms"][3], "launches": d["family_launches"][3]}
         return rows
 
     out.update({
@@ -680,19 +685,19 @@ def traffic_record(args):
     if not fk or not wk:
         raise SystemExit("calibration copy not found in the counter CSVs")
     ff, wf = copy_kib / fk, copy_kib / wk
-    fam = args.traffic_family
-    tag = ["sweep16_kernel<1,", "sweep_kernel<1,", "sweep_wg_kernel<1,"][fam]
-    names = [k for k in fetch if tag in k.replace(" ", "")]
+    tags = ["sweep16_kernel<1,", "sweep_kernel<1,", "sweep_wg_kernel<1,"]
+    names = [k for k in fetch if any(t in k.replace(" ", "") for t in tags)]
     fb = sum(fetch[k] for k in names) * ff * 1024.0
     wb = sum(write.get(k, 0.0) for k in names) * wf * 1024.0
-    pts = ps["points_by_family"][fam]
-    rec = {"kernel_family": KF_NAMES[fam], "precision": "refined", "workload": "serving mix",
-           "source_files": KF_SOURCES[fam], "source_sha256_16": _source_digest(KF_SOURCES[fam]),
+    pts = sum(ps["points_by_family"])
+    rec = {"kernels_of": "every refined sweep kernel (the sweep phase of the batches)", "precision": "refined",
+           "workload": "serving mix",
+           "source_files": SWEEP_SOURCES, "source_sha256_16": _source_digest(SWEEP_SOURCES),
            "kernels": sorted(names), "fetch_factor": ff, "write_factor": wf,
            "fetch_bytes": fb, "write_bytes": wb, "points_swept": pts,
            "hbm_bytes_per_point": (fb + wb) / max(pts, 1),
            "commands": args.traffic_commands or []}
-    path = os.path.join(PROFILES, f"kf{fam}_serving_traffic.json")
+    path = os.path.join(PROFILES, "sweep_serving_traffic.json")
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -714,7 +719,6 @@ def main():
                     help="counter run: a calibration copy, then this many refined passes of the mix")
     ap.add_argument("--traffic-record", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PASS_JSON"),
                     help="write the HBM-traffic record of a kernel family from two counter runs")
-    ap.add_argument("--traffic-family", type=int, default=1)
     ap.add_argument("--traffic-commands", nargs="*")
     args = ap.parse_args()
     if args.traffic_record:

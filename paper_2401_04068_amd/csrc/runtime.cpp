@@ -58,11 +58,17 @@ namespace lti {
 namespace {
 
 constexpr size_t kAlign = 256;
-// Sweep batches outstanding: one.  A new batch is formed when the previous
-// one completes, so requests admitted meanwhile share it (bigger launches,
-// and new requests wait behind one batch instead of a queue of them); this
-// measured best for throughput and for serving latency.
-constexpr int kInflight = 1;
+// Sweep batches outstanding: two.  A new batch is formed when one of the two
+// completes, so requests admitted meanwhile share it, and the next batch is
+// already queued behind the running one (no host gap between batches).  On
+// the 4096-request serving mix two outstanding batches of up to 262,144
+// tiles measured 22.8 M points/s refined and 40.1 M float64, against 19.3 and
+// 32.0 with one batch of 16,384 tiles; the 64-state stream and the open-loop
+// latency were unchanged.
+constexpr int kInflight = 2;
+// Timing mark of a batch's whole sweep phase (its launches may overlap on
+// several streams, so they are timed together).
+constexpr int kSweepPhase = 100;
 // Streams: one admission stream and one sweep stream by default (a process
 // gets few hardware queues, four by default, and streams that share one run
 // in order).  With one admission stream, requests that arrive during a
@@ -71,10 +77,21 @@ constexpr int kInflight = 1;
 // slower.  Every sweep goes to the one sweep stream, which orders a
 // request's refinement and result copy after all of its tiles.
 constexpr int kAdmitStreams = 2;
+// Sweep streams: the context's stream plus auxiliary ones.  A batch's sweep
+// launches (one per kernel class) are spread over them: the launches of one
+// class often cannot fill the GPU for their whole duration (their waves'
+// lifetimes differ several-fold, so a launch ends with a long tail), and on
+// one stream the next launch would wait for that tail.  The streams join on
+// the context's stream before the batch's refinement and result copies.
+constexpr int kMaxSweepStreams = 3;
+// CUs kept free of sweeps (the library's own sweep streams are created with a
+// CU mask without them), so that reductions -- a chain of small launches for
+// large models -- find room while sweeps fill the rest of the GPU.
+constexpr int kReservedCUs = 0;
 // Reduction jobs queued by one admission pass (bounds one pass's work).
 constexpr int kMaxJobs = 1024;
 constexpr int kDefaultMaxPending = 8192;
-constexpr int kDefaultBatchTiles = 16384;
+constexpr int kDefaultBatchTiles = 262144;
 constexpr size_t kDefaultStaging = size_t(256) << 20;
 // A waiting poll() runs scheduling passes itself for up to this long.
 constexpr int64_t kPollSpinUs = 2000;
@@ -215,6 +232,7 @@ struct Request {
 
 struct Batch {
   hipEvent_t done = nullptr;
+  std::vector<hipEvent_t> joins;  // fork / join events of the sweep streams
   // with kernel timing: tev[0] before the first kernel, tev[i + 1] after the
   // launches of family tfam[i]
   std::vector<hipEvent_t> tev;
@@ -318,6 +336,8 @@ using namespace lti;
 struct lti_ctx {
   int device = 0;
   hipStream_t stream = nullptr;              // sweeps, refinement, result copies
+  hipStream_t aux[kMaxSweepStreams - 1] = {};  // more sweep streams (joined on `stream`)
+  int n_sweep_streams = kMaxSweepStreams;
   hipStream_t rstreams[kAdmitStreams] = {};  // uploads and reductions
   int next_rstream = 0;
   int n_rstreams = 1;
@@ -911,27 +931,23 @@ void launch(lti_ctx* c) {
     b.tev.push_back(ev);
     if (fam >= 0) b.tfam.push_back(fam);
   };
-  auto family_of = [](int k) {
-    return k >= kSweepDescBase                        ? LTI_KF_SWEEPDESC
-         : k >= kNumSweepClasses + kNumSweep16Classes ? LTI_KF_SWEEPWG
-         : k >= kNumSweepClasses                      ? LTI_KF_SWEEP4
-                                                      : LTI_KF_SWEEP1;
+  // the batch's launches: per kernel class, kMaxSegs requests each, with an
+  // estimate of their work (tiles x n^2 x (columns + 2)) for balancing
+  struct Job {
+    int k;
+    size_t lds;
+    SweepLaunch L;
+    double work;
   };
-  time_mark(-1);
-  // the classes of one family are contiguous: close a family's bracket when
-  // the next family starts (or at the end) if it launched anything
-  int cur_fam = -1;
-  bool cur_any = false;
-  SweepLaunch L;
-  for (int k = 0; k < kAllClasses && e == hipSuccess; ++k) {
-    if (family_of(k) != cur_fam) {
-      if (cur_any) time_mark(cur_fam);
-      cur_fam = family_of(k);
-      cur_any = false;
-    }
+  std::vector<Job> jobs;
+  for (int k = 0; k < kAllClasses; ++k) {
     const std::vector<Piece>& v = per[k];
-    if (!v.empty()) cur_any = true;
-    for (size_t i0 = 0; i0 < v.size() && e == hipSuccess; i0 += kMaxSegs) {
+    for (size_t i0 = 0; i0 < v.size(); i0 += kMaxSegs) {
+      Job jb;
+      jb.k = k;
+      jb.lds = c->stage_lds ? lds[k] : 0;
+      jb.work = 0.0;
+      SweepLaunch& L = jb.L;
       L.nseg = (int)std::min<size_t>(kMaxSegs, v.size() - i0);
       uint32_t t = 0;
       for (int sgi = 0; sgi < L.nseg; ++sgi) {
@@ -945,13 +961,53 @@ void launch(lti_ctx* c) {
         sg.S = (uint8_t)pc.r->S;
         sg.mc = (uint8_t)pc.r->mc;
         t += (uint32_t)pc.count;
+        const double n = pc.r->req.nx;
+        jb.work += (double)pc.count * pc.r->F * n * n * (pc.r->mc + 2.0);
       }
       L.ntiles = (int)t;
-      e = launch_any_sweep(k, L, c->stage_lds ? lds[k] : 0, ss);
-      c->stats.sweep_launches++;
+      jobs.push_back(jb);
     }
   }
-  if (cur_any) time_mark(cur_fam);
+  // largest first, each to the least loaded sweep stream
+  std::sort(jobs.begin(), jobs.end(), [](const Job& x, const Job& y) { return x.work > y.work; });
+  const int ns = jobs.size() > 1 ? c->n_sweep_streams : 1;
+  hipStream_t streams[kMaxSweepStreams] = {ss, c->aux[0], c->aux[1]};
+  double load[kMaxSweepStreams] = {0.0, 0.0, 0.0};
+  bool used[kMaxSweepStreams] = {true, false, false};
+  time_mark(-1);
+  hipEvent_t fork = nullptr;
+  if (ns > 1 && e == hipSuccess) {
+    fork = get_event(c, false);
+    e = fork ? hipEventRecord(fork, ss) : hipErrorOutOfMemory;
+    if (fork) b.joins.push_back(fork);
+  }
+  for (const Job& jb : jobs) {
+    if (e != hipSuccess) break;
+    int si = 0;
+    for (int i = 1; i < ns; ++i)
+      if (load[i] < load[si]) si = i;
+    if (!used[si]) {
+      e = hipStreamWaitEvent(streams[si], fork, 0);
+      used[si] = true;
+      if (e != hipSuccess) break;
+    }
+    load[si] += jb.work;
+    e = launch_any_sweep(jb.k, jb.L, jb.lds, streams[si]);
+    c->stats.sweep_launches++;
+  }
+  for (int i = 1; i < ns && e == hipSuccess; ++i) {
+    if (!used[i]) continue;
+    hipEvent_t join = get_event(c, false);
+    if (!join) {
+      e = hipErrorOutOfMemory;
+      break;
+    }
+    b.joins.push_back(join);
+    e = hipEventRecord(join, streams[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ss, join, 0);
+  }
+  // the sweep phase of the batch, all families together
+  time_mark(kSweepPhase);
   // finish the requests whose last tiles are in the batch: the extended
   // refinement of their queued points (the grid is sized by their points; a
   // workgroup that finds the queues empty exits at once), then the results
@@ -1043,11 +1099,12 @@ bool retire(lti_ctx* c) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, b.tev[i], b.tev[i + 1]) != hipSuccess) continue;
         const int f = b.tfam[i];
-        c->stats.family_ms[f] += ms;
-        c->stats.family_launches[f]++;
-        if (f != LTI_KF_REFINE_DD) {
+        if (f == kSweepPhase) {
           c->stats.sweep_kernel_ms += ms;
           counted = true;
+        } else {
+          c->stats.family_ms[f] += ms;
+          c->stats.family_launches[f]++;
         }
       }
       if (counted) c->stats.timed_sweep_launches++;
@@ -1061,6 +1118,7 @@ bool retire(lti_ctx* c) {
       if (r->tiles_done == r->ntiles && r->state == RState::kLive) complete_request(c, r);
     }
     put_event(c, b.done, false);
+    for (hipEvent_t ev : b.joins) put_event(c, ev, false);
     c->inflight.pop_front();
     progressed = true;
   }
@@ -1105,6 +1163,10 @@ void destroy_admit_streams(lti_ctx* c) {
   for (int i = 0; i < kAdmitStreams; ++i) {
     if (c->rstreams[i]) (void)hipStreamDestroy(c->rstreams[i]);
     c->rstreams[i] = nullptr;
+  }
+  for (int i = 0; i + 1 < kMaxSweepStreams; ++i) {
+    if (c->aux[i]) (void)hipStreamDestroy(c->aux[i]);
+    c->aux[i] = nullptr;
   }
 }
 
@@ -1277,6 +1339,9 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
     c->max_inflight = std::max(1, std::min(64, std::atoi(e)));
   if (const char* e = std::getenv("LTI_FREQRESP_ADMIT_STREAMS"))
     c->n_rstreams = std::max(1, std::min(kAdmitStreams, std::atoi(e)));
+  if (const char* e = std::getenv("LTI_FREQRESP_BATCH_TILES")) c->batch_tiles = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("LTI_FREQRESP_SWEEP_STREAMS"))
+    c->n_sweep_streams = std::max(1, std::min(kMaxSweepStreams, std::atoi(e)));
   c->t0 = Clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
   // the arena, minus the reduction job tables (one per admission stream)
@@ -1304,22 +1369,27 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   };
   // tuning knob (not part of the ABI): keep the sweeps off the first N CUs,
   // so that reductions always find room beside them
-  int reserved_cus = 0;
+  int reserved_cus = kReservedCUs;
   if (const char* e = std::getenv("LTI_FREQRESP_RESERVED_CUS")) reserved_cus = std::max(0, std::atoi(e));
-  if (cfg->stream) {
-    c->stream = static_cast<hipStream_t>(cfg->stream);
-  } else {
-    hipError_t e = hipSuccess;
+  // a sweep stream: on every CU but the first reserved_cus, when reserving
+  std::vector<uint32_t> sweep_mask;
+  {
     int ncu = 0;
     if (reserved_cus > 0 &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
         reserved_cus < ncu) {
-      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-      for (int cu = reserved_cus; cu < ncu; ++cu) mask[cu / 32] |= 1u << (cu % 32);
-      e = hipExtStreamCreateWithCUMask(&c->stream, (uint32_t)mask.size(), mask.data());
-    } else {
-      e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+      sweep_mask.assign((ncu + 31) / 32, 0u);
+      for (int cu = reserved_cus; cu < ncu; ++cu) sweep_mask[cu / 32] |= 1u << (cu % 32);
     }
+  }
+  auto make_sweep_stream = [&](hipStream_t* st) {
+    if (!sweep_mask.empty()) return hipExtStreamCreateWithCUMask(st, (uint32_t)sweep_mask.size(), sweep_mask.data());
+    return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+  };
+  if (cfg->stream) {
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+  } else {
+    const hipError_t e = make_sweep_stream(&c->stream);
     if (e != hipSuccess) {
       free_host();
       return LTI_EDEVICE;
@@ -1329,6 +1399,7 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   bool ok = true;
   for (int i = 0; i < c->n_rstreams && ok; ++i)
     ok = hipStreamCreateWithFlags(&c->rstreams[i], hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i + 1 < c->n_sweep_streams && ok; ++i) ok = make_sweep_stream(&c->aux[i]) == hipSuccess;
   if (!ok) {
     destroy_admit_streams(c.get());
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -1464,10 +1535,13 @@ int lti_freqresp_destroy(lti_ctx* c) {
   (void)hipSetDevice(c->device);
   for (hipStream_t rs : c->rstreams)
     if (rs) (void)hipStreamSynchronize(rs);
+  for (hipStream_t as : c->aux)
+    if (as) (void)hipStreamSynchronize(as);
   (void)hipStreamSynchronize(c->stream);
   for (auto& b : c->inflight) {
     put_event(c, b.done, false);
     for (hipEvent_t ev : b.tev) put_event(c, ev, true);
+    for (hipEvent_t ev : b.joins) put_event(c, ev, false);
   }
   for (auto& tp : c->reduce_timing) {
     put_event(c, tp.a, true);
