@@ -68,6 +68,9 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
   const int lane = threadIdx.x & 63;
   st.singular = false;
   const gptr<T> TT = (gptr<T>)Tm;
+  // the pivot row's right-hand side reaches the lanes through scalar
+  // registers when it takes at most 16 of them, else through LDS
+  constexpr bool kBcastSgpr = false;
   auto toff = [](int j) { return j * (j + 1) / 2; };
   {
     const int off = hoff32(n - 1);
@@ -118,12 +121,15 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
     const int klo = (64 * s > 1) ? 64 * s : 1;
     for (int k = khi; k >= klo; --k) {
       const int kl = k - 64 * s;
-      // b_k to LDS (lane kl), read back below as a broadcast
-      if (lane == kl) {
+      // b_k to LDS (lane kl), read back below as a broadcast, unless it is
+      // small enough to go through scalar registers (readlane)
+      if constexpr (!kBcastSgpr) {
+        if (lane == kl) {
 #pragma unroll
-        for (int j = 0; j < MM; ++j) {
-          bcast[2 * j] = st.br[s][j];
-          bcast[2 * j + 1] = st.bi[s][j];
+          for (int j = 0; j < MM; ++j) {
+            bcast[2 * j] = st.br[s][j];
+            bcast[2 * j + 1] = st.bi[s][j];
+          }
         }
       }
       // prefetch: column k-2 (rows 0..k-1) and subdiagonal H(k-2, k-3)
@@ -138,7 +144,15 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
 #pragma unroll
         for (int t = 0; t <= s; ++t) {
           const int i = lane + 64 * t;
-          if (i <= k - 1) hn[t] = H[off + i];
+          // with two or more slices (n > 64) the pivot slice's loads past
+          // row k-1 stay inside the packed array (its last column k-2 = n-3
+          // has 3n - 1 entries after it, n + 62 of them read at most), and
+          // those lanes never use the values: no per-lane test
+          if constexpr (R >= 2 && !kE) {
+            hn[t] = H[off + i];
+          } else {
+            if (i <= k - 1) hn[t] = H[off + i];
+          }
           if constexpr (kE) {
             if (i <= k - 2) tn[t] = TT[toff(k - 2) + i];
           }
@@ -163,16 +177,28 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
         si = (T)0;
         st.singular = true;
       }
-      // the LDS write above must land before any lane reads it back
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       T bkr[MM], bki[MM];
+      if constexpr (kBcastSgpr) {
 #pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        bkr[j] = bcast[2 * j];
-        bki[j] = bcast[2 * j + 1];
+        for (int j = 0; j < MM; ++j) {
+          bkr[j] = readlane(st.br[s][j], kl);
+          bki[j] = readlane(st.bi[s][j], kl);
+        }
+      } else {
+        // the LDS write above must land before any lane reads it back
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int j = 0; j < MM; ++j) {
+          bkr[j] = bcast[2 * j];
+          bki[j] = bcast[2 * j + 1];
+        }
       }
+      // the shift s = sg + j w on the diagonal entry of column k-1 (row
+      // k-1, in slice s or s-1), added to that row's results afterwards
+      const T csg = c * sg, cw = c * w;
+      const T d1 = sr * sg - si * w, d2 = si * sg + sr * w;
 #pragma unroll
       for (int t = 0; t <= s; ++t) {
         const int i = lane + 64 * t;
@@ -188,16 +214,19 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
             n1r = sr * orr - c * cr_ - si * oi;
             n1i = si * orr + sr * oi - c * ci_;
           } else {
-            // M(i, k-1): real off the diagonal; the diagonal entry also holds s
-            const T o = (i == k - 1) ? sg - hc[t] : -hc[t];
+            // M(i, k-1) = -H(i, k-1) off the diagonal; the diagonal entry
+            // also holds s: its share is added on row k-1 only
+            const T o = -hc[t];
             nkr = c * o + sr * cr_ + si * ci_;
             nki = sr * ci_ - si * cr_;
             n1r = sr * o - c * cr_;
             n1i = si * o - c * ci_;
-            if (i == k - 1) {  // imaginary part of the diagonal entry
-              nki += c * w;
-              n1r -= si * w;
-              n1i += sr * w;
+            if (t >= s - 1) {  // the slices that can hold row k-1
+              const T d = (i == k - 1) ? (T)1 : (T)0;
+              nkr = fma(d, csg, nkr);
+              nki = fma(d, cw, nki);
+              n1r = fma(d, d1, n1r);
+              n1i = fma(d, d2, n1i);
             }
           }
           st.cr[t] = n1r;
