@@ -57,24 +57,30 @@ TOL = 1e-10
 FP64_VALU_PEAK = 78.6
 FP32_VALU_PEAK = 157.3
 PROFILES = os.path.join(ROOT, "profiles")
-KF_NAMES = ["sweep16_kernel (four frequencies per wavefront, n <= 64)",
-            "sweep_kernel (one frequency per wavefront, n <= 256)",
-            "sweep_wg_kernel (one frequency per workgroup, n <= 1024)",
-            "refine_dd_kernel (double-double refinement)"]
+# kernel families (the library's LTI_KF_* numbers); the sweep phase of a
+# batch runs SWEEP_FAMILIES, the double-double refinement follows it
+KF_NAMES = {0: "sweep16_kernel (four frequencies per wavefront, n <= 64)",
+            5: "sweep32_kernel (two frequencies per wavefront, 64 < n <= 128)",
+            1: "sweep_kernel (one frequency per wavefront, n <= 256)",
+            2: "sweep_wg_kernel (one frequency per workgroup, n <= 1024)",
+            3: "refine_dd_kernel (double-double refinement)"}
+SWEEP_FAMILIES = [0, 5, 1, 2]
+KF_COUNT = 6
 SWEEP_SOURCES = ["sweep16.hip", "sweep.hip", "sweepwg.hip", "sweep_common.h", "dpp.h", "lti_kernels.h"]
-KF_SOURCES = [["sweep16.hip", "sweep_common.h", "dpp.h", "lti_kernels.h"],
-              ["sweep.hip", "sweep_common.h", "lti_kernels.h"],
-              ["sweepwg.hip", "sweep_common.h", "lti_kernels.h"],
-              ["sweepwg.hip", "sweep_common.h", "lti_kernels.h"]]
 
 
 def log(msg: str) -> None:
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def family_of(n: int) -> int:
-    """Kernel family the library runs an n-state request on."""
-    return 0 if n <= 64 else 1 if n <= 256 else 2
+def family_of(n: int, m: int, p: int) -> int:
+    """Kernel family the library runs a request on (state-space model, the
+    library's default knobs)."""
+    if n <= 64:
+        return 0
+    if n <= 128:
+        return 5
+    return 1 if n <= 256 else 2
 
 
 def solve_flops(n: int, m: int, p: int) -> float:
@@ -276,8 +282,8 @@ def roofline_of(delta, fam_flops, fp32: bool):
     the batch, spread over up to three streams and timed together by HIP
     events on the stream they join on): algorithmic flops per batch over the
     average phase time, against the vector peak of the arithmetic done."""
-    f32 = sum(ff[0] for ff in fam_flops[:3])
-    f64 = sum(ff[1] for ff in fam_flops[:3])
+    f32 = sum(fam_flops[f][0] for f in SWEEP_FAMILIES)
+    f64 = sum(fam_flops[f][1] for f in SWEEP_FAMILIES)
     launches = max(delta["timed_sweep_launches"], 1)
     t = delta["sweep_kernel_ms"] * 1e-3
     achieved = (f32 + f64) / t / 1e12
@@ -291,7 +297,7 @@ def roofline_of(delta, fam_flops, fp32: bool):
         "unit": "TFLOP/s",
         "frac": t_peak / t,
         "traffic": None,
-        "kernel": "sweep phase of a batch: " + "; ".join(KF_NAMES[:3]),
+        "kernel": "sweep phase of a batch: " + "; ".join(KF_NAMES[f] for f in SWEEP_FAMILIES),
         "kernel_source_sha256_16": _source_digest(SWEEP_SOURCES),
         "flops_per_launch": (f32 + f64) / launches,
         "fp32_share": f32 / max(f32 + f64, 1.0),
@@ -341,12 +347,12 @@ def serving_headline(args, out):
                 worst = max(worst, float(e.max()))
                 ok += int(np.sum(e <= TOL))
                 n += len(e)
-            fam_flops = [[0.0, 0.0] for _ in range(4)]
+            fam_flops = [[0.0, 0.0] for _ in range(KF_COUNT)]
             paths = np.zeros(5, dtype=np.int64)
             for i, r in enumerate(reqs):
                 info = mix.info(i)
                 f32, f64 = point_flops(r.n, r.m, r.p, info["iters"], prec == binding.PREC_REFINED)
-                f = family_of(r.n)
+                f = family_of(r.n, r.m, r.p)
                 fam_flops[f][0] += f32 * args.steps
                 fam_flops[f][1] += f64 * args.steps
                 paths += np.bincount(info["path"], minlength=5)[:5]
@@ -418,7 +424,7 @@ def serving_headline(args, out):
         whole sweep phase is timed) and the refinement kernel's time."""
         d = r["delta"]
         rows = {}
-        for f in range(3):
+        for f in SWEEP_FAMILIES:
             f32, fl64 = r["fam_flops"][f]
             if f32 + fl64 > 0:
                 rows[KF_NAMES[f].split(" ")[0]] = {"gflop_per_step": (f32 + fl64) / args.steps / 1e9}
@@ -635,9 +641,9 @@ def profile_pass(args):
         for _ in range(args.profile_pass):
             mix.run(eng, binding.PREC_REFINED)
     torch.cuda.synchronize()
-    pts = [0, 0, 0]
+    pts = [0] * KF_COUNT
     for r in reqs:
-        pts[family_of(r.n)] += r.K * args.profile_pass
+        pts[family_of(r.n, r.m, r.p)] += r.K * args.profile_pass
     print(json.dumps({"copy_bytes": 256 << 20, "passes": args.profile_pass, "requests": args.requests,
                       "points_by_family": pts}), flush=True)
 
@@ -685,7 +691,7 @@ def traffic_record(args):
     if not fk or not wk:
         raise SystemExit("calibration copy not found in the counter CSVs")
     ff, wf = copy_kib / fk, copy_kib / wk
-    tags = ["sweep16_kernel<1,", "sweep_kernel<1,", "sweep_wg_kernel<1,"]
+    tags = ["sweep16_kernel<1,", "sweep32_kernel<1,", "sweep_kernel<1,", "sweep_wg_kernel<1,"]
     names = [k for k in fetch if any(t in k.replace(" ", "") for t in tags)]
     fb = sum(fetch[k] for k in names) * ff * 1024.0
     wb = sum(write.get(k, 0.0) for k in names) * wf * 1024.0

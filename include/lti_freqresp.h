@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LTI_ABI_VERSION 3u
+#define LTI_ABI_VERSION 4u
 
 /* ---------------------------------------------------------------- codes */
 #define LTI_OK            0
@@ -197,7 +197,8 @@ typedef struct lti_result {
 #define LTI_KF_SWEEPWG    2  /* one frequency per workgroup (nx <= 1024)         */
 #define LTI_KF_REFINE_DD  3  /* double-double refinement of queued points       */
 #define LTI_KF_SWEEPDESC  4  /* descriptor systems (one frequency per wavefront) */
-#define LTI_KF_COUNT      5
+#define LTI_KF_SWEEP2     5  /* two frequencies per wavefront (64 < nx <= 128)   */
+#define LTI_KF_COUNT      6
 
 /* Counters of one context. */
 typedef struct lti_stats {

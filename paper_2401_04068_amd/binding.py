@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblti_freqresp.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 LTI_OK = 0
 LTI_PENDING = 1
@@ -52,7 +52,8 @@ KF_SWEEP1 = 1
 KF_SWEEPWG = 2
 KF_REFINE_DD = 3
 KF_SWEEPDESC = 4
-KF_COUNT = 5
+KF_SWEEP2 = 5
+KF_COUNT = 6
 
 CFG_KERNEL_TIMING = 1
 CFG_FORCE_DD = 2
@@ -157,8 +158,8 @@ class LtiStats(ctypes.Structure):
         ("reduce_kernel_ms", ctypes.c_double),
         ("timed_sweep_launches", ctypes.c_uint64),
         ("timed_reduce_launches", ctypes.c_uint64),
-        ("family_ms", ctypes.c_double * 5),
-        ("family_launches", ctypes.c_uint64 * 5),
+        ("family_ms", ctypes.c_double * KF_COUNT),
+        ("family_launches", ctypes.c_uint64 * KF_COUNT),
     ]
 
 

@@ -225,6 +225,13 @@ constexpr int kNumSweep16Classes = 18;
 int sweep16_class(int precision, int n, int mc);
 hipError_t launch_sweep16(int cls, const SweepLaunch& L, hipStream_t s);
 
+// Two-frequencies-per-wavefront kernels (sweep16.hip, 32-lane groups), both
+// precisions, 64 < n <= 128 and at most 4 right-hand-side columns per tile;
+// -1 when not covered.  Their tiles should hold a multiple of 2 frequencies.
+constexpr int kNumSweep32Classes = 12;
+int sweep32_class(int precision, int n, int mc);
+hipError_t launch_sweep32(int cls, const SweepLaunch& L, hipStream_t s);
+
 // Workgroup-per-frequency kernels (sweepwg.hip): both precisions,
 // 256 < n <= 1024, at most 4 right-hand-side columns per tile; -1 when not
 // covered.
@@ -295,9 +302,11 @@ hipError_t launch_sweep_desc(int kclass, const SweepLaunch& L, hipStream_t s);
 
 // All sweep kernel classes in one index space: [0, kNumSweepClasses) one
 // frequency per wavefront, then the four-frequency classes, then the
-// workgroup classes, then the descriptor classes.
+// workgroup classes, then the descriptor classes, then the two-frequency
+// classes.
 constexpr int kSweepDescBase = kNumSweepClasses + kNumSweep16Classes + kNumSweepWGClasses;
-constexpr int kAllSweepClasses = kSweepDescBase + kNumSweepDescClasses;
+constexpr int kSweep32Base = kSweepDescBase + kNumSweepDescClasses;
+constexpr int kAllSweepClasses = kSweep32Base + kNumSweep32Classes;
 hipError_t launch_any_sweep(int kclass, const SweepLaunch& L, size_t lds_bytes, hipStream_t s);
 
 // How a request's solves are cut into tiles (runtime.cpp): F frequencies
@@ -313,13 +322,16 @@ struct TilePlan {
 // Wavefronts a request alone should offer before its right-hand-side
 // columns stop being split over tiles, on an otherwise idle device: 256 CUs
 // x 4 SIMDs x 4 resident waves for one-frequency tiles, a quarter of that for
-// four-frequency tiles (each already carries four solves).
+// four-frequency tiles (each already carries four solves); two-frequency
+// tiles take half of the one-frequency figure.
 constexpr int64_t kTargetTilesOne = 4096;
 constexpr int64_t kTargetTilesFour = 1024;
 struct TileKnobs {
   int tile_points = 0;   // 0: automatic
   int rhs_split = 0;     // 0: automatic
   bool use_sweep16 = true;
+  bool use_sweep32 = true;
+  int sweep32_max_cols = kMaxRhs;  // widest request (min(m, p)) sent to the two-frequency kernels
   bool descriptor = false;  // descriptor system: float64 one-frequency kernels only
 };
 TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t avail_waves4, int64_t avail_waves1,

@@ -274,29 +274,35 @@ TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t ava
                     const TileKnobs& kn) {
   TilePlan t{};
   // Kernel family: four frequencies per wavefront (n <= 64, at most four
-  // right-hand-side columns per tile), one frequency per wavefront
-  // (n <= 256), or one frequency per workgroup (n <= 1024).
+  // right-hand-side columns per tile), two frequencies per wavefront
+  // (64 < n <= 128, at most four columns per tile), one frequency per
+  // wavefront (n <= 256), or one frequency per workgroup (n <= 1024).
   const bool wg = n > kMaxN && !kn.descriptor;
   const bool four = !wg && !kn.descriptor && kn.use_sweep16 && sweep16_class(precision, n, std::min(sm, 4)) >= 0;
+  const bool two = !wg && !four && !kn.descriptor && kn.use_sweep32 && sm <= kn.sweep32_max_cols &&
+                   sweep32_class(precision, n, std::min(sm, 4)) >= 0;
   int F = kn.tile_points;
-  if (F <= 0) F = four ? 4 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, K / 2048));
+  if (F <= 0) F = four ? 4 : two ? 2 : wg ? 1 : (int)std::min<int64_t>(8, std::max<int64_t>(1, K / 2048));
   if (four) F = (F + 3) & ~3;
+  if (two) F = (F + 1) & ~1;
   t.F = F;
   // Split the right-hand-side columns over several tiles (each split
   // repeats the rotations) only while the device would otherwise be short of
   // wavefronts: `avail` counts the waves it can still take.
   const int64_t fblocks = (K + F - 1) / F;
-  const int64_t avail = four ? avail_waves4 : avail_waves1;
+  const int64_t avail = four ? avail_waves4 : two ? avail_waves1 / 2 : avail_waves1;
   int S = kn.rhs_split;
   if (S <= 0) S = (fblocks >= avail) ? 1 : (int)((avail + fblocks - 1) / fblocks);
   S = std::max(1, std::min(S, sm));
-  if (four || wg) S = std::max(S, (sm + 3) / 4);
+  if (four || two || wg) S = std::max(S, (sm + 3) / 4);
   t.mc = (sm + S - 1) / S;
   t.S = (sm + t.mc - 1) / t.mc;
   if (wg) {
     t.kclass = kNumSweepClasses + kNumSweep16Classes + sweep_wg_class(precision, n, t.mc);
   } else if (four) {
     t.kclass = kNumSweepClasses + sweep16_class(precision, n, t.mc);
+  } else if (two) {
+    t.kclass = kSweep32Base + sweep32_class(precision, n, t.mc);
   } else {
     // one-frequency kernels keep R * MM <= 32 (R = 1, 2, 4 row slices):
     // split further until the column count fits
@@ -308,13 +314,14 @@ TilePlan plan_tiles(int precision, int n, int sm, int sp, int64_t K, int64_t ava
     t.kclass = sweep_class(precision, n, t.mc);
     if (kn.descriptor) t.kclass = t.kclass < 0 ? -1 : kSweepDescBase + sweep_class(LTI_PREC_FP64, n, t.mc);
   }
-  t.stage = (four || wg || kn.descriptor) ? 0 : stage_bytes(precision, n, sm, sp);
+  t.stage = (four || two || wg || kn.descriptor) ? 0 : stage_bytes(precision, n, sm, sp);
   t.ntiles = fblocks * t.S;
   t.waves_per_tile = wg ? 4 : 1;
   return t;
 }
 
 hipError_t launch_any_sweep(int k, const SweepLaunch& L, size_t lds_bytes, hipStream_t s) {
+  if (k >= kSweep32Base) return launch_sweep32(k - kSweep32Base, L, s);
   if (k >= kSweepDescBase) return launch_sweep_desc(k - kSweepDescBase, L, s);
   if (k >= kNumSweepClasses + kNumSweep16Classes) return launch_sweep_wg(k - kNumSweepClasses - kNumSweep16Classes, L, s);
   if (k >= kNumSweepClasses) return launch_sweep16(k - kNumSweepClasses, L, s);
@@ -360,6 +367,11 @@ struct lti_ctx {
   int rhs_split = 0;        // 0: automatic
   bool stage_lds = true;    // LDS staging of reduced models in the sweep
   bool use_sweep16 = true;  // four-frequencies-per-wavefront kernels where they apply
+  bool use_sweep32 = true;  // two-frequencies-per-wavefront kernels where they apply
+  // Requests of any width go to the two-frequency kernels, in groups of four
+  // columns: measured, groups of four with two frequencies per wavefront
+  // outrun the one-frequency kernels that hold 8 or 16 columns at once.
+  int sweep32_max_cols = kMaxRhs;
   int64_t target_tiles16 = kTargetTilesFour;
   int64_t target_tiles = kTargetTilesOne;
   int64_t outstanding_waves = 0;  // waves of admitted tiles not yet retired
@@ -716,6 +728,8 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   kn.tile_points = c->tile_points;
   kn.rhs_split = c->rhs_split;
   kn.use_sweep16 = c->use_sweep16;
+  kn.use_sweep32 = c->use_sweep32;
+  kn.sweep32_max_cols = c->sweep32_max_cols;
   kn.descriptor = q.E != nullptr;
   const TilePlan tp = plan_tiles(q.precision, n, sm, sp, r->K, std::max<int64_t>(0, c->target_tiles16 - c->outstanding_waves),
                                  std::max<int64_t>(0, c->target_tiles - c->outstanding_waves), kn);
@@ -1334,6 +1348,9 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES")) c->target_tiles = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("LTI_FREQRESP_STAGE_LDS")) c->stage_lds = std::atoi(e) != 0;
   if (const char* e = std::getenv("LTI_FREQRESP_SWEEP16")) c->use_sweep16 = std::atoi(e) != 0;
+  if (const char* e = std::getenv("LTI_FREQRESP_SWEEP32")) c->use_sweep32 = std::atoi(e) != 0;
+  if (const char* e = std::getenv("LTI_FREQRESP_SWEEP32_COLS"))
+    c->sweep32_max_cols = std::max(1, std::min(kMaxRhs, std::atoi(e)));
   if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES16")) c->target_tiles16 = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("LTI_FREQRESP_MAX_INFLIGHT"))
     c->max_inflight = std::max(1, std::min(64, std::atoi(e)));

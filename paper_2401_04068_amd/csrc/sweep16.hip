@@ -1,24 +1,26 @@
-// Shifted Hessenberg solves for models of at most 64 states: four
-// frequencies per wavefront.
+// Shifted Hessenberg solves with several frequencies per wavefront: four
+// (16-lane groups) for models of at most 64 states, two (32-lane groups) for
+// 64 < n <= 128.
 //
 // The arithmetic is the one of sweep.hip (right-to-left complex Givens column
 // rotations fused with back-substitution, then X = Z y by a scan of the
 // rotation recurrence, then G = (CQ) X + D; see the comments there).  Only
-// the mapping differs: frequency g = lane / 16 of the wavefront owns one
-// 16-lane DPP row, and row i of its system lives on lane 16 g + i % 16 in
-// register slice i / 16 (R <= 4 slices).  The four frequencies (consecutive
-// grid points of one request, so they share H, Q^T B and (CQ)^T) advance in
-// lockstep, which
+// the mapping differs: frequency g = lane / GW of the wavefront owns a group
+// of GW lanes (one 16-lane DPP row, or a pair of rows), and row i of its
+// system lives on lane GW g + i % GW in register slice i / GW (R <= 4
+// slices).  The frequencies of a wavefront (consecutive grid points of one
+// request, so they share H, Q^T B and (CQ)^T) advance in lockstep, which
 //   * shares the per-step scalar chain (pivot broadcast, rsqrt, rotation) and
-//     the column load of H among four solves,
-//   * keeps idle lanes to the pivot's own 16-row slice (slices above the
-//     pivot are skipped, not masked), and
-//   * keeps the cross-lane moves inside the row: the scan uses row_shr DPP
-//     with identity `old` values and the output reduce-scatter pairs lanes by
-//     row mirrors.
+//     the column load of H among the wavefront's solves,
+//   * keeps idle lanes to the pivot's own slice (slices above the pivot are
+//     skipped, not masked), and
+//   * keeps the cross-lane moves inside the group: the scan uses row_shr DPP
+//     with identity `old` values (and row_bcast:15 from the even to the odd
+//     row of a 32-lane group), the output reduce-scatter pairs lanes by row
+//     mirrors (after a sum over the row pair by v_permlane16_swap).
 // The pivot row's carry entry and right-hand side reach the other lanes of
-// its row through a small LDS slot per frequency, which lets the 16 steps of
-// a slice run as a loop (a fully unrolled step sequence does not fit the
+// its group through a small LDS slot per frequency, which lets the GW steps
+// of a slice run as a loop (a fully unrolled step sequence does not fit the
 // instruction cache).
 #include <cfloat>
 #include <cmath>
@@ -45,7 +47,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 template <typename T, int R, int MM>
-struct S16 {
+struct SG {
   T cr[R], ci[R];           // carry column
   T br[R][MM], bi[R][MM];   // right-hand side -> y -> x
   T rc[R], rsr[R], rsi[R];  // rotation k on row k (row 0 unused)
@@ -53,37 +55,90 @@ struct S16 {
   bool singular;            // this lane's frequency
 };
 
-template <typename T>
-__device__ __forceinline__ T group_min16(T x) {
+// The two 16-lane rows of each 32-lane group, at every lane of the group:
+// v_permlane16_swap with both operands x leaves the even row's x in the
+// first result and the odd row's x in the second.
+__device__ __forceinline__ void row_pair(float x, float& ev, float& od) {
+  const unsigned u = __float_as_uint(x);
+  const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  ev = __uint_as_float(a[0]);
+  od = __uint_as_float(a[1]);
+}
+__device__ __forceinline__ void row_pair(double x, double& ev, double& od) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  ev = __hiloint2double((int)b[0], (int)a[0]);
+  od = __hiloint2double((int)b[1], (int)a[1]);
+}
+
+template <int GW, typename T>
+__device__ __forceinline__ T group_min(T x) {
   x = fmin(x, dpp<kDppQuadSwap1>(x));
   x = fmin(x, dpp<kDppQuadSwap2>(x));
   x = fmin(x, dpp<kDppRowHalfMirror>(x));
-  return fmin(x, dpp<kDppRowMirror>(x));
+  x = fmin(x, dpp<kDppRowMirror>(x));
+  if constexpr (GW == 32) {
+    T e, o;
+    row_pair(x, e, o);
+    x = fmin(e, o);
+  }
+  return x;
 }
-template <typename T>
-__device__ __forceinline__ T group_max16(T x) {
+template <int GW, typename T>
+__device__ __forceinline__ T group_max(T x) {
   x = fmax(x, dpp<kDppQuadSwap1>(x));
   x = fmax(x, dpp<kDppQuadSwap2>(x));
   x = fmax(x, dpp<kDppRowHalfMirror>(x));
-  return fmax(x, dpp<kDppRowMirror>(x));
+  x = fmax(x, dpp<kDppRowMirror>(x));
+  if constexpr (GW == 32) {
+    T e, o;
+    row_pair(x, e, o);
+    x = fmax(e, o);
+  }
+  return x;
+}
+// Every lane of the group gets the group's total, summed in the same order.
+template <int GW>
+__device__ __forceinline__ double group_sum(double x) {
+  x = group_sum_dpp<16>(x);
+  if constexpr (GW == 32) {
+    double e, o;
+    row_pair(x, e, o);
+    x = e + o;
+  }
+  return x;
+}
+// Lane 0 (kLast false) or lane GW-1 (kLast true) of each group, at every
+// lane of the group.
+template <int GW, bool kLast, typename T>
+__device__ __forceinline__ T group_bcast(T x) {
+  const T y = dpp<dpp_row_newbcast(kLast ? 15 : 0)>(x);
+  if constexpr (GW == 16) {
+    return y;
+  } else {
+    T e, o;
+    row_pair(y, e, o);
+    return kLast ? o : e;
+  }
 }
 
-// Sweep and back-substitution for the four frequencies of the wavefront.  On
+// Sweep and back-substitution for the frequencies of the wavefront.  On
 // entry br/bi hold the right-hand sides, on exit y.  bcast: this wavefront's
-// 4 x (2 + 2 MM) values of LDS, one slot per frequency for the pivot row's
-// carry entry and right-hand side.  Slices are unrolled at compile time; the
-// 16 steps inside a slice are a loop, so the code stays small.
-template <typename T, int R, int MM, bool kLds>
-__device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T, R, MM>& st, T* bcast) {
+// (64 / GW) x (2 + 2 MM) values of LDS, one slot per frequency for the pivot
+// row's carry entry and right-hand side.  Slices are unrolled at compile
+// time; the GW steps inside a slice are a loop, so the code stays small.
+template <typename T, int R, int MM, bool kLds, int GW>
+__device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T, R, MM>& st, T* bcast) {
   const int lane = threadIdx.x & 63;
-  const int g = lane >> 4, gl = lane & 15;
+  const int g = lane / GW, gl = lane & (GW - 1);
   T* mine = bcast + g * (2 + 2 * MM);
   st.singular = false;
   {
     const int off = hoff32(n - 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = gl + 16 * r;
+      const int i = gl + GW * r;
       const T h = (i < n) ? H[off + i] : (T)0;
       st.cr[r] = (i == n - 1) ? sg - h : -h;
       st.ci[r] = (i == n - 1) ? w : (T)0;
@@ -100,7 +155,7 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T,
     const int off = hoff32(n - 2);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = gl + 16 * r;
+      const int i = gl + GW * r;
       if (i <= n - 1) hc[r] = H[off + i];
     }
   }
@@ -108,8 +163,8 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T,
   T sub1 = (n >= 3) ? H.uniform(hoff32(n - 3) + n - 2) : (T)0;
 
   // The pivot row's carry entry and right-hand side reach the other lanes of
-  // its 16-lane row through this wavefront's LDS slot.  Step k publishes the
-  // next pivot row k-1 as soon as the slice holding it is rotated: its carry
+  // its group through this wavefront's LDS slot.  Step k publishes the next
+  // pivot row k-1 as soon as the slice holding it is rotated: its carry
   // entry is read back at once (the next step's rotation starts from it), its
   // right-hand side after the other slices' back-substitution, which still
   // needs row k's; the LDS round trip overlaps the other slices' work.  LDS
@@ -146,25 +201,25 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T,
   // row n-1 is the first pivot
   static_for<0, R>([&](auto TT) {
     constexpr int t = decltype(TT)::value;
-    if ((n - 1) >> 4 == t) publish(TT, (n - 1) & 15);
+    if ((n - 1) / GW == t) publish(TT, (n - 1) & (GW - 1));
   });
   read_rhs();
 
-  // Step k = 16 s + jl; SP (compile-time) is the slice of row k-1: s for
+  // Step k = GW s + jl; SP (compile-time) is the slice of row k-1: s for
   // jl >= 1, s - 1 for jl = 0.
   auto step = [&](auto SC, auto SP, int jl) {
     constexpr int s = decltype(SC)::value;
     constexpr int sp = decltype(SP)::value;
-    const int k = 16 * s + jl;
+    const int k = GW * s + jl;
     // prefetch column k-2 (rows 0..k-1) and the subdiagonal two steps
     // ahead.  The loads of the pivot slice run past row k-1 into the next
-    // packed column (at most 15 entries, which the packed array and its LDS
-    // copy hold); those rows are never used.
+    // packed column (at most GW entries, all inside the packed array and its
+    // LDS copy); those rows are never used.
     T hn[R];
     if (k >= 2) {
       const int off = hoff32(k - 2) + gl;
 #pragma unroll
-      for (int t = 0; t <= s; ++t) hn[t] = H[off + 16 * t];
+      for (int t = 0; t <= s; ++t) hn[t] = H[off + GW * t];
     } else {
 #pragma unroll
       for (int t = 0; t <= s; ++t) hn[t] = (T)0;
@@ -191,7 +246,7 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T,
         // the diagonal entry of column k-1 (row k-1, in slice sp) also
         // holds s = sg + j w
         T d = (T)0;
-        if constexpr (t == sp) d = (gl + 16 * t == k - 1) ? (T)1 : (T)0;
+        if constexpr (t == sp) d = (gl + GW * t == k - 1) ? (T)1 : (T)0;
         const T o = (t == sp) ? fma(d, sg, -hc[t]) : -hc[t];
         T nkr = c * o + sr * cr_ + si * ci_;
         T nki = sr * ci_ - si * cr_;
@@ -216,7 +271,7 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T,
       }
     };
     rot(SP);
-    publish(SP, (k - 1) & 15);
+    publish(SP, (k - 1) & (GW - 1));
     // the other slices (for jl = 0, slice s holds no row below k)
     static_for<0, sp>([&](auto TT) { rot(TT); });
     if (gl == jl) {
@@ -234,21 +289,21 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T,
 
   static_for<0, R>([&](auto sc) {
     constexpr int s = R - 1 - decltype(sc)::value;
-    if (16 * s > n - 1) return;  // no pivot row in this slice (uniform)
-    const int jhi = (n - 1 - 16 * s < 15) ? n - 1 - 16 * s : 15;
+    if (GW * s > n - 1) return;  // no pivot row in this slice (uniform)
+    const int jhi = (n - 1 - GW * s < GW - 1) ? n - 1 - GW * s : GW - 1;
     using SC = std::integral_constant<int, s>;
     for (int jl = jhi; jl >= 1; --jl) step(SC{}, SC{}, jl);
     if constexpr (s >= 1) step(SC{}, std::integral_constant<int, s - 1>{}, 0);
   });
   // y_k = b_k / R(k,k); R(0,0) is the final carry entry of row 0
-  const T ar = dpp<dpp_row_newbcast(0)>(st.cr[0]);
-  const T ai = dpp<dpp_row_newbcast(0)>(st.ci[0]);
+  const T ar = group_bcast<GW, false>(st.cr[0]);
+  const T ai = group_bcast<GW, false>(st.ci[0]);
   const T d = ar * ar + ai * ai;
   st.singular = st.singular || !(d > (T)0);
   const T dinv = (T)1 / d;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = gl + 16 * r;
+    const int i = gl + GW * r;
     if (i == 0) {
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
@@ -267,61 +322,80 @@ __device__ __forceinline__ void sweep16(Src<T, kLds> H, int n, T sg, T w, S16<T,
 }
 
 // Largest over smallest |R(k,k)| for this lane's frequency.
-template <typename T, int R, int MM>
-__device__ __forceinline__ double diag_ratio16(int n, const S16<T, R, MM>& st) {
-  const int gl = threadIdx.x & 15;
+template <typename T, int R, int MM, int GW>
+__device__ __forceinline__ double diag_ratio_grp(int n, const SG<T, R, MM>& st) {
+  const int gl = threadIdx.x & (GW - 1);
   double lo = INFINITY, hi = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = gl + 16 * r;
+    const int i = gl + GW * r;
     if (i >= 1 && i < n) {
       lo = fmin(lo, (double)st.rinv[r]);
       hi = fmax(hi, (double)st.rinv[r]);
     }
   }
-  lo = group_min16(lo);
-  hi = group_max16(hi);
-  const double ar = (double)dpp<dpp_row_newbcast(0)>(st.cr[0]);
-  const double ai = (double)dpp<dpp_row_newbcast(0)>(st.ci[0]);
+  lo = group_min<GW>(lo);
+  hi = group_max<GW>(hi);
+  const double ar = (double)group_bcast<GW, false>(st.cr[0]);
+  const double ai = (double)group_bcast<GW, false>(st.ci[0]);
   const double r0 = sqrt(ar * ar + ai * ai);
   return fmax(1.0 / lo, r0) / fmin(1.0 / hi, r0);
 }
 
 // x := Z y in place (scan of t_k = -c_k t_{k-1} + conj(s_k) y_k within each
-// 16-lane row, slice by slice).
-template <typename T, int R, int MM>
-__device__ __forceinline__ void apply_rotations16(int n, S16<T, R, MM>& st) {
-  const int gl = threadIdx.x & 15;
+// group, slice by slice).
+template <typename T, int R, int MM, int GW>
+__device__ __forceinline__ void apply_rotations_grp(int n, SG<T, R, MM>& st) {
+  const int gl = threadIdx.x & (GW - 1);
   T tinr[MM], tini[MM];
 #pragma unroll
   for (int j = 0; j < MM; ++j) tinr[j] = tini[j] = (T)0;
+  // lane 0 of the odd row of a 32-lane group, at every lane of the group
+  auto lane0_of_odd = [](T x) {
+    T e, o;
+    row_pair(dpp<dpp_row_newbcast(0)>(x), e, o);
+    return o;
+  };
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (16 * r >= n) break;
-    const int i = gl + 16 * r;
+    if (GW * r >= n) break;
+    const int i = gl + GW * r;
     const bool inner = (i > 0 && i < n);
     T a = inner ? -st.rc[r] : (T)0;
-    T am[4];
+    constexpr int NQ = (GW == 32) ? 5 : 4;
+    T am[NQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       am[q] = a;
       T ap;
       if (q == 0) ap = dpp<dpp_row_shr(1)>(a, (T)1);
       if (q == 1) ap = dpp<dpp_row_shr(2)>(a, (T)1);
       if (q == 2) ap = dpp<dpp_row_shr(4)>(a, (T)1);
       if (q == 3) ap = dpp<dpp_row_shr(8)>(a, (T)1);
+      if (q == 4) ap = dpp<kDppRowBcast15, 0xa>(a, (T)1);  // odd rows <- lane 15 of the even row
       a = a * ap;
     }
-    // rotation of row i+1 (row 16(r+1) for the last lane of the row)
+    // rotation of row i+1 (lane 0 of the next slice for the group's last
+    // lane; in a 32-lane group, lane 0 of the odd row for lane 15)
     T nc = dpp<dpp_row_shl(1)>(st.rc[r]);
     T nsr = dpp<dpp_row_shl(1)>(st.rsr[r]);
     T nsi = dpp<dpp_row_shl(1)>(st.rsi[r]);
+    if constexpr (GW == 32) {
+      const T c1 = lane0_of_odd(st.rc[r]);
+      const T s1r = lane0_of_odd(st.rsr[r]);
+      const T s1i = lane0_of_odd(st.rsi[r]);
+      if (gl == 15) {
+        nc = c1;
+        nsr = s1r;
+        nsi = s1i;
+      }
+    }
     const int rn = (r + 1 < R) ? r + 1 : r;
     if (r + 1 < R) {
-      const T c0 = dpp<dpp_row_newbcast(0)>(st.rc[rn]);
-      const T s0r = dpp<dpp_row_newbcast(0)>(st.rsr[rn]);
-      const T s0i = dpp<dpp_row_newbcast(0)>(st.rsi[rn]);
-      if (gl == 15) {
+      const T c0 = group_bcast<GW, false>(st.rc[rn]);
+      const T s0r = group_bcast<GW, false>(st.rsr[rn]);
+      const T s0i = group_bcast<GW, false>(st.rsi[rn]);
+      if (gl == GW - 1) {
         nc = c0;
         nsr = s0r;
         nsi = s0i;
@@ -347,20 +421,32 @@ __device__ __forceinline__ void apply_rotations16(int n, S16<T, R, MM>& st) {
       ui = fma(am[2], dpp<dpp_row_shr(4)>(ui, (T)0), ui);
       ur = fma(am[3], dpp<dpp_row_shr(8)>(ur, (T)0), ur);
       ui = fma(am[3], dpp<dpp_row_shr(8)>(ui, (T)0), ui);
+      if constexpr (GW == 32) {
+        ur = fma(am[4], dpp<kDppRowBcast15, 0xa>(ur, (T)0), ur);
+        ui = fma(am[4], dpp<kDppRowBcast15, 0xa>(ui, (T)0), ui);
+      }
       const T tr = fma(a, tinr[j], ur);
       const T ti = fma(a, tini[j], ui);
       T nyr = dpp<dpp_row_shl(1)>(yr);
       T nyi = dpp<dpp_row_shl(1)>(yi);
-      if (r + 1 < R) {
-        const T y0r = dpp<dpp_row_newbcast(0)>(st.br[rn][j]);
-        const T y0i = dpp<dpp_row_newbcast(0)>(st.bi[rn][j]);
+      if constexpr (GW == 32) {
+        const T y1r = lane0_of_odd(yr);
+        const T y1i = lane0_of_odd(yi);
         if (gl == 15) {
+          nyr = y1r;
+          nyi = y1i;
+        }
+      }
+      if (r + 1 < R) {
+        const T y0r = group_bcast<GW, false>(st.br[rn][j]);
+        const T y0i = group_bcast<GW, false>(st.bi[rn][j]);
+        if (gl == GW - 1) {
           nyr = y0r;
           nyi = y0i;
         }
       }
-      tinr[j] = dpp<dpp_row_newbcast(15)>(tr);
-      tini[j] = dpp<dpp_row_newbcast(15)>(ti);
+      tinr[j] = group_bcast<GW, true>(tr);
+      tini[j] = group_bcast<GW, true>(ti);
       if (i < n - 1) {
         st.br[r][j] = nsr * tr - nsi * ti + nc * nyr;
         st.bi[r][j] = nsr * ti + nsi * tr + nc * nyi;
@@ -388,18 +474,20 @@ __device__ __forceinline__ void rs16_stage(double (&vr)[8], double (&vi)[8], boo
 }
 
 // G(:, j0 .. j0+mc-1) of this lane's frequency = (CQ) X + D; the sum over the
-// row's 16 lanes is a reduce-scatter of 8 complex values, after which lane gl
-// holds entry gl / 2.
-template <int R, int MM>
-__device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc, bool valid,
-                                               const double (&xr)[R][MM], const double (&xi)[R][MM],
-                                               double* __restrict__ G, bool deriv = false) {
-  const int gl = threadIdx.x & 15;
+// group's lanes is a reduce-scatter of 8 complex values over each 16-lane
+// row (in a 32-lane group after summing the two rows), after which lane gl
+// of the (first) row holds entry gl / 2.
+template <int R, int MM, int GW>
+__device__ __forceinline__ void write_output_grp(const ReqDesc& rd, int j0, int mc, bool valid,
+                                                 const double (&xr)[R][MM], const double (&xi)[R][MM],
+                                                 double* __restrict__ G, bool deriv = false) {
+  const int gl = threadIdx.x & (GW - 1);
+  const int rl = gl & 15;
   const int n = rd.n, m = rd.m, p = rd.p;
   const gptr<double> Ct = (gptr<double>)rd.Ct;
   constexpr int PC = (8 / MM > 0) ? 8 / MM : 1;
   constexpr int MC = (MM < 8) ? MM : 8;
-  const bool up8 = gl >= 8, up4 = (gl & 7) >= 4, up2 = (gl & 3) >= 2;
+  const bool up8 = rl >= 8, up4 = (rl & 7) >= 4, up2 = (rl & 3) >= 2;
   for (int a0 = 0; a0 < p; a0 += PC) {
 #pragma unroll
     for (int jb = 0; jb < MM; jb += MC) {
@@ -409,7 +497,7 @@ __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc
       for (int q = 0; q < 8; ++q) vr[q] = vi[q] = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = gl + 16 * r;
+        const int i = gl + GW * r;
         if (i < n) {
 #pragma unroll
           for (int q = 0; q < PC; ++q) {
@@ -423,12 +511,19 @@ __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc
           }
         }
       }
+      if constexpr (GW == 32) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          vr[q] = xor16_sum(vr[q]);
+          vi[q] = xor16_sum(vi[q]);
+        }
+      }
       rs16_stage<kDppRowMirror, 4>(vr, vi, up8);
       rs16_stage<kDppRowHalfMirror, 2>(vr, vi, up4);
       rs16_stage<0x1B, 1>(vr, vi, up2);  // quad_perm [3,2,1,0]
       vr[0] += dpp<kDppQuadSwap1>(vr[0]);
       vi[0] += dpp<kDppQuadSwap1>(vi[0]);
-      if (valid && (gl & 1) == 0) {
+      if (valid && gl < 16 && (gl & 1) == 0) {
         const int idx = gl >> 1;
         const int a = a0 + idx / MC;
         const int j = jb + idx % MC;
@@ -443,37 +538,37 @@ __device__ __forceinline__ void write_output16(const ReqDesc& rd, int j0, int mc
   }
 }
 
-template <int R, int MM, bool kLds>
-__device__ void solve16_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, bool valid, int j0, int mc,
-                             double* bcast) {
-  const int gl = threadIdx.x & 15;
+template <int R, int MM, bool kLds, int GW>
+__device__ void solve_grp_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, bool valid, int j0, int mc,
+                               double* bcast) {
+  const int gl = threadIdx.x & (GW - 1);
   const int n = rd.n, m = rd.m;
   const SPoint sp = point_of(rd, k);
   const gptr<double> Bt = (gptr<double>)rd.Bt;
-  S16<double, R, MM> st;
+  SG<double, R, MM> st;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = gl + 16 * r;
+    const int i = gl + GW * r;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       st.br[r][j] = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
       st.bi[r][j] = 0.0;
     }
   }
-  sweep16<double, R, MM, kLds>(H, n, sp.re, sp.im, st, bcast);
+  sweep_grp<double, R, MM, kLds, GW>(H, n, sp.re, sp.im, st, bcast);
   // estimated error from the spread of R's diagonal; points above the
   // request's tolerance are finished by the extended refinement
-  const double est = fp64_estimate(n, diag_ratio16<double, R, MM>(n, st));
+  const double est = fp64_estimate(n, diag_ratio_grp<double, R, MM, GW>(n, st));
   const bool dd = fp64_needs_dd(rd, est);
   if (dd && valid && gl == 0) enqueue_dd(rd, k, j0, mc, 0, kReasonFP64);
-  apply_rotations16<double, R, MM>(n, st);
+  apply_rotations_grp<double, R, MM, GW>(n, st);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
-  write_output16<R, MM>(rd, j0, mc, valid && !dd, st.br, st.bi, G);
+  write_output_grp<R, MM, GW>(rd, j0, mc, valid && !dd, st.br, st.bi, G);
   if (rd.dG) {
     // dG/ds = -C (sI - A)^{-2} B: the same sweep with X as right-hand side
-    sweep16<double, R, MM, kLds>(H, n, sp.re, sp.im, st, bcast);
-    apply_rotations16<double, R, MM>(n, st);
-    write_output16<R, MM>(rd, j0, mc, valid && !dd, st.br, st.bi, rd.dG + (size_t)k * rd.p * m * 2, true);
+    sweep_grp<double, R, MM, kLds, GW>(H, n, sp.re, sp.im, st, bcast);
+    apply_rotations_grp<double, R, MM, GW>(n, st);
+    write_output_grp<R, MM, GW>(rd, j0, mc, valid && !dd, st.br, st.bi, rd.dG + (size_t)k * rd.p * m * 2, true);
   }
   if (valid && !dd && gl == 0) {
     lti_point_info inf;
@@ -485,11 +580,6 @@ __device__ void solve16_fp64(const ReqDesc& rd, Src<double, kLds> H, int64_t k, 
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T group_sum16(T x) {
-  return group_sum_dpp<16>(x);
-}
-
 __device__ __forceinline__ double bperm_d(int addr, double v) {
   const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
   const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
@@ -497,17 +587,17 @@ __device__ __forceinline__ double bperm_d(int addr, double v) {
 }
 
 // r = Q^T B - (s X - H X) in float64 for this lane's frequency; the row
-// X(j, :) reaches the other lanes of its 16-lane row through ds_bpermute.
-template <int R, int MM, bool kLds>
-__device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> H, double sg, double w, int j0, int mc,
-                                           const double (&xr)[R][MM], const double (&xi)[R][MM],
-                                           double (&rr)[R][MM], double (&ri)[R][MM]) {
-  const int lane = threadIdx.x & 63, gl = lane & 15;
+// X(j, :) reaches the other lanes of its group through ds_bpermute.
+template <int R, int MM, bool kLds, int GW>
+__device__ __forceinline__ void residual_grp(const ReqDesc& rd, Src<double, kLds> H, double sg, double w, int j0,
+                                             int mc, const double (&xr)[R][MM], const double (&xi)[R][MM],
+                                             double (&rr)[R][MM], double (&ri)[R][MM]) {
+  const int lane = threadIdx.x & 63, gl = lane & (GW - 1);
   const int n = rd.n, m = rd.m;
   const gptr<double> Bt = (gptr<double>)rd.Bt;
 #pragma unroll
   for (int t = 0; t < R; ++t) {
-    const int i = gl + 16 * t;
+    const int i = gl + GW * t;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       const double b = (i < n && j < mc) ? Bt[i * m + j0 + j] : 0.0;
@@ -517,13 +607,13 @@ __device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> 
   }
   static_for<0, R>([&](auto sc) {
     constexpr int sj = decltype(sc)::value;
-    if (16 * sj >= n) return;
-    const int jend = (n - 16 * sj < 16) ? n - 16 * sj : 16;
+    if (GW * sj >= n) return;
+    const int jend = (n - GW * sj < GW) ? n - GW * sj : GW;
     for (int jl = 0; jl < jend; ++jl) {
-      const int jc = 16 * sj + jl;  // column of H
+      const int jc = GW * sj + jl;  // column of H
       const int off = hoff32(jc);
       const int len = (jc + 2 < n) ? jc + 2 : n;
-      const int addr = ((lane & 48) | jl) << 2;
+      const int addr = ((lane & (64 - GW)) | jl) << 2;
       double xjr[MM], xji[MM];
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
@@ -532,7 +622,7 @@ __device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> 
       }
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        const int i = gl + 16 * t;
+        const int i = gl + GW * t;
         if (i < len) {
           const double h = H[off + i];
 #pragma unroll
@@ -548,12 +638,12 @@ __device__ __forceinline__ void residual16(const ReqDesc& rd, Src<double, kLds> 
 
 // Refined path: complex-float32 solves, float64 residuals and accumulation;
 // stalled points go to the extended refinement (see solve_refined in
-// sweep.hip).  The four frequencies of the wavefront iterate in lockstep
-// until all have stopped.
-template <int R, int MM, bool kLds>
-__device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<float, kLds> H32, int64_t k, bool valid,
-                                int j0, int mc, double* bcast64) {
-  const int gl = threadIdx.x & 15;
+// sweep.hip).  The frequencies of the wavefront iterate in lockstep until
+// all have stopped.
+template <int R, int MM, bool kL64, bool kL32, int GW>
+__device__ void solve_grp_refined(const ReqDesc& rd, Src<double, kL64> H, Src<float, kL32> H32, int64_t k,
+                                  bool valid, int j0, int mc, double* bcast64) {
+  const int gl = threadIdx.x & (GW - 1);
   const int n = rd.n, m = rd.m;
   const SPoint sp = point_of(rd, k);
   const float sgf = (float)sp.re, wf = (float)sp.im;
@@ -563,18 +653,18 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
   const gptr<float> Bt32 = (gptr<float>)rd.Bt32;
 
   double xr[R][MM], xi[R][MM];
-  S16<float, R, MM> st;
+  SG<float, R, MM> st;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = gl + 16 * r;
+    const int i = gl + GW * r;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       st.br[r][j] = (i < n && j < mc) ? Bt32[i * m + j0 + j] : 0.0f;
       st.bi[r][j] = 0.0f;
     }
   }
-  sweep16<float, R, MM, kLds>(H32, n, sgf, wf, st, bcast);
-  apply_rotations16<float, R, MM>(n, st);
+  sweep_grp<float, R, MM, kL32, GW>(H32, n, sgf, wf, st, bcast);
+  apply_rotations_grp<float, R, MM, GW>(n, st);
   double s2 = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -584,7 +674,7 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
       xi[r][j] = (double)st.bi[r][j];
       s2 += xr[r][j] * xr[r][j] + xi[r][j] * xi[r][j];
     }
-  double dprev = sqrt(group_sum16(s2));
+  double dprev = sqrt(group_sum<GW>(s2));
   int iters = 1;
   double est = 1.0;
   bool done = false, ok = false;
@@ -593,13 +683,13 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
   for (int it = 0; it < kMaxIters; ++it) {
     if (__all(done)) break;
     double rr[R][MM], ri[R][MM];
-    residual16<R, MM, kLds>(rd, H, sp.re, sp.im, j0, mc, xr, xi, rr, ri);
+    residual_grp<R, MM, kL64, GW>(rd, H, sp.re, sp.im, j0, mc, xr, xi, rr, ri);
     double amax = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int j = 0; j < MM; ++j) amax = fmax(amax, fmax(fabs(rr[r][j]), fabs(ri[r][j])));
-    amax = group_max16(amax);
+    amax = group_max<GW>(amax);
     if (!done && amax == 0.0) {  // X solves the float64 system exactly
       est = 0.0;
       ok = true;
@@ -613,8 +703,8 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
         st.br[r][j] = (float)(rr[r][j] * scale);
         st.bi[r][j] = (float)(ri[r][j] * scale);
       }
-    sweep16<float, R, MM, kLds>(H32, n, sgf, wf, st, bcast);
-    apply_rotations16<float, R, MM>(n, st);
+    sweep_grp<float, R, MM, kL32, GW>(H32, n, sgf, wf, st, bcast);
+    apply_rotations_grp<float, R, MM, GW>(n, st);
     double d2 = 0.0, x2 = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -627,8 +717,8 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
         d2 += dr * dr + di * di;
         x2 += xr[r][j] * xr[r][j] + xi[r][j] * xi[r][j];
       }
-    const double dn = sqrt(group_sum16(d2));
-    const double xn = sqrt(group_sum16(x2));
+    const double dn = sqrt(group_sum<GW>(d2));
+    const double xn = sqrt(group_sum<GW>(x2));
     if (!done) {
       ++iters;
       if (!(dn < INFINITY) || !(xn > 0.0)) {
@@ -650,7 +740,7 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
   // stalled (or singular) points: the extended refinement finishes them
   if (!ok && valid && gl == 0) enqueue_dd(rd, k, j0, mc, iters, kReasonStall);
   double* G = rd.G + (size_t)k * rd.p * m * 2;
-  write_output16<R, MM>(rd, j0, mc, valid && ok, xr, xi, G);
+  write_output_grp<R, MM, GW>(rd, j0, mc, valid && ok, xr, xi, G);
   if (valid && ok && gl == 0) {
     lti_point_info inf;
     inf.est_rel_err = (float)est;
@@ -661,42 +751,39 @@ __device__ void solve16_refined(const ReqDesc& rd, Src<double, kLds> H, Src<floa
   }
 }
 
-constexpr int hlen_max(int R) { return (16 * R - 1) * (16 * R + 2) / 2 + 16 * R; }
+// Packed length of the largest H a kernel holds (n = GW R).
+constexpr int hlen_max(int R, int GW) { return (GW * R - 1) * (GW * R + 2) / 2 + GW * R; }
 
-template <int PREC, int R, int MM, bool kLds>
-__device__ __forceinline__ void run_tile16(const ReqDesc& rd, const Tile& td, Src<double, kLds> H,
-                                           Src<float, kLds> H32, double* bcast) {
-  const int g = (threadIdx.x & 63) >> 4;
-  for (uint32_t f0 = 0; f0 < td.count; f0 += 4) {
+template <int PREC, int R, int MM, bool kL64, bool kL32, int GW>
+__device__ __forceinline__ void run_tile_grp(const ReqDesc& rd, const Tile& td, Src<double, kL64> H,
+                                             Src<float, kL32> H32, double* bcast) {
+  constexpr int NG = 64 / GW;
+  const int g = (threadIdx.x & 63) / GW;
+  for (uint32_t f0 = 0; f0 < td.count; f0 += NG) {
     // group g solves frequency f0 + g; past the tile's end it repeats the
     // last frequency and writes nothing
     const uint32_t f = f0 + g;
     const bool valid = f < td.count;
     const int64_t k = (int64_t)td.start + (valid ? f : td.count - 1);
-    if (PREC == LTI_PREC_FP64)
-      solve16_fp64<R, MM, kLds>(rd, H, k, valid, td.j0, td.mc, bcast);
+    if constexpr (PREC == LTI_PREC_FP64)
+      solve_grp_fp64<R, MM, kL64, GW>(rd, H, k, valid, td.j0, td.mc, bcast);
     else
-      solve16_refined<R, MM, kLds>(rd, H, H32, k, valid, td.j0, td.mc, bcast);
+      solve_grp_refined<R, MM, kL64, kL32, GW>(rd, H, H32, k, valid, td.j0, td.mc, bcast);
   }
 }
 
-// The reduced model's H (and its float32 copy on the refined path) is staged
-// in LDS when the workgroup's four tiles belong to one request, which they do
-// except where two requests meet in a launch.
-//
-// The float64 kernels use at most 168 registers per lane (three wavefronts
-// per SIMD, and room for a reduction workgroup beside two sweep wavefronts):
-// a launch that carries several requests has more wavefronts than two per
-// SIMD.  The four-column kernel then keeps a few values of its set-up, slice
-// change and output phases in scratch memory, none in the step loops.  The
-// refined kernels keep their full register sets (capped the same way, they
-// would spill up to 740 bytes per lane).
-template <int PREC, int R, int MM>
-__global__ __launch_bounds__(64 * kWaves16)
-__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? 3 : 1))) void sweep16_kernel(const SweepLaunch L) {
-  __shared__ double bcast_all[kWaves16][4 * (2 + 2 * MM)];
-  __shared__ double sH[hlen_max(R)];
-  __shared__ float sH32[PREC == LTI_PREC_FP64 ? 1 : hlen_max(R)];
+// The reduced model's H is staged in LDS when the workgroup's four tiles
+// belong to one request, which they do except where two requests meet in a
+// launch: both copies of H for the 16-lane kernels, for the 32-lane kernels
+// (n <= 128) only the copy their sweeps read (the float32 one on the
+// refined path, whose float64 residuals read H from global memory).
+template <int PREC, int R, int MM, int GW>
+__device__ __forceinline__ void sweep_grp_body(const SweepLaunch& L) {
+  constexpr bool kStage64 = GW == 16 || PREC == LTI_PREC_FP64;
+  constexpr bool kStage32 = PREC != LTI_PREC_FP64;
+  __shared__ double bcast_all[kWaves16][(64 / GW) * (2 + 2 * MM)];
+  __shared__ double sH[kStage64 ? hlen_max(R, GW) : 1];
+  __shared__ float sH32[kStage32 ? hlen_max(R, GW) : 1];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tb = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves16;  // < ntiles
   const int tile = tb + wave;
@@ -705,9 +792,11 @@ __attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? 3 : 1))) void sweep16
   if (staged) {
     const ReqDesc& r0 = L.seg[s0].rd;
     const int nh = (int)hlen(r0.n);
-    const gptr<double> gH = (gptr<double>)r0.H;
-    for (int i = threadIdx.x; i < nh; i += 64 * kWaves16) sH[i] = gH[i];
-    if (PREC != LTI_PREC_FP64) {
+    if constexpr (kStage64) {
+      const gptr<double> gH = (gptr<double>)r0.H;
+      for (int i = threadIdx.x; i < nh; i += 64 * kWaves16) sH[i] = gH[i];
+    }
+    if constexpr (kStage32) {
       const gptr<float> gH32 = (gptr<float>)r0.H32;
       for (int i = threadIdx.x; i < nh; i += 64 * kWaves16) sH32[i] = gH32[i];
     }
@@ -719,23 +808,62 @@ __attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? 3 : 1))) void sweep16
   const Tile td = tile_of(L.seg[s], tile);
   double* bcast = bcast_all[wave];
   if (staged) {
-    run_tile16<PREC, R, MM, true>(rd, td, Src<double, true>{sH}, Src<float, true>{sH32}, bcast);
+    if constexpr (kStage64)
+      run_tile_grp<PREC, R, MM, true, true, GW>(rd, td, Src<double, true>{sH}, Src<float, true>{sH32}, bcast);
+    else
+      run_tile_grp<PREC, R, MM, false, true, GW>(rd, td, Src<double, false>{rd.H}, Src<float, true>{sH32}, bcast);
   } else {
-    run_tile16<PREC, R, MM, false>(rd, td, Src<double, false>{rd.H}, Src<float, false>{rd.H32}, bcast);
+    run_tile_grp<PREC, R, MM, false, false, GW>(rd, td, Src<double, false>{rd.H}, Src<float, false>{rd.H32},
+                                                bcast);
   }
 }
 
-using Kernel16Fn = void (*)(const SweepLaunch);
+// The float64 kernels use at most 168 registers per lane (three wavefronts
+// per SIMD, and room for a reduction workgroup beside two sweep wavefronts):
+// a launch that carries several requests has more wavefronts than two per
+// SIMD.  The four-column kernels then keep a few values of their set-up,
+// slice change and output phases in scratch memory, none in the step loops.
+// The refined kernels keep their full register sets (capped the same way,
+// they would spill up to 740 bytes per lane).
+template <int PREC, int R, int MM>
+__global__ __launch_bounds__(64 * kWaves16)
+__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? 3 : 1))) void sweep16_kernel(const SweepLaunch L) {
+  sweep_grp_body<PREC, R, MM, 16>(L);
+}
+
+// The 32-lane kernels: the float64 ones up to 96 states are capped like the
+// 16-lane ones; with up to 128 states they stage 67 KB of LDS per workgroup,
+// which leaves room for two wavefronts per SIMD, and are held to 256
+// registers, as are the refined ones (two wavefronts per SIMD).
+template <int PREC, int R, int MM>
+__global__ __launch_bounds__(64 * kWaves16)
+__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 && R < 4 ? 3 : 2))) void sweep32_kernel(const SweepLaunch L) {
+  sweep_grp_body<PREC, R, MM, 32>(L);
+}
+
+using KernelGrpFn = void (*)(const SweepLaunch);
 
 template <int PREC, int R>
-Kernel16Fn pick16_mm(int mi) {
+KernelGrpFn pick16_mm(int mi) {
   return mi == 0 ? sweep16_kernel<PREC, R, 1> : mi == 1 ? sweep16_kernel<PREC, R, 2> : sweep16_kernel<PREC, R, 4>;
 }
 
 template <int PREC>
-Kernel16Fn pick16(int ri, int mi) {
+KernelGrpFn pick16(int ri, int mi) {
   return ri == 0 ? pick16_mm<PREC, 1>(mi) : ri == 1 ? pick16_mm<PREC, 2>(mi) : pick16_mm<PREC, 4>(mi);
 }
+
+template <int PREC, int R>
+KernelGrpFn pick32_mm(int mi) {
+  return mi == 0 ? sweep32_kernel<PREC, R, 1> : mi == 1 ? sweep32_kernel<PREC, R, 2> : sweep32_kernel<PREC, R, 4>;
+}
+
+template <int PREC>
+KernelGrpFn pick32(int ri, int mi) {
+  return ri == 0 ? pick32_mm<PREC, 3>(mi) : pick32_mm<PREC, 4>(mi);
+}
+
+int rhs_index(int mc) { return (mc <= 1) ? 0 : (mc <= 2) ? 1 : 2; }
 
 }  // namespace
 
@@ -743,15 +871,31 @@ int sweep16_class(int precision, int n, int mc) {
   if (precision != LTI_PREC_FP64 && precision != LTI_PREC_REFINED) return -1;
   if (n < 1 || n > 64 || mc < 1 || mc > 4) return -1;
   const int ri = (n <= 16) ? 0 : (n <= 32) ? 1 : 2;
-  const int mi = (mc <= 1) ? 0 : (mc <= 2) ? 1 : 2;
-  return (precision * 3 + ri) * 3 + mi;
+  return (precision * 3 + ri) * 3 + rhs_index(mc);
 }
 
 hipError_t launch_sweep16(int cls, const SweepLaunch& L, hipStream_t s) {
   if (L.ntiles <= 0) return hipSuccess;
   if (cls < 0 || cls >= kNumSweep16Classes) return hipErrorInvalidValue;
   const int prec = cls / 9, ri = (cls / 3) % 3, mi = cls % 3;
-  const Kernel16Fn fn = prec == LTI_PREC_FP64 ? pick16<LTI_PREC_FP64>(ri, mi) : pick16<LTI_PREC_REFINED>(ri, mi);
+  const KernelGrpFn fn = prec == LTI_PREC_FP64 ? pick16<LTI_PREC_FP64>(ri, mi) : pick16<LTI_PREC_REFINED>(ri, mi);
+  const int blocks = (L.ntiles + kWaves16 - 1) / kWaves16;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves16), 0, s, L);
+  return hipGetLastError();
+}
+
+int sweep32_class(int precision, int n, int mc) {
+  if (precision != LTI_PREC_FP64 && precision != LTI_PREC_REFINED) return -1;
+  if (n <= 64 || n > 128 || mc < 1 || mc > 4) return -1;
+  const int ri = (n <= 96) ? 0 : 1;
+  return (precision * 2 + ri) * 3 + rhs_index(mc);
+}
+
+hipError_t launch_sweep32(int cls, const SweepLaunch& L, hipStream_t s) {
+  if (L.ntiles <= 0) return hipSuccess;
+  if (cls < 0 || cls >= kNumSweep32Classes) return hipErrorInvalidValue;
+  const int prec = cls / 6, ri = (cls / 3) % 2, mi = cls % 3;
+  const KernelGrpFn fn = prec == LTI_PREC_FP64 ? pick32<LTI_PREC_FP64>(ri, mi) : pick32<LTI_PREC_REFINED>(ri, mi);
   const int blocks = (L.ntiles + kWaves16 - 1) / kWaves16;
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * kWaves16), 0, s, L);
   return hipGetLastError();

@@ -195,6 +195,12 @@ int sweep16_class(int precision, int n, int mc) {
   const int mi = (mc <= 1) ? 0 : (mc <= 2) ? 1 : 2;
   return (precision * 3 + ri) * 3 + mi;
 }
+int sweep32_class(int precision, int n, int mc) {
+  if (n <= 64 || n > 128 || mc < 1 || mc > 4) return -1;
+  const int ri = (n <= 96) ? 0 : 1;
+  const int mi = (mc <= 1) ? 0 : (mc <= 2) ? 1 : 2;
+  return (precision * 2 + ri) * 3 + mi;
+}
 int sweep_wg_class(int precision, int n, int mc) {
   if (n <= kMaxN || n > 1024 || mc < 1 || mc > 4) return -1;
   return precision * 3 + ((mc <= 1) ? 0 : (mc <= 2) ? 1 : 2);
@@ -260,6 +266,10 @@ hipError_t launch_sweep(int, const SweepLaunch& L, size_t, hipStream_t s) {
   return hipSuccess;
 }
 hipError_t launch_sweep16(int, const SweepLaunch& L, hipStream_t s) {
+  s->push([L] { sweep_stub(L); });
+  return hipSuccess;
+}
+hipError_t launch_sweep32(int, const SweepLaunch& L, hipStream_t s) {
   s->push([L] { sweep_stub(L); });
   return hipSuccess;
 }

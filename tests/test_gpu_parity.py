@@ -335,6 +335,57 @@ def test_four_frequency_kernel_matches_single(n, monkeypatch):
     assert np.array_equal(outs["1"][1]["path"], outs["0"][1]["path"])
 
 
+@pytest.mark.parametrize("n,m,p", [(65, 3, 2), (66, 1, 1), (80, 2, 5), (95, 4, 4), (96, 3, 3), (97, 2, 1),
+                                   (100, 4, 6), (113, 1, 3), (127, 2, 2), (128, 4, 4)])
+def test_two_frequency_kernel_matches_single(n, m, p, monkeypatch):
+    """The two-frequencies-per-wavefront kernels (65 to 128 states, at most
+    four columns) against the one-frequency-per-wavefront kernels and the
+    oracle, both precisions; 29 grid points leave one pair half filled."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(9050 + n)
+    w = np.concatenate([[0.0, -1.25], wl.logspace_grid(1e-2, 1e2, 27)])
+    mdl = wl.mixed_pole_model(rng, n, m, p, w)
+    outs = {}
+    for knob in ("0", "1"):
+        monkeypatch.setenv("LTI_FREQRESP_SWEEP32", knob)
+        with binding.Engine(arena_bytes=256 << 20) as e:
+            for prec in ("fp64", "refined"):
+                print(f"case two-frequency n={n} m={m} p={p} knob={knob} {prec}", flush=True)
+                h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=_prec(prec))
+                assert e.poll(h, -1)
+                outs[(knob, prec)] = (h.G, h.info.copy())
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    assert oracle.rel_err(outs[("1", "fp64")][0], ref).max() <= TOL_FP64
+    assert oracle.rel_err(outs[("1", "fp64")][0], outs[("0", "fp64")][0]).max() <= 1e-13
+    assert np.array_equal(outs[("1", "fp64")][1]["path"], outs[("0", "fp64")][1]["path"])
+    assert oracle.rel_err(outs[("1", "refined")][0], ref).max() <= TOL_REFINED
+    assert np.all(outs[("1", "refined")][1]["path"] == binding.PATH_REFINED)
+
+
+@pytest.mark.parametrize("split,m", [("2", 4), ("0", 7), ("0", 16)])
+def test_two_frequency_kernel_column_groups(split, m, monkeypatch):
+    """Columns over several tiles of the two-frequency kernels: a forced
+    split of four columns into two groups, and 7 and 16 columns in groups of
+    four (merged point records)."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(9070 + m)
+    mdl = wl.mixed_pole_model(rng, 110, m, 16, wl.logspace_grid(1e-2, 1e2, 41))
+    ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+    monkeypatch.setenv("LTI_FREQRESP_RHS_SPLIT", split)
+    with binding.Engine(arena_bytes=256 << 20) as e:
+        for prec in ("fp64", "refined"):
+            print(f"case two-frequency columns split={split} m={m} {prec}", flush=True)
+            h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, precision=_prec(prec))
+            assert e.poll(h, -1)
+            tol = TOL_FP64 if prec == "fp64" else TOL_REFINED
+            assert oracle.rel_err(h.G, ref).max() <= tol
+            want = binding.PATH_FP64 if prec == "fp64" else binding.PATH_REFINED
+            assert np.all(h.info["path"] == want)
+            assert np.all(h.info["iters"] >= 1)
+
+
 @pytest.mark.parametrize("n,m,p", [(257, 3, 2), (300, 5, 4), (512, 2, 3), (1024, 16, 16)])
 def test_large_state_dimensions(eng, n, m, p):
     """Models above 256 states (one workgroup per frequency), float64 path."""

@@ -31,7 +31,7 @@ def _kappa(mdl):
     return d.max(axis=1) / d.min(axis=1)
 
 
-@pytest.mark.parametrize("n", [16, 64, 100, 300])
+@pytest.mark.parametrize("n", [16, 64, 72, 100, 300])
 def test_stall_goes_to_double_double_refinement(eng, n):
     """A pair with zeta = 1e-7 probed at its damped frequency: kappa * u32 is
     far above 1, so float32 refinement stalls; the float64 solve alone misses

@@ -143,7 +143,7 @@ def test_discrete_time_unit_circle(n, m, p):
             assert err.max() <= tol, (err.max(), theta[err.argmax()])
 
 
-@pytest.mark.parametrize("n,m,p", [(8, 1, 1), (40, 3, 2), (100, 2, 4), (300, 3, 3)])
+@pytest.mark.parametrize("n,m,p", [(8, 1, 1), (40, 3, 2), (100, 2, 4), (128, 4, 3), (300, 3, 3)])
 def test_derivative(n, m, p):
     """dG/ds = -C (sI - A)^{-2} B from the second sweep, on the frequency grid
     and at complex points, against the oracle (requests with a derivative run
