@@ -140,6 +140,22 @@ struct ZeroLaunch {
 };
 hipError_t launch_zero(const ZeroLaunch& Z, hipStream_t s);
 
+// Summaries of the point records of the requests a sweep batch finishes,
+// one workgroup per request: points per path code and the largest error
+// estimate, so that the host reads 64 bytes per request instead of every
+// record.  `tab` and `out` are device arrays of n entries.
+struct FinEntry {
+  const lti_point_info* info;
+  uint64_t K;
+};
+struct PointSummary {
+  uint32_t count[8];  // points per LTI_PATH_* code (codes 0-7)
+  float max_est;      // largest est_rel_err (NaN records ignored)
+  uint32_t pad[7];
+};
+static_assert(sizeof(PointSummary) == 64, "summary records are 64 bytes");
+hipError_t launch_summarize(const FinEntry* tab, PointSummary* out, int n, hipStream_t s);
+
 // Per-request descriptor, handed to the sweep kernels in their launch
 // arguments.
 //

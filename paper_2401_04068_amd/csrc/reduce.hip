@@ -456,6 +456,42 @@ __global__ __launch_bounds__(256) void zero_kernel(const ZeroLaunch Z) {
   for (uint32_t i = threadIdx.x; i < w; i += 256) p[i] = 0u;
 }
 
+// One workgroup per finished request: count its point records per path
+// code and take the largest estimate (fmaxf skips NaN).
+__global__ __launch_bounds__(256) void summarize_kernel(const FinEntry* __restrict__ tab,
+                                                        PointSummary* __restrict__ out) {
+  __shared__ uint32_t cnt[8];
+  __shared__ float mx[4];
+  const FinEntry fe = tab[blockIdx.x];
+  if (threadIdx.x < 8) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  uint32_t c[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  float m = 0.0f;
+  const uint2* rec = reinterpret_cast<const uint2*>(fe.info);
+  for (uint64_t k = threadIdx.x; k < fe.K; k += 256) {
+    const uint2 v = rec[k];  // est_rel_err | iters, path, reserved
+    const uint32_t path = (v.y >> 8) & 7u;
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) c[q] += (path == q) ? 1u : 0u;
+    m = fmaxf(m, __uint_as_float(v.x));
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    uint32_t x = c[q];
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    if ((threadIdx.x & 63) == 0 && x) atomicAdd(&cnt[q], x);
+  }
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    PointSummary s{};
+    for (int q = 0; q < 8; ++q) s.count[q] = cnt[q];
+    s.max_est = fmaxf(fmaxf(mx[0], mx[1]), fmaxf(mx[2], mx[3]));
+    out[blockIdx.x] = s;
+  }
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <int S>
@@ -519,6 +555,12 @@ hipError_t launch_zero(const ZeroLaunch& Z, hipStream_t s) {
   if (Z.n <= 0) return hipSuccess;
   if (Z.n > kMaxZero) return hipErrorInvalidValue;
   zero_kernel<<<Z.n, 256, 0, s>>>(Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_summarize(const FinEntry* tab, PointSummary* out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  summarize_kernel<<<n, 256, 0, s>>>(tab, out);
   return hipGetLastError();
 }
 

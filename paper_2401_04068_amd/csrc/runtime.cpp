@@ -93,6 +93,10 @@ constexpr int kMaxJobs = 1024;
 constexpr int kDefaultMaxPending = 8192;
 constexpr int kDefaultBatchTiles = 262144;
 constexpr size_t kDefaultStaging = size_t(256) << 20;
+// Requests a sweep batch may finish: the summaries of their point records
+// are computed on the device into a per-batch table of this many entries
+// (one slot per outstanding batch).
+constexpr int kMaxFin = 1024;
 // A waiting poll() runs scheduling passes itself for up to this long.
 constexpr int64_t kPollSpinUs = 2000;
 // The scheduler thread backs off while a caller's thread has run a
@@ -218,6 +222,7 @@ struct Request {
   size_t block_bytes = 0;
   size_t dOffG = 0;       // G (host requests; info follows at the staging offset)
   lti_point_info* dinfo = nullptr;  // the point records on the device
+  const PointSummary* sum = nullptr;  // their summary (pinned), set by the finishing batch
   ReqDesc desc{};         // handed to the sweep kernels in their arguments
   int kclass = -1;
   int64_t K = 0;
@@ -397,6 +402,15 @@ struct lti_ctx {
 
   char* staging_block = nullptr;  // the pinned allocation behind `staging`
   char* jobtab_block = nullptr;   // the pinned allocation behind jobtab_host
+  // per outstanding batch (slot = batch number % max_inflight): the table of
+  // finished requests' records and their summaries, on the device (in the
+  // arena) and pinned
+  FinEntry* fintab_host = nullptr;
+  FinEntry* fintab_dev = nullptr;
+  PointSummary* sum_host = nullptr;
+  PointSummary* sum_dev = nullptr;
+  char* fin_block = nullptr;  // the pinned allocation behind fintab_host, sum_host
+  uint64_t batch_seq = 0;
   std::vector<hipEvent_t> event_pool, timing_pool;
 
   lti_stats stats{};
@@ -591,14 +605,17 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   // pinned host memory for the results (pageable only for results larger
   // than the whole pool), then device memory; a request that does not fit
   // waits
+  // (device-memory requests need none: their records stay on the device and
+  // the finishing batch summarises them)
   HostStage& hs = r->hs;
-  const size_t ibytes = sizeof(lti_point_info) * q.n_omega;
-  const size_t gbytes = q.mem == LTI_MEM_HOST ? sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu : 0;
+  const bool host = q.mem == LTI_MEM_HOST;
+  const size_t ibytes = host ? sizeof(lti_point_info) * q.n_omega : 0;
+  const size_t gbytes = host ? sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu : 0;
   hs.offG = 0;
   hs.offInfo = align_up(gbytes);
   hs.offDG = hs.offInfo + align_up(ibytes);
-  hs.outBytes = (q.mem == LTI_MEM_HOST && q.dG_out) ? hs.offDG + gbytes : hs.offInfo + ibytes;
-  if (!take_buf(c, hs.out, hs.outBytes, align_up(hs.outBytes) > c->staging.size())) return false;
+  hs.outBytes = !host ? 0 : q.dG_out ? hs.offDG + gbytes : hs.offInfo + ibytes;
+  if (hs.outBytes && !take_buf(c, hs.out, hs.outBytes, align_up(hs.outBytes) > c->staging.size())) return false;
   void* mblock = nullptr;
   if (needs_model) {
     mblock = alloc_evicting(c, nd.model);
@@ -644,7 +661,6 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
   r->block_bytes = nd.block();
 
   char* b = static_cast<char*>(block);
-  const bool host = q.mem == LTI_MEM_HOST;
   const double* d_omega = q.omega;
   double* d_G = q.G_out;
   lti_point_info* d_info = q.info_out;
@@ -845,20 +861,15 @@ void admit(lti_ctx* c) {
   c->last_pass[rs] = pass_ref(pe);
 }
 
-// Copy a finished request's results to its pinned staging (host requests:
-// G and its records in one copy; device requests: the records, for the
-// counts of poll()'s result).
+// Copy a finished host-memory request's results to its pinned staging: G
+// and its records (and dG) in one copy, back to back in the block and in
+// staging (same offsets).  Device-memory requests copy nothing.
 hipError_t copy_results(lti_ctx* c, Request* r, hipStream_t s) {
-  const lti_request& q = r->req;
+  (void)c;
+  if (r->req.mem != LTI_MEM_HOST) return hipSuccess;
   HostStage& hs = r->hs;
-  const size_t ibytes = sizeof(lti_point_info) * q.n_omega;
-  if (q.mem == LTI_MEM_HOST) {
-    // G, info (and dG) are back to back in the block and in staging (same
-    // offsets)
-    const char* src = static_cast<const char*>(r->block) + r->dOffG;
-    return hipMemcpyAsync(hs.out.base + hs.offG, src, hs.outBytes, hipMemcpyDeviceToHost, s);
-  }
-  return hipMemcpyAsync(hs.out.base + hs.offInfo, r->dinfo, ibytes, hipMemcpyDeviceToHost, s);
+  const char* src = static_cast<const char*>(r->block) + r->dOffG;
+  return hipMemcpyAsync(hs.out.base + hs.offG, src, hs.outBytes, hipMemcpyDeviceToHost, s);
 }
 
 // Gather up to batch_tiles tiles from the live requests (oldest first) into
@@ -909,7 +920,7 @@ void launch(lti_ctx* c) {
   };
   std::vector<Request*> fin;  // requests whose last tiles are in this batch
   for (Request* r : c->live) {
-    if (total >= c->batch_tiles) break;
+    if (total >= c->batch_tiles || (int)fin.size() >= kMaxFin) break;
     if (r->state != RState::kLive || r->next_tile >= r->ntiles) continue;
     if (!eligible(r)) continue;
     const int64_t take = std::min<int64_t>(r->ntiles - r->next_tile, c->batch_tiles - total);
@@ -1042,8 +1053,25 @@ void launch(lti_ctx* c) {
       e = launch_refine_dd(D, grid, ss);
     }
     time_mark(LTI_KF_REFINE_DD);
+    // the summaries of their point records: one table up, one kernel, one
+    // copy down (this batch's slot; the batch that used it last has retired)
+    const size_t slot = (size_t)(c->batch_seq % (uint64_t)c->max_inflight) * kMaxFin;
+    FinEntry* th = c->fintab_host + slot;
+    for (size_t i = 0; i < fin.size(); ++i) {
+      th[i].info = fin[i]->dinfo;
+      th[i].K = (uint64_t)fin[i]->K;
+      fin[i]->sum = c->sum_host + slot + i;
+    }
+    const int nf = (int)fin.size();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->fintab_dev + slot, th, sizeof(FinEntry) * nf, hipMemcpyHostToDevice, ss);
+    if (e == hipSuccess) e = launch_summarize(c->fintab_dev + slot, c->sum_dev + slot, nf, ss);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->sum_host + slot, c->sum_dev + slot, sizeof(PointSummary) * nf, hipMemcpyDeviceToHost,
+                         ss);
     for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i) e = copy_results(c, fin[i], ss);
   }
+  c->batch_seq++;
   b.done = get_event(c, false);
   if (e == hipSuccess) e = b.done ? hipEventRecord(b.done, ss) : hipErrorOutOfMemory;
   c->stats.tiles_launched += total;
@@ -1061,21 +1089,18 @@ void complete_request(lti_ctx* c, Request* r) {
   r->res.status = LTI_OK;
   r->res.n_points = q.n_omega;
   HostStage& hs = r->hs;
-  const lti_point_info* info = reinterpret_cast<const lti_point_info*>(hs.out.base + hs.offInfo);
   if (q.mem == LTI_MEM_HOST) {
     std::memcpy(q.G_out, hs.out.base + hs.offG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
-    if (q.info_out) std::memcpy(q.info_out, info, sizeof(lti_point_info) * q.n_omega);
+    if (q.info_out) std::memcpy(q.info_out, hs.out.base + hs.offInfo, sizeof(lti_point_info) * q.n_omega);
     if (q.dG_out)
       std::memcpy(q.dG_out, hs.out.base + hs.offDG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
   }
-  for (int64_t k = 0; k < q.n_omega; ++k) {
-    const lti_point_info& pi = info[k];
-    if (pi.path == LTI_PATH_REFINED) r->res.n_refined++;
-    if (pi.path == LTI_PATH_FALLBACK) r->res.n_fallback++;
-    if (pi.path == LTI_PATH_SINGULAR) r->res.n_singular++;
-    if (pi.path == LTI_PATH_FP64_DD) r->res.n_fp64_dd++;
-    r->res.max_est_rel_err = std::max(r->res.max_est_rel_err, (double)pi.est_rel_err);
-  }
+  const PointSummary& ps = *r->sum;
+  r->res.n_refined = ps.count[LTI_PATH_REFINED];
+  r->res.n_fallback = ps.count[LTI_PATH_FALLBACK];
+  r->res.n_singular = ps.count[LTI_PATH_SINGULAR];
+  r->res.n_fp64_dd = ps.count[LTI_PATH_FP64_DD];
+  r->res.max_est_rel_err = std::max(0.0, (double)ps.max_est);
   release_stage(c, r->hs);
   r->res.t_done_us = c->now_us();
   r->state = RState::kDone;
@@ -1361,12 +1386,20 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
     c->n_sweep_streams = std::max(1, std::min(kMaxSweepStreams, std::atoi(e)));
   c->t0 = Clock::now();
   if (hipSetDevice(c->device) != hipSuccess) return LTI_EDEVICE;
-  // the arena, minus the reduction job tables (one per admission stream)
+  // the arena, minus the reduction job tables (one per admission stream) and
+  // the finished-request tables and summaries (one slot per outstanding
+  // batch)
   const size_t tab_bytes = align_up(sizeof(ReduceJob) * kMaxJobs);
-  if (cfg->arena_bytes < kAdmitStreams * tab_bytes + (size_t(1) << 20)) return LTI_EINVAL;
+  const size_t fin_slots = (size_t)c->max_inflight * kMaxFin;
+  const size_t fintab_bytes = align_up(sizeof(FinEntry) * fin_slots);
+  const size_t sum_bytes = align_up(sizeof(PointSummary) * fin_slots);
+  const size_t reserved = kAdmitStreams * tab_bytes + fintab_bytes + sum_bytes;
+  if (cfg->arena_bytes < reserved + (size_t(1) << 20)) return LTI_EINVAL;
   char* abase = static_cast<char*>(cfg->arena);
   for (int i = 0; i < kAdmitStreams; ++i) c->jobtab_dev[i] = reinterpret_cast<ReduceJob*>(abase + i * tab_bytes);
-  c->arena.init(abase + kAdmitStreams * tab_bytes, cfg->arena_bytes - kAdmitStreams * tab_bytes);
+  c->fintab_dev = reinterpret_cast<FinEntry*>(abase + kAdmitStreams * tab_bytes);
+  c->sum_dev = reinterpret_cast<PointSummary*>(abase + kAdmitStreams * tab_bytes + fintab_bytes);
+  c->arena.init(abase + reserved, cfg->arena_bytes - reserved);
   const size_t staging = cfg->host_staging_bytes ? cfg->host_staging_bytes : kDefaultStaging;
   void* hp = nullptr;
   if (hipHostMalloc(&hp, staging, hipHostMallocDefault) != hipSuccess) return LTI_EDEVICE;
@@ -1380,9 +1413,19 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   c->jobtab_block = static_cast<char*>(jp);
   for (int i = 0; i < kAdmitStreams; ++i)
     c->jobtab_host[i] = reinterpret_cast<ReduceJob*>(c->jobtab_block + i * tab_bytes);
+  void* fp = nullptr;
+  if (hipHostMalloc(&fp, fintab_bytes + sum_bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipHostFree(hp);
+    (void)hipHostFree(jp);
+    return LTI_EDEVICE;
+  }
+  c->fin_block = static_cast<char*>(fp);
+  c->fintab_host = reinterpret_cast<FinEntry*>(c->fin_block);
+  c->sum_host = reinterpret_cast<PointSummary*>(c->fin_block + fintab_bytes);
   auto free_host = [&] {
     (void)hipHostFree(hp);
     (void)hipHostFree(jp);
+    (void)hipHostFree(fp);
   };
   // tuning knob (not part of the ABI): keep the sweeps off the first N CUs,
   // so that reductions always find room beside them
@@ -1574,6 +1617,7 @@ int lti_freqresp_destroy(lti_ctx* c) {
   for (hipEvent_t e : c->timing_pool) (void)hipEventDestroy(e);
   if (c->staging_block) (void)hipHostFree(c->staging_block);
   if (c->jobtab_block) (void)hipHostFree(c->jobtab_block);
+  if (c->fin_block) (void)hipHostFree(c->fin_block);
   destroy_admit_streams(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;

@@ -206,6 +206,21 @@ int sweep_wg_class(int precision, int n, int mc) {
   return precision * 3 + ((mc <= 1) ? 0 : (mc <= 2) ? 1 : 2);
 }
 
+hipError_t launch_summarize(const FinEntry* tab, PointSummary* out, int n, hipStream_t s) {
+  s->push([tab, out, n] {
+    for (int i = 0; i < n; ++i) {
+      PointSummary ps{};
+      for (uint64_t k = 0; k < tab[i].K; ++k) {
+        const lti_point_info& pi = tab[i].info[k];
+        if (pi.path < 8) ps.count[pi.path]++;
+        if (pi.est_rel_err > ps.max_est) ps.max_est = pi.est_rel_err;
+      }
+      out[i] = ps;
+    }
+  });
+  return hipSuccess;
+}
+
 hipError_t launch_zero(const ZeroLaunch& Z, hipStream_t s) {
   s->push([Z] {
     for (int i = 0; i < Z.n; ++i) std::memset(Z.e[i].p, 0, 4 * (size_t)Z.e[i].words);
