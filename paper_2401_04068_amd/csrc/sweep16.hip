@@ -128,12 +128,23 @@ __device__ __forceinline__ T group_bcast(T x) {
 // (64 / GW) x (2 + 2 MM) values of LDS, one slot per frequency for the pivot
 // row's carry entry and right-hand side.  Slices are unrolled at compile
 // time; the GW steps inside a slice are a loop, so the code stays small.
-template <typename T, int R, int MM, bool kLds, int GW>
-__device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T, R, MM>& st, T* bcast) {
+//
+// The float32 sweeps (refined path) keep rotation k and 1 / R(k,k) in a
+// table in LDS, rot[k] = (c, Re s, Im s, 1 / R(k,k)), one per frequency,
+// written by the lane that publishes the next pivot; the float64 sweeps
+// keep them in registers, on the lane of row k.  kReuse (float32 only):
+// the rotations are those of the table, left by a sweep of the same matrix
+// (the correction solves of the refinement): each step then only reads them
+// and updates the carry column and the right-hand side.
+template <typename T, int R, int MM, bool kLds, int GW, bool kReuse = false>
+__device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T, R, MM>& st, T* bcast,
+                                          float4* rot = nullptr) {
+  constexpr bool kRot = std::is_same<T, float>::value;
+  static_assert(kRot || !kReuse, "only the float32 sweeps reuse their rotations");
   const int lane = threadIdx.x & 63;
   const int g = lane / GW, gl = lane & (GW - 1);
   T* mine = bcast + g * (2 + 2 * MM);
-  st.singular = false;
+  if constexpr (!kReuse) st.singular = false;
   {
     const int off = hoff32(n - 1);
 #pragma unroll
@@ -174,21 +185,28 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  T par, pai, pbr[MM], pbi[MM];
-  auto publish = [&](auto TT, int j) {
+  T par = (T)0, pai = (T)0, pbr[MM], pbi[MM];
+  // the lane of row j of slice t publishes it (and `extra`, the rotation of
+  // the step that made it the next pivot)
+  auto publish = [&](auto TT, int j, auto&& extra) {
     constexpr int t = decltype(TT)::value;
     if (gl == j) {
-      mine[0] = st.cr[t];
-      mine[1] = st.ci[t];
+      if constexpr (!kReuse) {
+        mine[0] = st.cr[t];
+        mine[1] = st.ci[t];
+      }
 #pragma unroll
       for (int jj = 0; jj < MM; ++jj) {
         mine[2 + 2 * jj] = st.br[t][jj];
         mine[3 + 2 * jj] = st.bi[t][jj];
       }
+      extra();
     }
     lds_order();
-    par = mine[0];
-    pai = mine[1];
+    if constexpr (!kReuse) {
+      par = mine[0];
+      pai = mine[1];
+    }
   };
   auto read_rhs = [&] {
     lds_order();
@@ -201,7 +219,7 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
   // row n-1 is the first pivot
   static_for<0, R>([&](auto TT) {
     constexpr int t = decltype(TT)::value;
-    if ((n - 1) / GW == t) publish(TT, (n - 1) & (GW - 1));
+    if ((n - 1) / GW == t) publish(TT, (n - 1) & (GW - 1), [] {});
   });
   read_rhs();
 
@@ -225,21 +243,30 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
       for (int t = 0; t <= s; ++t) hn[t] = (T)0;
     }
     const T sub2 = (k >= 3) ? H.uniform(hoff32(k - 3) + k - 2) : (T)0;
-    const T beta = -sub0;
-    const T nrm2 = par * par + pai * pai + beta * beta;
-    const bool ok = nrm2 > (T)0;
-    const T rq = rsqrt_t(ok ? nrm2 : (T)1);
-    // zero column (ok false, then par = pai = beta = 0): a zero rotation and
-    // R(k,k) = 0; the frequency is flagged singular
-    const T rinv = ok ? rq : (T)INFINITY;
-    const T c = beta * rq;
-    const T sr = par * rq;
-    const T si = pai * rq;
-    st.singular = st.singular || !ok;
+    T c, sr, si, rinv;
+    if constexpr (kReuse) {
+      const float4 rt = rot[k];
+      c = rt.x;
+      sr = rt.y;
+      si = rt.z;
+      rinv = rt.w;
+    } else {
+      const T beta = -sub0;
+      const T nrm2 = par * par + pai * pai + beta * beta;
+      const bool ok = nrm2 > (T)0;
+      const T rq = rsqrt_t(ok ? nrm2 : (T)1);
+      // zero column (ok false, then par = pai = beta = 0): a zero rotation
+      // and R(k,k) = 0; the frequency is flagged singular
+      rinv = ok ? rq : (T)INFINITY;
+      c = beta * rq;
+      sr = par * rq;
+      si = pai * rq;
+      st.singular = st.singular || !ok;
+    }
     const T cw = c * w, sw_r = sr * w, sw_i = si * w;
     // rows of slice t below k: rotate the carry column with column k-1, then
     // b_i -= (R(i,k) / R(k,k)) b_k
-    auto rot = [&](auto TT) {
+    auto rot_slice = [&](auto TT) {
       constexpr int t = decltype(TT)::value;
       if (t < s || gl < jl) {
         const T cr_ = st.cr[t], ci_ = st.ci[t];
@@ -270,15 +297,19 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
         }
       }
     };
-    rot(SP);
-    publish(SP, (k - 1) & (GW - 1));
+    rot_slice(SP);
+    publish(SP, (k - 1) & (GW - 1), [&] {
+      if constexpr (kRot && !kReuse) rot[k] = make_float4(c, sr, si, rinv);
+    });
     // the other slices (for jl = 0, slice s holds no row below k)
-    static_for<0, sp>([&](auto TT) { rot(TT); });
-    if (gl == jl) {
-      st.rc[s] = c;
-      st.rsr[s] = sr;
-      st.rsi[s] = si;
-      st.rinv[s] = rinv;
+    static_for<0, sp>([&](auto TT) { rot_slice(TT); });
+    if constexpr (!kRot) {
+      if (gl == jl) {
+        st.rc[s] = c;
+        st.rsr[s] = sr;
+        st.rsi[s] = si;
+        st.rinv[s] = rinv;
+      }
     }
     read_rhs();
 #pragma unroll
@@ -312,10 +343,17 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
         st.bi[0][j] = (xi * ar - xr * ai) * dinv;
       }
     } else {
+      T ri;
+      if constexpr (kRot) {
+        const float rv = rot[i].w;  // rows n.. hold no rotation of this sweep
+        ri = (i < n) ? rv : (T)1;
+      } else {
+        ri = st.rinv[r];
+      }
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
-        st.br[r][j] *= st.rinv[r];
-        st.bi[r][j] *= st.rinv[r];
+        st.br[r][j] *= ri;
+        st.bi[r][j] *= ri;
       }
     }
   }
@@ -343,9 +381,11 @@ __device__ __forceinline__ double diag_ratio_grp(int n, const SG<T, R, MM>& st) 
 }
 
 // x := Z y in place (scan of t_k = -c_k t_{k-1} + conj(s_k) y_k within each
-// group, slice by slice).
+// group, slice by slice).  The rotations come from the LDS table (float32)
+// or from the registers of their rows (float64).
 template <typename T, int R, int MM, int GW>
-__device__ __forceinline__ void apply_rotations_grp(int n, SG<T, R, MM>& st) {
+__device__ __forceinline__ void apply_rotations_grp(int n, SG<T, R, MM>& st, const float4* rot = nullptr) {
+  constexpr bool kRot = std::is_same<T, float>::value;
   const int gl = threadIdx.x & (GW - 1);
   T tinr[MM], tini[MM];
 #pragma unroll
@@ -361,7 +401,24 @@ __device__ __forceinline__ void apply_rotations_grp(int n, SG<T, R, MM>& st) {
     if (GW * r >= n) break;
     const int i = gl + GW * r;
     const bool inner = (i > 0 && i < n);
-    T a = inner ? -st.rc[r] : (T)0;
+    // rotation i of row i and rotation i+1 of the next row (table entries of
+    // rows 0 and n.. are not this sweep's; they are not used)
+    T rc_, rsr_, rsi_, nc, nsr, nsi;
+    if constexpr (kRot) {
+      const float4 cur = rot[i];
+      const float4 nx = rot[(i + 1 < GW * R) ? i + 1 : i];
+      rc_ = cur.x;
+      rsr_ = cur.y;
+      rsi_ = cur.z;
+      nc = nx.x;
+      nsr = nx.y;
+      nsi = nx.z;
+    } else {
+      rc_ = st.rc[r];
+      rsr_ = st.rsr[r];
+      rsi_ = st.rsi[r];
+    }
+    T a = inner ? -rc_ : (T)0;
     constexpr int NQ = (GW == 32) ? 5 : 4;
     T am[NQ];
 #pragma unroll
@@ -377,31 +434,33 @@ __device__ __forceinline__ void apply_rotations_grp(int n, SG<T, R, MM>& st) {
     }
     // rotation of row i+1 (lane 0 of the next slice for the group's last
     // lane; in a 32-lane group, lane 0 of the odd row for lane 15)
-    T nc = dpp<dpp_row_shl(1)>(st.rc[r]);
-    T nsr = dpp<dpp_row_shl(1)>(st.rsr[r]);
-    T nsi = dpp<dpp_row_shl(1)>(st.rsi[r]);
-    if constexpr (GW == 32) {
-      const T c1 = lane0_of_odd(st.rc[r]);
-      const T s1r = lane0_of_odd(st.rsr[r]);
-      const T s1i = lane0_of_odd(st.rsi[r]);
-      if (gl == 15) {
-        nc = c1;
-        nsr = s1r;
-        nsi = s1i;
-      }
-    }
     const int rn = (r + 1 < R) ? r + 1 : r;
-    if (r + 1 < R) {
-      const T c0 = group_bcast<GW, false>(st.rc[rn]);
-      const T s0r = group_bcast<GW, false>(st.rsr[rn]);
-      const T s0i = group_bcast<GW, false>(st.rsi[rn]);
-      if (gl == GW - 1) {
-        nc = c0;
-        nsr = s0r;
-        nsi = s0i;
+    if constexpr (!kRot) {
+      nc = dpp<dpp_row_shl(1)>(st.rc[r]);
+      nsr = dpp<dpp_row_shl(1)>(st.rsr[r]);
+      nsi = dpp<dpp_row_shl(1)>(st.rsi[r]);
+      if constexpr (GW == 32) {
+        const T c1 = lane0_of_odd(st.rc[r]);
+        const T s1r = lane0_of_odd(st.rsr[r]);
+        const T s1i = lane0_of_odd(st.rsi[r]);
+        if (gl == 15) {
+          nc = c1;
+          nsr = s1r;
+          nsi = s1i;
+        }
+      }
+      if (r + 1 < R) {
+        const T c0 = group_bcast<GW, false>(st.rc[rn]);
+        const T s0r = group_bcast<GW, false>(st.rsr[rn]);
+        const T s0i = group_bcast<GW, false>(st.rsi[rn]);
+        if (gl == GW - 1) {
+          nc = c0;
+          nsr = s0r;
+          nsi = s0i;
+        }
       }
     }
-    const T sr = st.rsr[r], si = st.rsi[r];
+    const T sr = rsr_, si = rsi_;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       const T yr = st.br[r][j], yi = st.bi[r][j];
@@ -642,7 +701,7 @@ __device__ __forceinline__ void residual_grp(const ReqDesc& rd, Src<double, kLds
 // all have stopped.
 template <int R, int MM, bool kL64, bool kL32, int GW>
 __device__ void solve_grp_refined(const ReqDesc& rd, Src<double, kL64> H, Src<float, kL32> H32, int64_t k,
-                                  bool valid, int j0, int mc, double* bcast64) {
+                                  bool valid, int j0, int mc, double* bcast64, float4* rot) {
   const int gl = threadIdx.x & (GW - 1);
   const int n = rd.n, m = rd.m;
   const SPoint sp = point_of(rd, k);
@@ -663,8 +722,8 @@ __device__ void solve_grp_refined(const ReqDesc& rd, Src<double, kL64> H, Src<fl
       st.bi[r][j] = 0.0f;
     }
   }
-  sweep_grp<float, R, MM, kL32, GW>(H32, n, sgf, wf, st, bcast);
-  apply_rotations_grp<float, R, MM, GW>(n, st);
+  sweep_grp<float, R, MM, kL32, GW>(H32, n, sgf, wf, st, bcast, rot);
+  apply_rotations_grp<float, R, MM, GW>(n, st, rot);
   double s2 = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -703,8 +762,8 @@ __device__ void solve_grp_refined(const ReqDesc& rd, Src<double, kL64> H, Src<fl
         st.br[r][j] = (float)(rr[r][j] * scale);
         st.bi[r][j] = (float)(ri[r][j] * scale);
       }
-    sweep_grp<float, R, MM, kL32, GW>(H32, n, sgf, wf, st, bcast);
-    apply_rotations_grp<float, R, MM, GW>(n, st);
+    sweep_grp<float, R, MM, kL32, GW, true>(H32, n, sgf, wf, st, bcast, rot);
+    apply_rotations_grp<float, R, MM, GW>(n, st, rot);
     double d2 = 0.0, x2 = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -756,7 +815,7 @@ constexpr int hlen_max(int R, int GW) { return (GW * R - 1) * (GW * R + 2) / 2 +
 
 template <int PREC, int R, int MM, bool kL64, bool kL32, int GW>
 __device__ __forceinline__ void run_tile_grp(const ReqDesc& rd, const Tile& td, Src<double, kL64> H,
-                                             Src<float, kL32> H32, double* bcast) {
+                                             Src<float, kL32> H32, double* bcast, float4* rot) {
   constexpr int NG = 64 / GW;
   const int g = (threadIdx.x & 63) / GW;
   for (uint32_t f0 = 0; f0 < td.count; f0 += NG) {
@@ -768,7 +827,7 @@ __device__ __forceinline__ void run_tile_grp(const ReqDesc& rd, const Tile& td, 
     if constexpr (PREC == LTI_PREC_FP64)
       solve_grp_fp64<R, MM, kL64, GW>(rd, H, k, valid, td.j0, td.mc, bcast);
     else
-      solve_grp_refined<R, MM, kL64, kL32, GW>(rd, H, H32, k, valid, td.j0, td.mc, bcast);
+      solve_grp_refined<R, MM, kL64, kL32, GW>(rd, H, H32, k, valid, td.j0, td.mc, bcast, rot);
   }
 }
 
@@ -784,6 +843,8 @@ __device__ __forceinline__ void sweep_grp_body(const SweepLaunch& L) {
   __shared__ double bcast_all[kWaves16][(64 / GW) * (2 + 2 * MM)];
   __shared__ double sH[kStage64 ? hlen_max(R, GW) : 1];
   __shared__ float sH32[kStage32 ? hlen_max(R, GW) : 1];
+  // the refined sweeps' rotation tables, one per frequency of each wavefront
+  __shared__ float4 rot_all[kStage32 ? kWaves16 * (64 / GW) : 1][kStage32 ? GW * R : 1];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tb = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves16;  // < ntiles
   const int tile = tb + wave;
@@ -807,14 +868,16 @@ __device__ __forceinline__ void sweep_grp_body(const SweepLaunch& L) {
   const ReqDesc rd = L.seg[s].rd;
   const Tile td = tile_of(L.seg[s], tile);
   double* bcast = bcast_all[wave];
+  float4* rot = kStage32 ? rot_all[wave * (64 / GW) + (threadIdx.x & 63) / GW] : nullptr;
   if (staged) {
     if constexpr (kStage64)
-      run_tile_grp<PREC, R, MM, true, true, GW>(rd, td, Src<double, true>{sH}, Src<float, true>{sH32}, bcast);
+      run_tile_grp<PREC, R, MM, true, true, GW>(rd, td, Src<double, true>{sH}, Src<float, true>{sH32}, bcast, rot);
     else
-      run_tile_grp<PREC, R, MM, false, true, GW>(rd, td, Src<double, false>{rd.H}, Src<float, true>{sH32}, bcast);
+      run_tile_grp<PREC, R, MM, false, true, GW>(rd, td, Src<double, false>{rd.H}, Src<float, true>{sH32}, bcast,
+                                                 rot);
   } else {
     run_tile_grp<PREC, R, MM, false, false, GW>(rd, td, Src<double, false>{rd.H}, Src<float, false>{rd.H32},
-                                                bcast);
+                                                bcast, rot);
   }
 }
 
@@ -827,7 +890,7 @@ __device__ __forceinline__ void sweep_grp_body(const SweepLaunch& L) {
 // they would spill up to 740 bytes per lane).
 template <int PREC, int R, int MM>
 __global__ __launch_bounds__(64 * kWaves16)
-__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? 3 : 1))) void sweep16_kernel(const SweepLaunch L) {
+__attribute__((amdgpu_waves_per_eu(3))) void sweep16_kernel(const SweepLaunch L) {
   sweep_grp_body<PREC, R, MM, 16>(L);
 }
 
@@ -837,7 +900,7 @@ __attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? 3 : 1))) void sweep16
 // registers, as are the refined ones (two wavefronts per SIMD).
 template <int PREC, int R, int MM>
 __global__ __launch_bounds__(64 * kWaves16)
-__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 && R < 4 ? 3 : 2))) void sweep32_kernel(const SweepLaunch L) {
+__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 && R == 4 ? 2 : 3))) void sweep32_kernel(const SweepLaunch L) {
   sweep_grp_body<PREC, R, MM, 32>(L);
 }
 

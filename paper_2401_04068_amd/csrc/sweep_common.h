@@ -159,7 +159,11 @@ __device__ __forceinline__ float readlane(float v, int l) {
 }
 
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
-__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+// float32 (the refined path's solves, which its float64 residuals check):
+// the hardware reciprocal square root (1 ulp), with the input held at the
+// smallest normal number instead of the library's rescaling of denormal
+// inputs, which the instruction does not take.
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(fmaxf(x, FLT_MIN)); }
 
 __device__ __forceinline__ int hoff32(int j) { return j * (j + 3) / 2; }
 
