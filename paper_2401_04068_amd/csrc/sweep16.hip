@@ -281,8 +281,13 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
         T n1i = si * o - c * ci_;
         if constexpr (t == sp) {
           nki = fma(d, cw, nki);
-          n1r = fma(-d, sw_i, n1r);
-          n1i = fma(d, sw_r, n1i);
+          // row k-1's new carry entry only matters as the next pivot (whose
+          // rotation a reusing sweep reads from the table) and, for k = 1,
+          // as R(0,0) (which the table keeps too)
+          if constexpr (!kReuse) {
+            n1r = fma(-d, sw_i, n1r);
+            n1i = fma(d, sw_r, n1i);
+          }
         }
         st.cr[t] = n1r;
         st.ci[t] = n1i;
@@ -326,9 +331,20 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
     for (int jl = jhi; jl >= 1; --jl) step(SC{}, SC{}, jl);
     if constexpr (s >= 1) step(SC{}, std::integral_constant<int, s - 1>{}, 0);
   });
-  // y_k = b_k / R(k,k); R(0,0) is the final carry entry of row 0
-  const T ar = group_bcast<GW, false>(st.cr[0]);
-  const T ai = group_bcast<GW, false>(st.ci[0]);
+  // y_k = b_k / R(k,k); R(0,0) is the final carry entry of row 0 (kept in
+  // the table's unused entry 0 for the sweeps that reuse the rotations)
+  T ar, ai;
+  if constexpr (kReuse) {
+    const float4 r00 = rot[0];
+    ar = r00.x;
+    ai = r00.y;
+  } else {
+    ar = group_bcast<GW, false>(st.cr[0]);
+    ai = group_bcast<GW, false>(st.ci[0]);
+    if constexpr (kRot) {
+      if (gl == 0) rot[0] = make_float4(ar, ai, 0.0f, 0.0f);
+    }
+  }
   const T d = ar * ar + ai * ai;
   st.singular = st.singular || !(d > (T)0);
   const T dinv = (T)1 / d;
@@ -833,18 +849,19 @@ __device__ __forceinline__ void run_tile_grp(const ReqDesc& rd, const Tile& td, 
 
 // The reduced model's H is staged in LDS when the workgroup's four tiles
 // belong to one request, which they do except where two requests meet in a
-// launch: both copies of H for the 16-lane kernels, for the 32-lane kernels
-// (n <= 128) only the copy their sweeps read (the float32 one on the
-// refined path, whose float64 residuals read H from global memory).
+// launch: both copies of H up to 64 states, above that only the copy the
+// sweeps read (the float32 one on the refined path, whose float64
+// residuals read H from global memory).
 template <int PREC, int R, int MM, int GW>
 __device__ __forceinline__ void sweep_grp_body(const SweepLaunch& L) {
-  constexpr bool kStage64 = GW == 16 || PREC == LTI_PREC_FP64;
+  constexpr bool kStage64 = PREC == LTI_PREC_FP64 || GW * R <= 64;
   constexpr bool kStage32 = PREC != LTI_PREC_FP64;
+  constexpr bool kRotTab = PREC != LTI_PREC_FP64;
   __shared__ double bcast_all[kWaves16][(64 / GW) * (2 + 2 * MM)];
   __shared__ double sH[kStage64 ? hlen_max(R, GW) : 1];
   __shared__ float sH32[kStage32 ? hlen_max(R, GW) : 1];
   // the refined sweeps' rotation tables, one per frequency of each wavefront
-  __shared__ float4 rot_all[kStage32 ? kWaves16 * (64 / GW) : 1][kStage32 ? GW * R : 1];
+  __shared__ float4 rot_all[kRotTab ? kWaves16 * (64 / GW) : 1][kRotTab ? GW * R : 1];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tb = xcd_swizzle(blockIdx.x, gridDim.x) * kWaves16;  // < ntiles
   const int tile = tb + wave;
@@ -868,10 +885,13 @@ __device__ __forceinline__ void sweep_grp_body(const SweepLaunch& L) {
   const ReqDesc rd = L.seg[s].rd;
   const Tile td = tile_of(L.seg[s], tile);
   double* bcast = bcast_all[wave];
-  float4* rot = kStage32 ? rot_all[wave * (64 / GW) + (threadIdx.x & 63) / GW] : nullptr;
-  if (staged) {
-    if constexpr (kStage64)
+  float4* rot = kRotTab ? rot_all[wave * (64 / GW) + (threadIdx.x & 63) / GW] : nullptr;
+  if (staged && (kStage64 || kStage32)) {
+    if constexpr (kStage64 && kStage32)
       run_tile_grp<PREC, R, MM, true, true, GW>(rd, td, Src<double, true>{sH}, Src<float, true>{sH32}, bcast, rot);
+    else if constexpr (kStage64)
+      run_tile_grp<PREC, R, MM, true, false, GW>(rd, td, Src<double, true>{sH}, Src<float, false>{rd.H32}, bcast,
+                                                 rot);
     else
       run_tile_grp<PREC, R, MM, false, true, GW>(rd, td, Src<double, false>{rd.H}, Src<float, true>{sH32}, bcast,
                                                  rot);
