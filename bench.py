@@ -367,29 +367,35 @@ def serving_headline(args, out):
             log(f"{name}: {res[name]['points_per_s_raw'] / 1e6:.2f} M points/s, max err {worst:.2e}")
         del mix
         torch.cuda.empty_cache()
-        # open loop: host-memory requests at their Poisson arrival times
-        for r in reqs[:16]:
-            eng.wait(eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED))
-        handles = []
-        t0 = time.perf_counter()
-        for r, ta in zip(reqs, arrivals):
-            now = time.perf_counter() - t0
-            if ta > now:
-                time.sleep(ta - now)
-            lag = max(0.0, time.perf_counter() - t0 - ta)
-            handles.append((eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED), lag))
-        for h, _ in handles:
-            eng.wait(h)
-        t_open = time.perf_counter() - t0
-        lat = [lag + (h.result["t_done_us"] - h.result["t_submit_us"]) * 1e-6 for h, lag in handles]
-        rs = [h.result for h, _ in handles]
-        open_loop = {
-            "wall_s": t_open,
-            "latency_ms": _pct(lat),
-            "queue_ms": _pct([(x["t_admit_us"] - x["t_submit_us"]) * 1e-6 for x in rs]),
-            "run_ms": _pct([(x["t_done_us"] - x["t_first_launch_us"]) * 1e-6 for x in rs]),
-        }
-        del handles
+        # open loop: host-memory requests at their Poisson arrival times.  The
+        # trace is replayed twice and the second replay reported: the first
+        # one pays the process's first touches of the host result arrays
+        # (page faults that delay the submitting thread by milliseconds).
+        def replay():
+            handles = []
+            t0 = time.perf_counter()
+            for r, ta in zip(reqs, arrivals):
+                now = time.perf_counter() - t0
+                if ta > now:
+                    time.sleep(ta - now)
+                lag = max(0.0, time.perf_counter() - t0 - ta)
+                handles.append((eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED), lag))
+            for h, _ in handles:
+                eng.wait(h)
+            t_open = time.perf_counter() - t0
+            lat = [lag + (h.result["t_done_us"] - h.result["t_submit_us"]) * 1e-6 for h, lag in handles]
+            rs = [h.result for h, _ in handles]
+            return {
+                "wall_s": t_open,
+                "latency_ms": _pct(lat),
+                "submit_lag_ms": _pct([lag for _, lag in handles]),
+                "queue_ms": _pct([(x["t_admit_us"] - x["t_submit_us"]) * 1e-6 for x in rs]),
+                "run_ms": _pct([(x["t_done_us"] - x["t_first_launch_us"]) * 1e-6 for x in rs]),
+            }
+
+        cold = replay()
+        open_loop = replay()
+        open_loop["first_replay"] = cold
         # closed loop from host memory (H2D and D2H inside the timed region)
         t0 = time.perf_counter()
         hs = [eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED) for r in reqs]

@@ -1370,6 +1370,7 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   c->batch_tiles = cfg->max_batch_tiles > 0 ? cfg->max_batch_tiles : kDefaultBatchTiles;
   // debug knobs for tuning sweeps (not part of the ABI)
   if (const char* e = std::getenv("LTI_FREQRESP_RHS_SPLIT")) c->rhs_split = std::atoi(e);
+  if (const char* e = std::getenv("LTI_FREQRESP_TILE_POINTS")) c->tile_points = std::max(0, std::atoi(e));
   if (const char* e = std::getenv("LTI_FREQRESP_TARGET_TILES")) c->target_tiles = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("LTI_FREQRESP_STAGE_LDS")) c->stage_lds = std::atoi(e) != 0;
   if (const char* e = std::getenv("LTI_FREQRESP_SWEEP16")) c->use_sweep16 = std::atoi(e) != 0;

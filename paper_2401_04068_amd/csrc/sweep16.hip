@@ -901,26 +901,24 @@ __device__ __forceinline__ void sweep_grp_body(const SweepLaunch& L) {
   }
 }
 
-// The float64 kernels use at most 168 registers per lane (three wavefronts
-// per SIMD, and room for a reduction workgroup beside two sweep wavefronts):
-// a launch that carries several requests has more wavefronts than two per
-// SIMD.  The four-column kernels then keep a few values of their set-up,
-// slice change and output phases in scratch memory, none in the step loops.
-// The refined kernels keep their full register sets (capped the same way,
-// they would spill up to 740 bytes per lane).
+// Occupancy: waves per SIMD, which the register caps buy with a few spills
+// outside the step loops (measured on the serving mix: three waves beat two
+// by about 8 % refined, four beat three by about 4 % where LDS leaves room).
+//   * float64: three (168 registers), except the 32-lane kernels up to 128
+//     states, whose 67 KB of staged H leave room for two (256 registers);
+//   * refined: four (128 registers) up to 32 (16-lane) or 96 (32-lane)
+//     states, three above (33-64 and 97-128 states), where the staged H and
+//     the rotation tables take 42-50 KB of LDS per workgroup.
 template <int PREC, int R, int MM>
 __global__ __launch_bounds__(64 * kWaves16)
-__attribute__((amdgpu_waves_per_eu(3))) void sweep16_kernel(const SweepLaunch L) {
+__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 || R == 4 ? 3 : 4))) void sweep16_kernel(const SweepLaunch L) {
   sweep_grp_body<PREC, R, MM, 16>(L);
 }
 
-// The 32-lane kernels: the float64 ones up to 96 states are capped like the
-// 16-lane ones; with up to 128 states they stage 67 KB of LDS per workgroup,
-// which leaves room for two wavefronts per SIMD, and are held to 256
-// registers, as are the refined ones (two wavefronts per SIMD).
 template <int PREC, int R, int MM>
 __global__ __launch_bounds__(64 * kWaves16)
-__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 && R == 4 ? 2 : 3))) void sweep32_kernel(const SweepLaunch L) {
+__attribute__((amdgpu_waves_per_eu(PREC == LTI_PREC_FP64 ? (R == 4 ? 2 : 3) : (R == 4 ? 3 : 4)))) void sweep32_kernel(
+    const SweepLaunch L) {
   sweep_grp_body<PREC, R, MM, 32>(L);
 }
 
