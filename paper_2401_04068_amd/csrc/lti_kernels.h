@@ -97,8 +97,8 @@ constexpr int kMaxReduceN = 1024;
 // Reduction kernel classes: 0 .. kNumRegClasses-1 keep the working matrix in
 // registers (class S-1 for S = ceil(max(n+p, n+m) / 16) <= 9, n <= 128);
 // kReduceGlobal keeps it in a global scratch area (one workgroup per model);
-// kReduceBlocked runs the blocked reduction over the whole GPU, one model at a
-// time (reduce_blocked.hip).
+// kReduceBlocked runs the blocked reduction over the whole GPU, up to eight
+// models in each launch of its kernel sequence (reduce_blocked.hip).
 constexpr int kMaxRegReduceN = 128;
 constexpr int kNumRegClasses = 9;
 constexpr int kReduceGlobal = kNumRegClasses;       // 128 < n <= kMaxGlobalReduceN
@@ -114,9 +114,9 @@ int reduce_class(int n, int m, int p);
 // Global scratch bytes a job of this shape needs (0 for register classes).
 size_t reduce_work_bytes(int n, int m, int p);
 size_t reduce_blocked_work_bytes(int n, int m, int p);
-hipError_t launch_reduce_blocked(const ReduceJob& job, hipStream_t s);
+hipError_t launch_reduce_blocked(const ReduceJob* jobs, int njobs, hipStream_t s);
 // The reduction jobs of one class in one launch, one workgroup per job (the
-// blocked class runs its jobs one after another): `jobs` is a table in device
+// blocked class: one kernel sequence per eight jobs): `jobs` is a table in device
 // memory, uploaded with the pass that queued them.  `host_jobs` is the same
 // table in host memory (the blocked class reads its jobs from there).
 struct ReduceLaunch {

@@ -582,11 +582,7 @@ hipError_t launch_reduce(const ReduceLaunch& L, int rclass, hipStream_t s) {
     case kReduceHT:
       return launch_reduce_ht(L, s);
     case kReduceBlocked:
-      for (int i = 0; i < L.njobs; ++i) {
-        const hipError_t e = launch_reduce_blocked(L.host_jobs[i], s);
-        if (e != hipSuccess) return e;
-      }
-      return hipSuccess;
+      return launch_reduce_blocked(L.host_jobs, L.njobs, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -76,12 +76,22 @@ __host__ __device__ inline BlkLayout blk_layout(int n, int m, int p) {
   return L;
 }
 
+// Up to kBlkBatch models per launch, model z on blockIdx.z: the per-column
+// kernels are latency chains that use a few CUs, so the models of one
+// admission pass run them side by side.  Models of different sizes share the
+// column loop of the largest; a model's kernels return once its own panel
+// (or column) range is done.
+constexpr int kBlkBatch = 8;
 struct BlkArgs {
-  ReduceJob job;
-  int k;    // first column of the panel
-  int nbk;  // panel width
-  int j;    // column within the panel
+  ReduceJob job[kBlkBatch];
+  int k;  // first column of the panel
+  int j;  // column within the panel
 };
+static_assert(sizeof(BlkArgs) <= 3072, "blocked reduction arguments must stay small");
+
+// Width of the panel starting at column k of an n-state model (<= 0 once
+// its last reflector, column n-3, is done).
+__host__ __device__ inline int blk_nbk(int n, int k) { return (kNB < n - 2 - k) ? kNB : n - 2 - k; }
 
 struct Blk {
   int n, m, p, N, C;
@@ -110,9 +120,10 @@ struct Blk {
 // The solved system is also kept as given (A0, B0, C0) for the extended
 // refinement.
 __global__ __launch_bounds__(256) void blk_load(const BlkArgs a) {
-  const Blk b(a.job);
-  const ModelIn in(a.job);
-  const ReducedModel& o = a.job.out;
+  const ReduceJob& job = a.job[blockIdx.z];
+  const Blk b(job);
+  const ModelIn in(job);
+  const ReducedModel& o = job.out;
   const size_t total = (size_t)b.L.ldm * b.C;
   for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
     const int i = (int)(idx % b.L.ldm);
@@ -142,9 +153,11 @@ __global__ __launch_bounds__(kPThreads) void blk_panel(const BlkArgs a) {
   __shared__ double red[kNB];                      // u, then w
   __shared__ double zz[kNB];                       // T^T u
   __shared__ double sc[4];                         // beta, tau, scale
-  const Blk B(a.job);
+  const ReduceJob& job = a.job[blockIdx.z];
+  const Blk B(job);
   const int n = B.n, N = B.N, ldv = B.L.ldv, ldm = B.L.ldm;
   const int k = a.k, j = a.j, c = k + j;
+  if (j >= blk_nbk(n, k)) return;  // this model's columns are done (uniform)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int kWavesP = kPThreads / 64;
 
@@ -218,11 +231,11 @@ __global__ __launch_bounds__(kPThreads) void blk_panel(const BlkArgs a) {
   for (int i = k + 1 + tid; i < n; i += kPThreads) {
     const double vi = (i <= c) ? 0.0 : (i == c + 1) ? 1.0 : bv[i] * scale;
     B.V[(size_t)j * ldv + i] = vi;
-    if (i >= c + 2) a.job.out.V[vo + i] = vi;
+    if (i >= c + 2) job.out.V[vo + i] = vi;
   }
   if (tid == 0) {
     B.tau[j] = tau;
-    a.job.out.tau[c] = tau;
+    job.out.tau[c] = tau;
   }
   __syncthreads();
   if (j > 0) {
@@ -259,9 +272,11 @@ __global__ __launch_bounds__(kPThreads) void blk_panel(const BlkArgs a) {
 __global__ __launch_bounds__(256) void blk_rows(const BlkArgs a) {
   __shared__ double red[16][kRows + 1];
   __shared__ double sb[kRows];
-  const Blk B(a.job);
+  const Blk B(a.job[blockIdx.z]);
   const int n = B.n, ldm = B.L.ldm, ldv = B.L.ldv;
   const int k = a.k, j = a.j, c = k + j;
+  const int nbk = blk_nbk(n, k);
+  if (j >= nbk || (int)blockIdx.x >= B.L.nrb) return;  // uniform
   const int tid = threadIdx.x, r = tid & (kRows - 1), cl = tid >> 4;  // row, column lane
   const int i = blockIdx.x * kRows + r;  // < ldm
   const double* vj = B.V + (size_t)j * ldv;
@@ -297,7 +312,7 @@ __global__ __launch_bounds__(256) void blk_rows(const BlkArgs a) {
       if (l < j) y = fma(-yr[l], B.w[l], y);
     y *= B.tau[j];
     B.Y[(size_t)j * ldm + i] = y;
-    if (j + 1 < a.nbk) {
+    if (j + 1 < nbk) {
       const int c1 = c + 1;
       double x = B.M[(size_t)c1 * ldm + i];
 #pragma unroll
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(256) void blk_rows(const BlkArgs a) {
       sb[r] = (i > k && i < n) ? x : 0.0;
     }
   }
-  if (j + 1 >= a.nbk) return;  // uniform
+  if (j + 1 >= nbk) return;  // uniform
   __syncthreads();
   // partial V^T b for l = 0 .. j over this block's rows
   for (int l = tid; l <= j; l += 256) {
@@ -333,10 +348,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void blk_right(const BlkArgs a) {
   __shared__ double sY[kNB][kRowBlock + 1];
   __shared__ double sV[kNB][kRowBlock + 1];
-  const Blk B(a.job);
+  const Blk B(a.job[blockIdx.z]);
   const int n = B.n, ldm = B.L.ldm, ldv = B.L.ldv;
-  const int nbk = a.nbk, cstart = a.k + nbk;
+  const int nbk = blk_nbk(n, a.k), cstart = a.k + nbk;
   const int r0 = blockIdx.x * kRowBlock, cc0 = cstart + blockIdx.y * 64;
+  if (nbk <= 0 || r0 >= ldm || cc0 >= n) return;  // uniform
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kNB * kRowBlock; idx += 256) {
     const int l = idx / kRowBlock, r = idx % kRowBlock;
@@ -382,10 +398,11 @@ __global__ __launch_bounds__(256) void blk_left(const BlkArgs a) {
   __shared__ double sV[kRowBlock][kNB + 1];
   __shared__ double sM[kRowBlock][kLeftCols + 1];
   __shared__ double sW[4][kNB][kLeftCols + 1];
-  const Blk B(a.job);
+  const Blk B(a.job[blockIdx.z]);
   const int n = B.n, C = B.C, ldm = B.L.ldm, ldv = B.L.ldv;
-  const int nbk = a.nbk, k = a.k;
+  const int k = a.k, nbk = blk_nbk(n, k);
   const int col0 = k + nbk + blockIdx.x * kLeftCols;
+  if (nbk <= 0 || col0 >= C) return;  // uniform
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
@@ -457,9 +474,10 @@ __global__ __launch_bounds__(256) void blk_left(const BlkArgs a) {
 }
 
 __global__ __launch_bounds__(256) void blk_store(const BlkArgs a) {
-  const Blk B(a.job);
+  const ReduceJob& job = a.job[blockIdx.z];
+  const Blk B(job);
   const int n = B.n, m = B.m, p = B.p, ldm = B.L.ldm;
-  const ReducedModel& o = a.job.out;
+  const ReducedModel& o = job.out;
   const size_t gsz = (size_t)gridDim.x * 256, t0 = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t nh = (size_t)hlen(n);
   for (size_t idx = t0; idx < nh; idx += gsz) {
@@ -484,7 +502,7 @@ __global__ __launch_bounds__(256) void blk_store(const BlkArgs a) {
     o.Ct[idx] = x;
     o.Ct32[idx] = (float)x;
   }
-  const ModelIn in(a.job);
+  const ModelIn in(job);
   for (size_t idx = t0; idx < (size_t)p * m; idx += gsz) o.D[idx] = in.d((int)(idx / m), (int)(idx % m));
 }
 
@@ -492,32 +510,50 @@ __global__ __launch_bounds__(256) void blk_store(const BlkArgs a) {
 
 size_t reduce_blocked_work_bytes(int n, int m, int p) { return blk_layout(n, m, p).total * sizeof(double); }
 
-hipError_t launch_reduce_blocked(const ReduceJob& job, hipStream_t s) {
-  const int n = job.out.n, m = job.out.m, p = job.out.p;
-  if (n > kMaxReduceN || !job.work) return hipErrorInvalidValue;
-  const BlkLayout Lo = blk_layout(n, m, p);
-  BlkArgs a{job, 0, 0, 0};
-  const int C = n + m;
-  const int load_blocks = (int)std::min<size_t>(2048, ((size_t)Lo.ldm * C + 255) / 256);
-  blk_load<<<load_blocks, 256, 0, s>>>(a);
-  for (int k = 0; k + 2 < n; k += kNB) {
-    const int nbk = std::min(kNB, n - 2 - k);
-    a.k = k;
-    a.nbk = nbk;
-    for (int j = 0; j < nbk; ++j) {
-      a.j = j;
-      blk_panel<<<1, kPThreads, 0, s>>>(a);
-      blk_rows<<<Lo.nrb, 256, 0, s>>>(a);
+hipError_t launch_reduce_blocked(const ReduceJob* jobs, int njobs, hipStream_t s) {
+  for (int g0 = 0; g0 < njobs; g0 += kBlkBatch) {
+    const int nj = std::min(kBlkBatch, njobs - g0);
+    BlkArgs a{};
+    int nmax = 0, ldm_max = 0, nrb_max = 0;
+    size_t load_max = 0, store_max = 0;
+    for (int z = 0; z < nj; ++z) {
+      const ReduceJob& job = jobs[g0 + z];
+      const int n = job.out.n, m = job.out.m, p = job.out.p;
+      if (n > kMaxReduceN || !job.work) return hipErrorInvalidValue;
+      a.job[z] = job;
+      const BlkLayout Lo = blk_layout(n, m, p);
+      nmax = std::max(nmax, n);
+      ldm_max = std::max(ldm_max, Lo.ldm);
+      nrb_max = std::max(nrb_max, Lo.nrb);
+      load_max = std::max(load_max, ((size_t)Lo.ldm * (n + m) + 255) / 256);
+      store_max = std::max(store_max, ((size_t)hlen(n) + 255) / 256);
     }
-    // trailing updates: right on columns k+nbk .. n-1, left on k+nbk .. n+m-1
-    const int rcols = n - (k + nbk);
-    blk_right<<<dim3(Lo.ldm / kRowBlock, (rcols + 63) / 64), 256, 0, s>>>(a);
-    const int lcols = C - (k + nbk);
-    blk_left<<<(lcols + kLeftCols - 1) / kLeftCols, 256, 0, s>>>(a);
+    const unsigned Z = (unsigned)nj;
+    blk_load<<<dim3((unsigned)std::min<size_t>(2048, load_max), 1, Z), 256, 0, s>>>(a);
+    for (int k = 0; k + 2 < nmax; k += kNB) {
+      a.k = k;
+      int nbk_max = 0, rcols = 0, lcols = 0;
+      for (int z = 0; z < nj; ++z) {
+        const int n = a.job[z].out.n, nbk = blk_nbk(n, k);
+        if (nbk <= 0) continue;
+        nbk_max = std::max(nbk_max, nbk);
+        rcols = std::max(rcols, n - (k + nbk));                   // right: columns k+nbk .. n-1
+        lcols = std::max(lcols, n + a.job[z].out.m - (k + nbk));  // left: .. n+m-1
+      }
+      for (int j = 0; j < nbk_max; ++j) {
+        a.j = j;
+        blk_panel<<<dim3(1, 1, Z), kPThreads, 0, s>>>(a);
+        blk_rows<<<dim3((unsigned)nrb_max, 1, Z), 256, 0, s>>>(a);
+      }
+      if (rcols > 0)
+        blk_right<<<dim3((unsigned)(ldm_max / kRowBlock), (unsigned)((rcols + 63) / 64), Z), 256, 0, s>>>(a);
+      if (lcols > 0) blk_left<<<dim3((unsigned)((lcols + kLeftCols - 1) / kLeftCols), 1, Z), 256, 0, s>>>(a);
+    }
+    blk_store<<<dim3((unsigned)std::min<size_t>(1024, store_max), 1, Z), 256, 0, s>>>(a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  const int store_blocks = (int)std::min<size_t>(1024, ((size_t)hlen(n) + 255) / 256);
-  blk_store<<<store_blocks, 256, 0, s>>>(a);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace lti

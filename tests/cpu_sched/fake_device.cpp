@@ -239,7 +239,7 @@ hipError_t launch_reduce(const ReduceLaunch& L, int, hipStream_t s) {
   });
   return hipSuccess;
 }
-hipError_t launch_reduce_blocked(const ReduceJob&, hipStream_t) { return hipSuccess; }
+hipError_t launch_reduce_blocked(const ReduceJob*, int, hipStream_t) { return hipSuccess; }
 
 static void sweep_stub(const SweepLaunch& L) {
   for (int t = 0; t < L.ntiles; ++t) {

@@ -42,3 +42,34 @@ def test_large1024_full_grid_and_repeat(prec):
             assert h.result["n_refined"] + h.result["n_fallback"] == 10_000
             assert h.result["n_refined"] >= 9_990
             assert np.all(h.info["iters"][h.info["path"] == binding.PATH_REFINED] >= 2)
+
+
+def test_blocked_reductions_of_one_pass_side_by_side(monkeypatch):
+    """Models above 256 states of different sizes admitted together share the
+    blocked reduction's launches (one model per blockIdx.z, the column loop
+    of the largest): each result equals the one computed alone, bitwise (the
+    column split of the sweep tiles is pinned, as it decides the order of the
+    output sums), and matches the oracle."""
+    from paper_2401_04068_amd import binding
+
+    monkeypatch.setenv("LTI_FREQRESP_RHS_SPLIT", "1")
+    rng = np.random.default_rng(4700)
+    w = np.concatenate([[0.0, -2.0], wl.logspace_grid(1e-2, 1e2, 9)])
+    shapes = [(257, 3, 2), (300, 1, 4), (384, 5, 5), (520, 2, 3), (290, 4, 1), (333, 2, 2)]
+    mdls = [wl.mixed_pole_model(rng, n, m, p, w) for n, m, p in shapes]
+    alone = []
+    with binding.Engine(arena_bytes=2 << 30) as eng:
+        for (n, m, p), mdl in zip(shapes, mdls):
+            print(f"case blocked alone n={n}", flush=True)
+            h = eng.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+            assert eng.poll(h, -1)
+            alone.append(h.G)
+    with binding.Engine(arena_bytes=2 << 30) as eng:
+        print("case blocked together", flush=True)
+        hs = [eng.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega) for mdl in mdls]
+        for h in hs:
+            assert eng.poll(h, -1)
+    for (n, m, p), mdl, h, g in zip(shapes, mdls, hs, alone):
+        np.testing.assert_array_equal(h.G, g)
+        ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+        assert oracle.rel_err(h.G, ref).max() <= 1e-10, (n, m, p)
