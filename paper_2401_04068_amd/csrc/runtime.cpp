@@ -66,9 +66,6 @@ constexpr size_t kAlign = 256;
 // 32.0 with one batch of 16,384 tiles; the 64-state stream and the open-loop
 // latency were unchanged.
 constexpr int kInflight = 2;
-// Timing mark of a batch's whole sweep phase (its launches may overlap on
-// several streams, so they are timed together).
-constexpr int kSweepPhase = 100;
 // Streams: one admission stream and one sweep stream by default (a process
 // gets few hardware queues, four by default, and streams that share one run
 // in order).  With one admission stream, requests that arrive during a
@@ -81,9 +78,16 @@ constexpr int kAdmitStreams = 2;
 // launches (one per kernel class) are spread over them: the launches of one
 // class often cannot fill the GPU for their whole duration (their waves'
 // lifetimes differ several-fold, so a launch ends with a long tail), and on
-// one stream the next launch would wait for that tail.  The streams join on
-// the context's stream before the batch's refinement and result copies.
+// one stream the next launch would wait for that tail.  The batch's
+// refinement and result copies go to a finishing stream that waits for the
+// batch's launches on every stream it used; the sweep streams are not joined
+// between batches.
 constexpr int kMaxSweepStreams = 3;
+// Two by default: with the admission and finishing streams that makes four,
+// the hardware queues a process gets by default (more streams share queues
+// and then run in order).  Serving mix: 49.7 M points/s refined with two,
+// 46.3 with three.
+constexpr int kDefaultSweepStreams = 2;
 // CUs kept free of sweeps (the library's own sweep streams are created with a
 // CU mask without them), so that reductions -- a chain of small launches for
 // large models -- find room while sweeps fill the rest of the GPU.
@@ -237,7 +241,9 @@ struct Request {
 
 struct Batch {
   hipEvent_t done = nullptr;
-  std::vector<hipEvent_t> joins;  // fork / join events of the sweep streams
+  std::vector<hipEvent_t> joins;   // the end of the batch's sweeps on each stream it used
+  bool joins_timed = false;        // joins come from the timing pool
+  std::vector<hipEvent_t> tstart;  // timing: the start of its sweeps on each stream it used
   // with kernel timing: tev[0] before the first kernel, tev[i + 1] after the
   // launches of family tfam[i]
   std::vector<hipEvent_t> tev;
@@ -347,9 +353,14 @@ using namespace lti;
 
 struct lti_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;              // sweeps, refinement, result copies
-  hipStream_t aux[kMaxSweepStreams - 1] = {};  // more sweep streams (joined on `stream`)
-  int n_sweep_streams = kMaxSweepStreams;
+  hipStream_t stream = nullptr;              // sweeps (and passes while no batch is out)
+  hipStream_t aux[kMaxSweepStreams - 1] = {};  // more sweep streams
+  int n_sweep_streams = kDefaultSweepStreams;
+  // the refinement, record summaries and result copies of the requests a
+  // batch finishes, after the batch's sweeps on every stream it used; the
+  // sweep streams go on with the next batch meanwhile
+  hipStream_t fstream = nullptr;
+  hipEvent_t union_end = nullptr;  // timing: the latest sweep end of the retired batches
   hipStream_t rstreams[kAdmitStreams] = {};  // uploads and reductions
   int next_rstream = 0;
   int n_rstreams = 1;
@@ -934,28 +945,7 @@ void launch(lti_ctx* c) {
   }
   if (total == 0) return;
   hipError_t e = hipSuccess;
-  hipStream_t ss = c->stream;
-  // wait for the uploads and reductions the batch's requests depend on
-  std::vector<PassEvent*> waited;
-  for (auto& cr : b.credit)
-    for (PassEvent* pe : {cr.first->ready, cr.first->model_ready})
-      if (pe && pe->stream != ss && !pass_done(pe) && std::find(waited.begin(), waited.end(), pe) == waited.end()) {
-        waited.push_back(pe);
-        if (e == hipSuccess) e = hipStreamWaitEvent(ss, pe->ev, 0);
-      }
   const bool timed = (c->flags & LTI_CFG_KERNEL_TIMING) != 0;
-  // bracket the launches of one kernel family with timing events
-  auto time_mark = [&](int fam) {
-    if (!timed || e != hipSuccess) return;
-    hipEvent_t ev = get_event(c, true);
-    if (!ev) {
-      e = hipErrorOutOfMemory;
-      return;
-    }
-    e = hipEventRecord(ev, ss);
-    b.tev.push_back(ev);
-    if (fam >= 0) b.tfam.push_back(fam);
-  };
   // the batch's launches: per kernel class, kMaxSegs requests each, with an
   // estimate of their work (tiles x n^2 x (columns + 2)) for balancing
   struct Job {
@@ -993,51 +983,77 @@ void launch(lti_ctx* c) {
       jobs.push_back(jb);
     }
   }
-  // largest first, each to the least loaded sweep stream
+  // largest first, each to the least loaded sweep stream.  The streams are
+  // not joined between batches: a stream whose share of this batch is done
+  // goes on with the next batch's launches while the others finish.
   std::sort(jobs.begin(), jobs.end(), [](const Job& x, const Job& y) { return x.work > y.work; });
   const int ns = jobs.size() > 1 ? c->n_sweep_streams : 1;
-  hipStream_t streams[kMaxSweepStreams] = {ss, c->aux[0], c->aux[1]};
+  hipStream_t streams[kMaxSweepStreams] = {c->stream, c->aux[0], c->aux[1]};
   double load[kMaxSweepStreams] = {0.0, 0.0, 0.0};
-  bool used[kMaxSweepStreams] = {true, false, false};
-  time_mark(-1);
-  hipEvent_t fork = nullptr;
-  if (ns > 1 && e == hipSuccess) {
-    fork = get_event(c, false);
-    e = fork ? hipEventRecord(fork, ss) : hipErrorOutOfMemory;
-    if (fork) b.joins.push_back(fork);
-  }
-  for (const Job& jb : jobs) {
-    if (e != hipSuccess) break;
+  std::vector<int> on(jobs.size());
+  bool used[kMaxSweepStreams] = {false, false, false};
+  for (size_t q = 0; q < jobs.size(); ++q) {
     int si = 0;
     for (int i = 1; i < ns; ++i)
       if (load[i] < load[si]) si = i;
-    if (!used[si]) {
-      e = hipStreamWaitEvent(streams[si], fork, 0);
-      used[si] = true;
-      if (e != hipSuccess) break;
+    load[si] += jobs[q].work;
+    on[q] = si;
+    used[si] = true;
+  }
+  // each stream used first waits for the uploads and reductions the batch's
+  // requests depend on (passes on that stream itself are ordered by it)
+  for (int i = 0; i < ns && e == hipSuccess; ++i) {
+    if (!used[i]) continue;
+    std::vector<const PassEvent*> waited;
+    for (auto& cr : b.credit)
+      for (const PassEvent* pe : {cr.first->ready, cr.first->model_ready})
+        if (pe && pe->stream != streams[i] && !pass_done(pe) &&
+            std::find(waited.begin(), waited.end(), pe) == waited.end()) {
+          waited.push_back(pe);
+          if (e == hipSuccess) e = hipStreamWaitEvent(streams[i], pe->ev, 0);
+        }
+    if (timed && e == hipSuccess) {
+      hipEvent_t ev = get_event(c, true);
+      e = ev ? hipEventRecord(ev, streams[i]) : hipErrorOutOfMemory;
+      if (ev) b.tstart.push_back(ev);
     }
-    load[si] += jb.work;
-    e = launch_any_sweep(jb.k, jb.L, jb.lds, streams[si]);
+  }
+  for (size_t q = 0; q < jobs.size() && e == hipSuccess; ++q) {
+    e = launch_any_sweep(jobs[q].k, jobs[q].L, jobs[q].lds, streams[on[q]]);
     c->stats.sweep_launches++;
   }
-  for (int i = 1; i < ns && e == hipSuccess; ++i) {
+  // the finishing stream waits for the batch's sweeps on every stream used
+  hipStream_t fs = c->fstream;
+  b.joins_timed = timed;
+  for (int i = 0; i < ns && e == hipSuccess; ++i) {
     if (!used[i]) continue;
-    hipEvent_t join = get_event(c, false);
+    hipEvent_t join = get_event(c, timed);
     if (!join) {
       e = hipErrorOutOfMemory;
       break;
     }
     b.joins.push_back(join);
     e = hipEventRecord(join, streams[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ss, join, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(fs, join, 0);
   }
-  // the sweep phase of the batch, all families together
-  time_mark(kSweepPhase);
+  auto time_mark = [&](int fam) {
+    if (!timed || e != hipSuccess) return;
+    hipEvent_t ev = get_event(c, true);
+    if (!ev) {
+      e = hipErrorOutOfMemory;
+      return;
+    }
+    e = hipEventRecord(ev, fs);
+    b.tev.push_back(ev);
+    if (fam >= 0) b.tfam.push_back(fam);
+  };
   // finish the requests whose last tiles are in the batch: the extended
   // refinement of their queued points (the grid is sized by their points; a
   // workgroup that finds the queues empty exits at once), then the results
-  // to host memory
+  // to host memory.  Their earlier tiles, in earlier batches, are done: the
+  // finishing stream runs the batches' finishing work in order.
   if (!fin.empty() && e == hipSuccess) {
+    time_mark(-1);
     DDLaunch D;
     for (size_t i0 = 0; i0 < fin.size() && e == hipSuccess; i0 += kMaxDDSegs) {
       D.nseg = (int)std::min<size_t>(kMaxDDSegs, fin.size() - i0);
@@ -1050,7 +1066,7 @@ void launch(lti_ctx* c) {
         pts += r->K * r->S;
       }
       const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(1024, pts / 32));
-      e = launch_refine_dd(D, grid, ss);
+      e = launch_refine_dd(D, grid, fs);
     }
     time_mark(LTI_KF_REFINE_DD);
     // the summaries of their point records: one table up, one kernel, one
@@ -1064,16 +1080,16 @@ void launch(lti_ctx* c) {
     }
     const int nf = (int)fin.size();
     if (e == hipSuccess)
-      e = hipMemcpyAsync(c->fintab_dev + slot, th, sizeof(FinEntry) * nf, hipMemcpyHostToDevice, ss);
-    if (e == hipSuccess) e = launch_summarize(c->fintab_dev + slot, c->sum_dev + slot, nf, ss);
+      e = hipMemcpyAsync(c->fintab_dev + slot, th, sizeof(FinEntry) * nf, hipMemcpyHostToDevice, fs);
+    if (e == hipSuccess) e = launch_summarize(c->fintab_dev + slot, c->sum_dev + slot, nf, fs);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->sum_host + slot, c->sum_dev + slot, sizeof(PointSummary) * nf, hipMemcpyDeviceToHost,
-                         ss);
-    for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i) e = copy_results(c, fin[i], ss);
+                         fs);
+    for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i) e = copy_results(c, fin[i], fs);
   }
   c->batch_seq++;
   b.done = get_event(c, false);
-  if (e == hipSuccess) e = b.done ? hipEventRecord(b.done, ss) : hipErrorOutOfMemory;
+  if (e == hipSuccess) e = b.done ? hipEventRecord(b.done, fs) : hipErrorOutOfMemory;
   c->stats.tiles_launched += total;
   if (e != hipSuccess) {
     fail_all(c, LTI_EDEVICE);
@@ -1133,22 +1149,49 @@ bool retire(lti_ctx* c) {
       return true;
     }
     if (!b.tev.empty()) {
-      bool counted = false;
       for (size_t i = 0; i + 1 < b.tev.size() && i < b.tfam.size(); ++i) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, b.tev[i], b.tev[i + 1]) != hipSuccess) continue;
         const int f = b.tfam[i];
-        if (f == kSweepPhase) {
-          c->stats.sweep_kernel_ms += ms;
-          counted = true;
-        } else {
-          c->stats.family_ms[f] += ms;
-          c->stats.family_launches[f]++;
-        }
+        c->stats.family_ms[f] += ms;
+        c->stats.family_launches[f]++;
       }
-      if (counted) c->stats.timed_sweep_launches++;
       for (hipEvent_t ev : b.tev) put_event(c, ev, true);
       b.tev.clear();
+    }
+    if (!b.tstart.empty() && b.joins_timed && !b.joins.empty()) {
+      // the batch's sweep interval, from its first start to its last join,
+      // counted where it goes past the end of the batches retired before
+      // (batches overlap on the streams): times relative to tstart[0]
+      float lo = 0.f, hi = 0.f, ms = 0.f;
+      bool ok = true;
+      for (hipEvent_t ev : b.tstart) {
+        ok = ok && hipEventElapsedTime(&ms, b.tstart[0], ev) == hipSuccess;
+        lo = std::min(lo, ms);
+      }
+      size_t last = 0;
+      for (size_t i = 0; i < b.joins.size(); ++i) {
+        ok = ok && hipEventElapsedTime(&ms, b.tstart[0], b.joins[i]) == hipSuccess;
+        if (i == 0 || ms > hi) {
+          hi = ms;
+          last = i;
+        }
+      }
+      float from = lo;
+      if (ok && c->union_end && hipEventElapsedTime(&ms, b.tstart[0], c->union_end) == hipSuccess)
+        from = std::max(from, ms);
+      if (ok) {
+        if (hi > from) c->stats.sweep_kernel_ms += hi - from;
+        c->stats.timed_sweep_launches++;
+        if (!c->union_end || hi > from) {
+          // the batch's last join becomes the new end of the union
+          if (c->union_end) put_event(c, c->union_end, true);
+          c->union_end = b.joins[last];
+          b.joins[last] = nullptr;
+        }
+      }
+      for (hipEvent_t ev : b.tstart) put_event(c, ev, true);
+      b.tstart.clear();
     }
     for (auto& cr : b.credit) {
       Request* r = cr.first;
@@ -1157,7 +1200,8 @@ bool retire(lti_ctx* c) {
       if (r->tiles_done == r->ntiles && r->state == RState::kLive) complete_request(c, r);
     }
     put_event(c, b.done, false);
-    for (hipEvent_t ev : b.joins) put_event(c, ev, false);
+    for (hipEvent_t ev : b.joins)
+      if (ev) put_event(c, ev, b.joins_timed);
     c->inflight.pop_front();
     progressed = true;
   }
@@ -1207,6 +1251,8 @@ void destroy_admit_streams(lti_ctx* c) {
     if (c->aux[i]) (void)hipStreamDestroy(c->aux[i]);
     c->aux[i] = nullptr;
   }
+  if (c->fstream) (void)hipStreamDestroy(c->fstream);
+  c->fstream = nullptr;
 }
 
 bool busy(const lti_ctx* c) {
@@ -1461,6 +1507,7 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   for (int i = 0; i < c->n_rstreams && ok; ++i)
     ok = hipStreamCreateWithFlags(&c->rstreams[i], hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; i + 1 < c->n_sweep_streams && ok; ++i) ok = make_sweep_stream(&c->aux[i]) == hipSuccess;
+  if (ok) ok = hipStreamCreateWithFlags(&c->fstream, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     destroy_admit_streams(c.get());
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -1599,11 +1646,15 @@ int lti_freqresp_destroy(lti_ctx* c) {
   for (hipStream_t as : c->aux)
     if (as) (void)hipStreamSynchronize(as);
   (void)hipStreamSynchronize(c->stream);
+  if (c->fstream) (void)hipStreamSynchronize(c->fstream);
   for (auto& b : c->inflight) {
     put_event(c, b.done, false);
     for (hipEvent_t ev : b.tev) put_event(c, ev, true);
-    for (hipEvent_t ev : b.joins) put_event(c, ev, false);
+    for (hipEvent_t ev : b.tstart) put_event(c, ev, true);
+    for (hipEvent_t ev : b.joins)
+      if (ev) put_event(c, ev, b.joins_timed);
   }
+  if (c->union_end) put_event(c, c->union_end, true);
   for (auto& tp : c->reduce_timing) {
     put_event(c, tp.a, true);
     put_event(c, tp.b, true);
