@@ -361,6 +361,10 @@ struct lti_ctx {
   // sweep streams go on with the next batch meanwhile
   hipStream_t fstream = nullptr;
   hipEvent_t union_end = nullptr;  // timing: the latest sweep end of the retired batches
+  // batches launched and retired (they retire in order), and the last batch
+  // that used each sweep stream and the finishing stream (-1: none)
+  int64_t batches_retired = 0;
+  int64_t last_use[kMaxSweepStreams + 1] = {-1, -1, -1, -1};
   hipStream_t rstreams[kAdmitStreams] = {};  // uploads and reductions
   int next_rstream = 0;
   int n_rstreams = 1;
@@ -1022,11 +1026,27 @@ void launch(lti_ctx* c) {
     e = launch_any_sweep(jobs[q].k, jobs[q].L, jobs[q].lds, streams[on[q]]);
     c->stats.sweep_launches++;
   }
-  // the finishing stream waits for the batch's sweeps on every stream used
-  hipStream_t fs = c->fstream;
+  // The finishing stream waits for the batch's sweeps on every stream used.
+  // A batch on one sweep stream while every earlier batch has retired
+  // finishes on that stream itself: nothing else can be outstanding, and a
+  // short request then makes no cross-stream hop.
+  const int64_t seq = (int64_t)c->batch_seq;
+  int n_used = 0, only = 0;
+  for (int i = 0; i < ns; ++i)
+    if (used[i]) {
+      ++n_used;
+      only = i;
+    }
+  bool inline_finish = n_used == 1;
+  for (int i = 0; i <= kMaxSweepStreams && inline_finish; ++i)
+    if (i != only && c->last_use[i] >= c->batches_retired) inline_finish = false;
+  hipStream_t fs = inline_finish ? streams[only] : c->fstream;
+  for (int i = 0; i < ns; ++i)
+    if (used[i]) c->last_use[i] = seq;
+  if (!inline_finish) c->last_use[kMaxSweepStreams] = seq;
   b.joins_timed = timed;
   for (int i = 0; i < ns && e == hipSuccess; ++i) {
-    if (!used[i]) continue;
+    if (!used[i] || (inline_finish && !timed)) continue;
     hipEvent_t join = get_event(c, timed);
     if (!join) {
       e = hipErrorOutOfMemory;
@@ -1034,7 +1054,7 @@ void launch(lti_ctx* c) {
     }
     b.joins.push_back(join);
     e = hipEventRecord(join, streams[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(fs, join, 0);
+    if (e == hipSuccess && !inline_finish) e = hipStreamWaitEvent(fs, join, 0);
   }
   auto time_mark = [&](int fam) {
     if (!timed || e != hipSuccess) return;
@@ -1203,6 +1223,7 @@ bool retire(lti_ctx* c) {
     for (hipEvent_t ev : b.joins)
       if (ev) put_event(c, ev, b.joins_timed);
     c->inflight.pop_front();
+    c->batches_retired++;
     progressed = true;
   }
   for (auto it = c->live.begin(); it != c->live.end();) {

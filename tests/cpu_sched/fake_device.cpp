@@ -241,7 +241,9 @@ hipError_t launch_reduce(const ReduceLaunch& L, int, hipStream_t s) {
 }
 hipError_t launch_reduce_blocked(const ReduceJob*, int, hipStream_t) { return hipSuccess; }
 
-static void sweep_stub(const SweepLaunch& L) {
+static std::mutex g_merge_mu;  // merged point records of the sweep stand-ins
+
+void sweep_stub(const SweepLaunch& L) {
   for (int t = 0; t < L.ntiles; ++t) {
     int s = 0;
     for (int i = 1; i < L.nseg; ++i)
@@ -266,6 +268,9 @@ static void sweep_stub(const SweepLaunch& L) {
       uint32_t* rec = reinterpret_cast<uint32_t*>(rd.info) + 2 * k;
       const uint32_t w1 = (uint32_t)(1 + j0) | (1u << 8);
       if (rd.flags & kFlagMergeInfo) {
+        // column groups of one point can be on two streams at once (the
+        // device merges with atomic maxima)
+        std::lock_guard<std::mutex> lk(g_merge_mu);
         rec[0] = std::max(rec[0], 0u);
         rec[1] = std::max(rec[1], w1);
       } else {
