@@ -602,6 +602,9 @@ def _damped256(args, sec):
     models = wl.damped256(args.damped_models)
     with binding.Engine(arena_bytes=16 << 30, kernel_timing=True, host_staging_bytes=2 << 30) as eng:
         row = {}
+        for prec in (binding.PREC_REFINED, binding.PREC_FP64):  # untimed: code objects, pinned pages
+            for h in [eng.submit(m.A, m.B, m.C, m.D, m.omega, precision=prec) for m in models[:8]]:
+                eng.wait(h)
         for name, prec in (("refined", binding.PREC_REFINED), ("fp64", binding.PREC_FP64)):
             t0 = time.perf_counter()
             hs = [eng.submit(m.A, m.B, m.C, m.D, m.omega, precision=prec) for m in models]

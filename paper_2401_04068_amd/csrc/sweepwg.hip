@@ -50,6 +50,7 @@ struct ShWG {
   double red[4][8][2];            // per-wavefront partial sums of G
   double misc[4];
   double ring[2][8];              // block reductions (alternating buffers)
+  double ringN[2][4 * 16];        // block reductions of up to 16 values
 };
 
 // Reductions over the workgroup's four wavefronts; every thread gets the same
@@ -88,6 +89,21 @@ struct BlockRed {
     if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = x;
     __syncthreads();
     return fmax(fmax(b[0], b[1]), fmax(b[2], b[3]));
+  }
+  // N (<= 16) sums at once, in place
+  template <int N>
+  __device__ void sumN(double (&v)[N]) {
+    static_assert(N <= 16, "at most 16 sums per call");
+    double* b = sh.ringN[parity];
+    parity ^= 1;
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int q = 0; q < N; ++q) b[4 * q + (threadIdx.x >> 6)] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = (b[4 * q] + b[4 * q + 1]) + (b[4 * q + 2] + b[4 * q + 3]);
   }
 };
 
@@ -742,55 +758,75 @@ __device__ __forceinline__ dd dd_mul_d(dd x, double a) {
 
 struct DDShared {
   ShWG sh;
-  double4 x[kMaxNWG];  // x (re hi, re lo, im hi, im lo) for the row products
+  // x (re hi, re lo, im hi, im lo) of the columns solved together, for the
+  // row products: entry c * CB + j (n CB <= kMaxNWG)
+  double4 x[kMaxNWG];
 };
 
+// The refinement works on CB right-hand sides of one point at once (rows
+// i = tid + 256 r, r < R, of each), so that every block reduction and every
+// float64 sweep serves all of them: (R, CB) = (1, 4) for n <= 256, (2, 2)
+// for n <= 512, (4, 1) above.
+
 // v <- Q^T v (forward = true) or Q v, Q = P_0 ... P_{n-3}.
-__device__ __forceinline__ void apply_q(const ReducedModel& rm, bool forward, double (&vr)[kRWG],
-                                        double (&vi)[kRWG], BlockRed& br) {
+template <int R, int CB>
+__device__ __forceinline__ void apply_q(const ReducedModel& rm, bool forward, double (&vr)[R][CB],
+                                        double (&vi)[R][CB], BlockRed& br) {
   const int n = rm.n, tid = threadIdx.x;
   const gptr<double> V = (gptr<double>)rm.V;
   const gptr<double> tau = (gptr<double>)rm.tau;
   for (int q = 0; q + 2 < n; ++q) {
     const int kk = forward ? q : n - 3 - q;
     const int64_t vo = voff(n, kk) - (kk + 2);
-    double v[kRWG];
-    double pr = 0.0, pi = 0.0;
+    double v[R];
+    double pq[2 * CB];
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
+    for (int j = 0; j < 2 * CB; ++j) pq[j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       const int i = tid + kThreadsWG * r;
       v[r] = (i == kk + 1) ? 1.0 : (i >= kk + 2 && i < n) ? V[vo + i] : 0.0;
-      pr = fma(v[r], vr[r], pr);
-      pi = fma(v[r], vi[r], pi);
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        pq[2 * j] = fma(v[r], vr[r][j], pq[2 * j]);
+        pq[2 * j + 1] = fma(v[r], vi[r][j], pq[2 * j + 1]);
+      }
     }
-    const double2 d = br.sum2(pr, pi);
+    br.sumN<2 * CB>(pq);
     const double t = tau[kk];
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
-      vr[r] = fma(-t * d.x, v[r], vr[r]);
-      vi[r] = fma(-t * d.y, v[r], vi[r]);
-    }
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        vr[r][j] = fma(-t * pq[2 * j], v[r], vr[r][j]);
+        vi[r][j] = fma(-t * pq[2 * j + 1], v[r], vi[r][j]);
+      }
   }
 }
 
-// (s I - H) y = c for one right-hand side through the float64 sweep; on
+// (s I - H) y = c for CB right-hand sides through the float64 sweep; on
 // return y = (yr, yi); returns whether R had a zero diagonal entry.
-__device__ __forceinline__ bool hess_solve(const ReducedModel& rm, SPoint sp, double (&yr)[kRWG],
-                                           double (&yi)[kRWG], ShWG& sh, BlockRed& br) {
-  SWG<double, 1> st;
+template <int R, int CB>
+__device__ __forceinline__ bool hess_solve(const ReducedModel& rm, SPoint sp, double (&yr)[R][CB],
+                                           double (&yi)[R][CB], ShWG& sh, BlockRed& br) {
+  SWG<double, CB> st;
 #pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
-    st.br[r][0] = yr[r];
-    st.bi[r][0] = yi[r];
-  }
-  sweep_wg<double, 1>(rm.H, rm.n, sp.re, sp.im, st, sh);
+  for (int r = 0; r < kRWG; ++r)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      st.br[r][j] = (r < R) ? yr[r < R ? r : 0][j] : 0.0;
+      st.bi[r][j] = (r < R) ? yi[r < R ? r : 0][j] : 0.0;
+    }
+  sweep_wg<double, CB>(rm.H, rm.n, sp.re, sp.im, st, sh);
   const bool singular = br.max(st.singular ? 1.0 : 0.0) > 0.0;
-  apply_rotations_wg<double, 1>(rm.n, st, sh);
+  apply_rotations_wg<double, CB>(rm.n, st, sh);
 #pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
-    yr[r] = st.br[r][0];
-    yi[r] = st.bi[r][0];
-  }
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      yr[r][j] = st.br[r][j];
+      yi[r][j] = st.bi[r][j];
+    }
   return singular;
 }
 
@@ -800,186 +836,286 @@ struct DDResult {
   bool singular;
 };
 
-// x = (s I - A)^{-1} c for one right-hand side c (in the model's own
+// x = (s I - A)^{-1} c for CB right-hand sides c (in the model's own
 // coordinates, float64), refined with the residual in double-double.  On
-// return x = (xr, xi) in double-double; res.est is the last correction norm
-// ||dx|| / ||x||.  If the float64 solve meets an exactly zero diagonal entry
-// of R, returns at once with res.singular and y = (s I - H)^{-1} Q^T c in
-// (yr, yi), reduced coordinates.
-__device__ DDResult refine_solve(const ReducedModel& rm, SPoint sp, double tol, const double (&cr)[kRWG],
-                                 const double (&ci)[kRWG], dd (&xr)[kRWG], dd (&xi)[kRWG], double (&yr)[kRWG],
-                                 double (&yi)[kRWG], DDShared& S, BlockRed& br) {
+// return x = (xr, xi) in double-double; res.est is the largest last
+// correction norm ||dx|| / ||x|| over the columns.  If the float64 solve
+// meets an exactly zero diagonal entry of R, returns at once with
+// res.singular and y = (s I - H)^{-1} Q^T c in (yr, yi), reduced
+// coordinates.
+template <int R, int CB>
+__device__ DDResult refine_solve(const ReducedModel& rm, SPoint sp, double tol, const double (&cr)[R][CB],
+                                 const double (&ci)[R][CB], dd (&xr)[R][CB], dd (&xi)[R][CB],
+                                 double (&yr)[R][CB], double (&yi)[R][CB], DDShared& S, BlockRed& br) {
   const int tid = threadIdx.x;
   const int n = rm.n;
   constexpr int kMaxDD = 4;
   const gptr<double> A0 = (gptr<double>)rm.A0;  // column-major
   DDResult res{0.0, 1, false};
 #pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
-    yr[r] = cr[r];
-    yi[r] = ci[r];
-  }
-  apply_q(rm, true, yr, yi, br);  // Q^T c
-  res.singular = hess_solve(rm, sp, yr, yi, S.sh, br);
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      yr[r][j] = cr[r][j];
+      yi[r][j] = ci[r][j];
+    }
+  apply_q<R, CB>(rm, true, yr, yi, br);  // Q^T c
+  res.singular = hess_solve<R, CB>(rm, sp, yr, yi, S.sh, br);
   if (res.singular) {
     res.est = INFINITY;
     return res;
   }
-  double tr[kRWG], ti[kRWG];
+  double tr[R][CB], ti[R][CB];
 #pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
-    tr[r] = yr[r];
-    ti[r] = yi[r];
-  }
-  apply_q(rm, false, tr, ti, br);  // x = Q y
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
-    xr[r] = dd{tr[r], 0.0};
-    xi[r] = dd{ti[r], 0.0};
+    for (int j = 0; j < CB; ++j) {
+      tr[r][j] = yr[r][j];
+      ti[r][j] = yi[r][j];
+    }
+  apply_q<R, CB>(rm, false, tr, ti, br);  // x = Q y
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      xr[r][j] = dd{tr[r][j], 0.0};
+      xi[r][j] = dd{ti[r][j], 0.0};
+    }
+  double dprev[CB];
+  bool done[CB];
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    dprev[j] = INFINITY;
+    done[j] = false;
   }
-  double dprev = INFINITY;
+  double est[CB];
+#pragma unroll
+  for (int j = 0; j < CB; ++j) est[j] = 0.0;
   for (int it = 0; it < kMaxDD; ++it) {
     // r = c - s x + A0 x, in double-double, then rounded
     __syncthreads();  // S.x of the previous pass has been read
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int i = tid + kThreadsWG * r;
-      if (i < n) S.x[i] = double4{xr[r].hi, xr[r].lo, xi[r].hi, xi[r].lo};
+      if (i < n)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) S.x[i * CB + j] = double4{xr[r][j].hi, xr[r][j].lo, xi[r][j].hi, xi[r][j].lo};
     }
     __syncthreads();
-    dd ar[kRWG], ai[kRWG];
+    dd ar[R][CB], ai[R][CB];
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
-      // c - sg x + w i x:  re = c - sg xr + w xi,  im = ci - sg xi - w xr
-      ar[r] = dd_add(dd_add(dd{cr[r], 0.0}, dd_mul_d(xr[r], -sp.re)), dd_mul_d(xi[r], sp.im));
-      ai[r] = dd_add(dd_add(dd{ci[r], 0.0}, dd_mul_d(xi[r], -sp.re)), dd_mul_d(xr[r], -sp.im));
-    }
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        // c - sg x + w i x:  re = c - sg xr + w xi,  im = ci - sg xi - w xr
+        ar[r][j] = dd_add(dd_add(dd{cr[r][j], 0.0}, dd_mul_d(xr[r][j], -sp.re)), dd_mul_d(xi[r][j], sp.im));
+        ai[r][j] = dd_add(dd_add(dd{ci[r][j], 0.0}, dd_mul_d(xi[r][j], -sp.re)), dd_mul_d(xr[r][j], -sp.im));
+      }
     for (int c = 0; c < n; ++c) {
-      const double4 xc = S.x[c];
 #pragma unroll
-      for (int r = 0; r < kRWG; ++r) {
+      for (int r = 0; r < R; ++r) {
         const int i = tid + kThreadsWG * r;
         if (i < n) {
           const double a = A0[(size_t)c * n + i];
-          ar[r] = dd_add(ar[r], dd_mul_d(dd{xc.x, xc.y}, a));
-          ai[r] = dd_add(ai[r], dd_mul_d(dd{xc.z, xc.w}, a));
+#pragma unroll
+          for (int j = 0; j < CB; ++j) {
+            const double4 xc = S.x[c * CB + j];
+            ar[r][j] = dd_add(ar[r][j], dd_mul_d(dd{xc.x, xc.y}, a));
+            ai[r][j] = dd_add(ai[r][j], dd_mul_d(dd{xc.z, xc.w}, a));
+          }
         }
       }
     }
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
-      tr[r] = ar[r].hi + ar[r].lo;
-      ti[r] = ai[r].hi + ai[r].lo;
-    }
-    // d = Q (s I - H)^{-1} Q^T r
-    apply_q(rm, true, tr, ti, br);
-    hess_solve(rm, sp, tr, ti, S.sh, br);
-    apply_q(rm, false, tr, ti, br);
-    ++res.solves;
-    double d2 = 0.0, x2 = 0.0;
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
-      xr[r] = dd_add(xr[r], dd{tr[r], 0.0});
-      xi[r] = dd_add(xi[r], dd{ti[r], 0.0});
-      d2 += tr[r] * tr[r] + ti[r] * ti[r];
-      x2 += xr[r].hi * xr[r].hi + xi[r].hi * xi[r].hi;
+      for (int j = 0; j < CB; ++j) {
+        tr[r][j] = ar[r][j].hi + ar[r][j].lo;
+        ti[r][j] = ai[r][j].hi + ai[r][j].lo;
+      }
+    // d = Q (s I - H)^{-1} Q^T r
+    apply_q<R, CB>(rm, true, tr, ti, br);
+    hess_solve<R, CB>(rm, sp, tr, ti, S.sh, br);
+    apply_q<R, CB>(rm, false, tr, ti, br);
+    ++res.solves;
+    double nrm[2 * CB];
+#pragma unroll
+    for (int j = 0; j < 2 * CB; ++j) nrm[j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        // a column that has stopped keeps its x
+        const double dr = done[j] ? 0.0 : tr[r][j], di = done[j] ? 0.0 : ti[r][j];
+        xr[r][j] = dd_add(xr[r][j], dd{dr, 0.0});
+        xi[r][j] = dd_add(xi[r][j], dd{di, 0.0});
+        nrm[2 * j] += dr * dr + di * di;
+        nrm[2 * j + 1] += xr[r][j].hi * xr[r][j].hi + xi[r][j].hi * xi[r][j].hi;
+      }
+    br.sumN<2 * CB>(nrm);
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      if (done[j]) continue;
+      const double dn = sqrt(nrm[2 * j]), xn = sqrt(nrm[2 * j + 1]);
+      est[j] = (xn > 0.0) ? dn / xn : (dn > 0.0 ? INFINITY : 0.0);
+      if (!(est[j] > tol) || !(dn < 0.5 * dprev[j])) done[j] = true;  // converged (or x = 0), or stalled
+      dprev[j] = dn;
+      all = all && done[j];
     }
-    const double2 dx = br.sum2(d2, x2);
-    const double dn = sqrt(dx.x), xn = sqrt(dx.y);
-    res.est = (xn > 0.0) ? dn / xn : (dn > 0.0 ? INFINITY : 0.0);
-    if (!(res.est > tol)) break;     // converged (or x = 0 exactly)
-    if (!(dn < 0.5 * dprev)) break;  // no longer contracting
-    dprev = dn;
+    if (all) break;
   }
+#pragma unroll
+  for (int j = 0; j < CB; ++j) res.est = fmax(res.est, est[j]);
   return res;
 }
 
-// out(:, j) = sign * C0 x (+ D(:, j) for G): per-thread double-double sums,
-// then the workgroup sum of the high and low parts.
-__device__ void write_cx(const ReqDesc& rd, const ReducedModel& rm, int j, const dd (&xr)[kRWG],
-                         const dd (&xi)[kRWG], double* out, bool deriv, BlockRed& br) {
+// out(:, j0 + j) = sign * C0 x_j (+ D(:, j0 + j) for G), j < nb: per-thread
+// double-double sums, then the workgroup sum of the high and low parts.
+template <int R, int CB>
+__device__ void write_cx(const ReqDesc& rd, const ReducedModel& rm, int j0, int nb, const dd (&xr)[R][CB],
+                         const dd (&xi)[R][CB], double* out, bool deriv, BlockRed& br) {
   const int tid = threadIdx.x;
   const int n = rm.n, m = rm.m, p = rm.p;
   const gptr<double> C0 = (gptr<double>)rm.C0;  // row-major
   for (int a = 0; a < p; ++a) {
-    dd gr{0.0, 0.0}, gi{0.0, 0.0};
+    dd gr[CB], gi[CB];
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
+    for (int j = 0; j < CB; ++j) gr[j] = gi[j] = dd{0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       const int i = tid + kThreadsWG * r;
       if (i < n) {
         const double c = C0[(size_t)a * n + i];
-        gr = dd_add(gr, dd_mul_d(xr[r], c));
-        gi = dd_add(gi, dd_mul_d(xi[r], c));
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          gr[j] = dd_add(gr[j], dd_mul_d(xr[r][j], c));
+          gi[j] = dd_add(gi[j], dd_mul_d(xi[r][j], c));
+        }
       }
     }
-    const double2 hi = br.sum2(gr.hi, gi.hi);
-    const double2 lo = br.sum2(gr.lo, gi.lo);
-    if (tid == 0) {
+    double v[4 * CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      v[4 * j] = gr[j].hi;
+      v[4 * j + 1] = gi[j].hi;
+      v[4 * j + 2] = gr[j].lo;
+      v[4 * j + 3] = gi[j].lo;
+    }
+    br.sumN<4 * CB>(v);
+    if (tid < CB && tid < nb) {
+      const int j = j0 + tid;
+      double vv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vv[q] = v[4 * 0 + q];
+#pragma unroll
+      for (int jj = 1; jj < CB; ++jj)
+        if (tid == jj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) vv[q] = v[4 * jj + q];
       double2 g;
       if (deriv) {
-        g.x = -(hi.x + lo.x);
-        g.y = -(hi.y + lo.y);
+        g.x = -(vv[0] + vv[2]);
+        g.y = -(vv[1] + vv[3]);
       } else {
-        g.x = (hi.x + lo.x) + ((gptr<double>)rm.D)[a * m + j];
-        g.y = hi.y + lo.y;
+        g.x = (vv[0] + vv[2]) + ((gptr<double>)rm.D)[a * m + j];
+        g.y = vv[1] + vv[3];
       }
       store_c(out, g_index(rd, a, j), g);
     }
   }
 }
 
-// Column j of point k: G(:, j) = C0 x + D(:, j) with x = (s I - A)^{-1}
-// B0(:, j) refined as above; with a derivative requested, also
-// dG/ds(:, j) = -C0 (s I - A)^{-1} x, the second solve refined the same way.
-__device__ DDResult refine_column(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j, DDShared& S,
-                                  BlockRed& br) {
+// Columns j0 .. j0+nb-1 (nb <= CB) of point k: G(:, j) = C0 x + D(:, j) with
+// x = (s I - A)^{-1} B0(:, j) refined as above; with a derivative requested,
+// also dG/ds(:, j) = -C0 (s I - A)^{-1} x, the second solve refined the same
+// way.  Columns past nb solve a zero right-hand side and write nothing.
+template <int R, int CB>
+__device__ DDResult refine_block(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j0, int nb,
+                                 DDShared& S, BlockRed& br) {
   const int tid = threadIdx.x;
   const int n = rm.n;
   const SPoint sp = point_of(rd, k);
   const double tol = 0.1 * rd.rtol;
   const gptr<double> B0 = (gptr<double>)rm.B0;  // column-major
-  double cr[kRWG], ci[kRWG], yr[kRWG], yi[kRWG];
+  double cr[R][CB], ci[R][CB], yr[R][CB], yi[R][CB];
 #pragma unroll
-  for (int r = 0; r < kRWG; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int i = tid + kThreadsWG * r;
-    cr[r] = (i < n) ? B0[(size_t)j * n + i] : 0.0;
-    ci[r] = 0.0;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      cr[r][j] = (i < n && j < nb) ? B0[(size_t)(j0 + j) * n + i] : 0.0;
+      ci[r][j] = 0.0;
+    }
   }
-  dd xr[kRWG], xi[kRWG];
-  DDResult res = refine_solve(rm, sp, tol, cr, ci, xr, xi, yr, yi, S, br);
+  dd xr[R][CB], xi[R][CB];
+  DDResult res = refine_solve<R, CB>(rm, sp, tol, cr, ci, xr, xi, yr, yi, S, br);
   double* G = rd.G + (size_t)k * rd.p * rd.m * 2;
   if (res.singular) {  // the float64 solution as it is (IEEE values)
-    double xr1[kRWG][1], xi1[kRWG][1];
+    for (int j = 0; j < nb; ++j) {
+      double xr1[kRWG][1], xi1[kRWG][1];
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
-      xr1[r][0] = yr[r];
-      xi1[r][0] = yi[r];
+      for (int r = 0; r < kRWG; ++r) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int jj = 0; jj < CB; ++jj)
+            if (rr == r && jj == j) {
+              a = yr[rr][jj];
+              b = yi[rr][jj];
+            }
+        xr1[r][0] = a;
+        xi1[r][0] = b;
+      }
+      write_output_wg<1>(rd, j0 + j, 1, xr1, xi1, G, S.sh);
     }
-    write_output_wg<1>(rd, j, 1, xr1, xi1, G, S.sh);
     return res;
   }
-  write_cx(rd, rm, j, xr, xi, G, false, br);
+  write_cx<R, CB>(rd, rm, j0, nb, xr, xi, G, false, br);
   if (rd.dG) {
 #pragma unroll
-    for (int r = 0; r < kRWG; ++r) {
-      cr[r] = xr[r].hi + xr[r].lo;
-      ci[r] = xi[r].hi + xi[r].lo;
-    }
-    dd x2r[kRWG], x2i[kRWG];
-    const DDResult r2 = refine_solve(rm, sp, tol, cr, ci, x2r, x2i, yr, yi, S, br);
-    write_cx(rd, rm, j, x2r, x2i, rd.dG + (size_t)k * rd.p * rd.m * 2, true, br);
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        cr[r][j] = xr[r][j].hi + xr[r][j].lo;
+        ci[r][j] = xi[r][j].hi + xi[r][j].lo;
+      }
+    dd x2r[R][CB], x2i[R][CB];
+    const DDResult r2 = refine_solve<R, CB>(rm, sp, tol, cr, ci, x2r, x2i, yr, yi, S, br);
+    write_cx<R, CB>(rd, rm, j0, nb, x2r, x2i, rd.dG + (size_t)k * rd.p * rd.m * 2, true, br);
     res.est = fmax(res.est, r2.est);
     res.solves += r2.solves;
   }
   return res;
 }
 
-// One workgroup per queued entry at a time; entries of every segment are
-// spread over the grid.
+// Columns j0 .. j0+mc-1 of point k, CB at a time.
+template <int R, int CB>
+__device__ void refine_columns(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j0, int mc, DDShared& S,
+                               BlockRed& br, double& est, int& solves, bool& singular) {
+  for (int jb = j0; jb < j0 + mc; jb += CB) {
+    const int nb = min(CB, j0 + mc - jb);
+    const DDResult rr = refine_block<R, CB>(rd, rm, k, jb, nb, S, br);
+    est = fmax(est, rr.est);
+    solves = max(solves, rr.solves);
+    singular = singular || rr.singular;
+  }
+}
+
+// Size class of the refinement: (R, CB) = (1, 4), (2, 2), (4, 1).
+__host__ __device__ constexpr int dd_class(int n) { return n <= kThreadsWG ? 0 : n <= 2 * kThreadsWG ? 1 : 2; }
+
+// One workgroup per queued entry at a time; entries of every segment of the
+// kernel's size class are spread over the grid (one kernel per class, so
+// that each is register-allocated for its own block shape).
+template <int R, int CB>
 __global__ __launch_bounds__(kThreadsWG) void refine_dd_kernel(const DDLaunch L) {
+  constexpr int kClass = R == 1 ? 0 : R == 2 ? 1 : 2;
   __shared__ DDShared S;
   for (int sgi = 0; sgi < L.nseg; ++sgi) {
     const DDSeg& g = L.seg[sgi];
+    if (dd_class(g.rm.n) != kClass) continue;
     // entries: one per (point, column group) at most, K x m
     const uint32_t cap = g.rd.n > 0 ? (uint32_t)min((uint64_t)UINT32_MAX, (uint64_t)L.seg[sgi].K * g.rd.m) : 0u;
     const uint32_t cnt = min(*((const volatile uint32_t*)g.rd.fbq), cap);
@@ -992,12 +1128,7 @@ __global__ __launch_bounds__(kThreadsWG) void refine_dd_kernel(const DDLaunch L)
       double est = 0.0;
       int solves = 0;
       bool singular = false;
-      for (int j = j0; j < j0 + mc; ++j) {
-        const DDResult rr = refine_column(g.rd, g.rm, (int64_t)k, j, S, br);
-        est = fmax(est, rr.est);
-        solves = max(solves, rr.solves);
-        singular = singular || rr.singular;
-      }
+      refine_columns<R, CB>(g.rd, g.rm, (int64_t)k, j0, mc, S, br, est, solves, singular);
       if (threadIdx.x == 0) {
         lti_point_info inf;
         inf.est_rel_err = (float)est;
@@ -1034,8 +1165,17 @@ hipError_t launch_sweep_wg(int cls, const SweepLaunch& L, hipStream_t s) {
 hipError_t launch_refine_dd(const DDLaunch& L, int grid, hipStream_t s) {
   if (L.nseg <= 0) return hipSuccess;
   if (L.nseg > kMaxDDSegs || grid <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(refine_dd_kernel, dim3(grid), dim3(kThreadsWG), 0, s, L);
-  return hipGetLastError();
+  bool used[3] = {false, false, false};
+  for (int i = 0; i < L.nseg; ++i) used[dd_class(L.seg[i].rm.n)] = true;
+  using Fn = void (*)(const DDLaunch);
+  static const Fn fns[3] = {refine_dd_kernel<1, 4>, refine_dd_kernel<2, 2>, refine_dd_kernel<4, 1>};
+  for (int c = 0; c < 3; ++c) {
+    if (!used[c]) continue;
+    hipLaunchKernelGGL(fns[c], dim3(grid), dim3(kThreadsWG), 0, s, L);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace lti
