@@ -43,6 +43,7 @@ struct SWG {
 // LDS of one workgroup (bytes sized for MM <= 4 and T = double).
 struct ShWG {
   double piv[2][2 + 2 * 4];       // carry entry and right-hand side of the pivot row
+  double subd[kMaxNWG];           // H(j + 1, j) of the sweep's model (as T)
   double segA[4 * kRWG];          // scan: per-segment products
   double segU[4 * kRWG][2 * 4];   // scan: per-segment sums (complex, per column)
   double tin[4 * kRWG][2 * 4];    // scan: carry into each segment
@@ -111,7 +112,6 @@ template <typename T, int MM>
 __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, MM>& st, ShWG& sh) {
   const int tid = threadIdx.x;
   const gptr<T> H = (gptr<T>)Hg;
-  const cptr<T> Hs = (cptr<T>)Hg;
   st.singular = false;
   {
     const int off = hoff32(n - 1);
@@ -138,11 +138,14 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, M
       if (i <= n - 1) hc[r] = H[off + i];
     }
   }
-  T sub0 = (n >= 2) ? Hs[hoff32(n - 2) + n - 1] : (T)0;
-  T sub1 = (n >= 3) ? Hs[hoff32(n - 3) + n - 2] : (T)0;
+  // the subdiagonal, read by every step, into LDS (ordered before its first
+  // read by the first step's barrier; the previous sweep's reads ended at its
+  // closing barrier)
+  T* const subd = reinterpret_cast<T*>(sh.subd);
+  for (int j = tid; j < n - 1; j += kThreadsWG) subd[j] = H[hoff32(j) + j + 1];
   for (int k = n - 1; k >= 1; --k) {
     const int tk = k % kThreadsWG, rk = k / kThreadsWG;
-    double* slot = sh.piv[k & 1];
+    T* slot = reinterpret_cast<T*>(sh.piv[k & 1]);
     if (tid == tk) {
       // select the pivot slice's values (selects, not a branch per slice:
       // merged branches turn into pointer phis that keep st in memory)
@@ -166,7 +169,7 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, M
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2 + 2 * MM; ++q) slot[q] = (double)pv[q];
+      for (int q = 0; q < 2 + 2 * MM; ++q) slot[q] = pv[q];
     }
     T hn[kRWG];
 #pragma unroll
@@ -179,16 +182,15 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, M
         if (r <= rk && i <= k - 1) hn[r] = H[off + i];
       }
     }
-    const T sub2 = (k >= 3) ? Hs[hoff32(k - 3) + k - 2] : (T)0;
     __syncthreads();
-    const T ar = (T)slot[0], ai = (T)slot[1];
+    const T ar = slot[0], ai = slot[1];
     T bkr[MM], bki[MM];
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
-      bkr[j] = (T)slot[2 + 2 * j];
-      bki[j] = (T)slot[3 + 2 * j];
+      bkr[j] = slot[2 + 2 * j];
+      bki[j] = slot[3 + 2 * j];
     }
-    const T beta = -sub0;
+    const T beta = -subd[k - 1];
     const T nrm2 = ar * ar + ai * ai + beta * beta;
     const bool ok = nrm2 > (T)0;
     const T rq = rsqrt_t(ok ? nrm2 : (T)1);
@@ -235,8 +237,6 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, M
     }
 #pragma unroll
     for (int r = 0; r < kRWG; ++r) hc[r] = hn[r];
-    sub0 = sub1;
-    sub1 = sub2;
   }
   // R(0,0): the final carry entry of row 0 (thread 0, slice 0)
   if (tid == 0) {
