@@ -35,6 +35,7 @@ error against the CPU oracle is <= 1e-10.  Also reported:
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import multiprocessing as mp
@@ -393,8 +394,16 @@ def serving_headline(args, out):
                 "run_ms": _pct([(x["t_done_us"] - x["t_first_launch_us"]) * 1e-6 for x in rs]),
             }
 
-        cold = replay()
-        open_loop = replay()
+        # the submitting thread's own pauses count as latency (submit_lag);
+        # Python's cyclic collector, which a replay's allocations trigger and
+        # which walks every live object of the process, is held off meanwhile
+        gc.collect()
+        gc.disable()
+        try:
+            cold = replay()
+            open_loop = replay()
+        finally:
+            gc.enable()
         open_loop["first_replay"] = cold
         # closed loop from host memory (H2D and D2H inside the timed region)
         t0 = time.perf_counter()
