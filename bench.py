@@ -405,12 +405,21 @@ def serving_headline(args, out):
         finally:
             gc.enable()
         open_loop["first_replay"] = cold
-        # closed loop from host memory (H2D and D2H inside the timed region)
-        t0 = time.perf_counter()
-        hs = [eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED) for r in reqs]
-        for h in hs:
-            eng.wait(h)
-        t_host = time.perf_counter() - t0
+        # closed loop from host memory (H2D and D2H inside the timed region),
+        # twice: the first pass's result arrays are fresh allocations whose
+        # pages the library's result copies touch first (page faults taken
+        # on the thread that copies, about 0.5 s for the mix's 2.9 GB of
+        # results); the second pass is reported
+        t_host_first = None
+        for _ in range(2):
+            hs = None
+            t0 = time.perf_counter()
+            hs = [eng.submit(r.A, r.B, r.C, r.D, r.omega, precision=binding.PREC_REFINED) for r in reqs]
+            for h in hs:
+                eng.wait(h)
+            t_host = time.perf_counter() - t0
+            if t_host_first is None:
+                t_host_first = t_host
         worst_h = 0.0
         for i in samp[::4]:
             worst_h = max(worst_h, float(oracle.rel_err(hs[i].G[sidx[i]], G_ref[i]).max()))
@@ -472,7 +481,9 @@ def serving_headline(args, out):
         "refined_vs_fp64": value / v64 if v64 else None,
         "open_loop": open_loop,
         "pcie_inclusive": {"points_per_s": total / t_host, "wall_s": t_host, "sampled_max_rel_err": worst_h,
-                           "note": "host-memory requests, all submitted at once: H2D and D2H inside"},
+                           "first_pass": {"points_per_s": total / t_host_first, "wall_s": t_host_first},
+                           "note": "host-memory requests, all submitted at once: H2D and D2H inside; second "
+                                   "of two passes (the first touches fresh result arrays)"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "engine_kernel_totals": engine_totals,

@@ -86,10 +86,12 @@ def test_fallback_in_second_column_group_is_reported(eng):
 
 
 @pytest.mark.parametrize("n,m,p", [(1, 1, 1), (2, 3, 3), (5, 2, 4), (64, 4, 4), (100, 3, 5), (256, 2, 2),
-                                   (300, 4, 4), (520, 1, 2)])
+                                   (300, 4, 4), (400, 3, 3), (520, 1, 2), (700, 2, 3)])
 def test_forced_refinement_matches_oracle(n, m, p):
     """Every point through the double-double refinement (a testing flag),
-    both precisions, at sizes that span the kernel families."""
+    both precisions, at sizes that span the kernel families and the
+    refinement's column blocks (up to 4, 2 and 1 columns together for
+    n <= 256, <= 512 and above, with ragged last blocks)."""
     from paper_2401_04068_amd import binding
 
     rng = np.random.default_rng(4300 + n)
