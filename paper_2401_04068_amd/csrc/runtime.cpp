@@ -190,7 +190,9 @@ struct Resident {
   uint64_t last_use = 0;
 };
 
-enum class RState { kPending, kLive, kDone, kFailed };
+// kCopy: results in pinned staging, the copy to the caller's arrays not yet
+// done (it runs outside the context's lock)
+enum class RState { kPending, kLive, kCopy, kDone, kFailed };
 
 // Host memory of a request, from the pinned pool when it has room.
 struct HostBuf {
@@ -402,6 +404,11 @@ struct lti_ctx {
   std::mutex mu;
   std::condition_variable cv_work;
   std::condition_variable cv_done;
+  // host-memory requests whose results wait for the copy out of pinned
+  // staging into the caller's arrays; one thread at a time drains the queue
+  // with the lock released (the caller's pages may fault on first touch)
+  std::vector<Request*> copyq;
+  bool copy_busy = false;
   std::thread thread;
   bool stop = false;
   bool device_error = false;
@@ -470,9 +477,13 @@ void pass_release(lti_ctx* c, PassEvent*& pe) {
 
 void fail_all(lti_ctx* c, int code) {
   c->device_error = true;
+  // a queued copy fails with the rest; one that a thread is running (state
+  // kCopy, no longer queued) completes, as its results are whole
+  for (Request* r : c->copyq) r->state = RState::kPending;
+  c->copyq.clear();
   for (auto& kv : c->all) {
     Request* r = kv.second.get();
-    if (r->state != RState::kDone && r->state != RState::kFailed) {
+    if (r->state != RState::kDone && r->state != RState::kFailed && r->state != RState::kCopy) {
       r->state = RState::kFailed;
       r->status = code;
       r->res.status = code;
@@ -591,7 +602,7 @@ void release_request_memory(lti_ctx* c, Request* r) {
   if (r->model) {
     Resident* res = r->model;
     // a user of the model has completed, so its reduction has too
-    if (r->state == RState::kDone) pass_release(c, res->ready);
+    if (r->state == RState::kDone || r->state == RState::kCopy) pass_release(c, res->ready);
     res->refs--;
     r->model = nullptr;
     if (res->key == 0 && res->refs == 0) drop_resident(c, res);
@@ -1120,29 +1131,62 @@ void launch(lti_ctx* c) {
 
 // Results are in pinned staging (the batch that finished the request copied
 // them there): hand them to the caller and count the point records.
+// The copy of a host-memory request's results from pinned staging into the
+// caller's arrays (no context state: runs with the lock released).
+void copy_to_caller(const Request* r) {
+  const lti_request& q = r->req;
+  const HostStage& hs = r->hs;
+  std::memcpy(q.G_out, hs.out.base + hs.offG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
+  if (q.info_out) std::memcpy(q.info_out, hs.out.base + hs.offInfo, sizeof(lti_point_info) * q.n_omega);
+  if (q.dG_out) std::memcpy(q.dG_out, hs.out.base + hs.offDG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
+}
+
+// Last step of a completed request (lock held): its staging goes back to the
+// pool and poll() sees it done.
+void finish_request(lti_ctx* c, Request* r) {
+  release_stage(c, r->hs);
+  if (r->state == RState::kFailed) return;  // failed meanwhile (fail_all)
+  r->res.t_done_us = c->now_us();
+  r->state = RState::kDone;
+  c->stats.requests_done++;
+  c->stats.points_done += r->req.n_omega;
+}
+
+// Copies of the queued requests, with the lock released while they run;
+// callers hold `lk`, which is held again on return.  A thread that finds
+// another one draining returns at once (that one takes the new entries too).
+void drain_copies(lti_ctx* c, std::unique_lock<std::mutex>& lk) {
+  if (c->copy_busy || c->copyq.empty()) return;
+  c->copy_busy = true;
+  while (!c->copyq.empty()) {
+    std::vector<Request*> work;
+    work.swap(c->copyq);
+    lk.unlock();
+    for (const Request* r : work) copy_to_caller(r);
+    lk.lock();
+    for (Request* r : work) finish_request(c, r);
+    c->cv_done.notify_all();
+  }
+  c->copy_busy = false;
+}
+
 void complete_request(lti_ctx* c, Request* r) {
   const lti_request& q = r->req;
   r->res.status = LTI_OK;
   r->res.n_points = q.n_omega;
-  HostStage& hs = r->hs;
-  if (q.mem == LTI_MEM_HOST) {
-    std::memcpy(q.G_out, hs.out.base + hs.offG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
-    if (q.info_out) std::memcpy(q.info_out, hs.out.base + hs.offInfo, sizeof(lti_point_info) * q.n_omega);
-    if (q.dG_out)
-      std::memcpy(q.dG_out, hs.out.base + hs.offDG, sizeof(double) * 2 * (size_t)q.n_omega * q.ny * q.nu);
-  }
   const PointSummary& ps = *r->sum;
   r->res.n_refined = ps.count[LTI_PATH_REFINED];
   r->res.n_fallback = ps.count[LTI_PATH_FALLBACK];
   r->res.n_singular = ps.count[LTI_PATH_SINGULAR];
   r->res.n_fp64_dd = ps.count[LTI_PATH_FP64_DD];
   r->res.max_est_rel_err = std::max(0.0, (double)ps.max_est);
-  release_stage(c, r->hs);
-  r->res.t_done_us = c->now_us();
-  r->state = RState::kDone;
-  c->stats.requests_done++;
-  c->stats.points_done += q.n_omega;
-  release_request_memory(c, r);
+  if (q.mem == LTI_MEM_HOST) {
+    r->state = RState::kCopy;
+    c->copyq.push_back(r);
+  } else {
+    finish_request(c, r);
+  }
+  release_request_memory(c, r);  // the device side is done either way
 }
 
 bool retire(lti_ctx* c) {
@@ -1226,9 +1270,12 @@ bool retire(lti_ctx* c) {
     c->batches_retired++;
     progressed = true;
   }
+  // completed requests leave the live list here, those with a copy still to
+  // run included (the copy queue holds them; poll() may free a request as
+  // soon as it is done, so nothing else may keep a pointer to it)
   for (auto it = c->live.begin(); it != c->live.end();) {
     Request* r = *it;
-    if (r->state == RState::kDone || r->state == RState::kFailed) {
+    if (r->state == RState::kDone || r->state == RState::kFailed || r->state == RState::kCopy) {
       it = c->live.erase(it);
       progressed = true;
       c->cv_done.notify_all();
@@ -1277,7 +1324,8 @@ void destroy_admit_streams(lti_ctx* c) {
 }
 
 bool busy(const lti_ctx* c) {
-  return !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty() || !c->pending.empty();
+  return !c->inflight.empty() || !c->live.empty() || !c->reduce_timing.empty() || !c->pending.empty() ||
+         !c->copyq.empty();
 }
 
 // Makes the context's device current on the calling thread for a scope and
@@ -1307,7 +1355,9 @@ void scheduler(lti_ctx* c) {
       c->cv_work.wait(lk, [&] { return c->stop; });
       break;
     }
-    if (pump(c)) {
+    const bool progressed = pump(c);
+    drain_copies(c, lk);
+    if (progressed) {
       idle_since = Clock::now();
       continue;
     }
@@ -1628,6 +1678,7 @@ int lti_freqresp_poll(lti_ctx* c, uint64_t id, int32_t timeout_us, lti_result* o
       while (!finished() && !c->device_error && Clock::now() - t_start < limit) {
         const bool progressed = pump(c);
         c->client_pump_us.store(c->now_us(), std::memory_order_relaxed);
+        drain_copies(c, lk);
         if (progressed) continue;
         lk.unlock();
         std::this_thread::yield();
