@@ -280,8 +280,8 @@ def timed_steps(eng, mix, precision, steps, warmup, label):
 
 def roofline_of(delta, fam_flops, fp32: bool):
     """The sweep phase of a batch (the launches of every sweep kernel class of
-    the batch, spread over up to three streams and timed together by HIP
-    events on the stream they join on): algorithmic flops per batch over the
+    the batch, spread over the sweep streams and timed by the library as the
+    union of the batches' intervals): algorithmic flops per batch over the
     average phase time, against the vector peak of the arithmetic done."""
     f32 = sum(fam_flops[f][0] for f in SWEEP_FAMILIES)
     f64 = sum(fam_flops[f][1] for f in SWEEP_FAMILIES)
@@ -306,6 +306,9 @@ def roofline_of(delta, fam_flops, fp32: bool):
         "launches": launches,
         "peak_note": ("float64 FMA at 78.6 TFLOP/s, float32 FMA at the chip's 157.3 TFLOP/s vector rate "
                       "(blended by the kernel's flop mix)" if fp32 else "float64 FMA, 78.6 TFLOP/s"),
+        # the library is compiled without packed float32 instructions, so its
+        # float32 FMAs issue at the float64 rate: the rate this code can reach
+        "frac_of_unpacked_peak": achieved / FP64_VALU_PEAK,
     }
 
 
