@@ -51,7 +51,7 @@ struct ShWG {
   double red[4][8][2];            // per-wavefront partial sums of G
   double misc[4];
   double ring[2][8];              // block reductions (alternating buffers)
-  double ringN[2][4 * 16];        // block reductions of up to 16 values
+  double ringN[2][4 * 24];        // block reductions of up to 24 values
 };
 
 // Reductions over the workgroup's four wavefronts; every thread gets the same
@@ -91,10 +91,10 @@ struct BlockRed {
     __syncthreads();
     return fmax(fmax(b[0], b[1]), fmax(b[2], b[3]));
   }
-  // N (<= 16) sums at once, in place
+  // N (<= 24) sums at once, in place
   template <int N>
   __device__ void sumN(double (&v)[N]) {
-    static_assert(N <= 16, "at most 16 sums per call");
+    static_assert(N <= 24, "at most 24 sums per call");
     double* b = sh.ringN[parity];
     parity ^= 1;
 #pragma unroll
@@ -768,39 +768,76 @@ struct DDShared {
 // float64 sweep serves all of them: (R, CB) = (1, 4) for n <= 256, (2, 2)
 // for n <= 512, (4, 1) above.
 
-// v <- Q^T v (forward = true) or Q v, Q = P_0 ... P_{n-3}.
+// v <- Q^T v (forward = true) or Q v, Q = P_0 ... P_{n-3}, P_k = I - tau_k
+// u_k u_k^T.  G reflectors per block reduction: applied in order, the j-th
+// one's dot product with the vector it meets is d_j = u_j^T v -
+// sum_{i<j} tau_i d_i (u_j^T u_i), so one reduction of the u_j^T v and the
+// u_j^T u_i serves the group; then v -= sum_j tau_j d_j u_j.
 template <int R, int CB>
 __device__ __forceinline__ void apply_q(const ReducedModel& rm, bool forward, double (&vr)[R][CB],
                                         double (&vi)[R][CB], BlockRed& br) {
+  constexpr int G = CB >= 4 ? 2 : 4;            // reflectors per reduction
+  constexpr int NX = 2 * G * CB;                // u_j^T v (re, im) per column
+  constexpr int NS = NX + G * (G - 1) / 2;      // and u_j^T u_i, i < j
   const int n = rm.n, tid = threadIdx.x;
+  const int nq = n - 2;
   const gptr<double> V = (gptr<double>)rm.V;
   const gptr<double> tau = (gptr<double>)rm.tau;
-  for (int q = 0; q + 2 < n; ++q) {
-    const int kk = forward ? q : n - 3 - q;
-    const int64_t vo = voff(n, kk) - (kk + 2);
-    double v[R];
-    double pq[2 * CB];
+  for (int q0 = 0; q0 < nq; q0 += G) {
+    double u[G][R], t[G];
 #pragma unroll
-    for (int j = 0; j < 2 * CB; ++j) pq[j] = 0.0;
+    for (int j = 0; j < G; ++j) {
+      const bool live = q0 + j < nq;  // past the last reflector: u = 0, tau = 0
+      const int kk = forward ? q0 + j : n - 3 - (q0 + j);
+      t[j] = live ? tau[kk] : 0.0;
+      const int64_t vo = live ? voff(n, kk) - (kk + 2) : 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = tid + kThreadsWG * r;
-      v[r] = (i == kk + 1) ? 1.0 : (i >= kk + 2 && i < n) ? V[vo + i] : 0.0;
-#pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        pq[2 * j] = fma(v[r], vr[r][j], pq[2 * j]);
-        pq[2 * j + 1] = fma(v[r], vi[r][j], pq[2 * j + 1]);
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + kThreadsWG * r;
+        u[j][r] = !live ? 0.0 : (i == kk + 1) ? 1.0 : (i >= kk + 2 && i < n) ? V[vo + i] : 0.0;
       }
     }
-    br.sumN<2 * CB>(pq);
-    const double t = tau[kk];
+    double sm[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sm[q] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          sm[2 * (j * CB + c)] = fma(u[j][r], vr[r][c], sm[2 * (j * CB + c)]);
+          sm[2 * (j * CB + c) + 1] = fma(u[j][r], vi[r][c], sm[2 * (j * CB + c) + 1]);
+        }
+#pragma unroll
+      for (int j = 1; j < G; ++j)
+#pragma unroll
+        for (int i = 0; i < j; ++i) sm[NX + j * (j - 1) / 2 + i] = fma(u[j][r], u[i][r], sm[NX + j * (j - 1) / 2 + i]);
+    }
+    br.sumN<NS>(sm);
+    double dr[G][CB], di[G][CB];
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        dr[j][c] = sm[2 * (j * CB + c)];
+        di[j][c] = sm[2 * (j * CB + c) + 1];
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+          const double w = t[i] * sm[NX + j * (j - 1) / 2 + i];
+          dr[j][c] = fma(-w, dr[i][c], dr[j][c]);
+          di[j][c] = fma(-w, di[i][c], di[j][c]);
+        }
+      }
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        vr[r][j] = fma(-t * pq[2 * j], v[r], vr[r][j]);
-        vi[r][j] = fma(-t * pq[2 * j + 1], v[r], vi[r][j]);
-      }
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+          vr[r][c] = fma(-t[j] * dr[j][c], u[j][r], vr[r][c]);
+          vi[r][c] = fma(-t[j] * di[j][c], u[j][r], vi[r][c]);
+        }
   }
 }
 
@@ -844,7 +881,7 @@ struct DDResult {
 // res.singular and y = (s I - H)^{-1} Q^T c in (yr, yi), reduced
 // coordinates.
 template <int R, int CB>
-__device__ DDResult refine_solve(const ReducedModel& rm, SPoint sp, double tol, const double (&cr)[R][CB],
+__device__ __forceinline__ DDResult refine_solve(const ReducedModel& rm, SPoint sp, double tol, const double (&cr)[R][CB],
                                  const double (&ci)[R][CB], dd (&xr)[R][CB], dd (&xi)[R][CB],
                                  double (&yr)[R][CB], double (&yi)[R][CB], DDShared& S, BlockRed& br) {
   const int tid = threadIdx.x;
@@ -973,7 +1010,7 @@ __device__ DDResult refine_solve(const ReducedModel& rm, SPoint sp, double tol, 
 // out(:, j0 + j) = sign * C0 x_j (+ D(:, j0 + j) for G), j < nb: per-thread
 // double-double sums, then the workgroup sum of the high and low parts.
 template <int R, int CB>
-__device__ void write_cx(const ReqDesc& rd, const ReducedModel& rm, int j0, int nb, const dd (&xr)[R][CB],
+__device__ __forceinline__ void write_cx(const ReqDesc& rd, const ReducedModel& rm, int j0, int nb, const dd (&xr)[R][CB],
                          const dd (&xi)[R][CB], double* out, bool deriv, BlockRed& br) {
   const int tid = threadIdx.x;
   const int n = rm.n, m = rm.m, p = rm.p;
@@ -1031,7 +1068,7 @@ __device__ void write_cx(const ReqDesc& rd, const ReducedModel& rm, int j0, int 
 // also dG/ds(:, j) = -C0 (s I - A)^{-1} x, the second solve refined the same
 // way.  Columns past nb solve a zero right-hand side and write nothing.
 template <int R, int CB>
-__device__ DDResult refine_block(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j0, int nb,
+__device__ __forceinline__ DDResult refine_block(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j0, int nb,
                                  DDShared& S, BlockRed& br) {
   const int tid = threadIdx.x;
   const int n = rm.n;
@@ -1092,7 +1129,7 @@ __device__ DDResult refine_block(const ReqDesc& rd, const ReducedModel& rm, int6
 
 // Columns j0 .. j0+mc-1 of point k, CB at a time.
 template <int R, int CB>
-__device__ void refine_columns(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j0, int mc, DDShared& S,
+__device__ __forceinline__ void refine_columns(const ReqDesc& rd, const ReducedModel& rm, int64_t k, int j0, int mc, DDShared& S,
                                BlockRed& br, double& est, int& solves, bool& singular) {
   for (int jb = j0; jb < j0 + mc; jb += CB) {
     const int nb = min(CB, j0 + mc - jb);
@@ -1106,39 +1143,57 @@ __device__ void refine_columns(const ReqDesc& rd, const ReducedModel& rm, int64_
 // Size class of the refinement: (R, CB) = (1, 4), (2, 2), (4, 1).
 __host__ __device__ constexpr int dd_class(int n) { return n <= kThreadsWG ? 0 : n <= 2 * kThreadsWG ? 1 : 2; }
 
-// One workgroup per queued entry at a time; entries of every segment of the
-// kernel's size class are spread over the grid (one kernel per class, so
-// that each is register-allocated for its own block shape).
+// One workgroup per queued entry at a time.  The entries of all segments of
+// the kernel's size class are numbered in segment order and dealt out over
+// the grid together, so that the few entries of many requests run side by
+// side (one kernel per class, so that each is register-allocated for its
+// own block shape).
 template <int R, int CB>
 __global__ __launch_bounds__(kThreadsWG) void refine_dd_kernel(const DDLaunch L) {
   constexpr int kClass = R == 1 ? 0 : R == 2 ? 1 : 2;
   __shared__ DDShared S;
-  for (int sgi = 0; sgi < L.nseg; ++sgi) {
-    const DDSeg& g = L.seg[sgi];
-    if (dd_class(g.rm.n) != kClass) continue;
-    // entries: one per (point, column group) at most, K x m
-    const uint32_t cap = g.rd.n > 0 ? (uint32_t)min((uint64_t)UINT32_MAX, (uint64_t)L.seg[sgi].K * g.rd.m) : 0u;
-    const uint32_t cnt = min(*((const volatile uint32_t*)g.rd.fbq), cap);
-    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
-      const uint32_t k = ((gptr<uint32_t>)g.rd.fbq)[2 + 2 * (size_t)e];
-      const uint32_t w1 = ((gptr<uint32_t>)g.rd.fbq)[3 + 2 * (size_t)e];
-      const int j0 = (int)(w1 & 0xffu), mc = (int)((w1 >> 8) & 0xffu);
-      const int solves32 = (int)((w1 >> 16) & 0xffu), reason = (int)(w1 >> 24);
-      BlockRed br(S.sh);
-      double est = 0.0;
-      int solves = 0;
-      bool singular = false;
-      refine_columns<R, CB>(g.rd, g.rm, (int64_t)k, j0, mc, S, br, est, solves, singular);
-      if (threadIdx.x == 0) {
-        lti_point_info inf;
-        inf.est_rel_err = (float)est;
-        inf.iters = (uint8_t)min(255, solves32 + solves);
-        inf.path = singular ? LTI_PATH_SINGULAR : (reason == kReasonStall ? LTI_PATH_FALLBACK : LTI_PATH_FP64_DD);
-        inf.reserved = 0;
-        put_info(g.rd, (int64_t)k, inf);
-      }
-      __syncthreads();  // LDS reuse by the next entry
+  // queued entries per segment: one per (point, column group) at most, K x m
+  uint32_t cnt[kMaxDDSegs];
+  uint32_t total = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxDDSegs; ++i) {
+    cnt[i] = 0;
+    if (i < L.nseg && dd_class(L.seg[i].rm.n) == kClass && L.seg[i].rd.n > 0) {
+      const uint32_t cap = (uint32_t)min((uint64_t)UINT32_MAX, L.seg[i].K * (uint64_t)L.seg[i].rd.m);
+      cnt[i] = min(*((const volatile uint32_t*)L.seg[i].rd.fbq), cap);
     }
+    total += cnt[i];
+  }
+  for (uint32_t e = blockIdx.x; e < total; e += gridDim.x) {
+    // the segment of entry e and its index there (uniform over the workgroup)
+    int sgi = 0;
+    uint32_t loc = e;
+#pragma unroll
+    for (int i = 0; i < kMaxDDSegs - 1; ++i) {
+      if (sgi == i && loc >= cnt[i]) {
+        loc -= cnt[i];
+        sgi = i + 1;
+      }
+    }
+    const DDSeg& g = L.seg[sgi];
+    const uint32_t k = ((gptr<uint32_t>)g.rd.fbq)[2 + 2 * (size_t)loc];
+    const uint32_t w1 = ((gptr<uint32_t>)g.rd.fbq)[3 + 2 * (size_t)loc];
+    const int j0 = (int)(w1 & 0xffu), mc = (int)((w1 >> 8) & 0xffu);
+    const int solves32 = (int)((w1 >> 16) & 0xffu), reason = (int)(w1 >> 24);
+    BlockRed br(S.sh);
+    double est = 0.0;
+    int solves = 0;
+    bool singular = false;
+    refine_columns<R, CB>(g.rd, g.rm, (int64_t)k, j0, mc, S, br, est, solves, singular);
+    if (threadIdx.x == 0) {
+      lti_point_info inf;
+      inf.est_rel_err = (float)est;
+      inf.iters = (uint8_t)min(255, solves32 + solves);
+      inf.path = singular ? LTI_PATH_SINGULAR : (reason == kReasonStall ? LTI_PATH_FALLBACK : LTI_PATH_FP64_DD);
+      inf.reserved = 0;
+      put_info(g.rd, (int64_t)k, inf);
+    }
+    __syncthreads();  // LDS reuse by the next entry
   }
 }
 
