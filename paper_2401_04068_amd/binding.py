@@ -363,11 +363,14 @@ class Engine:
     # ------------------------------------------------------------ requests
     def submit(self, A, B, C, D, omega, precision: int = PREC_FP64, model_key: int = 0,
                rtol: float = 0.0, want_info: bool = True, points: int = POINTS_JW,
-               want_derivative: bool = False, E=None) -> Handle:
+               want_derivative: bool = False, E=None, out=None) -> Handle:
         """Host-memory request; inputs are copied before this returns.
 
         points: POINTS_JW (omega real, s = j omega), POINTS_S (omega complex
-        points s), POINTS_Z (omega = theta in rad/sample, z = exp(j theta))."""
+        points s), POINTS_Z (omega = theta in rad/sample, z = exp(j theta)).
+        out: optional (G, info) host arrays to receive the results (G
+        complex128 (K, p, m), info POINT_INFO_DTYPE (K,) or None), e.g. buffers
+        a caller reuses; by default new arrays are allocated."""
         A, B, C = _f64(A), _f64(B), _f64(C)
         n, m, p = A.shape[0], B.shape[1], C.shape[0]
         Dm = None if D is None else _f64(D)
@@ -377,8 +380,17 @@ class Engine:
         else:
             w = _f64(omega).reshape(-1)
             K = w.shape[0]
-        G = np.empty((K, p, m), dtype=np.complex128)
-        info = np.zeros(K, dtype=POINT_INFO_DTYPE) if want_info else None
+        if out is None:
+            G = np.empty((K, p, m), dtype=np.complex128)
+            info = np.zeros(K, dtype=POINT_INFO_DTYPE) if want_info else None
+        else:
+            G, info = out
+            if (not isinstance(G, np.ndarray) or G.dtype != np.complex128 or G.shape != (K, p, m)
+                    or not G.flags.c_contiguous):
+                raise ValueError("out G must be a C-contiguous complex128 array of shape (K, p, m)")
+            if info is not None and (not isinstance(info, np.ndarray) or info.dtype != POINT_INFO_DTYPE
+                                     or info.shape != (K,) or not info.flags.c_contiguous):
+                raise ValueError("out info must be a C-contiguous POINT_INFO_DTYPE array of shape (K,)")
         req = LtiRequest()
         req.nx, req.nu, req.ny = n, m, p
         req.mem = MEM_HOST
