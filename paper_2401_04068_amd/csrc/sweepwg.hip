@@ -948,17 +948,34 @@ __device__ __forceinline__ DDResult refine_solve(const ReducedModel& rm, SPoint 
         ar[r][j] = dd_add(dd_add(dd{cr[r][j], 0.0}, dd_mul_d(xr[r][j], -sp.re)), dd_mul_d(xi[r][j], sp.im));
         ai[r][j] = dd_add(dd_add(dd{ci[r][j], 0.0}, dd_mul_d(xi[r][j], -sp.re)), dd_mul_d(xr[r][j], -sp.im));
       }
+    // A0's columns are read two ahead of their use (the loads' latency
+    // overlaps two columns' pair arithmetic)
+    double an[2][R];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + kThreadsWG * r;
+        an[q][r] = (i < n && q < n) ? A0[(size_t)q * n + i] : 0.0;
+      }
     for (int c = 0; c < n; ++c) {
+      double a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + kThreadsWG * r;
+        a[r] = an[0][r];
+        an[0][r] = an[1][r];
+        an[1][r] = (i < n && c + 2 < n) ? A0[(size_t)(c + 2) * n + i] : 0.0;
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = tid + kThreadsWG * r;
         if (i < n) {
-          const double a = A0[(size_t)c * n + i];
 #pragma unroll
           for (int j = 0; j < CB; ++j) {
             const double4 xc = S.x[c * CB + j];
-            ar[r][j] = dd_add(ar[r][j], dd_mul_d(dd{xc.x, xc.y}, a));
-            ai[r][j] = dd_add(ai[r][j], dd_mul_d(dd{xc.z, xc.w}, a));
+            ar[r][j] = dd_add(ar[r][j], dd_mul_d(dd{xc.x, xc.y}, a[r]));
+            ai[r][j] = dd_add(ai[r][j], dd_mul_d(dd{xc.z, xc.w}, a[r]));
           }
         }
       }
