@@ -371,6 +371,7 @@ struct lti_ctx {
   int next_rstream = 0;
   int n_rstreams = 1;
   int max_inflight = kInflight;  // sweep batches outstanding
+  int n_cus = 256;               // the device's compute units
   hipStream_t rstream = nullptr;             // the current pass's stream
   PassEvent* last_pass[kAdmitStreams] = {};  // the last pass on each
   // reduction job tables, one per admission stream (a pass claims the
@@ -1096,7 +1097,10 @@ void launch(lti_ctx* c) {
         D.seg[i].K = (uint64_t)r->K;
         pts += r->K * r->S;
       }
-      const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(1024, pts / 32));
+      // at most one workgroup per CU: the kernel's registers allow one
+      // resident workgroup per CU, so a larger grid adds only dispatches
+      // (every launch pays them, and most find their queues empty)
+      const int grid = (int)std::max<int64_t>(16, std::min<int64_t>(c->n_cus, pts / 32));
       e = launch_refine_dd(D, grid, fs);
     }
     time_mark(LTI_KF_REFINE_DD);
@@ -1553,6 +1557,8 @@ int lti_freqresp_create(const lti_config* cfg, lti_ctx** out) {
   std::vector<uint32_t> sweep_mask;
   {
     int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+      c->n_cus = ncu;
     if (reserved_cus > 0 &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
         reserved_cus < ncu) {
