@@ -188,6 +188,7 @@ struct Resident {
   ReducedModel rm{};
   int refs = 0;
   uint64_t last_use = 0;
+  size_t slot = 0;             // its index in the context's resident list
 };
 
 // kCopy: results in pinned staging, the copy to the caller's arrays not yet
@@ -420,6 +421,9 @@ struct lti_ctx {
   std::vector<Request*> live;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
   std::vector<std::unique_ptr<Resident>> residents;
+  // the keyed residents by model key: a lookup per admitted request must not
+  // scan every resident model (thousands stay resident in a serving process)
+  std::unordered_multimap<uint64_t, Resident*> by_key;
   std::deque<Batch> inflight;
   std::deque<TimedPair> reduce_timing;
 
@@ -560,24 +564,43 @@ Need request_need(const lti_request& q, bool needs_model, int sm, int sp) {
 
 Resident* find_resident(lti_ctx* c, const Request& r) {
   if (r.req.model_key == 0) return nullptr;
-  for (auto& up : c->residents) {
-    Resident* res = up.get();
-    if (res->key == r.req.model_key && res->n == r.req.nx && res->m == r.req.nu && res->p == r.req.ny &&
-        res->hash == r.hash && res->trans == r.trans && res->desc == (r.req.E ? 1 : 0))
+  const auto range = c->by_key.equal_range(r.req.model_key);
+  for (auto it = range.first; it != range.second; ++it) {
+    Resident* res = it->second;
+    if (res->n == r.req.nx && res->m == r.req.nu && res->p == r.req.ny && res->hash == r.hash &&
+        res->trans == r.trans && res->desc == (r.req.E ? 1 : 0))
       return res;
   }
   return nullptr;
 }
 
+void add_resident(lti_ctx* c, std::unique_ptr<Resident> up) {
+  Resident* res = up.get();
+  res->slot = c->residents.size();
+  c->residents.push_back(std::move(up));
+  if (res->key != 0) c->by_key.emplace(res->key, res);
+}
+
+// Frees the model's memory and its record (res is invalid afterwards).
 void drop_resident(lti_ctx* c, Resident* res) {
   pass_release(c, res->ready);
   c->arena.release(res->block, res->bytes);
-  for (auto it = c->residents.begin(); it != c->residents.end(); ++it) {
-    if (it->get() == res) {
-      c->residents.erase(it);
-      return;
+  if (res->key != 0) {
+    const auto range = c->by_key.equal_range(res->key);
+    for (auto it = range.first; it != range.second; ++it) {
+      if (it->second == res) {
+        c->by_key.erase(it);
+        break;
+      }
     }
   }
+  // swap with the last record and drop it
+  const size_t s = res->slot;
+  if (s + 1 != c->residents.size()) {
+    c->residents[s] = std::move(c->residents.back());
+    c->residents[s]->slot = s;
+  }
+  c->residents.pop_back();
 }
 
 // Allocate, evicting unreferenced resident models (least recently used
@@ -670,7 +693,7 @@ bool admit_one(lti_ctx* c, Request* r, PassWork& pw) {
     res->block = mblock;
     res->bytes = nd.model;
     reduced_layout(mblock, n, sm, sp, r->trans, &res->rm, q.E != nullptr);
-    c->residents.push_back(std::move(up));
+    add_resident(c, std::move(up));
     c->stats.reductions++;
   } else {
     c->stats.reduction_cache_hits++;
@@ -1762,8 +1785,12 @@ int lti_freqresp_get_reduced(lti_ctx* c, uint64_t key, int32_t nx, int32_t nu, i
   {
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->device_error) return LTI_EDEVICE;
-    for (auto& up : c->residents)
-      if (up->key == key && up->n == nx && up->m == nu && up->p == ny) held = up.get();
+    // the most recently used model of this key and these sizes
+    const auto range = c->by_key.equal_range(key);
+    for (auto it = range.first; it != range.second; ++it) {
+      Resident* res = it->second;
+      if (res->n == nx && res->m == nu && res->p == ny && (!held || res->last_use > held->last_use)) held = res;
+    }
     if (!held) return LTI_ENOENT;
     rm = held->rm;
     held->refs++;
