@@ -41,6 +41,45 @@ def test_arena_pressure_requests_wait_and_match(monkeypatch):
         assert oracle.rel_err(h.G[sub], ref).max() <= 1e-9
 
 
+def test_many_keyed_models_reused_and_evicted(monkeypatch):
+    """Hundreds of models under their own keys in an arena that holds only
+    part of them: a second round of queries reuses the models still resident
+    and reduces the evicted ones again (least recently used first); every
+    result equals the first round's bit for bit (column split fixed) and the
+    oracle's."""
+    from paper_2401_04068_amd import binding
+
+    monkeypatch.setenv("LTI_FREQRESP_RHS_SPLIT", "1")
+    rng = np.random.default_rng(4800)
+    w = wl.logspace_grid(1e-2, 1e2, 48)
+    mdls = [wl.mixed_pole_model(rng, int(rng.integers(24, 72)), 2, 2, w) for _ in range(240)]
+    with binding.Engine(arena_bytes=8 << 20) as e:
+        first = []
+        for i, mdl in enumerate(mdls):
+            h = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, model_key=5000 + i)
+            first.append(h)
+        for h in first:
+            assert e.poll(h, -1)
+        # the second round in reverse: the most recently used come first
+        second = [None] * len(mdls)
+        for i in reversed(range(len(mdls))):
+            mdl = mdls[i]
+            second[i] = e.submit(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega, model_key=5000 + i)
+        for h in second:
+            assert e.poll(h, -1)
+        st = e.stats()
+    reused = sum(h.result["reduction_reused"] for h in second)
+    print(f"keyed models: {reused} of {len(mdls)} reused in the second round", flush=True)
+    assert 0 < reused < len(mdls)
+    assert st["reductions"] + st["reduction_cache_hits"] == 2 * len(mdls)
+    assert st["reduction_cache_hits"] == reused
+    for i, (mdl, h1, h2) in enumerate(zip(mdls, first, second)):
+        assert np.array_equal(h1.G, h2.G), i
+        if i % 16 == 0:
+            ref = oracle.freqresp(mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega)
+            assert oracle.rel_err(h2.G, ref).max() <= 1e-10
+
+
 def test_pending_queue_bound_returns_eagain():
     from paper_2401_04068_amd import binding
 
