@@ -166,3 +166,39 @@ def test_damped_batch_side_by_side(eng):
         worst = max(worst, float(err.max()))
         assert err.max() <= TOL, (j, err.max(), int(idx[err.argmax()]), kap[idx[err.argmax()]])
     print(f"damped batch: sampled max err {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("case", ["B_1e36", "A_w_1e20", "B_1e39", "B_1e-42", "C_1e-30"])
+@pytest.mark.parametrize("n", [40, 100, 300])
+def test_values_at_the_edges_of_float32(eng, case, n):
+    """Models whose numbers leave float32's range, on the refined path:
+    right-hand sides above float32's maximum (1e39) or in its subnormal range
+    (1e-42), right-hand sides whose products overflow (1e36), a matrix and
+    grid scaled by 1e20 (squares above float32's maximum), tiny outputs.
+    Every point must come out of the refinement or the float64 fallback within
+    the refined tolerance of the oracle (relative error is scale-invariant)."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(4900 + n)
+    w = wl.logspace_grid(1e-2, 1e2, 24)
+    mdl = wl.mixed_pole_model(rng, n, 3, 2, w)
+    A, B, C, D, om = mdl.A, mdl.B, mdl.C, mdl.D, mdl.omega
+    if case == "B_1e36":
+        B, D = B * 1e36, D * 1e36
+    elif case == "A_w_1e20":
+        A, om = A * 1e20, om * 1e20
+    elif case == "B_1e39":
+        B, D = B * 1e39, D * 1e39
+    elif case == "B_1e-42":
+        B, D = B * 1e-42, D * 1e-42
+    else:
+        C, D = C * 1e-30, D * 1e-30
+    ref = oracle.freqresp(A, B, C, D, om)
+    print(f"case float32 edges {case} n={n}", flush=True)
+    h = eng.submit(A, B, C, D, om, precision=binding.PREC_REFINED)
+    assert eng.poll(h, -1)
+    assert np.all(np.isfinite(h.G.view(np.float64)))
+    paths = h.info["path"]
+    assert set(np.unique(paths)) <= {binding.PATH_REFINED, binding.PATH_FALLBACK}
+    err = oracle.rel_err(h.G, ref)
+    assert err.max() <= 1e-9, (case, n, err.max(), int(err.argmax()), int(paths[err.argmax()]))
