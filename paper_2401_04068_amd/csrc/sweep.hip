@@ -165,12 +165,12 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
       const T beta = -sub0;
       const T nrm2 = ar * ar + ai * ai + beta * beta;
       T rinv, c, sr, si;
-      if (nrm2 > (T)0) {
+      if (norm2_ok(nrm2)) {
         rinv = rsqrt_t(nrm2);
         c = beta * rinv;
         sr = ar * rinv;
         si = ai * rinv;
-      } else {  // column already zero: identity rotation, R(k,k) = 0
+      } else {  // zero column (or out of range): identity rotation, flagged
         rinv = (T)INFINITY;
         c = (T)0;
         sr = (T)1;
@@ -265,7 +265,7 @@ __device__ __forceinline__ void givens_sweep(Src<T, kLds> H, int n, T sg, T w, S
   const T ar = readlane(st.cr[0], 0);
   const T ai = readlane(st.ci[0], 0);
   const T d = ar * ar + ai * ai;
-  if (!(d > (T)0)) st.singular = true;
+  if (!norm2_ok(d)) st.singular = true;
   const T dinv = (T)1 / d;
 #pragma unroll
   for (int r = 0; r < R; ++r) {

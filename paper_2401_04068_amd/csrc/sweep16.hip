@@ -253,10 +253,11 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
     } else {
       const T beta = -sub0;
       const T nrm2 = par * par + pai * pai + beta * beta;
-      const bool ok = nrm2 > (T)0;
+      const bool ok = norm2_ok(nrm2);
       const T rq = rsqrt_t(ok ? nrm2 : (T)1);
       // zero column (ok false, then par = pai = beta = 0): a zero rotation
-      // and R(k,k) = 0; the frequency is flagged singular
+      // and R(k,k) = 0; the frequency is flagged singular (also when the
+      // norm is out of the format's range)
       rinv = ok ? rq : (T)INFINITY;
       c = beta * rq;
       sr = par * rq;
@@ -346,7 +347,7 @@ __device__ __forceinline__ void sweep_grp(Src<T, kLds> H, int n, T sg, T w, SG<T
     }
   }
   const T d = ar * ar + ai * ai;
-  st.singular = st.singular || !(d > (T)0);
+  st.singular = st.singular || !norm2_ok(d);
   const T dinv = (T)1 / d;
 #pragma unroll
   for (int r = 0; r < R; ++r) {

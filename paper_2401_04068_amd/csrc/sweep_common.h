@@ -159,6 +159,14 @@ __device__ __forceinline__ float readlane(float v, int l) {
 }
 
 __device__ __forceinline__ double rsqrt_t(double x) { return rsqrt(x); }
+// A squared norm usable for a rotation or a reciprocal: a normal number of
+// the format (not zero, not subnormal, not infinite, not NaN).  A step whose
+// norm falls outside that range -- a zero column, or a model whose scale
+// squares out of the format -- is treated as singular, so that the point is
+// flagged (the float32 solves then hand it to the float64 refinement)
+// instead of returning a silently wrong value.
+__device__ __forceinline__ bool norm2_ok(double x) { return x >= DBL_MIN && x <= DBL_MAX; }
+__device__ __forceinline__ bool norm2_ok(float x) { return x >= FLT_MIN && x <= FLT_MAX; }
 // float32 (the refined path's solves, which its float64 residuals check):
 // the hardware reciprocal square root (1 ulp), with the input held at the
 // smallest normal number instead of the library's rescaling of denormal

@@ -192,7 +192,7 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, M
     }
     const T beta = -subd[k - 1];
     const T nrm2 = ar * ar + ai * ai + beta * beta;
-    const bool ok = nrm2 > (T)0;
+    const bool ok = norm2_ok(nrm2);
     const T rq = rsqrt_t(ok ? nrm2 : (T)1);
     const T rinv = ok ? rq : (T)INFINITY;
     const T c = ok ? beta * rq : (T)0;
@@ -246,7 +246,7 @@ __device__ __forceinline__ void sweep_wg(const T* Hg, int n, T sg, T w, SWG<T, M
   __syncthreads();
   const T ar = (T)sh.misc[0], ai = (T)sh.misc[1];
   const T d = ar * ar + ai * ai;
-  st.singular = st.singular || !(d > (T)0);
+  st.singular = st.singular || !norm2_ok(d);
   const T dinv = (T)1 / d;
 #pragma unroll
   for (int r = 0; r < kRWG; ++r) {

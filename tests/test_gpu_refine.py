@@ -202,3 +202,30 @@ def test_values_at_the_edges_of_float32(eng, case, n):
     assert set(np.unique(paths)) <= {binding.PATH_REFINED, binding.PATH_FALLBACK}
     err = oracle.rel_err(h.G, ref)
     assert err.max() <= 1e-9, (case, n, err.max(), int(err.argmax()), int(paths[err.argmax()]))
+
+
+@pytest.mark.parametrize("scale", [1e-200, 1e-160, 1e-150, 1e-100, 1e100, 1e150, 1e160, 1e200])
+@pytest.mark.parametrize("prec", ["fp64", "refined"])
+def test_extreme_model_scales_are_accurate_or_flagged(eng, scale, prec):
+    """A and the grid scaled together (G itself barely changes): within
+    float64's squared range every point is accurate; beyond it (the rotation
+    norms square out of the format) a point is either accurate or flagged
+    singular, never a silently wrong value."""
+    from paper_2401_04068_amd import binding
+
+    rng = np.random.default_rng(5000)
+    w = wl.logspace_grid(1e-2, 1e2, 8)
+    mdl = wl.mixed_pole_model(rng, 40, 2, 2, w)
+    A, om = mdl.A * scale, mdl.omega * scale
+    ref = oracle.freqresp(A, mdl.B, mdl.C, mdl.D, om)
+    precision = binding.PREC_FP64 if prec == "fp64" else binding.PREC_REFINED
+    print(f"case scale {scale:g} {prec}", flush=True)
+    h = eng.submit(A, mdl.B, mdl.C, mdl.D, om, precision=precision)
+    assert eng.poll(h, -1)
+    with np.errstate(invalid="ignore", over="ignore"):
+        err = oracle.rel_err(h.G, ref)
+    good = np.isfinite(err) & (err <= 1e-9)
+    flagged = h.info["path"] == binding.PATH_SINGULAR
+    assert np.all(good | flagged), (scale, prec, err, h.info["path"])
+    if 1e-150 <= scale <= 1e150:
+        assert np.all(good) and not np.any(flagged)
