@@ -323,13 +323,17 @@ __device__ __forceinline__ double col_value_stream(const Dev& d, int j, int a, i
 }
 
 // Column classes by length: up to 64 R destinations stay in registers
-// (R = 1, 2, 4, 8, 16); longer columns are re-read on every pass.  A kernel
-// instance handles the states whose longest column is in class RMAX, so that
-// its register budget (and occupancy) is set by that class only.
-constexpr int kNumClasses = 6;
-__host__ __device__ constexpr int class_rmax(int c) { return c < 5 ? (1 << c) : 0; }
+// (R = 1, 2, 3, 4, 6, 8, 12, 16: steps of at most half the length, so that a
+// column's registers are not far above what it needs); longer columns are
+// re-read on every pass.  A kernel instance handles the states whose longest
+// column is in class RMAX, so that its register budget (and occupancy) is set
+// by that class only.
+constexpr int kNumClasses = 9;
+constexpr int kClassR[kNumClasses] = {1, 2, 3, 4, 6, 8, 12, 16, 0};
+__host__ __device__ constexpr int class_rmax(int c) { return kClassR[c]; }
 __host__ __device__ inline int class_of_len(int m) {
-  return m <= 64 ? 0 : m <= 128 ? 1 : m <= 256 ? 2 : m <= 512 ? 3 : m <= 1024 ? 4 : 5;
+  return m <= 64 ? 0 : m <= 128 ? 1 : m <= 192 ? 2 : m <= 256 ? 3 : m <= 384 ? 4 : m <= 512 ? 5 : m <= 768 ? 6
+         : m <= 1024 ? 7 : 8;
 }
 
 template <int RMAX>
@@ -339,15 +343,26 @@ __device__ __forceinline__ double col_value(const Dev& d, int j, const double* V
   if (m <= 0) return 0.0;
   if (m <= 64) return col_value_reg<1>(d, j, a, m, V, pess);
   if (RMAX >= 2 && m <= 128) return col_value_reg<(RMAX >= 2 ? 2 : 1)>(d, j, a, m, V, pess);
+  if (RMAX >= 3 && m <= 192) return col_value_reg<(RMAX >= 3 ? 3 : 1)>(d, j, a, m, V, pess);
   if (RMAX >= 4 && m <= 256) return col_value_reg<(RMAX >= 4 ? 4 : 1)>(d, j, a, m, V, pess);
+  if (RMAX >= 6 && m <= 384) return col_value_reg<(RMAX >= 6 ? 6 : 1)>(d, j, a, m, V, pess);
   if (RMAX >= 8 && m <= 512) return col_value_reg<(RMAX >= 8 ? 8 : 1)>(d, j, a, m, V, pess);
+  if (RMAX >= 12 && m <= 768) return col_value_reg<(RMAX >= 12 ? 12 : 1)>(d, j, a, m, V, pess);
   if (RMAX >= 16 && m <= 1024) return col_value_reg<(RMAX >= 16 ? 16 : 1)>(d, j, a, m, V, pess);
   return col_value_stream(d, j, a, m, V, pess);
 }
 
+// Occupancy floors per class (waves per SIMD): the loads of a column are
+// in flight while the wave waits, so waves are what hides HBM latency; the
+// floors keep each class at the occupancy its own registers allow.
+constexpr int step_waves(int rmax) {
+  return rmax <= 3 ? 8 : rmax == 4 ? 7 : rmax == 6 ? 7 : rmax == 8 ? 6 : rmax == 12 ? 4 : 3;
+}
+
 // One iteration of Eq. 2: one wavefront per state.
 template <int RMAX>
-__global__ __launch_bounds__(kThreads) void vi_step_kernel(const StepArgs A) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(step_waves(RMAX)))) void vi_step_kernel(
+    const StepArgs A) {
   __shared__ double wres[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -458,8 +473,9 @@ bool dev_alloc(T** p, size_t n) {
 int blocks_of(int n_states) { return (n_states + kWavesPerBlock - 1) / kWavesPerBlock; }
 
 using StepFn = void (*)(const StepArgs);
-const StepFn kStep[kNumClasses] = {vi_step_kernel<1>, vi_step_kernel<2>, vi_step_kernel<4>,
-                                   vi_step_kernel<8>, vi_step_kernel<16>, vi_step_kernel<0>};
+const StepFn kStep[kNumClasses] = {vi_step_kernel<1>, vi_step_kernel<2>,  vi_step_kernel<3>,
+                                   vi_step_kernel<4>, vi_step_kernel<6>,  vi_step_kernel<8>,
+                                   vi_step_kernel<12>, vi_step_kernel<16>, vi_step_kernel<0>};
 
 }  // namespace
 

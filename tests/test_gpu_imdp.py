@@ -122,7 +122,8 @@ def test_three_state_reward_and_reach_avoid():
 
 # (n_states, n_actions, window): columns of 1 .. 2000+ destinations cover every
 # register class and the streaming path
-SHAPES = [(40, 2, 3), (64, 3, 30), (120, 2, 100), (300, 1, 250), (400, 2, 500), (900, 1, 1000), (2600, 1, 2200)]
+SHAPES = [(40, 2, 3), (64, 3, 30), (120, 2, 100), (150, 2, 160), (300, 1, 250), (350, 1, 300), (400, 2, 500),
+          (700, 1, 600), (900, 1, 1000), (2600, 1, 2200)]
 
 
 MODES = [(True, True), (False, True), (True, False), (False, False)]
