@@ -353,10 +353,13 @@ __device__ __forceinline__ double col_value(const Dev& d, int j, const double* V
 }
 
 // Occupancy floors per class (waves per SIMD): the loads of a column are
-// in flight while the wave waits, so waves are what hides HBM latency; the
-// floors keep each class at the occupancy its own registers allow.
+// in flight while the wave waits, so waves are what hides HBM latency.  The
+// floors are measured: R = 6 gains from 7 waves despite a few spilled values
+// (0.246 against 0.249 ms per iteration at 376 destinations per column),
+// while R = 8 and R = 12 lose with spills (0.150 against 0.162 ms at 451, and
+// 0.214 against 0.249 ms at 701, at 6 and 5 waves instead of 5 and 4).
 constexpr int step_waves(int rmax) {
-  return rmax <= 3 ? 8 : rmax == 4 ? 7 : rmax == 6 ? 7 : rmax == 8 ? 6 : rmax == 12 ? 4 : 3;
+  return rmax <= 3 ? 8 : rmax == 4 ? 7 : rmax == 6 ? 7 : rmax == 8 ? 5 : rmax == 12 ? 4 : 3;
 }
 
 // One iteration of Eq. 2: one wavefront per state.
